@@ -1,0 +1,333 @@
+"""Python access to the FP64 CPU oracle (oracle/octmc_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: only tests/, the smoke check and the benchmark's CPU
+baseline leg import this package.  The product path (paper_2010_06931_amd)
+never imports it and shares no code with it.
+
+Every array handed to the C code is converted to contiguous float64 first;
+displacement fields are [2][h][w][3] (scan, row j, column i, (dx, dy, dz)).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "octmc_oracle.c")
+_LIB = os.path.join(_HERE, "liboctmc_oracle.so")
+
+T_F, T_DATA, T_STR, T_ANG, T_REG, T_MEAN, T_STR05, T_ANG05 = range(8)
+TERM_NAMES = ("F", "data", "str", "ang", "reg", "mean", "str05", "ang05")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("delta0", C.c_double), ("eps_h", C.c_double),
+                ("eps_r", C.c_double), ("flyback_frac", C.c_double), ("mean_weight", C.c_double),
+                ("levels", C.c_int), ("iters", C.c_int), ("lbfgs_m", C.c_int), ("ls_max_evals", C.c_int),
+                ("c1", C.c_double), ("c2", C.c_double), ("merge_kappa", C.c_double),
+                ("merge_tau", C.c_double)]
+
+
+@dataclass
+class Params:
+    alpha: float = 1.0
+    delta0: float = 0.5
+    eps_h: float = 1e-3
+    eps_r: float = 0.1
+    flyback_frac: float = 0.25
+    mean_weight: float = 1.0
+    levels: int = 3
+    iters: int = 100
+    lbfgs_m: int = 5
+    ls_max_evals: int = 20
+    c1: float = 1e-4
+    c2: float = 0.9
+    merge_kappa: float = 1.0
+    merge_tau: float = 0.05
+
+    def c(self) -> _Params:
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+
+class _Report(C.Structure):
+    _fields_ = [("iters", C.c_int), ("evals", C.c_int), ("ls_fail", C.c_int), ("converged", C.c_int),
+                ("f_start", C.c_double), ("f_end", C.c_double)]
+
+
+_FG = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double))
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        L.orc_hermite_taps.argtypes = [C.c_double, dp, dp]
+        L.orc_sample1.argtypes = [dp, C.c_int, C.c_double, dp]
+        L.orc_sample2.argtypes = [dp, C.c_int, C.c_int, C.c_double, C.c_double, dp]
+        L.orc_sample3.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_pseudo_huber.argtypes = [C.c_double, C.c_double, dp]
+        L.orc_eval.argtypes = [dp] * 6 + [C.c_int] * 3 + [dp, C.POINTER(_Params), C.c_double, dp, dp]
+        L.orc_eval.restype = C.c_int
+        L.orc_eta_from_terms.argtypes = [C.c_double, C.c_double]
+        L.orc_eta_from_terms.restype = C.c_double
+        L.orc_pyr_down3.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
+        L.orc_pyr_down2.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.orc_pyr_down1.argtypes = [dp, C.c_int, dp]
+        L.orc_upsample.argtypes = [dp, C.c_int, C.c_int, dp, C.c_int, C.c_int]
+        L.orc_lbfgs.argtypes = [C.c_int, dp, _FG, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double,
+                                C.c_double, C.POINTER(_Report)]
+        L.orc_lbfgs.restype = C.c_int
+        L.orc_register.argtypes = [dp] * 6 + [C.c_int] * 3 + [C.POINTER(_Params), dp, dp]
+        L.orc_register.restype = C.c_int
+        L.orc_density.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.orc_merge.argtypes = [dp] * 6 + [C.c_int] * 3 + [dp, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.orc_enface_mean.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
+        L.orc_substitute_invalid.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ----------------------------------------------------------------------------
+# small building blocks
+
+def hermite_taps(t: float):
+    w = np.zeros(4)
+    dw = np.zeros(4)
+    lib().orc_hermite_taps(float(t), _p(w), _p(dw))
+    return w, dw
+
+
+def sample1(v, x: float):
+    v = _f64(v)
+    out = np.zeros(2)
+    lib().orc_sample1(_p(v), v.shape[0], float(x), _p(out))
+    return out
+
+
+def sample2(img, x: float, y: float):
+    img = _f64(img)
+    out = np.zeros(3)
+    lib().orc_sample2(_p(img), img.shape[1], img.shape[0], float(x), float(y), _p(out))
+    return out
+
+
+def sample3(vol, x: float, y: float, z: float):
+    vol = _f64(vol)
+    out = np.zeros(4)
+    h, w, d = vol.shape
+    lib().orc_sample3(_p(vol), w, h, d, float(x), float(y), float(z), _p(out))
+    return out
+
+
+def pseudo_huber(x: float, eps: float):
+    out = np.zeros(2)
+    lib().orc_pseudo_huber(float(x), float(eps), _p(out))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# objective
+
+@dataclass
+class Level:
+    """One pyramid level of a pair, all float64 numpy arrays."""
+    sx: np.ndarray
+    sy: np.ndarray
+    ax: np.ndarray
+    ay: np.ndarray
+    vx: np.ndarray
+    vy: np.ndarray
+
+    @property
+    def whd(self):
+        h, w, d = self.sx.shape
+        return w, h, d
+
+
+def level_from(sx, sy, ax, ay, vx=None, vy=None) -> Level:
+    sx, sy, ax, ay = _f64(sx), _f64(sy), _f64(ax), _f64(ay)
+    h, w, _ = sx.shape
+    vx = np.ones(h) if vx is None else _f64(vx)
+    vy = np.ones(w) if vy is None else _f64(vy)
+    return Level(sx, sy, ax, ay, vx, vy)
+
+
+def level_from_pair(pair) -> Level:
+    return level_from(pair.sx, pair.sy, pair.ax, pair.ay, pair.vx, pair.vy)
+
+
+def evaluate(lv: Level, D, params: Params | None = None, eta: float = 1.0, grad: bool = True):
+    """Objective terms (dict) and gradient ([2][h][w][3] float64 or None)."""
+    params = params or Params()
+    D = _f64(D)
+    w, h, d = lv.whd
+    assert D.shape == (2, h, w, 3)
+    terms = np.zeros(8)
+    g = np.zeros_like(D) if grad else None
+    pc = params.c()
+    rc = lib().orc_eval(_p(lv.sx), _p(lv.sy), _p(lv.ax), _p(lv.ay), _p(lv.vx), _p(lv.vy), w, h, d,
+                        _p(D), C.byref(pc), float(eta), _p(terms), _p(g) if grad else None)
+    if rc:
+        raise RuntimeError(f"orc_eval failed ({rc})")
+    return dict(zip(TERM_NAMES, terms.tolist())), g
+
+
+def eta_from_terms(s_str05: float, s_ang05: float) -> float:
+    return lib().orc_eta_from_terms(float(s_str05), float(s_ang05))
+
+
+def eta_at(lv: Level, D, params: Params | None = None) -> float:
+    t, _ = evaluate(lv, D, params, 1.0, grad=False)
+    return eta_from_terms(t["str05"], t["ang05"])
+
+
+# ----------------------------------------------------------------------------
+# pyramid, solve, merge
+
+def pyr_down3(vol):
+    vol = _f64(vol)
+    h, w, d = vol.shape
+    out = np.zeros(((h + 1) // 2, (w + 1) // 2, (d + 1) // 2))
+    lib().orc_pyr_down3(_p(vol), w, h, d, _p(out))
+    return out
+
+
+def pyr_down2(img):
+    img = _f64(img)
+    h, w = img.shape
+    out = np.zeros(((h + 1) // 2, (w + 1) // 2))
+    lib().orc_pyr_down2(_p(img), w, h, _p(out))
+    return out
+
+
+def pyr_down1(v):
+    v = _f64(v)
+    out = np.zeros((v.shape[0] + 1) // 2)
+    lib().orc_pyr_down1(_p(v), v.shape[0], _p(out))
+    return out
+
+
+def pyramid(lv: Level, levels: int):
+    out = [lv]
+    for _ in range(1, levels):
+        p = out[-1]
+        out.append(Level(pyr_down3(p.sx), pyr_down3(p.sy), pyr_down2(p.ax), pyr_down2(p.ay),
+                         pyr_down1(p.vx), pyr_down1(p.vy)))
+    return out
+
+
+def upsample(Dc, wf: int, hf: int):
+    Dc = _f64(Dc)
+    _, hc, wc, _ = Dc.shape
+    out = np.zeros((2, hf, wf, 3))
+    lib().orc_upsample(_p(Dc), wc, hc, _p(out), wf, hf)
+    return out
+
+
+def lbfgs(fg, x0, m=5, max_iter=100, ls_max_evals=20, c1=1e-4, c2=0.9):
+    """Minimise a Python objective fg(x) -> (f, g) with the oracle's L-BFGS."""
+    x = _f64(x0).copy()
+    n = x.size
+
+    def cb(_ctx, xp, fp, gp):
+        try:
+            xv = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+            f, g = fg(xv)
+            fp[0] = float(f)
+            np.ctypeslib.as_array(gp, shape=(n,))[:] = np.asarray(g, dtype=np.float64).ravel()
+            return 0
+        except Exception:  # noqa: BLE001 - reported through the return code
+            return 1
+
+    cfun = _FG(cb)
+    rep = _Report()
+    rc = lib().orc_lbfgs(n, _p(x), cfun, None, m, max_iter, ls_max_evals, c1, c2, C.byref(rep))
+    if rc:
+        raise RuntimeError(f"orc_lbfgs failed ({rc})")
+    return x, dict(iters=rep.iters, evals=rep.evals, ls_fail=rep.ls_fail, converged=rep.converged,
+                   f_start=rep.f_start, f_end=rep.f_end)
+
+
+def register(lv: Level, params: Params | None = None):
+    """Full multi-resolution solve; returns D ([2][h][w][3]) and per-level
+    reports (coarsest first)."""
+    params = params or Params()
+    w, h, d = lv.whd
+    D = np.zeros((2, h, w, 3))
+    rep = np.zeros((params.levels, 5))
+    pc = params.c()
+    rc = lib().orc_register(_p(lv.sx), _p(lv.sy), _p(lv.ax), _p(lv.ay), _p(lv.vx), _p(lv.vy), w, h, d,
+                            C.byref(pc), _p(D), _p(rep))
+    if rc:
+        raise RuntimeError(f"orc_register failed ({rc})")
+    reps = [dict(eta=r[0], f_start=r[1], f_end=r[2], iters=int(r[3]), evals=int(r[4])) for r in rep]
+    return D, reps
+
+
+def density(D):
+    D = _f64(D)
+    _, h, w, _ = D.shape
+    out = np.zeros((2, h, w))
+    lib().orc_density(_p(D), w, h, _p(out))
+    return out
+
+
+def merge(sx, sy, D, ox=None, oy=None, vx=None, vy=None, kappa=1.0, tau=0.05):
+    sx, sy, D = _f64(sx), _f64(sy), _f64(D)
+    h, w, d = sx.shape
+    octa = ox is not None
+    ox = _f64(ox) if octa else np.zeros(1)
+    oy = _f64(oy) if octa else np.zeros(1)
+    vx = np.ones(h) if vx is None else _f64(vx)
+    vy = np.ones(w) if vy is None else _f64(vy)
+    m_oct = np.zeros((h, w, d))
+    m_octa = np.zeros((h, w, d)) if octa else None
+    rho = np.zeros((2, h, w))
+    wt = np.zeros((2, h, w))
+    lib().orc_merge(_p(sx), _p(sy), _p(ox), _p(oy), _p(vx), _p(vy), w, h, d, _p(D), float(kappa), float(tau),
+                    _p(m_oct), _p(m_octa) if octa else None, _p(rho), _p(wt))
+    return m_oct, m_octa, rho, wt
+
+
+def enface_mean(vol):
+    vol = _f64(vol)
+    h, w, d = vol.shape
+    out = np.zeros((h, w))
+    lib().orc_enface_mean(_p(vol), w, h, d, _p(out))
+    return out
+
+
+def substitute_invalid(vol, valid, V: int):
+    vol = _f64(vol).copy()
+    valid = _f64(valid)
+    h, w, d = vol.shape
+    lib().orc_substitute_invalid(_p(vol), w, h, d, _p(valid), int(V))
+    return vol

@@ -1,0 +1,912 @@
+/*
+ * octmc oracle: a plain, slow FP64 CPU implementation of orthogonal-raster
+ * OCT/OCTA 3-D motion correction (Ploner et al., "Efficient and high accuracy
+ * 3-D OCT angiography motion correction in pathology", arXiv:2010.06931).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product path (the
+ * HIP library under paper_2010_06931_amd/) shares no code, header, table or
+ * helper with this file, and never calls it.
+ *
+ * Every quantity is computed in double precision with plain loops in the order
+ * the definitions give them; there is no blocking, fusion or reordering beyond
+ * what a definition states.  Per-A-scan partials are summed sequentially in
+ * A-scan index order, so results are deterministic for any thread count.
+ *
+ * Conventions (Sec. 2.1, "definitions"):
+ *   - voxel positions use 0-based pixel coordinates x_i = i, y_j = j, z_k = k;
+ *   - a volume is stored [j][i][k] (depth contiguous), w = h (square, Sec. 5);
+ *   - a displacement field D is [2][h][w][3]: scan V = 0 (X-fast) or 1
+ *     (Y-fast), output A-scan (i, j), component (dx, dy, dz), in pixels of the
+ *     current pyramid level.  Scan V's sample for output voxel (i, j, k) is
+ *     taken at (i + dx, j + dy, k + dz) of its own volume ("pull" field).
+ *
+ * Readings of points the paper leaves open are stated where they are used.
+ * Parity pins for every function live in tests/ (closed forms, invariants,
+ * library routines and finite differences).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define EXPORT __attribute__((visibility("default")))
+
+/* Parameters of the objective and the solver.  Field meaning:
+ *   alpha        weight of the scan-order regulariser R (Eq. 1)
+ *   delta0       default angiography weight (Eq. 8)
+ *   eps_h        pseudo-Huber parameter of the data term (Eq. 4)
+ *   eps_r        pseudo-Huber parameter of R (reading: R uses a smoothed
+ *                absolute difference, Sec. 2.1 "regularizers")
+ *   flyback_frac flyback duration per B-scan as a fraction of the B-scan
+ *                length, in A-scan periods (reading)
+ *   mean_weight  gamma_M of the mean-displacement term M (reading)
+ *   levels, iters, lbfgs_m, ls_max_evals, c1, c2: the L-BFGS solve
+ *   merge_kappa, merge_tau: the density-based merge weights (Sec. 2.1,
+ *                "merging"; reading) */
+typedef struct {
+    double alpha, delta0, eps_h, eps_r, flyback_frac, mean_weight;
+    int levels, iters, lbfgs_m, ls_max_evals;
+    double c1, c2;
+    double merge_kappa, merge_tau;
+} orc_params;
+
+/* Terms returned by orc_eval (indices). */
+enum {
+    T_F = 0,      /* full objective: data + alpha R + M                     */
+    T_DATA = 1,   /* eta S_str + S_ang / eta (Eq. 9)                         */
+    T_STR = 2,    /* S_str at the given delta0 (Eq. 6)                       */
+    T_ANG = 3,    /* S_ang at the given delta0 (Eq. 7)                       */
+    T_REG = 4,    /* R (without alpha)                                       */
+    T_MEAN = 5,   /* M                                                       */
+    T_STR05 = 6,  /* S_str at delta0 = 0.5, used for eta (Eq. 10)            */
+    T_ANG05 = 7,  /* S_ang at delta0 = 0.5                                   */
+    T_COUNT = 8
+};
+
+static inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* ------------------------------------------------------------------------ */
+/* Interpolator I: "Hermitian" interpolation with continuous first
+ * derivatives (Eq. 2 and the text after Eq. 5).  Reading: the cubic Hermite
+ * spline whose knot tangents are central differences (Catmull-Rom).  On the
+ * interval [p_n, p_{n+1}] with t in [0, 1):
+ *   f(t) = h00(t) p_n + h10(t) m_n + h01(t) p_{n+1} + h11(t) m_{n+1},
+ *   m_n = (p_{n+1} - p_{n-1}) / 2,
+ * with the Hermite basis h00 = 2t^3 - 3t^2 + 1, h10 = t^3 - 2t^2 + t,
+ * h01 = -2t^3 + 3t^2, h11 = t^3 - t^2.  Collecting the coefficients of the
+ * four samples p_{n-1}, p_n, p_{n+1}, p_{n+2} gives the tap weights below, and
+ * differentiating the basis gives the derivative weights. */
+EXPORT void orc_hermite_taps(double t, double w[4], double dw[4])
+{
+    double h00 = 2 * t * t * t - 3 * t * t + 1;
+    double h10 = t * t * t - 2 * t * t + t;
+    double h01 = -2 * t * t * t + 3 * t * t;
+    double h11 = t * t * t - t * t;
+    double d00 = 6 * t * t - 6 * t;
+    double d10 = 3 * t * t - 4 * t + 1;
+    double d01 = -6 * t * t + 6 * t;
+    double d11 = 3 * t * t - 2 * t;
+    /* p_{n-1} enters only through m_n, p_{n+2} only through m_{n+1}. */
+    w[0] = -0.5 * h10;
+    w[1] = h00 - 0.5 * h11;
+    w[2] = h01 + 0.5 * h10;
+    w[3] = 0.5 * h11;
+    dw[0] = -0.5 * d10;
+    dw[1] = d00 - 0.5 * d11;
+    dw[2] = d01 + 0.5 * d10;
+    dw[3] = 0.5 * d11;
+}
+
+/* Boundary reading: tap indices are clamped to the volume (constant
+ * extension), so that A-scans sampled beyond a gap replicate the edge
+ * (Sec. 2.1, "merging", describes exactly that replication). */
+
+/* 1-D sample and derivative at x of an array of n values. */
+EXPORT void orc_sample1(const double* v, int n, double x, double out[2])
+{
+    double fx = floor(x);
+    int nx = (int)fx;
+    double w[4], dw[4];
+    orc_hermite_taps(x - fx, w, dw);
+    double val = 0, der = 0;
+    for (int a = 0; a < 4; a++) {
+        double s = v[clampi(nx - 1 + a, 0, n - 1)];
+        val += w[a] * s;
+        der += dw[a] * s;
+    }
+    out[0] = val;
+    out[1] = der;
+}
+
+/* 2-D sample of an image stored [j][i] (w columns, h rows): value, d/dx, d/dy. */
+EXPORT void orc_sample2(const double* img, int w, int h, double x, double y, double out[3])
+{
+    double fx = floor(x), fy = floor(y);
+    int nx = (int)fx, ny = (int)fy;
+    double wx[4], dwx[4], wy[4], dwy[4];
+    orc_hermite_taps(x - fx, wx, dwx);
+    orc_hermite_taps(y - fy, wy, dwy);
+    double val = 0, gx = 0, gy = 0;
+    for (int b = 0; b < 4; b++) {
+        int yy = clampi(ny - 1 + b, 0, h - 1);
+        for (int a = 0; a < 4; a++) {
+            int xx = clampi(nx - 1 + a, 0, w - 1);
+            double s = img[(size_t)yy * w + xx];
+            val += wx[a] * wy[b] * s;
+            gx += dwx[a] * wy[b] * s;
+            gy += wx[a] * dwy[b] * s;
+        }
+    }
+    out[0] = val;
+    out[1] = gx;
+    out[2] = gy;
+}
+
+/* 3-D sample of a volume stored [j][i][k]: value, d/dx, d/dy, d/dz.
+ * Direct 64-tap tensor product. */
+EXPORT void orc_sample3(const double* vol, int w, int h, int d,
+                        double x, double y, double z, double out[4])
+{
+    double fx = floor(x), fy = floor(y), fz = floor(z);
+    int nx = (int)fx, ny = (int)fy, nz = (int)fz;
+    double wx[4], dwx[4], wy[4], dwy[4], wz[4], dwz[4];
+    orc_hermite_taps(x - fx, wx, dwx);
+    orc_hermite_taps(y - fy, wy, dwy);
+    orc_hermite_taps(z - fz, wz, dwz);
+    double val = 0, gx = 0, gy = 0, gz = 0;
+    for (int b = 0; b < 4; b++) {
+        int yy = clampi(ny - 1 + b, 0, h - 1);
+        for (int a = 0; a < 4; a++) {
+            int xx = clampi(nx - 1 + a, 0, w - 1);
+            const double* col = vol + ((size_t)yy * w + xx) * (size_t)d;
+            for (int c = 0; c < 4; c++) {
+                double s = col[clampi(nz - 1 + c, 0, d - 1)];
+                val += wx[a] * wy[b] * wz[c] * s;
+                gx += dwx[a] * wy[b] * wz[c] * s;
+                gy += wx[a] * dwy[b] * wz[c] * s;
+                gz += wx[a] * wy[b] * dwz[c] * s;
+            }
+        }
+    }
+    out[0] = val;
+    out[1] = gx;
+    out[2] = gy;
+    out[3] = gz;
+}
+
+/* Pseudo-Huber loss (Eq. 4): L(x) = eps (sqrt(1 + (x/eps)^2) - 1), written in
+ * the algebraically identical form eps u^2 / (sqrt(1 + u^2) + 1), u = x/eps,
+ * which does not cancel for small |x|.  dL/dx = u / sqrt(1 + u^2). */
+EXPORT void orc_pseudo_huber(double x, double eps, double out[2])
+{
+    double u = x / eps;
+    double s = sqrt(1.0 + u * u);
+    out[0] = eps * u * u / (s + 1.0);
+    out[1] = u / s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Data term of one output A-scan (Eqs. 2-9).  Outputs:
+ *   part[0] = contribution to eta S_str + S_ang / eta   (Eq. 9)
+ *   part[1] = (1 - delta) Lambda                          (Eq. 6 summand)
+ *   part[2] = delta d L(R^A)                              (Eq. 7 summand)
+ *   part[3] = (1 - delta_0.5) Lambda,  part[4] = delta_0.5 d L(R^A)
+ *   g[0..2] = d/d(d^X), g[3..5] = d/d(d^Y) of part[0].
+ * Readings:
+ *   - Eq. 7 writes the angiographic residual with a free depth index k while
+ *     A is a 2-D en face image; the text says the depth sum is replaced by a
+ *     multiplication with d.  So R^A_ij = I(A^X, i+dx^X, j+dy^X) -
+ *     I(A^Y, i+dx^Y, j+dy^Y), weighted by d; dz does not enter it.
+ *   - The resampled validity (Eq. 5) can over- or undershoot [0, 1] at a step
+ *     of v, which would give a negative loss weight; it is clamped to [0, 1]
+ *     and its derivative is 0 where clamped.
+ *   - eta is a constant of the level; no derivative flows through it. */
+static void data_ascan(const double* sx, const double* sy, const double* ax, const double* ay,
+                       const double* vx, const double* vy, int w, int h, int d,
+                       const double* dX, const double* dY, int i, int j,
+                       double delta0, double eps_h, double eta,
+                       double part[5], double g[6])
+{
+    double lam = 0, gam_x[3] = {0, 0, 0}, gam_y[3] = {0, 0, 0};
+    for (int k = 0; k < d; k++) {
+        double ix[4], iy[4], lh[2];
+        orc_sample3(sx, w, h, d, i + dX[0], j + dX[1], k + dX[2], ix);
+        orc_sample3(sy, w, h, d, i + dY[0], j + dY[1], k + dY[2], iy);
+        double r = ix[0] - iy[0]; /* Eq. 2 */
+        orc_pseudo_huber(r, eps_h, lh);
+        lam += lh[0];
+        for (int c = 0; c < 3; c++) {
+            gam_x[c] += lh[1] * ix[1 + c];
+            gam_y[c] += lh[1] * iy[1 + c];
+        }
+    }
+    double jx[3], jy[3], la[2];
+    orc_sample2(ax, w, h, i + dX[0], j + dX[1], jx);
+    orc_sample2(ay, w, h, i + dY[0], j + dY[1], jy);
+    orc_pseudo_huber(jx[0] - jy[0], eps_h, la);
+
+    /* Eq. 5: X validity varies along y (X-fast B-scans are rows j), Y validity
+     * along x (Y-fast B-scans are columns i). */
+    double rx[2], ry[2];
+    orc_sample1(vx, h, j + dX[1], rx);
+    orc_sample1(vy, w, i + dY[0], ry);
+    double tvx = rx[0] <= 0 ? 0 : (rx[0] >= 1 ? 1 : rx[0]);
+    double dtvx = (rx[0] > 0 && rx[0] < 1) ? rx[1] : 0;
+    double tvy = ry[0] <= 0 ? 0 : (ry[0] >= 1 ? 1 : ry[0]);
+    double dtvy = (ry[0] > 0 && ry[0] < 1) ? ry[1] : 0;
+
+    double delta = delta0 * tvx * tvy; /* Eq. 8 */
+    double dd = (double)d;
+    part[0] = eta * (1 - delta) * lam + (dd / eta) * delta * la[0];
+    part[1] = (1 - delta) * lam;
+    part[2] = delta * dd * la[0];
+    part[3] = (1 - 0.5 * tvx * tvy) * lam;
+    part[4] = 0.5 * tvx * tvy * dd * la[0];
+
+    /* d part[0] / d delta */
+    double dpd = -eta * lam + (dd / eta) * la[0];
+    /* X scan: dR/d(d^X) = +grad I^X; Y scan: dR/d(d^Y) = -grad I^Y. */
+    g[0] = eta * (1 - delta) * gam_x[0] + (dd / eta) * delta * la[1] * jx[1];
+    g[1] = eta * (1 - delta) * gam_x[1] + (dd / eta) * delta * la[1] * jx[2] + dpd * delta0 * tvy * dtvx;
+    g[2] = eta * (1 - delta) * gam_x[2];
+    g[3] = -(eta * (1 - delta) * gam_y[0] + (dd / eta) * delta * la[1] * jy[1]) + dpd * delta0 * tvx * dtvy;
+    g[4] = -(eta * (1 - delta) * gam_y[1] + (dd / eta) * delta * la[1] * jy[2]);
+    g[5] = -(eta * (1 - delta) * gam_y[2]);
+}
+
+/* Scan-order regulariser R (Sec. 2.1, "regularizers").  The paper defers the
+ * formula to earlier work; reading: pseudo-Huber (eps_r) of the per-component
+ * difference between displacements of A-scans that are consecutive in the
+ * scan's acquisition order, i.e. along the fast axis with weight 1, and one
+ * link per B-scan boundary (last A-scan of a B-scan to the first of the next)
+ * with the lower weight 1/sqrt(1 + f), f = round(flyback_frac * B-scan length)
+ * A-scan periods of flyback.  The sum is multiplied by d, so the balance
+ * between R and the per-A-scan data term does not depend on depth.
+ * Acquisition order: X-fast visits (i, j) at t = j (w + f) + i, Y-fast at
+ * t = i (h + f) + j.  Adds alpha dR/dD into grad (if grad != NULL) and
+ * returns R. */
+static double reg_term(const double* D, int w, int h, int d, double eps_r, double flyback_frac,
+                       double alpha, double* grad)
+{
+    double total = 0;
+    for (int V = 0; V < 2; V++) {
+        int blen = (V == 0) ? w : h;   /* A-scans per B-scan */
+        int nb = (V == 0) ? h : w;     /* number of B-scans */
+        double f = floor(flyback_frac * blen + 0.5);
+        double wfb = 1.0 / sqrt(1.0 + f);
+        const double* DV = D + (size_t)V * w * h * 3;
+        double* GV = grad ? grad + (size_t)V * w * h * 3 : NULL;
+        long n = (long)nb * blen;
+        for (long t = 0; t + 1 < n; t++) {
+            long t1 = t + 1;
+            int fa = (int)(t % blen), sa = (int)(t / blen);
+            int fb = (int)(t1 % blen), sb = (int)(t1 / blen);
+            /* (fast, slow) -> (i, j) */
+            int ia = (V == 0) ? fa : sa, ja = (V == 0) ? sa : fa;
+            int ib = (V == 0) ? fb : sb, jb = (V == 0) ? sb : fb;
+            double om = (sa == sb) ? 1.0 : wfb;
+            const double* da = DV + ((size_t)ja * w + ia) * 3;
+            const double* db = DV + ((size_t)jb * w + ib) * 3;
+            for (int c = 0; c < 3; c++) {
+                double lh[2];
+                orc_pseudo_huber(db[c] - da[c], eps_r, lh);
+                total += om * d * lh[0];
+                if (GV) {
+                    GV[((size_t)jb * w + ib) * 3 + c] += alpha * om * d * lh[1];
+                    GV[((size_t)ja * w + ia) * 3 + c] -= alpha * om * d * lh[1];
+                }
+            }
+        }
+    }
+    return total;
+}
+
+/* Mean-displacement term M (Sec. 2.1): penalises the sum of displacements of
+ * both scans, fixing the three translational degrees of freedom.  Reading:
+ * M = gamma_M d / (2 N_A) * sum_c (sum_V sum_ij d^V_ij,c)^2, N_A = w h. */
+static double mean_term(const double* D, int w, int h, int d, double gamma, double* grad)
+{
+    double sum[3] = {0, 0, 0};
+    size_t na = (size_t)w * h;
+    for (size_t q = 0; q < 2 * na; q++)
+        for (int c = 0; c < 3; c++) sum[c] += D[q * 3 + c];
+    double m = 0;
+    for (int c = 0; c < 3; c++) m += sum[c] * sum[c];
+    m *= gamma * d / (2.0 * (double)na);
+    if (grad)
+        for (size_t q = 0; q < 2 * na; q++)
+            for (int c = 0; c < 3; c++) grad[q * 3 + c] += gamma * d * sum[c] / (double)na;
+    return m;
+}
+
+/* Full objective (Eq. 1 without the stage-1 tilt term T) and its gradient at
+ * displacement D, with the level constant eta.  terms[T_COUNT] receives the
+ * pieces listed in the enum above; grad ([2][h][w][3]) may be NULL. */
+EXPORT int orc_eval(const double* sx, const double* sy, const double* ax, const double* ay,
+                    const double* vx, const double* vy, int w, int h, int d,
+                    const double* D, const orc_params* p, double eta,
+                    double* terms, double* grad)
+{
+    size_t na = (size_t)w * h;
+    double* part = (double*)malloc(na * 5 * sizeof(double));
+    double* g = (double*)malloc(na * 6 * sizeof(double));
+    if (!part || !g) {
+        free(part);
+        free(g);
+        return -1;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long a = 0; a < (long)na; a++) {
+        int i = (int)(a % w), j = (int)(a / w);
+        data_ascan(sx, sy, ax, ay, vx, vy, w, h, d, D + (size_t)a * 3, D + (na + a) * 3, i, j,
+                   p->delta0, p->eps_h, eta, part + a * 5, g + a * 6);
+    }
+    double s[5] = {0, 0, 0, 0, 0};
+    for (size_t a = 0; a < na; a++)
+        for (int q = 0; q < 5; q++) s[q] += part[a * 5 + q];
+    if (grad) {
+        for (size_t a = 0; a < na; a++)
+            for (int c = 0; c < 3; c++) {
+                grad[a * 3 + c] = g[a * 6 + c];
+                grad[(na + a) * 3 + c] = g[a * 6 + 3 + c];
+            }
+    }
+    double r = reg_term(D, w, h, d, p->eps_r, p->flyback_frac, p->alpha, grad);
+    double m = mean_term(D, w, h, d, p->mean_weight, grad);
+    terms[T_DATA] = s[0];
+    terms[T_STR] = s[1];
+    terms[T_ANG] = s[2];
+    terms[T_STR05] = s[3];
+    terms[T_ANG05] = s[4];
+    terms[T_REG] = r;
+    terms[T_MEAN] = m;
+    terms[T_F] = s[0] + p->alpha * r + m;
+    free(part);
+    free(g);
+    return 0;
+}
+
+/* eta (Eq. 10): sqrt(S_ang_0.5 / S_str_0.5) at the level's initial field.
+ * Reading: where either term is zero (e.g. identical inputs) eta = 1. */
+EXPORT double orc_eta_from_terms(double s_str05, double s_ang05)
+{
+    if (!(s_str05 > 1e-300) || !(s_ang05 > 1e-300)) return 1.0;
+    return sqrt(s_ang05 / s_str05);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Factor-2 pyramid (Sec. 2.1, "optimization").  Reading: all three axes are
+ * halved with ceil(n/2); coarse sample I is the mean of fine samples 2I and
+ * 2I+1, the latter clamped to the last sample for odd sizes.  The en face
+ * images use the 2-D version and the validity vectors the 1-D version ("in the
+ * same way", Sec. 2.2). */
+EXPORT void orc_pyr_down3(const double* in, int w, int h, int d, double* out)
+{
+    int w2 = (w + 1) / 2, h2 = (h + 1) / 2, d2 = (d + 1) / 2;
+    for (int J = 0; J < h2; J++)
+        for (int I = 0; I < w2; I++)
+            for (int K = 0; K < d2; K++) {
+                double s = 0;
+                for (int b = 0; b < 2; b++)
+                    for (int a = 0; a < 2; a++)
+                        for (int c = 0; c < 2; c++) {
+                            int y = clampi(2 * J + b, 0, h - 1);
+                            int x = clampi(2 * I + a, 0, w - 1);
+                            int z = clampi(2 * K + c, 0, d - 1);
+                            s += in[((size_t)y * w + x) * d + z];
+                        }
+                out[((size_t)J * w2 + I) * d2 + K] = s / 8.0;
+            }
+}
+
+EXPORT void orc_pyr_down2(const double* in, int w, int h, double* out)
+{
+    int w2 = (w + 1) / 2, h2 = (h + 1) / 2;
+    for (int J = 0; J < h2; J++)
+        for (int I = 0; I < w2; I++) {
+            double s = 0;
+            for (int b = 0; b < 2; b++)
+                for (int a = 0; a < 2; a++)
+                    s += in[(size_t)clampi(2 * J + b, 0, h - 1) * w + clampi(2 * I + a, 0, w - 1)];
+            out[(size_t)J * w2 + I] = s / 4.0;
+        }
+}
+
+EXPORT void orc_pyr_down1(const double* in, int n, double* out)
+{
+    int n2 = (n + 1) / 2;
+    for (int I = 0; I < n2; I++) out[I] = 0.5 * (in[2 * I] + in[clampi(2 * I + 1, 0, n - 1)]);
+}
+
+/* Level transition: the fine field is twice the bilinear interpolation of the
+ * coarse field at the fine pixel's coarse position ((i - 0.5)/2, (j - 0.5)/2),
+ * clamped to the coarse grid; all three components double because every axis
+ * was halved.  coarse is [2][hc][wc][3], fine [2][hf][wf][3]. */
+EXPORT void orc_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf)
+{
+    for (int V = 0; V < 2; V++)
+        for (int j = 0; j < hf; j++)
+            for (int i = 0; i < wf; i++) {
+                double x = (i - 0.5) / 2.0, y = (j - 0.5) / 2.0;
+                if (x < 0) x = 0;
+                if (x > wc - 1) x = wc - 1;
+                if (y < 0) y = 0;
+                if (y > hc - 1) y = hc - 1;
+                int x0 = (int)floor(x), y0 = (int)floor(y);
+                int x1 = x0 + 1 < wc ? x0 + 1 : wc - 1, y1 = y0 + 1 < hc ? y0 + 1 : hc - 1;
+                double fx = x - x0, fy = y - y0;
+                for (int c = 0; c < 3; c++) {
+                    const double* C = coarse + (size_t)V * wc * hc * 3;
+                    double v00 = C[((size_t)y0 * wc + x0) * 3 + c], v10 = C[((size_t)y0 * wc + x1) * 3 + c];
+                    double v01 = C[((size_t)y1 * wc + x0) * 3 + c], v11 = C[((size_t)y1 * wc + x1) * 3 + c];
+                    double v = (1 - fy) * ((1 - fx) * v00 + fx * v10) + fy * ((1 - fx) * v01 + fx * v11);
+                    fine[(((size_t)V * hf + j) * wf + i) * 3 + c] = 2.0 * v;
+                }
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* L-BFGS (Sec. 2.1: "gradient-based L-BFGS solver").  The paper names only
+ * the method; reading (textbook limited-memory BFGS, Nocedal & Wright,
+ * "Numerical Optimization", Alg. 7.4 / 7.5 with the line search of
+ * Alg. 3.5 / 3.6):
+ *   - memory m pairs; initial inverse Hessian gamma I, gamma = s'y / y'y of
+ *     the newest pair;
+ *   - with an empty memory the direction is -g / max|g| (a step of at most one
+ *     pixel at alpha = 1);
+ *   - a pair is stored only if s'y > 1e-12 y'y;
+ *   - strong Wolfe line search with c1, c2, first trial alpha = 1, doubling
+ *     while bracketing, cubic interpolation in the zoom phase with the
+ *     interpolant kept at least 10 % of the interval away from its ends
+ *     (bisection otherwise), at most ls_max_evals evaluations;
+ *   - the solve stops after max_iter accepted steps, when the line search
+ *     fails, or when max|g| <= 1e-10 max(1, |f|). */
+typedef int (*orc_fg_fn)(void* ctx, const double* x, double* f, double* g);
+
+typedef struct {
+    int iters, evals, ls_fail, converged;
+    double f_start, f_end;
+} orc_lbfgs_report;
+
+typedef struct {
+    int n;
+    orc_fg_fn fg;
+    void* ctx;
+    const double* x;
+    const double* p;
+    double* xt;
+    double* gt;
+    int evals;
+} ls_state;
+
+static double dotn(int n, const double* a, const double* b)
+{
+    double s = 0;
+    for (int q = 0; q < n; q++) s += a[q] * b[q];
+    return s;
+}
+
+/* phi(alpha) = f(x + alpha p) and phi'(alpha) = g(x + alpha p)' p */
+static int ls_eval(ls_state* st, double alpha, double* phi, double* dphi)
+{
+    for (int q = 0; q < st->n; q++) st->xt[q] = st->x[q] + alpha * st->p[q];
+    if (st->fg(st->ctx, st->xt, phi, st->gt)) return -1;
+    st->evals++;
+    *dphi = dotn(st->n, st->gt, st->p);
+    return 0;
+}
+
+/* Minimiser of the cubic that matches phi and phi' at a0 and a1
+ * (Nocedal & Wright eq. 3.59), kept inside the bracket. */
+static double cubic_step(double a0, double f0, double g0, double a1, double f1, double g1)
+{
+    double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0, span = hi - lo;
+    double mid = 0.5 * (a0 + a1);
+    double d1 = g0 + g1 - 3.0 * (f0 - f1) / (a0 - a1);
+    double disc = d1 * d1 - g0 * g1;
+    if (!(disc >= 0)) return mid;
+    double d2 = (a1 > a0 ? 1.0 : -1.0) * sqrt(disc);
+    double den = g1 - g0 + 2.0 * d2;
+    if (den == 0) return mid;
+    double a = a1 - (a1 - a0) * (g1 + d2 - d1) / den;
+    if (!isfinite(a) || a < lo + 0.1 * span || a > hi - 0.1 * span) return mid;
+    return a;
+}
+
+/* Strong Wolfe line search.  On success xt/gt hold the accepted point. */
+static int line_search(ls_state* st, double f0, double g0, double c1, double c2, int max_evals,
+                       double* alpha_out, double* f_out)
+{
+    double a_prev = 0, f_prev = f0, g_prev = g0;
+    double a = 1.0;
+    double lo, flo, glo, hi, fhi, ghi;
+    for (int i = 1;; i++) {
+        if (st->evals >= max_evals) return -1;
+        double fa, ga;
+        if (ls_eval(st, a, &fa, &ga)) return -2;
+        if (fa > f0 + c1 * a * g0 || (i > 1 && fa >= f_prev)) {
+            lo = a_prev; flo = f_prev; glo = g_prev;
+            hi = a; fhi = fa; ghi = ga;
+            break;
+        }
+        if (fabs(ga) <= -c2 * g0) {
+            *alpha_out = a;
+            *f_out = fa;
+            return 0;
+        }
+        if (ga >= 0) {
+            lo = a; flo = fa; glo = ga;
+            hi = a_prev; fhi = f_prev; ghi = g_prev;
+            break;
+        }
+        a_prev = a; f_prev = fa; g_prev = ga;
+        a = 2.0 * a;
+    }
+    /* zoom: lo satisfies sufficient decrease and has the lowest phi so far;
+     * the minimiser lies between lo and hi. */
+    for (;;) {
+        if (st->evals >= max_evals) return -1;
+        double aj = cubic_step(lo, flo, glo, hi, fhi, ghi);
+        double fj, gj;
+        if (ls_eval(st, aj, &fj, &gj)) return -2;
+        if (fj > f0 + c1 * aj * g0 || fj >= flo) {
+            hi = aj; fhi = fj; ghi = gj;
+        } else {
+            if (fabs(gj) <= -c2 * g0) {
+                *alpha_out = aj;
+                *f_out = fj;
+                return 0;
+            }
+            if (gj * (hi - lo) >= 0) {
+                hi = lo; fhi = flo; ghi = glo;
+            }
+            lo = aj; flo = fj; glo = gj;
+        }
+    }
+}
+
+EXPORT int orc_lbfgs(int n, double* x, orc_fg_fn fg, void* ctx, int m, int max_iter,
+                     int ls_max_evals, double c1, double c2, orc_lbfgs_report* rep)
+{
+    double* g = (double*)calloc(n, sizeof(double));
+    double* p = (double*)calloc(n, sizeof(double));
+    double* q = (double*)calloc(n, sizeof(double));
+    double* xt = (double*)calloc(n, sizeof(double));
+    double* gt = (double*)calloc(n, sizeof(double));
+    double* S = (double*)calloc((size_t)m * n, sizeof(double));
+    double* Y = (double*)calloc((size_t)m * n, sizeof(double));
+    double* rho = (double*)calloc(m, sizeof(double));
+    double* al = (double*)calloc(m, sizeof(double));
+    int rc = 0;
+    memset(rep, 0, sizeof(*rep));
+    if (!g || !p || !q || !xt || !gt || !S || !Y || !rho || !al) {
+        rc = -1;
+        goto done;
+    }
+    double f;
+    if (fg(ctx, x, &f, g)) {
+        rc = -2;
+        goto done;
+    }
+    rep->evals = 1;
+    rep->f_start = f;
+    int count = 0, newest = -1; /* ring buffer of stored pairs */
+    int it = 0;
+    while (it < max_iter) {
+        double gmax = 0;
+        for (int k = 0; k < n; k++) gmax = fmax(gmax, fabs(g[k]));
+        if (gmax <= 1e-10 * fmax(1.0, fabs(f))) {
+            rep->converged = 1;
+            break;
+        }
+        if (count == 0) {
+            for (int k = 0; k < n; k++) p[k] = -g[k] / gmax;
+        } else {
+            /* two-loop recursion: q = H g */
+            memcpy(q, g, n * sizeof(double));
+            for (int c = 0; c < count; c++) {
+                int s = (newest - c + m) % m;
+                al[s] = rho[s] * dotn(n, S + (size_t)s * n, q);
+                for (int k = 0; k < n; k++) q[k] -= al[s] * Y[(size_t)s * n + k];
+            }
+            double gamma = dotn(n, S + (size_t)newest * n, Y + (size_t)newest * n) /
+                           dotn(n, Y + (size_t)newest * n, Y + (size_t)newest * n);
+            for (int k = 0; k < n; k++) q[k] *= gamma;
+            for (int c = count - 1; c >= 0; c--) {
+                int s = (newest - c + m) % m;
+                double b = rho[s] * dotn(n, Y + (size_t)s * n, q);
+                for (int k = 0; k < n; k++) q[k] += (al[s] - b) * S[(size_t)s * n + k];
+            }
+            for (int k = 0; k < n; k++) p[k] = -q[k];
+        }
+        double g0 = dotn(n, g, p);
+        if (!(g0 < 0)) {
+            /* not a descent direction: drop the memory and restart */
+            count = 0;
+            for (int k = 0; k < n; k++) p[k] = -g[k] / gmax;
+            g0 = dotn(n, g, p);
+        }
+        ls_state st = {n, fg, ctx, x, p, xt, gt, 0};
+        double alpha, fn;
+        int ls = line_search(&st, f, g0, c1, c2, ls_max_evals, &alpha, &fn);
+        rep->evals += st.evals;
+        if (ls == -2) {
+            rc = -2;
+            goto done;
+        }
+        if (ls != 0) {
+            rep->ls_fail = 1;
+            break;
+        }
+        /* new pair s = x_new - x, y = g_new - g */
+        int slot = (newest + 1) % m;
+        double* sv = S + (size_t)slot * n;
+        double* yv = Y + (size_t)slot * n;
+        for (int k = 0; k < n; k++) {
+            sv[k] = xt[k] - x[k];
+            yv[k] = gt[k] - g[k];
+        }
+        double sy = dotn(n, sv, yv), yy = dotn(n, yv, yv);
+        if (sy > 1e-12 * yy && yy > 0) {
+            rho[slot] = 1.0 / sy;
+            newest = slot;
+            if (count < m) count++;
+        }
+        memcpy(x, xt, n * sizeof(double));
+        memcpy(g, gt, n * sizeof(double));
+        f = fn;
+        it++;
+    }
+    rep->iters = it;
+    rep->f_end = f;
+done:
+    free(g); free(p); free(q); free(xt); free(gt); free(S); free(Y); free(rho); free(al);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multi-resolution 3-D registration (Sec. 2.1, "optimization"): a factor-2
+ * pyramid, zero displacement at the coarsest level, eta fixed per level at
+ * the level's initial field (Eq. 10), L-BFGS per level, upsampling between
+ * levels.  Volumes are the finest level; D_out is [2][h][w][3] at the finest
+ * level.  levels_rep (may be NULL) receives per level, coarsest first:
+ * eta, f_start, f_end, iters, evals. */
+typedef struct {
+    const double *sx, *sy, *ax, *ay, *vx, *vy;
+    int w, h, d;
+    const orc_params* p;
+    double eta;
+    double terms[T_COUNT];
+} level_ctx;
+
+static int level_fg(void* vctx, const double* x, double* f, double* g)
+{
+    level_ctx* c = (level_ctx*)vctx;
+    if (orc_eval(c->sx, c->sy, c->ax, c->ay, c->vx, c->vy, c->w, c->h, c->d, x, c->p, c->eta,
+                 c->terms, g))
+        return -1;
+    *f = c->terms[T_F];
+    return 0;
+}
+
+EXPORT int orc_register(const double* sx, const double* sy, const double* ax, const double* ay,
+                        const double* vx, const double* vy, int w, int h, int d,
+                        const orc_params* p, double* D_out, double* levels_rep)
+{
+    int L = p->levels;
+    if (L < 1 || L > 8) return -1;
+    int W[8], H[8], Dd[8];
+    double *SX[8], *SY[8], *AX[8], *AY[8], *VX[8], *VY[8];
+    W[0] = w; H[0] = h; Dd[0] = d;
+    SX[0] = (double*)sx; SY[0] = (double*)sy; AX[0] = (double*)ax; AY[0] = (double*)ay;
+    VX[0] = (double*)vx; VY[0] = (double*)vy;
+    for (int l = 1; l < L; l++) {
+        W[l] = (W[l - 1] + 1) / 2; H[l] = (H[l - 1] + 1) / 2; Dd[l] = (Dd[l - 1] + 1) / 2;
+        size_t nv = (size_t)W[l] * H[l] * Dd[l], ni = (size_t)W[l] * H[l];
+        SX[l] = (double*)malloc(nv * sizeof(double));
+        SY[l] = (double*)malloc(nv * sizeof(double));
+        AX[l] = (double*)malloc(ni * sizeof(double));
+        AY[l] = (double*)malloc(ni * sizeof(double));
+        VX[l] = (double*)malloc(H[l] * sizeof(double));
+        VY[l] = (double*)malloc(W[l] * sizeof(double));
+        orc_pyr_down3(SX[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SX[l]);
+        orc_pyr_down3(SY[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SY[l]);
+        orc_pyr_down2(AX[l - 1], W[l - 1], H[l - 1], AX[l]);
+        orc_pyr_down2(AY[l - 1], W[l - 1], H[l - 1], AY[l]);
+        orc_pyr_down1(VX[l - 1], H[l - 1], VX[l]);
+        orc_pyr_down1(VY[l - 1], W[l - 1], VY[l]);
+    }
+    int rc = 0;
+    double* Dc = NULL;
+    for (int l = L - 1; l >= 0; l--) {
+        size_t n = (size_t)2 * W[l] * H[l] * 3;
+        double* Dl = (double*)calloc(n, sizeof(double));
+        if (Dc) {
+            orc_upsample(Dc, W[l + 1], H[l + 1], Dl, W[l], H[l]);
+            free(Dc);
+        }
+        level_ctx ctx = {SX[l], SY[l], AX[l], AY[l], VX[l], VY[l], W[l], H[l], Dd[l], p, 1.0, {0}};
+        double terms[T_COUNT];
+        orc_eval(SX[l], SY[l], AX[l], AY[l], VX[l], VY[l], W[l], H[l], Dd[l], Dl, p, 1.0, terms, NULL);
+        ctx.eta = orc_eta_from_terms(terms[T_STR05], terms[T_ANG05]);
+        orc_lbfgs_report rep;
+        rc = orc_lbfgs((int)n, Dl, level_fg, &ctx, p->lbfgs_m, p->iters, p->ls_max_evals, p->c1, p->c2, &rep);
+        if (levels_rep) {
+            double* r = levels_rep + (size_t)(L - 1 - l) * 5;
+            r[0] = ctx.eta; r[1] = rep.f_start; r[2] = rep.f_end; r[3] = rep.iters; r[4] = rep.evals;
+        }
+        Dc = Dl;
+        if (rc) break;
+    }
+    if (rc == 0) memcpy(D_out, Dc, (size_t)2 * w * h * 3 * sizeof(double));
+    free(Dc);
+    for (int l = 1; l < L; l++) {
+        free(SX[l]); free(SY[l]); free(AX[l]); free(AY[l]); free(VX[l]); free(VY[l]);
+    }
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Output (Sec. 2.1 "merging" and Sec. 2.5).  Each scan is resampled with its
+ * final field; the two are fused by a weighted average whose weights decay
+ * exponentially with the sampling density of the input.  Readings:
+ *   - density rho^V_ij: every output A-scan splats its sample position
+ *     (i+dx, j+dy), clamped to the image, bilinearly into an h x w grid; the
+ *     grid is read back bilinearly at the same position.  Regular sampling
+ *     gives rho = 1;
+ *   - weight exp(-kappa max(0, rho - 1)), set to 0 below tau, then the two
+ *     weights are normalised to sum 1;
+ *   - if both weights are 0 the scan with the lower density is used (the data
+ *     of the B-scan with less oversampling remains);
+ *   - for OCTA (Sec. 2.5) the weights are further multiplied by the resampled
+ *     validity of Eq. 5, and where both are 0 the output is 0 (a black gap).
+ * rho_out ([2][h][w]) and weight_out ([2][h][w], OCT weights after
+ * normalisation) may be NULL. */
+EXPORT void orc_density(const double* D, int w, int h, double* rho)
+{
+    for (int V = 0; V < 2; V++) {
+        double* grid = (double*)calloc((size_t)w * h, sizeof(double));
+        const double* DV = D + (size_t)V * w * h * 3;
+        for (int j = 0; j < h; j++)
+            for (int i = 0; i < w; i++) {
+                double x = i + DV[((size_t)j * w + i) * 3 + 0];
+                double y = j + DV[((size_t)j * w + i) * 3 + 1];
+                x = x < 0 ? 0 : (x > w - 1 ? w - 1 : x);
+                y = y < 0 ? 0 : (y > h - 1 ? h - 1 : y);
+                int x0 = (int)floor(x), y0 = (int)floor(y);
+                int x1 = x0 + 1 < w ? x0 + 1 : w - 1, y1 = y0 + 1 < h ? y0 + 1 : h - 1;
+                double fx = x - x0, fy = y - y0;
+                grid[(size_t)y0 * w + x0] += (1 - fx) * (1 - fy);
+                grid[(size_t)y0 * w + x1] += fx * (1 - fy);
+                grid[(size_t)y1 * w + x0] += (1 - fx) * fy;
+                grid[(size_t)y1 * w + x1] += fx * fy;
+            }
+        for (int j = 0; j < h; j++)
+            for (int i = 0; i < w; i++) {
+                double x = i + DV[((size_t)j * w + i) * 3 + 0];
+                double y = j + DV[((size_t)j * w + i) * 3 + 1];
+                x = x < 0 ? 0 : (x > w - 1 ? w - 1 : x);
+                y = y < 0 ? 0 : (y > h - 1 ? h - 1 : y);
+                int x0 = (int)floor(x), y0 = (int)floor(y);
+                int x1 = x0 + 1 < w ? x0 + 1 : w - 1, y1 = y0 + 1 < h ? y0 + 1 : h - 1;
+                double fx = x - x0, fy = y - y0;
+                rho[((size_t)V * h + j) * w + i] =
+                    (1 - fx) * (1 - fy) * grid[(size_t)y0 * w + x0] + fx * (1 - fy) * grid[(size_t)y0 * w + x1] +
+                    (1 - fx) * fy * grid[(size_t)y1 * w + x0] + fx * fy * grid[(size_t)y1 * w + x1];
+            }
+        free(grid);
+    }
+}
+
+EXPORT void orc_merge(const double* sx, const double* sy, const double* ox, const double* oy,
+                      const double* vx, const double* vy, int w, int h, int d, const double* D,
+                      double kappa, double tau, double* merged_oct, double* merged_octa,
+                      double* rho_out, double* weight_out)
+{
+    size_t na = (size_t)w * h;
+    double* rho = (double*)malloc(2 * na * sizeof(double));
+    orc_density(D, w, h, rho);
+    if (rho_out) memcpy(rho_out, rho, 2 * na * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long a = 0; a < (long)na; a++) {
+        int i = (int)(a % w), j = (int)(a / w);
+        const double* dX = D + (size_t)a * 3;
+        const double* dY = D + (na + a) * 3;
+        double rx = rho[a], ry = rho[na + a];
+        double wx = exp(-kappa * fmax(0.0, rx - 1.0)), wy = exp(-kappa * fmax(0.0, ry - 1.0));
+        if (wx < tau) wx = 0;
+        if (wy < tau) wy = 0;
+        double ax_w, ay_w;
+        if (wx + wy > 0) {
+            ax_w = wx / (wx + wy);
+            ay_w = wy / (wx + wy);
+        } else if (rx <= ry) {
+            ax_w = 1; ay_w = 0;
+        } else {
+            ax_w = 0; ay_w = 1;
+        }
+        if (weight_out) {
+            weight_out[a] = ax_w;
+            weight_out[na + a] = ay_w;
+        }
+        /* OCTA weights: density weights times the resampled validity (Eq. 5) */
+        double ow_x = 0, ow_y = 0;
+        if (merged_octa) {
+            double r1[2], r2[2];
+            orc_sample1(vx, h, j + dX[1], r1);
+            orc_sample1(vy, w, i + dY[0], r2);
+            double tvx = r1[0] <= 0 ? 0 : (r1[0] >= 1 ? 1 : r1[0]);
+            double tvy = r2[0] <= 0 ? 0 : (r2[0] >= 1 ? 1 : r2[0]);
+            ow_x = wx * tvx;
+            ow_y = wy * tvy;
+            double sum = ow_x + ow_y;
+            if (sum > 0) {
+                ow_x /= sum;
+                ow_y /= sum;
+            }
+        }
+        for (int k = 0; k < d; k++) {
+            double s1[4], s2[4];
+            orc_sample3(sx, w, h, d, i + dX[0], j + dX[1], k + dX[2], s1);
+            orc_sample3(sy, w, h, d, i + dY[0], j + dY[1], k + dY[2], s2);
+            merged_oct[(size_t)a * d + k] = ax_w * s1[0] + ay_w * s2[0];
+            if (merged_octa) {
+                double o1[4], o2[4];
+                orc_sample3(ox, w, h, d, i + dX[0], j + dX[1], k + dX[2], o1);
+                orc_sample3(oy, w, h, d, i + dY[0], j + dY[1], k + dY[2], o2);
+                merged_octa[(size_t)a * d + k] = ow_x * o1[0] + ow_y * o2[0];
+            }
+        }
+    }
+    free(rho);
+}
+
+/* Plain depth mean of an OCTA volume: the en face image used in place of the
+ * paper's segmentation-free projection (Sec. 2.3), which is not part of this
+ * oracle. */
+EXPORT void orc_enface_mean(const double* vol, int w, int h, int d, double* out)
+{
+    for (size_t a = 0; a < (size_t)w * h; a++) {
+        double s = 0;
+        for (int k = 0; k < d; k++) s += vol[a * d + k];
+        out[a] = s / d;
+    }
+}
+
+/* Nearest-valid substitution of invalid B-scans (Sec. 2.3 and 2.5) for an
+ * OCTA volume of scan V (V = 0: B-scans are rows j; V = 1: columns i).  An
+ * invalid B-scan takes the data of the closest valid one (the lower index on
+ * a tie); with no valid B-scan the volume is left unchanged. */
+EXPORT void orc_substitute_invalid(double* vol, int w, int h, int d, const double* valid, int V)
+{
+    int nb = (V == 0) ? h : w;
+    int* src = (int*)malloc(nb * sizeof(int));
+    int any = 0;
+    for (int b = 0; b < nb; b++) any |= valid[b] > 0.5;
+    if (!any) {
+        free(src);
+        return;
+    }
+    for (int b = 0; b < nb; b++) {
+        if (valid[b] > 0.5) {
+            src[b] = b;
+            continue;
+        }
+        int best = -1;
+        for (int dist = 1; dist < nb && best < 0; dist++) {
+            if (b - dist >= 0 && valid[b - dist] > 0.5) best = b - dist;
+            else if (b + dist < nb && valid[b + dist] > 0.5) best = b + dist;
+        }
+        src[b] = best;
+    }
+    for (int b = 0; b < nb; b++) {
+        if (src[b] == b) continue;
+        for (int o = 0; o < ((V == 0) ? w : h); o++) {
+            size_t dst = (V == 0) ? ((size_t)b * w + o) : ((size_t)o * w + b);
+            size_t from = (V == 0) ? ((size_t)src[b] * w + o) : ((size_t)o * w + src[b]);
+            memcpy(vol + dst * d, vol + from * d, d * sizeof(double));
+        }
+    }
+    free(src);
+}

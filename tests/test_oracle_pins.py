@@ -1,0 +1,543 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here checks the oracle against something other than itself:
+closed forms, invariants the paper states, special cases that reduce to a
+library routine (scipy's cubic Hermite spline), finite differences, exact
+constructions (integer shifts) and brute force on tiny inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.interpolate import CubicHermiteSpline
+
+import synth
+
+RNG = np.random.default_rng(7)
+
+
+# ---------------------------------------------------------------------------
+# scipy-based separable interpolation: the library pin of the interpolator.
+
+def _scipy_axis_interp(arr, axis, x, deriv=False, pad=8):
+    """Cubic Hermite interpolation of `arr` along `axis` at position x with
+    central-difference knot slopes and constant extension beyond the ends."""
+    ap = np.pad(arr, [(pad, pad) if a == axis else (0, 0) for a in range(arr.ndim)], mode="edge")
+    n = ap.shape[axis]
+    knots = np.arange(n, dtype=float) - pad
+    slopes = np.zeros_like(ap)
+    sl = [slice(None)] * ap.ndim
+    up, dn, mid = list(sl), list(sl), list(sl)
+    up[axis], dn[axis], mid[axis] = slice(2, None), slice(None, -2), slice(1, -1)
+    slopes[tuple(mid)] = 0.5 * (ap[tuple(up)] - ap[tuple(dn)])
+    sp = CubicHermiteSpline(knots, ap, slopes, axis=axis)
+    if deriv:
+        sp = sp.derivative()
+    return sp(x)
+
+
+def scipy_sample3(vol, x, y, z):
+    """Value and the three partial derivatives at (x, y, z) of a [h][w][d]
+    volume, by successive 1-D scipy interpolation along z, x and y."""
+    out = []
+    for dx, dy, dz in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]:
+        a = _scipy_axis_interp(vol, 2, z, deriv=bool(dz))      # -> [h][w]
+        a = _scipy_axis_interp(a, 1, x, deriv=bool(dx))        # -> [h]
+        a = _scipy_axis_interp(a, 0, y, deriv=bool(dy))        # -> scalar
+        out.append(float(a))
+    return np.array(out)
+
+
+def scipy_sample2(img, x, y):
+    out = []
+    for dx, dy in [(0, 0), (1, 0), (0, 1)]:
+        a = _scipy_axis_interp(img, 1, x, deriv=bool(dx))
+        a = _scipy_axis_interp(a, 0, y, deriv=bool(dy))
+        out.append(float(a))
+    return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# interpolator (Eq. 2 "Hermitian interpolation", C1 per the text after Eq. 5)
+
+@pytest.mark.parametrize("t", [0.0, 0.1, 0.25, 0.5, 0.73, 0.999])
+def test_taps_partition_and_polynomial_reproduction(orc, t):
+    w, dw = orc.hermite_taps(t)
+    offs = np.array([-1.0, 0.0, 1.0, 2.0])
+    assert abs(w.sum() - 1) < 1e-15
+    assert abs(dw.sum()) < 1e-14
+    # linear and quadratic fields are reproduced exactly, with their slopes
+    assert abs((offs * w).sum() - t) < 1e-14
+    assert abs((offs ** 2 * w).sum() - t * t) < 1e-14
+    assert abs((offs * dw).sum() - 1) < 1e-14
+    assert abs((offs ** 2 * dw).sum() - 2 * t) < 1e-14
+    # cubics are not (central-difference tangents are not exact for x^3;
+    # the error vanishes at the knots and, by symmetry, at t = 1/2)
+    if t not in (0.0, 0.5):
+        assert abs((offs ** 3 * w).sum() - t ** 3) > 1e-6
+
+
+def test_taps_at_knot(orc):
+    w, dw = orc.hermite_taps(0.0)
+    np.testing.assert_array_equal(w, [0, 1, 0, 0])
+    np.testing.assert_allclose(dw, [-0.5, 0, 0.5, 0], atol=0)
+
+
+def test_sample1_matches_scipy_and_is_c1(orc):
+    v = RNG.normal(size=23)
+    for x in [-4.2, -0.5, 0.0, 0.3, 5.5, 11.01, 21.7, 22.0, 25.3]:
+        ref_v = float(_scipy_axis_interp(v, 0, x))
+        ref_d = float(_scipy_axis_interp(v, 0, x, deriv=True))
+        got = orc.sample1(v, x)
+        assert abs(got[0] - ref_v) < 1e-12, x
+        assert abs(got[1] - ref_d) < 1e-12, x
+    for n in range(0, 22):  # C1 across every knot, including clamped ones
+        left = orc.sample1(v, n - 1e-9)
+        right = orc.sample1(v, n)
+        assert abs(left[0] - right[0]) < 1e-7
+        assert abs(left[1] - right[1]) < 1e-7
+        assert right[0] == v[n]  # exact at knots
+
+
+def test_sample1_constant_extension(orc):
+    v = RNG.normal(size=9)
+    assert orc.sample1(v, -3.5)[0] == pytest.approx(v[0], abs=1e-15)
+    assert orc.sample1(v, -3.5)[1] == pytest.approx(0.0, abs=1e-15)
+    assert orc.sample1(v, 12.25)[0] == pytest.approx(v[-1], abs=1e-15)
+
+
+def test_sample2_sample3_match_scipy(orc):
+    img = RNG.normal(size=(9, 11))
+    vol = RNG.normal(size=(7, 9, 10))
+    for x, y in [(3.3, 4.6), (-1.2, 0.4), (10.7, 8.9), (5.0, 2.0)]:
+        np.testing.assert_allclose(orc.sample2(img, x, y), scipy_sample2(img, x, y), atol=1e-12)
+    for x, y, z in [(3.3, 4.6, 2.2), (-1.7, 0.25, -2.5), (8.9, 6.6, 9.7), (4.0, 3.0, 5.0), (2.5, 7.5, 11.2)]:
+        np.testing.assert_allclose(orc.sample3(vol, x, y, z), scipy_sample3(vol, x, y, z), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# loss (Eq. 4)
+
+def test_pseudo_huber_closed_forms(orc):
+    eps = 1e-3
+    assert orc.pseudo_huber(0.0, eps).tolist() == [0.0, 0.0]
+    L, dL = orc.pseudo_huber(eps, eps)
+    assert L == pytest.approx(eps * (math.sqrt(2) - 1), rel=1e-15)
+    assert dL == pytest.approx(1 / math.sqrt(2), rel=1e-15)
+    L, dL = orc.pseudo_huber(-3 * eps, eps)
+    assert L == pytest.approx(eps * (math.sqrt(10) - 1), rel=1e-14)
+    assert dL == pytest.approx(-3 / math.sqrt(10), rel=1e-14)
+    # far from 0 the loss approaches |x| - eps + eps^2 / (2|x|) (robust to outliers)
+    L, dL = orc.pseudo_huber(5.0, eps)
+    assert L == pytest.approx(5.0 - eps + eps * eps / 10, abs=1e-12)
+    assert dL == pytest.approx(1.0, abs=1e-7)
+    # small residuals are quadratic: L ~ x^2 / (2 eps), no cancellation
+    L, _ = orc.pseudo_huber(1e-9, eps)
+    assert L == pytest.approx(1e-18 / (2 * eps), rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# brute force of the whole objective on a tiny pair through scipy
+
+def _brute_objective(sx, sy, ax, ay, vx, vy, D, delta0, eps, eta):
+    """Eqs. 2-9 on a tiny pair with every interpolant taken from scipy."""
+    h, w, d = sx.shape
+
+    def L(r):
+        return eps * (np.sqrt(1 + (r / eps) ** 2) - 1)
+
+    data = s_str = s_ang = 0.0
+    for j in range(h):
+        for i in range(w):
+            dX, dY = D[0, j, i], D[1, j, i]
+            lam = 0.0
+            for k in range(d):
+                ix = scipy_sample3(sx, i + dX[0], j + dX[1], k + dX[2])[0]
+                iy = scipy_sample3(sy, i + dY[0], j + dY[1], k + dY[2])[0]
+                lam += L(ix - iy)
+            ra = scipy_sample2(ax, i + dX[0], j + dX[1])[0] - scipy_sample2(ay, i + dY[0], j + dY[1])[0]
+            tvx = min(max(float(_scipy_axis_interp(vx, 0, j + dX[1])), 0.0), 1.0)
+            tvy = min(max(float(_scipy_axis_interp(vy, 0, i + dY[0])), 0.0), 1.0)
+            delta = delta0 * tvx * tvy
+            s_str += (1 - delta) * lam
+            s_ang += delta * d * L(ra)
+            data += eta * (1 - delta) * lam + delta * d * L(ra) / eta
+    return data, s_str, s_ang
+
+
+def test_objective_matches_scipy_brute_force(orc):
+    rng = np.random.default_rng(3)
+    h = w = 5
+    d = 6
+    sx, sy = rng.uniform(0, 1, (h, w, d)), rng.uniform(0, 1, (h, w, d))
+    ax, ay = rng.uniform(0, 1, (h, w)), rng.uniform(0, 1, (h, w))
+    vx = np.array([1, 1, 0, 1, 1.0])
+    vy = np.array([1, 0.5, 1, 1, 1.0])
+    D = rng.uniform(-1.5, 1.5, (2, h, w, 3))
+    lv = orc.level_from(sx, sy, ax, ay, vx, vy)
+    p = orc.Params(alpha=0.0, mean_weight=0.0, delta0=0.5)
+    eta = 1.37
+    t, _ = orc.evaluate(lv, D, p, eta, grad=False)
+    data, s_str, s_ang = _brute_objective(sx, sy, ax, ay, vx, vy, D, 0.5, 1e-3, eta)
+    assert t["data"] == pytest.approx(data, rel=1e-12)
+    assert t["str"] == pytest.approx(s_str, rel=1e-12)
+    assert t["ang"] == pytest.approx(s_ang, rel=1e-12)
+    assert t["F"] == pytest.approx(data, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# invariants the paper states
+
+def _tiny_pair(seed=0, h=12, d=16):
+    rng = np.random.default_rng(seed)
+    sx = rng.uniform(0, 1, (h, h, d))
+    sy = rng.uniform(0, 1, (h, h, d))
+    ax = rng.uniform(0, 1, (h, h))
+    ay = rng.uniform(0, 1, (h, h))
+    return sx, sy, ax, ay
+
+
+def test_zero_data_term_identical_inputs(orc):
+    sx, _, ax, _ = _tiny_pair()
+    lv = orc.level_from(sx, sx, ax, ax)
+    p = orc.Params(alpha=0.0, mean_weight=0.0)
+    t, g = orc.evaluate(lv, np.zeros((2, 12, 12, 3)), p, 1.3)
+    assert t["data"] == 0.0 and t["str"] == 0.0 and t["ang"] == 0.0
+    assert np.all(g == 0.0)
+    # any field that moves both scans the same way keeps the term at zero
+    D1 = np.random.default_rng(1).uniform(-2, 2, (12, 12, 3))
+    t, g = orc.evaluate(lv, np.stack([D1, D1]), p, 0.7)
+    assert t["data"] == 0.0
+    assert np.all(g == 0.0)
+
+
+def test_integer_shift_resamples_exactly(orc):
+    """S^Y(q) = S^X(q + s) for an integer s: d^Y = d^X - s aligns the scans
+    exactly, for any fractional d^X (same taps, same weights)."""
+    rng = np.random.default_rng(5)
+    n, d, s = 24, 26, np.array([2, -1, 3])
+    o = 4
+    big = np.zeros((n + 2 * o,) * 2 + (d + 2 * o,))
+    big2d = np.zeros((n + 2 * o,) * 2)
+    # content only where both crops have a zero band of >= 4 samples, so the
+    # clamped edges of both scans see zeros as well
+    lo = o + np.maximum(0, s) + 4
+    hi = o + np.minimum(0, s) + np.array([n, n, d]) - 4
+    big[lo[1]:hi[1], lo[0]:hi[0], lo[2]:hi[2]] = rng.uniform(0.1, 1, (hi - lo)[[1, 0, 2]])
+    big2d[lo[1]:hi[1], lo[0]:hi[0]] = rng.uniform(0.1, 1, (hi - lo)[[1, 0]])
+    sx = big[o:o + n, o:o + n, o:o + d]
+    sy = big[o + s[1]:o + s[1] + n, o + s[0]:o + s[0] + n, o + s[2]:o + s[2] + d]
+    ax = big2d[o:o + n, o:o + n]
+    ay = big2d[o + s[1]:o + s[1] + n, o + s[0]:o + s[0] + n]
+    lv = orc.level_from(sx, sy, ax, ay)
+    dX = np.broadcast_to(np.array([0.37, -0.21, 0.64]), (n, n, 3))
+    D = np.stack([dX, dX - s])
+    t, _ = orc.evaluate(lv, D, orc.Params(alpha=0.0, mean_weight=0.0), 1.0, grad=False)
+    # zero up to the rounding of the fractional parts of i + dx and i - 2 + dx
+    assert t["data"] < 1e-18
+    # and a different fractional offset between the scans is not aligned
+    D[1, :, :, 0] += 0.5
+    t, _ = orc.evaluate(lv, D, orc.Params(alpha=0.0, mean_weight=0.0), 1.0, grad=False)
+    assert t["data"] > 1.0
+
+
+def test_transpose_symmetry(orc):
+    """Transposing both scans (i <-> j), swapping the X/Y roles and the x/y
+    displacement components maps the problem onto itself: R -> -R."""
+    sx, sy, ax, ay = _tiny_pair(2)
+    vx = np.array([1, 1, 1, 0.2, 0, 0.7, 1, 1, 1, 1, 1, 1.0])
+    vy = np.array([1, 0.6, 1, 1, 1, 1, 1, 1, 0, 1, 1, 1.0])
+    D = np.random.default_rng(4).uniform(-1.5, 1.5, (2, 12, 12, 3))
+    p = orc.Params()
+    lv = orc.level_from(sx, sy, ax, ay, vx, vy)
+    t1, g1 = orc.evaluate(lv, D, p, 1.1)
+    lvT = orc.level_from(sy.transpose(1, 0, 2), sx.transpose(1, 0, 2), ay.T, ax.T, vy, vx)
+    DT = np.stack([D[1].transpose(1, 0, 2)[..., [1, 0, 2]], D[0].transpose(1, 0, 2)[..., [1, 0, 2]]])
+    t2, g2 = orc.evaluate(lvT, DT, p, 1.1)
+    for k in t1:
+        assert t2[k] == pytest.approx(t1[k], rel=1e-12, abs=1e-12), k
+    g1T = np.stack([g1[1].transpose(1, 0, 2)[..., [1, 0, 2]], g1[0].transpose(1, 0, 2)[..., [1, 0, 2]]])
+    np.testing.assert_allclose(g2, g1T, rtol=1e-10, atol=1e-10)
+
+
+def test_delta0_zero_is_oct_only(orc):
+    """With delta0 = 0 the en face images have no influence and the data term
+    is eta times the OCT-only similarity (Eq. 3); the paper compares against
+    exactly that configuration."""
+    sx, sy, ax, ay = _tiny_pair(3)
+    D = np.random.default_rng(6).uniform(-1, 1, (2, 12, 12, 3))
+    p0 = orc.Params(delta0=0.0)
+    t1, g1 = orc.evaluate(orc.level_from(sx, sy, ax, ay), D, p0, 1.7)
+    t2, g2 = orc.evaluate(orc.level_from(sx, sy, 5 * ay, -ax), D, p0, 1.7)
+    assert t1["F"] == t2["F"]
+    np.testing.assert_array_equal(g1, g2)
+    t3, _ = orc.evaluate(orc.level_from(sx, sy, ax, ay), D, orc.Params(delta0=0.0, alpha=0, mean_weight=0), 1.0,
+                         grad=False)
+    assert t1["data"] == pytest.approx(1.7 * t3["data"], rel=1e-14)
+    assert t1["ang"] == 0.0
+
+
+def test_invalid_scans_remove_angiographic_term(orc):
+    """v = 0 makes delta = 0: the angiographic term vanishes and the
+    structural term becomes the basic one (Sec. 2.4)."""
+    sx, sy, ax, ay = _tiny_pair(4)
+    D = np.random.default_rng(8).uniform(-1, 1, (2, 12, 12, 3))
+    z = np.zeros(12)
+    t, _ = orc.evaluate(orc.level_from(sx, sy, ax, ay, z, None), D, orc.Params(), 1.0, grad=False)
+    assert t["ang"] == 0.0
+    t0, _ = orc.evaluate(orc.level_from(sx, sy, ax, ay), D, orc.Params(delta0=0.0), 1.0, grad=False)
+    assert t["str"] == pytest.approx(t0["str"], rel=1e-14)
+
+
+def test_eta_equalises_terms(orc):
+    p = synth.make_pair("tiny", n=24, d=32)
+    lv = orc.level_from_pair(p)
+    t, _ = orc.evaluate(lv, np.zeros((2, 24, 24, 3)), orc.Params(), 1.0, grad=False)
+    eta = orc.eta_from_terms(t["str05"], t["ang05"])
+    # eta S_str = S_ang / eta: both equal the geometric mean (Eq. 10)
+    assert eta * t["str05"] == pytest.approx(t["ang05"] / eta, rel=1e-14)
+    assert eta * t["str05"] == pytest.approx(math.sqrt(t["str05"] * t["ang05"]), rel=1e-14)
+    assert orc.eta_from_terms(0.0, 3.0) == 1.0
+
+
+# ---------------------------------------------------------------------------
+# gradient
+
+def test_gradient_matches_finite_differences(orc):
+    rng = np.random.default_rng(11)
+    pair = synth.make_pair("tiny", n=16, d=24)
+    vx = np.ones(16)
+    vx[5] = 0.0
+    vy = np.ones(16)
+    vy[9] = 0.3
+    lv = orc.level_from(pair.sx, pair.sy, pair.ax, pair.ay, vx, vy)
+    D = pair.d_gt.numpy() + rng.normal(0, 0.3, (2, 16, 16, 3))
+    p = orc.Params(alpha=0.7, mean_weight=2.0)
+    eta = 0.9
+    _, g = orc.evaluate(lv, D, p, eta)
+    h = 1e-5
+    idx = [tuple(int(v) for v in rng.integers([0, 0, 0, 0], [2, 16, 16, 3])) for _ in range(40)]
+    for ix in idx:
+        # keep sample positions away from knots, where the spline's third
+        # derivative jumps and central differences lose accuracy
+        base = (ix[2], ix[1], 0)[ix[3]] + D[ix]
+        frac = base - math.floor(base)
+        if min(frac, 1 - frac) < 1e-3:
+            D[ix] += 0.01
+    _, g = orc.evaluate(lv, D, p, eta)
+    for ix in idx:
+        Dp, Dm = D.copy(), D.copy()
+        Dp[ix] += h
+        Dm[ix] -= h
+        fp = orc.evaluate(lv, Dp, p, eta, grad=False)[0]["F"]
+        fm = orc.evaluate(lv, Dm, p, eta, grad=False)[0]["F"]
+        fd = (fp - fm) / (2 * h)
+        assert fd == pytest.approx(g[ix], rel=2e-6, abs=2e-4 * max(1.0, abs(g).max() * 1e-3)), ix
+
+
+# ---------------------------------------------------------------------------
+# regulariser and mean term: closed forms
+
+def test_regulariser_closed_forms(orc):
+    n, d = 10, 7
+    sx = np.zeros((n, n, d))
+    lv = orc.level_from(sx, sx, np.zeros((n, n)), np.zeros((n, n)))
+    p = orc.Params(alpha=1.0, mean_weight=0.0, eps_r=0.1, flyback_frac=0.25)
+    # a constant field costs nothing
+    D = np.broadcast_to(np.array([0.3, -0.2, 1.1]), (2, n, n, 3)).copy()
+    t, _ = orc.evaluate(lv, D, p, grad=False)
+    assert t["reg"] == 0.0
+    # a single jump J inside an X-fast B-scan (between (3, 4) and (4, 4))
+    eps = 0.1
+    D = np.zeros((2, n, n, 3))
+    D[0, 4, 4:, 0] = eps     # from A-scan (4, 4) on in time: rest of row 4 ...
+    D[0, 5:, :, 0] = eps     # ... and every later B-scan
+    t, _ = orc.evaluate(lv, D, p, grad=False)
+    assert t["reg"] == pytest.approx(d * eps * (math.sqrt(2) - 1), rel=1e-13)
+    # the same jump across a B-scan boundary is weighted by 1/sqrt(1 + f)
+    f = math.floor(0.25 * n + 0.5)  # round half up: 2.5 -> 3
+    D = np.zeros((2, n, n, 3))
+    D[0, 5:, :, 0] = eps
+    t, _ = orc.evaluate(lv, D, p, grad=False)
+    assert t["reg"] == pytest.approx(d * eps * (math.sqrt(2) - 1) / math.sqrt(1 + f), rel=1e-13)
+    # Y-fast: a jump between (i=2, j=7) and (i=2, j=8)
+    D = np.zeros((2, n, n, 3))
+    D[1, 8:, 2, 1] = eps
+    D[1, :, 3:, 1] = eps
+    t, _ = orc.evaluate(lv, D, p, grad=False)
+    assert t["reg"] == pytest.approx(d * eps * (math.sqrt(2) - 1), rel=1e-13)
+
+
+def test_mean_term_closed_form(orc):
+    n, d = 8, 5
+    sx = np.zeros((n, n, d))
+    lv = orc.level_from(sx, sx, np.zeros((n, n)), np.zeros((n, n)))
+    c = np.array([0.5, -1.5, 2.0])
+    D = np.broadcast_to(c, (2, n, n, 3)).copy()
+    p = orc.Params(alpha=0.0, mean_weight=1.7)
+    t, g = orc.evaluate(lv, D, p)
+    na = n * n
+    assert t["mean"] == pytest.approx(2 * 1.7 * d * na * (c ** 2).sum(), rel=1e-14)
+    np.testing.assert_allclose(g, np.broadcast_to(2 * 1.7 * d * c, g.shape), rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# pyramid and level transition
+
+def test_pyramid_closed_forms(orc):
+    rng = np.random.default_rng(2)
+    # constants stay constant, including odd sizes
+    v = np.full((5, 7, 9), 2.5)
+    np.testing.assert_array_equal(orc.pyr_down3(v), np.full((3, 4, 5), 2.5))
+    # a field linear in the coordinates: the coarse sample is the value at the
+    # centre of its 2x2x2 block (fine position 2I + 1/2), for even sizes
+    j, i, k = np.meshgrid(np.arange(8), np.arange(6), np.arange(10), indexing="ij")
+    lin = 0.3 * i - 1.2 * j + 0.7 * k + 4
+    J, I, K = np.meshgrid(np.arange(4), np.arange(3), np.arange(5), indexing="ij")
+    np.testing.assert_allclose(orc.pyr_down3(lin), 0.3 * (2 * I + .5) - 1.2 * (2 * J + .5) + 0.7 * (2 * K + .5) + 4,
+                               atol=1e-13)
+    # odd sizes: the last coarse sample averages the last fine one with itself
+    a = rng.normal(size=(3, 3, 3))
+    assert orc.pyr_down3(a)[1, 1, 1] == pytest.approx(a[2, 2, 2], abs=1e-15)
+    np.testing.assert_allclose(orc.pyr_down1(np.array([1.0, 3, 5, 9, 11])), [2, 7, 11])
+    np.testing.assert_allclose(orc.pyr_down2(np.arange(6.0).reshape(2, 3)), [[2.0, 3.5]])
+    # even sizes keep the mean
+    b = rng.normal(size=(6, 8, 4))
+    assert orc.pyr_down3(b).mean() == pytest.approx(b.mean(), abs=1e-14)
+
+
+def test_upsample_closed_forms(orc):
+    c = np.broadcast_to(np.array([0.5, -0.25, 1.5]), (2, 4, 5, 3)).copy()
+    np.testing.assert_allclose(orc.upsample(c, 10, 8), np.broadcast_to(2 * c[0, 0, 0], (2, 8, 10, 3)))
+    # a linear coarse field a*I + b*J maps to 2 (a (i - 1/2)/2 + b (j - 1/2)/2)
+    # away from the clamped border
+    J, I = np.meshgrid(np.arange(6), np.arange(6), indexing="ij")
+    lin = np.zeros((2, 6, 6, 3))
+    lin[..., 0] = 0.4 * I - 0.7 * J
+    up = orc.upsample(lin, 12, 12)
+    j, i = np.meshgrid(np.arange(12), np.arange(12), indexing="ij")
+    exp = 0.4 * (i - 0.5) - 0.7 * (j - 0.5)
+    sl = (slice(1, 11), slice(1, 11))
+    np.testing.assert_allclose(up[0][sl][..., 0], exp[sl], atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# L-BFGS
+
+def test_lbfgs_quadratic_closed_form(orc):
+    rng = np.random.default_rng(9)
+    n = 40
+    Q = rng.normal(size=(n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.normal(size=n)
+    x, rep = orc.lbfgs(lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b), np.zeros(n), m=5, max_iter=200)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-7, atol=1e-9)
+
+
+def test_lbfgs_rosenbrock(orc):
+    def fg(x):
+        f = 100 * (x[1] - x[0] ** 2) ** 2 + (1 - x[0]) ** 2
+        g = np.array([-400 * x[0] * (x[1] - x[0] ** 2) - 2 * (1 - x[0]), 200 * (x[1] - x[0] ** 2)])
+        return f, g
+
+    x, rep = orc.lbfgs(fg, np.array([-1.2, 1.0]), m=5, max_iter=500)
+    np.testing.assert_allclose(x, [1.0, 1.0], atol=1e-6)
+
+
+def test_lbfgs_agrees_with_scipy(orc):
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(10)
+    n = 30
+    c = rng.normal(size=n)
+
+    def fg(x):  # smooth, strictly convex
+        r = x - c
+        return float(np.sum(np.sqrt(1 + r ** 2)) + 0.1 * x @ x), r / np.sqrt(1 + r ** 2) + 0.2 * x
+
+    x, _ = orc.lbfgs(fg, np.zeros(n), max_iter=300)
+    ref = minimize(fg, np.zeros(n), jac=True, method="L-BFGS-B", options=dict(gtol=1e-12, ftol=1e-15))
+    np.testing.assert_allclose(x, ref.x, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# merge
+
+def test_merge_identity_and_density(orc):
+    rng = np.random.default_rng(12)
+    sx = rng.uniform(size=(9, 9, 6))
+    sy = rng.uniform(size=(9, 9, 6))
+    D = np.zeros((2, 9, 9, 3))
+    m, _, rho, wt = orc.merge(sx, sy, D)
+    np.testing.assert_allclose(rho, 1.0, atol=1e-15)
+    np.testing.assert_allclose(wt, 0.5, atol=1e-15)
+    np.testing.assert_allclose(m, 0.5 * (sx + sy), atol=1e-15)
+    m, _, _, _ = orc.merge(sx, sx, D)
+    np.testing.assert_allclose(m, sx, atol=1e-15)
+    # X-fast A-scans of row 4 all sample row 3: row 3 is sampled twice as
+    # often, row 4 not at all; the weights favour Y there
+    D[0, 4, :, 1] = -1.0
+    m, _, rho, wt = orc.merge(sx, sy, D)
+    assert rho[0, 3, 4] == pytest.approx(2.0)
+    assert rho[0, 4, 4] == pytest.approx(2.0)
+    assert wt[0, 4, 4] == pytest.approx(math.exp(-1) / (1 + math.exp(-1)))
+
+
+def test_merge_octa_validity_gap(orc):
+    rng = np.random.default_rng(13)
+    sx, sy = rng.uniform(size=(2, 8, 8, 4))
+    ox, oy = rng.uniform(size=(2, 8, 8, 4))
+    vx = np.ones(8)
+    vx[3] = 0.0
+    vy = np.ones(8)
+    vy[5] = 0.0
+    m, mo, _, _ = orc.merge(sx, sy, np.zeros((2, 8, 8, 3)), ox, oy, vx, vy)
+    np.testing.assert_allclose(mo[3, 2], oy[3, 2])   # X invalid in row 3 -> Y only
+    np.testing.assert_allclose(mo[2, 5], ox[2, 5])   # Y invalid in column 5 -> X only
+    np.testing.assert_array_equal(mo[3, 5], 0.0)     # both invalid: a black gap
+    np.testing.assert_allclose(mo[1, 1], 0.5 * (ox[1, 1] + oy[1, 1]))
+
+
+def test_substitute_invalid_and_enface(orc):
+    vol = np.arange(5 * 5 * 2, dtype=float).reshape(5, 5, 2)
+    out = orc.substitute_invalid(vol, np.array([1, 0, 0, 0, 1.0]), 0)
+    np.testing.assert_array_equal(out[1], vol[0])
+    np.testing.assert_array_equal(out[2], vol[0])   # tie -> lower index
+    np.testing.assert_array_equal(out[3], vol[4])
+    out = orc.substitute_invalid(vol, np.array([0, 1, 1, 1, 1.0]), 1)
+    np.testing.assert_array_equal(out[:, 0], vol[:, 1])
+    np.testing.assert_allclose(orc.enface_mean(vol), vol.mean(axis=2))
+
+
+# ---------------------------------------------------------------------------
+# end to end: synthetic recovery
+
+def recovery_mask(pair):
+    """A-scans away from the border and from B-scans that contain a saccade."""
+    n = pair.meta["n"]
+    fly = pair.meta["flyback"]
+    m = np.ones((2, n, n), bool)
+    tsX, tsY = pair.meta["saccade_times"]
+    for t in tsX:
+        b = t // (n + fly)
+        m[:, max(0, b - 2):b + 3, :] = False
+    for t in tsY:
+        b = t // (n + fly)
+        m[:, :, max(0, b - 2):b + 3] = False
+    m[:, :3] = m[:, -3:] = False
+    m[:, :, :3] = m[:, :, -3:] = False
+    return m
+
+
+@pytest.mark.slow
+def test_synthetic_recovery_tiny(orc):
+    pair = synth.make_pair("tiny")
+    D, reps = orc.register(orc.level_from_pair(pair), orc.Params(levels=3))
+    m = recovery_mask(pair)
+    e = D - pair.d_gt.numpy()
+    e -= e[m].mean(axis=0)
+    rms = np.sqrt((e[m] ** 2).mean(axis=0))
+    zero = pair.d_gt.numpy()[m]
+    assert m.mean() > 0.4
+    assert np.all(rms < 0.25), rms
+    assert np.all(np.sqrt((zero ** 2).mean(axis=0)) > 1.0)  # the motion was real
+    assert reps[-1]["f_end"] < reps[-1]["f_start"]
