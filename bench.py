@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the registration hot path on one MI355X.
+
+A step is one evaluation of the full objective and its gradient (displacement
+sum, structural resample + residual + depth reduction, en face / validity /
+regulariser / mean terms and the float64 global sums) at the finest level of
+the dense synthetic pair (500 x 500 A-scans x 800 samples per scan, X-fast +
+Y-fast), with the inputs resident in HBM.  The line printed last is one JSON
+object: evals/s, the roofline of the dominant kernel (timed live with HIP
+events on the stream it runs on), the FP64 oracle's rate on the host cores
+for a bounded sample of A-scans, and secondary figures (full solve, BF16/FP16
+storage).
+
+    python bench.py [--steps K] [--warmup W] [--dtype f32|bf16|f16]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "obj+grad evals/s & HBM GB/s (500²×800 pair); pairs/s, p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# float32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flop per FMA (no packed FP32)
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# algorithmic work of the structural kernel per voxel pair: per scan 16 FMA
+# lateral blend + 4 + 4 depth FIR (value, d/dz) + 4 adjoint FIR + 16 column
+# dots + 1 (Gamma_z) = 45 FMA; two scans = 90 FMA = 180 flop; plus 12 single
+# operations for residual, pseudo-Huber value and derivative and the sum
+FLOP_PER_VOXEL_PAIR = 192
+EXTRA_BYTES_PER_ASCAN = 2 * 12 + 32  # displacements in, partial sums out
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha():
+    p = os.path.join(ROOT, "paper_2010_06931_amd", "csrc", "kernels_eval.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(dtype):
+    """HBM traffic of the structural kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "k_struct_dense_counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+        r = rec.get(dtype)
+        if not r or rec.get("source_sha") != source_sha():
+            return None
+        return r["bytes_per_launch"]
+    except Exception:  # noqa: BLE001 - a malformed file means no figure
+        return None
+
+
+def cpu_baseline(pair, D, target_s=15.0):
+    """The FP64 oracle (as it stands) on the host: data term of a bounded
+    sample of A-scans, scaled to evaluations per second."""
+    import numpy as np
+
+    import oracle
+    lv = oracle.Level(*(oracle._f64(t) for t in (pair.sx, pair.sy, pair.ax, pair.ay, pair.vx, pair.vy)))
+    Dn = D.double().cpu().numpy()
+    w, h, d = lv.whd
+    na = w * h
+    rng = np.random.default_rng(0)
+    prm = oracle.Params()
+    probe = rng.choice(na, size=256, replace=False)
+    t0 = time.perf_counter()
+    oracle.data_ascans(lv, Dn, probe, prm, 1.0)
+    t_probe = time.perf_counter() - t0
+    nsample = int(min(na, max(256, 256 * target_s / max(t_probe, 1e-3))))
+    sample = rng.choice(na, size=nsample, replace=False)
+    t0 = time.perf_counter()
+    oracle.data_ascans(lv, Dn, sample, prm, 1.0)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": (nsample / na) / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"data term of {nsample} random A-scans of the {w}x{h}x{d} pair ({dt:.1f} s), scaled by "
+                      f"{na}/{nsample}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--n", type=int, default=500)
+    ap.add_argument("--d", type=int, default=800)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="only the timed evaluations (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (pairs are independent: a multi-GPU "
+              f"deployment runs one process per GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2010_06931_amd as octmc
+    import synth
+
+    torch.cuda.set_device(0)
+    log(f"generating the dense pair {args.n}x{args.n}x{args.d} on cuda")
+    pair = synth.make_pair("dense", n=args.n, d=args.d, device="cuda", octa_volumes=False)
+    log("ingest")
+    P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=args.dtype, levels=4)
+    rng = np.random.default_rng(1)
+    D = (pair.d_gt + torch.from_numpy(rng.normal(0, 0.2, tuple(pair.d_gt.shape)))).float().cuda()
+    terms = torch.empty(octmc.NTERMS, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(D)
+    P.eval(0, D, grad=grad, terms=terms, eta_mode=0)  # eta of this level (Eq. 10)
+    for _ in range(args.warmup):
+        P.eval(0, D, grad=grad, terms=terms)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} evaluations")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        P.eval(0, D, grad=grad, terms=terms)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    evals_s = 1000.0 / ms
+    log(f"{ms:.4f} ms/eval ({evals_s:.1f} evals/s), wall {wall:.2f} s")
+    if args.profile_only:
+        print(json.dumps({"ms_per_eval": ms}))
+        return
+
+    # dominant kernel timed live with HIP events on its stream
+    stages = np.array([P.eval_profile(0, D, grad=grad, terms=terms) for _ in range(max(20, args.steps // 4))])
+    st_ms = stages.mean(axis=0)
+    w, h, d = args.n, args.n, args.d
+    esz = 4 if args.dtype == "f32" else 2
+    alg_bytes = 2 * w * h * d * esz + w * h * EXTRA_BYTES_PER_ASCAN
+    t_struct = st_ms[1] * 1e-3
+    hbm = alg_bytes / t_struct / 1e9
+    flops = FLOP_PER_VOXEL_PAIR * w * h * d / t_struct / 1e12
+    traffic = load_traffic(args.dtype)
+    hbm_obj = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": traffic}
+    alu_obj = {"bound": "alu", "achieved": round(flops, 2), "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+               "frac": round(flops / VALU_PEAK_TFLOPS, 4), "traffic": traffic}
+    roof, other = (alu_obj, hbm_obj) if alu_obj["frac"] >= hbm_obj["frac"] else (hbm_obj, alu_obj)
+
+    out = {"metric": METRIC, "value": round(evals_s, 2), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"dense orthogonal pair {w}x{h} A-scans x {d} samples, finest level, "
+                                  f"storage {args.dtype}", "w": w, "h": h, "d": d, "level": 0,
+                      "storage": args.dtype, "parallelism": "single GPU"},
+           "roofline": roof, "roofline_other": other,
+           "kernel_ms": {"sum": round(st_ms[0], 5), "struct": round(st_ms[1], 5), "combine": round(st_ms[2], 5)},
+           "hbm_GBps_algorithmic": round(hbm, 1)}
+
+    if not args.no_variants:
+        var = {}
+        for dt in ("f32", "bf16", "f16"):
+            if dt == args.dtype:
+                continue
+            log(f"variant storage {dt}")
+            Q = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=dt, levels=4)
+            Q.eval(0, D, grad=grad, terms=terms, eta_mode=0)
+            for _ in range(args.warmup):
+                Q.eval(0, D, grad=grad, terms=terms)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                Q.eval(0, D, grad=grad, terms=terms)
+            e1.record()
+            torch.cuda.synchronize()
+            vms = e0.elapsed_time(e1) / args.steps
+            vst = np.array([Q.eval_profile(0, D, grad=grad, terms=terms) for _ in range(20)]).mean(axis=0)
+            vb = 2 * w * h * d * (4 if dt == "f32" else 2) + w * h * EXTRA_BYTES_PER_ASCAN
+            var[dt] = {"evals_per_s": round(1000 / vms, 2), "struct_ms": round(vst[1], 5),
+                       "hbm_GBps_algorithmic": round(vb / (vst[1] * 1e-3) / 1e9, 1)}
+            Q.close()
+            del Q
+        out["storage_variants"] = var
+
+    if not args.no_solve:
+        log("full solve (4 levels x 100 L-BFGS steps)")
+        P.register()  # warm
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            Dsol, _, _, rep = P.register()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+        m = np.ones((2, h, w), bool)
+        m[:, :8] = m[:, -8:] = False
+        m[:, :, :8] = m[:, :, -8:] = False
+        e = Dsol.double().cpu().numpy() - pair.d_gt.numpy()
+        e -= e[m].mean(axis=0)
+        out["solve"] = {"seconds_median": round(float(np.median(lat)), 4), "pairs_per_s": round(1 / float(np.median(lat)), 3),
+                        "levels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in rep],
+                        "evals_total": int(sum(r["evals"] for r in rep)),
+                        "rms_vs_ground_truth_px": [round(float(x), 4) for x in np.sqrt((e[m] ** 2).mean(axis=0))]}
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(pair, D)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

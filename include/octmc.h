@@ -1,0 +1,211 @@
+/*
+ * octmc.h -- C ABI of the MI355X (gfx950) implementation of orthogonal-raster
+ * OCT/OCTA 3-D motion correction (Ploner et al., arXiv:2010.06931).
+ *
+ * Problem statement (Sec. 2.1): two raster scans of the same eye, one with
+ * B-scans along x ("X-fast") and one along y ("Y-fast"), each w x h A-scans of
+ * d samples, go in; one displacement vector per output A-scan and scan
+ * (dx, dy, dz) and a merged volume come out.  The implementation is limited to
+ * square scans (w == h, Sec. 5).
+ *
+ * Conventions shared by every call:
+ *   - Volumes are [h][w][d] float32, row j (y), column i (x), depth k
+ *     contiguous, both scans in the common (x, y) frame (a Y-fast scan is
+ *     transposed by the caller).  En face images are [h][w] float32.
+ *   - A displacement field ("disp") is [2][h][w][3] float32: scan V (0 = X-fast,
+ *     1 = Y-fast), row j, column i, component (dx, dy, dz), in pixels of the
+ *     pyramid level it belongs to.  Scan V's sample for output voxel (i, j, k)
+ *     is taken at (i + dx, j + dy, k + dz) of its own volume (Eq. 2).
+ *   - Every function returns an octmc_status: 0 on success, < 0 on error.
+ *     Nothing throws across the ABI.  octmc_last_error() describes the last
+ *     error of the calling thread.
+ *   - Ownership: the caller owns every pointer it passes and the library never
+ *     frees caller memory.  Device pointers must belong to the context's
+ *     device.  Objects created by the library are freed by the matching
+ *     *_destroy call.
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Device
+ *     outputs are valid once that stream has completed the call's work; calls
+ *     that return host values synchronise the stream themselves.
+ *   - Asynchronous device faults surface at a later call as OCTMC_E_DEVICE.
+ *   - Threading: one host thread per pair object at a time.
+ */
+#ifndef OCTMC_H
+#define OCTMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(OCTMC_BUILD)
+#define OCTMC_API __attribute__((visibility("default")))
+#else
+#define OCTMC_API
+#endif
+
+typedef enum {
+    OCTMC_OK = 0,
+    OCTMC_E_INVALID = -1, /* bad argument (NULL pointer, out-of-range parameter) */
+    OCTMC_E_SHAPE = -2,   /* unsupported shape (w != h, too small for the pyramid, too large) */
+    OCTMC_E_DTYPE = -3,   /* unknown storage type */
+    OCTMC_E_OOM = -4,     /* device allocation failed / request can never fit */
+    OCTMC_E_DEVICE = -5,  /* HIP runtime error */
+    OCTMC_E_NAN = -6,     /* non-finite input with OCTMC_CHECK_NAN set */
+    OCTMC_E_BUSY = -7     /* object in use */
+} octmc_status;
+
+/* Storage type of the structural volumes inside the library (the inputs are
+ * always float32; they are rounded to nearest-even on ingest).  Arithmetic is
+ * float32 in the kernels and float64 in every global reduction and in the
+ * L-BFGS state. */
+typedef enum { OCTMC_F32 = 0, OCTMC_BF16 = 1, OCTMC_F16 = 2 } octmc_dtype;
+
+typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
+
+/* flags */
+#define OCTMC_CHECK_NAN 0x1u /* scan the inputs for NaN/Inf at pair creation */
+
+/* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
+ * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
+ * paper leaves open. */
+typedef struct {
+    double alpha;        /* weight of the scan-order regulariser R (Eq. 1)       [R: 1.0]  */
+    double delta0;       /* angiography weight of a valid A-scan (Eq. 8)          [P: 0.5]  */
+    double eps_huber;    /* pseudo-Huber parameter of the data term (Eq. 4)       [P: 1e-3] */
+    double eps_reg;      /* pseudo-Huber parameter of R, in pixels                [R: 0.1]  */
+    double flyback_frac; /* flyback per B-scan, fraction of the B-scan length     [R: 0.25] */
+    double mean_weight;  /* gamma_M of the mean-displacement term M               [R: 1.0]  */
+    int32_t levels;      /* pyramid levels (factor 2, Sec. 2.1)                   [3]       */
+    int32_t iters_per_level; /* accepted L-BFGS steps per level                   [100]     */
+    int32_t lbfgs_m;     /* L-BFGS memory (1..8)                                  [R: 5]    */
+    int32_t ls_max_evals;/* evaluations per line search                           [R: 20]   */
+    double c1, c2;       /* strong Wolfe constants                                [R: 1e-4, 0.9] */
+    double merge_kappa;  /* density weight decay exp(-kappa (rho - 1))            [R: 1.0]  */
+    double merge_tau;    /* weights below tau are clipped to 0                    [R: 0.05] */
+    uint32_t flags;      /* OCTMC_CHECK_NAN */
+} octmc_params;
+
+typedef struct {
+    int32_t w, h, d;   /* A-scans per row, rows, samples per A-scan; w == h */
+    octmc_dtype dtype; /* storage type of the structural volumes */
+    octmc_mem mem;     /* where the input pointers of octmc_pair_create live */
+} octmc_shape;
+
+/* Indices into the terms array written by octmc_eval (float64). */
+enum {
+    OCTMC_TERM_F = 0,     /* objective: data + alpha R + M                        (Eq. 1) */
+    OCTMC_TERM_DATA = 1,  /* eta S_str + S_ang / eta                              (Eq. 9) */
+    OCTMC_TERM_STR = 2,   /* S_str at delta0                                      (Eq. 6) */
+    OCTMC_TERM_ANG = 3,   /* S_ang at delta0                                      (Eq. 7) */
+    OCTMC_TERM_REG = 4,   /* R (not multiplied by alpha)                                  */
+    OCTMC_TERM_MEAN = 5,  /* M                                                            */
+    OCTMC_TERM_STR05 = 6, /* S_str at delta0 = 0.5 (for eta, Eq. 10)                      */
+    OCTMC_TERM_ANG05 = 7, /* S_ang at delta0 = 0.5                                        */
+    OCTMC_TERM_ETA = 8,   /* the eta the evaluation used                                  */
+    OCTMC_TERM_GP = 9,    /* reserved (directional derivative inside the solver)          */
+    OCTMC_NTERMS = 10
+};
+
+#define OCTMC_MAX_LEVELS 8
+
+/* Per-level solve report, coarsest level first. */
+typedef struct {
+    int32_t nlevels;
+    int32_t iters[OCTMC_MAX_LEVELS];
+    int32_t evals[OCTMC_MAX_LEVELS];
+    int32_t ls_fail[OCTMC_MAX_LEVELS];
+    double eta[OCTMC_MAX_LEVELS];
+    double f_start[OCTMC_MAX_LEVELS];
+    double f_end[OCTMC_MAX_LEVELS];
+} octmc_report;
+
+typedef struct octmc_ctx octmc_ctx;
+typedef struct octmc_pair octmc_pair;
+
+/* Library version string (static storage). */
+OCTMC_API const char* octmc_version(void);
+
+/* Description of the calling thread's last error (valid until its next call). */
+OCTMC_API const char* octmc_last_error(void);
+
+/* Fill *out with the defaults listed in octmc_params. */
+OCTMC_API int octmc_params_default(octmc_params* out);
+
+/* Create a context bound to HIP device `device_ordinal`. */
+OCTMC_API int octmc_create(int device_ordinal, octmc_ctx** out);
+OCTMC_API int octmc_destroy(octmc_ctx* ctx);
+
+/* Ingest one orthogonal scan pair (Sec. 2.1 input; pyramid of Sec. 2.1
+ * "optimization"; validity of Sec. 2.2; en face images of Sec. 2.3/2.4).
+ *   oct_x, oct_y       structural volumes [h][w][d] float32 (required);
+ *   octa_x, octa_y     OCTA volumes [h][w][d] float32, or NULL; when given,
+ *                      the en face images are their depth means (a stand-in
+ *                      for the projection of Sec. 2.3) unless enface_* are
+ *                      given, and invalid B-scans are replaced by their
+ *                      nearest valid neighbour for the OCTA merge (Sec. 2.5);
+ *   enface_x, enface_y en face OCTA images [h][w] float32, or NULL;
+ *   valid_x[h], valid_y[w] B-scan validity (Sec. 2.2, 1 = valid), or NULL for
+ *                      all valid.  X-fast B-scans are rows, Y-fast columns.
+ * Either both OCTA volumes or both en face images must be given.  All input
+ * pointers live in shape->mem memory.  The library copies every input into
+ * its own device memory; the caller may free them once the call returns.
+ * Errors: OCTMC_E_SHAPE (w != h, min(w, d) at the coarsest level < 4,
+ * volume > 2^31 bytes), OCTMC_E_DTYPE, OCTMC_E_INVALID, OCTMC_E_OOM,
+ * OCTMC_E_NAN (with OCTMC_CHECK_NAN), OCTMC_E_DEVICE. */
+OCTMC_API int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape,
+                      const float* oct_x, const float* oct_y, const float* octa_x, const float* octa_y,
+                      const float* enface_x, const float* enface_y, const float* valid_x,
+                      const float* valid_y, void* stream, octmc_pair** out);
+OCTMC_API int octmc_pair_destroy(octmc_pair* pair);
+
+/* Shape (w, h, d) of pyramid level `level` (0 = finest). */
+OCTMC_API int octmc_pair_level_shape(const octmc_pair* pair, int32_t level, int32_t* w, int32_t* h, int32_t* d);
+
+/* One evaluation of the objective (Eq. 1 without T: Eqs. 2-9 plus R and M)
+ * and its gradient at pyramid level `level` -- the hot path.
+ *   disp   device [2][h][w][3] float32 displacement in level pixels;
+ *   terms  device float64[OCTMC_NTERMS] (see OCTMC_TERM_*);
+ *   grad   device [2][h][w][3] float32 dF/d(disp), or NULL;
+ *   eta_mode 0: set the level's eta from this displacement (Eq. 10, delta0 =
+ *            0.5) before evaluating; 1: use the level's stored eta (1.0 until
+ *            set).
+ * Asynchronous on `stream`; nothing is copied to the host. */
+OCTMC_API int octmc_eval(octmc_pair* pair, int32_t level, const float* disp, double* terms, float* grad,
+               int32_t eta_mode, void* stream);
+
+/* The same evaluation for npairs pairs whose level `level` has one common
+ * shape, in one grouped launch per kernel.  disp and grad are
+ * [npairs][2][h][w][3] float32 (device), terms [npairs][OCTMC_NTERMS]
+ * float64 (device).  Errors: OCTMC_E_SHAPE if the shapes differ. */
+OCTMC_API int octmc_eval_batched(octmc_pair* const* pairs, int32_t npairs, int32_t level, const float* disp,
+                       double* terms, float* grad, int32_t eta_mode, void* stream);
+
+/* octmc_eval with HIP events recorded on `stream` between its kernels:
+ * stage_ms[0] = displacement sum (mean term), [1] = structural resample /
+ * residual / depth reduction (the dominant kernel), [2] = en face, validity,
+ * combination, regulariser and global sums (both passes when eta_mode = 0).
+ * Synchronises the stream.  For measurement; results equal octmc_eval's. */
+OCTMC_API int octmc_eval_profile(octmc_pair* pair, int32_t level, const float* disp, double* terms, float* grad,
+                                 int32_t eta_mode, float* stage_ms, void* stream);
+
+/* Full multi-resolution registration (Sec. 2.1): zero displacement at the
+ * coarsest level, eta fixed per level at its initial field (Eq. 10), L-BFGS
+ * with a strong Wolfe line search per level, bilinear x2 upsampling between
+ * levels.  disp_out: device [2][h][w][3] float32 at the finest level.
+ * merged_oct / merged_octa: device [h][w][d] float32 or NULL (Sec. 2.1
+ * "merging", Sec. 2.5); merged_octa needs OCTA volumes at pair creation.
+ * rep: host report or NULL.  Synchronises `stream`. */
+OCTMC_API int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oct, float* merged_octa,
+                   octmc_report* rep, void* stream);
+
+/* Merge only (Sec. 2.1 "merging", Sec. 2.5), with a given finest-level
+ * displacement field disp (device).  merged_octa may be NULL. */
+OCTMC_API int octmc_merge(octmc_pair* pair, const float* disp, float* merged_oct, float* merged_octa, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTMC_H */

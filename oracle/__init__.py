@@ -86,6 +86,8 @@ def lib():
         L.orc_pseudo_huber.argtypes = [C.c_double, C.c_double, dp]
         L.orc_eval.argtypes = [dp] * 6 + [C.c_int] * 3 + [dp, C.POINTER(_Params), C.c_double, dp, dp]
         L.orc_eval.restype = C.c_int
+        L.orc_data_ascans.argtypes = [dp] * 6 + [C.c_int] * 3 + [dp, C.POINTER(_Params), C.c_double,
+                                                                C.POINTER(C.c_int64), C.c_int, dp, dp]
         L.orc_eta_from_terms.argtypes = [C.c_double, C.c_double]
         L.orc_eta_from_terms.restype = C.c_double
         L.orc_pyr_down3.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
@@ -198,6 +200,23 @@ def evaluate(lv: Level, D, params: Params | None = None, eta: float = 1.0, grad:
     if rc:
         raise RuntimeError(f"orc_eval failed ({rc})")
     return dict(zip(TERM_NAMES, terms.tolist())), g
+
+
+def data_ascans(lv: Level, D, ascans, params: Params | None = None, eta: float = 1.0):
+    """Data term pieces and data gradient of selected A-scans (index j w + i):
+    part [n][5] = (eta-weighted data, S_str, S_ang, S_str05, S_ang05 summands),
+    grad [n][6] = (d/d d^X, d/d d^Y)."""
+    params = params or Params()
+    D = _f64(D)
+    w, h, d = lv.whd
+    lst = np.ascontiguousarray(ascans, dtype=np.int64)
+    part = np.zeros((lst.size, 5))
+    g = np.zeros((lst.size, 6))
+    pc = params.c()
+    lib().orc_data_ascans(_p(lv.sx), _p(lv.sy), _p(lv.ax), _p(lv.ay), _p(lv.vx), _p(lv.vy), w, h, d, _p(D),
+                          C.byref(pc), float(eta), lst.ctypes.data_as(C.POINTER(C.c_int64)), lst.size,
+                          _p(part), _p(g))
+    return part, g
 
 
 def eta_from_terms(s_str05: float, s_ang05: float) -> float:

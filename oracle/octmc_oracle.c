@@ -367,6 +367,25 @@ EXPORT int orc_eval(const double* sx, const double* sy, const double* ax, const 
     return 0;
 }
 
+/* The data term of Eqs. 2-9 and its gradient for a list of output A-scans
+ * only (index a = j w + i), for checks at sizes where the full sum is too
+ * slow: part[q*5 + 0..4] and g[q*6 + 0..5] as in data_ascan. */
+EXPORT int orc_data_ascans(const double* sx, const double* sy, const double* ax, const double* ay,
+                           const double* vx, const double* vy, int w, int h, int d, const double* D,
+                           const orc_params* p, double eta, const int64_t* list, int nlist,
+                           double* part, double* g)
+{
+    size_t na = (size_t)w * h;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < nlist; q++) {
+        int64_t a = list[q];
+        int i = (int)(a % w), j = (int)(a / w);
+        data_ascan(sx, sy, ax, ay, vx, vy, w, h, d, D + (size_t)a * 3, D + (na + a) * 3, i, j,
+                   p->delta0, p->eps_h, eta, part + (size_t)q * 5, g + (size_t)q * 6);
+    }
+    return 0;
+}
+
 /* eta (Eq. 10): sqrt(S_ang_0.5 / S_str_0.5) at the level's initial field.
  * Reading: where either term is zero (e.g. identical inputs) eta = 1. */
 EXPORT double orc_eta_from_terms(double s_str05, double s_ang05)
@@ -639,16 +658,17 @@ EXPORT int orc_lbfgs(int n, double* x, orc_fg_fn fg, void* ctx, int m, int max_i
             rep->ls_fail = 1;
             break;
         }
-        /* new pair s = x_new - x, y = g_new - g */
-        int slot = (newest + 1) % m;
-        double* sv = S + (size_t)slot * n;
-        double* yv = Y + (size_t)slot * n;
+        /* new pair s = x_new - x, y = g_new - g; it replaces the oldest
+         * stored pair only if it passes the curvature test */
         for (int k = 0; k < n; k++) {
-            sv[k] = xt[k] - x[k];
-            yv[k] = gt[k] - g[k];
+            q[k] = xt[k] - x[k];   /* q is free here: reused as s */
+            p[k] = gt[k] - g[k];   /* p is no longer needed: reused as y */
         }
-        double sy = dotn(n, sv, yv), yy = dotn(n, yv, yv);
+        double sy = dotn(n, q, p), yy = dotn(n, p, p);
         if (sy > 1e-12 * yy && yy > 0) {
+            int slot = (newest + 1) % m;
+            memcpy(S + (size_t)slot * n, q, n * sizeof(double));
+            memcpy(Y + (size_t)slot * n, p, n * sizeof(double));
             rho[slot] = 1.0 / sy;
             newest = slot;
             if (count < m) count++;

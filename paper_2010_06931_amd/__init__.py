@@ -1,0 +1,278 @@
+"""octmc: orthogonal-raster OCT/OCTA 3-D motion correction on MI355X (gfx950).
+
+Thin ctypes binding of the C ABI in include/octmc.h (liboctmc.so, built
+in-tree by paper_2010_06931_amd.build).  The binding only marshals arguments:
+every step of the registration runs in the library's HIP kernels.  PyTorch
+supplies device memory and streams.  There is no fallback: if the library is
+missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboctmc.so")
+
+F32, BF16, F16 = 0, 1, 2
+_DTYPES = {"f32": F32, "float32": F32, "bf16": BF16, "bfloat16": BF16, "f16": F16, "float16": F16}
+MEM_HOST, MEM_DEVICE = 0, 1
+CHECK_NAN = 0x1
+MAX_LEVELS = 8
+
+TERM_F, TERM_DATA, TERM_STR, TERM_ANG, TERM_REG, TERM_MEAN, TERM_STR05, TERM_ANG05, TERM_ETA, TERM_GP = range(10)
+NTERMS = 10
+TERM_NAMES = ("F", "data", "str", "ang", "reg", "mean", "str05", "ang05", "eta", "gp")
+
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_DTYPE", -4: "E_OOM", -5: "E_DEVICE", -6: "E_NAN",
+          -7: "E_BUSY"}
+
+# exported symbols of include/octmc.h (checked by the CPU test suite)
+SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_create", "octmc_destroy",
+           "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_eval",
+           "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge")
+
+
+class Params(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("delta0", C.c_double), ("eps_huber", C.c_double),
+                ("eps_reg", C.c_double), ("flyback_frac", C.c_double), ("mean_weight", C.c_double),
+                ("levels", C.c_int32), ("iters_per_level", C.c_int32), ("lbfgs_m", C.c_int32),
+                ("ls_max_evals", C.c_int32), ("c1", C.c_double), ("c2", C.c_double),
+                ("merge_kappa", C.c_double), ("merge_tau", C.c_double), ("flags", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Shape(C.Structure):
+    _fields_ = [("w", C.c_int32), ("h", C.c_int32), ("d", C.c_int32), ("dtype", C.c_int), ("mem", C.c_int)]
+
+
+class Report(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("iters", C.c_int32 * MAX_LEVELS), ("evals", C.c_int32 * MAX_LEVELS),
+                ("ls_fail", C.c_int32 * MAX_LEVELS), ("eta", C.c_double * MAX_LEVELS),
+                ("f_start", C.c_double * MAX_LEVELS), ("f_end", C.c_double * MAX_LEVELS)]
+
+    def as_list(self):
+        n = self.nlevels
+        return [dict(iters=self.iters[k], evals=self.evals[k], ls_fail=self.ls_fail[k], eta=self.eta[k],
+                     f_start=self.f_start[k], f_end=self.f_end[k]) for k in range(n)]
+
+
+class OctmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"octmc {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded liboctmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2010_06931_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.octmc_version.restype = C.c_char_p
+        L.octmc_last_error.restype = C.c_char_p
+        L.octmc_params_default.argtypes = [C.POINTER(Params)]
+        L.octmc_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.octmc_destroy.argtypes = [vp]
+        L.octmc_pair_create.argtypes = [vp, C.POINTER(Params), C.POINTER(Shape)] + [vp] * 8 + [vp, C.POINTER(vp)]
+        L.octmc_pair_destroy.argtypes = [vp]
+        L.octmc_pair_level_shape.argtypes = [vp, C.c_int32] + [C.POINTER(C.c_int32)] * 3
+        L.octmc_eval.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
+        L.octmc_eval_profile.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), vp]
+        L.octmc_eval_batched.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
+        L.octmc_register.argtypes = [vp, vp, vp, vp, C.POINTER(Report), vp]
+        L.octmc_merge.argtypes = [vp, vp, vp, vp, vp]
+        for name in SYMBOLS:
+            if name not in ("octmc_version", "octmc_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise OctmcError(rc, lib().octmc_last_error().decode())
+
+
+def version() -> str:
+    return lib().octmc_version().decode()
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    _check(lib().octmc_params_default(C.byref(p)))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _f32(t, device):
+    if t is None:
+        return None
+    t = torch.as_tensor(t)
+    return t.to(device=device, dtype=torch.float32).contiguous()
+
+
+class Context:
+    """A library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self._h = C.c_void_p()
+        _check(lib().octmc_create(device, C.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().octmc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+_default_ctx = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+class Pair:
+    """One orthogonal scan pair resident on the GPU (pyramid of every input).
+
+    sx, sy: structural volumes [h][w][d]; ox, oy: OCTA volumes (optional);
+    ax, ay: en face images [h][w] (optional if ox, oy are given); vx[h], vy[w]:
+    B-scan validity (optional).  Tensors may live on the host or on the device;
+    the library copies them."""
+
+    def __init__(self, sx, sy, *, ox=None, oy=None, ax=None, ay=None, vx=None, vy=None, params: Params | None = None,
+                 dtype: str = "f32", ctx: Context | None = None, stream=None, **param_overrides):
+        self.ctx = ctx or context(0)
+        dev = torch.device("cuda", self.ctx.device)
+        self.params = params if params is not None else default_params()
+        for k, v in param_overrides.items():
+            setattr(self.params, k, v)
+        sx, sy = _f32(sx, dev), _f32(sy, dev)
+        h, w, d = sx.shape
+        if sy.shape != sx.shape:
+            raise ValueError("sx and sy differ in shape")
+        self.shape = Shape(w, h, d, _DTYPES[dtype], MEM_DEVICE)
+        self.dtype = dtype
+        ins = [sx, sy, _f32(ox, dev), _f32(oy, dev), _f32(ax, dev), _f32(ay, dev), _f32(vx, dev), _f32(vy, dev)]
+        self._h = C.c_void_p()
+        _check(lib().octmc_pair_create(self.ctx._h, C.byref(self.params), C.byref(self.shape),
+                                       *[_ptr(t) for t in ins], _stream(stream), C.byref(self._h)))
+        self.has_octa = ox is not None
+
+    @property
+    def levels(self) -> int:
+        return self.params.levels
+
+    def level_shape(self, level: int):
+        w, h, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().octmc_pair_level_shape(self._h, level, C.byref(w), C.byref(h), C.byref(d)))
+        return w.value, h.value, d.value
+
+    def eval(self, level: int, disp: torch.Tensor, *, grad: bool | torch.Tensor = True, terms=None,
+             eta_mode: int = 1, stream=None):
+        """Objective terms (float64[NTERMS], device) and gradient (like disp)."""
+        w, h, d = self.level_shape(level)
+        if disp.shape != (2, h, w, 3) or disp.dtype != torch.float32 or not disp.is_cuda:
+            raise ValueError(f"disp must be a float32 cuda tensor of shape (2, {h}, {w}, 3)")
+        disp = disp.contiguous()
+        if terms is None:
+            terms = torch.empty(NTERMS, dtype=torch.float64, device=disp.device)
+        g = None
+        if grad is True:
+            g = torch.empty_like(disp)
+        elif isinstance(grad, torch.Tensor):
+            g = grad
+        _check(lib().octmc_eval(self._h, level, _ptr(disp), _ptr(terms), _ptr(g), eta_mode, _stream(stream)))
+        return terms, g
+
+    def eval_profile(self, level: int, disp: torch.Tensor, *, grad: torch.Tensor | None = None, terms=None,
+                     eta_mode: int = 1, stream=None):
+        """octmc_eval with HIP events between its kernels; returns the stage
+        times in ms: (displacement sum, structural kernel, combine)."""
+        if terms is None:
+            terms = torch.empty(NTERMS, dtype=torch.float64, device=disp.device)
+        ms = (C.c_float * 3)()
+        _check(lib().octmc_eval_profile(self._h, level, _ptr(disp), _ptr(terms), _ptr(grad), eta_mode, ms,
+                                        _stream(stream)))
+        return list(ms)
+
+    def register(self, *, merged: bool = False, stream=None):
+        """Full solve.  Returns (disp [2][h][w][3], merged_oct or None,
+        merged_octa or None, per-level report list)."""
+        h, w, d = self.shape.h, self.shape.w, self.shape.d
+        dev = torch.device("cuda", self.ctx.device)
+        disp = torch.empty((2, h, w, 3), dtype=torch.float32, device=dev)
+        mo = torch.empty((h, w, d), dtype=torch.float32, device=dev) if merged else None
+        ma = torch.empty((h, w, d), dtype=torch.float32, device=dev) if (merged and self.has_octa) else None
+        rep = Report()
+        _check(lib().octmc_register(self._h, _ptr(disp), _ptr(mo), _ptr(ma), C.byref(rep), _stream(stream)))
+        return disp, mo, ma, rep.as_list()
+
+    def merge(self, disp: torch.Tensor, *, octa: bool = False, stream=None):
+        h, w, d = self.shape.h, self.shape.w, self.shape.d
+        mo = torch.empty((h, w, d), dtype=torch.float32, device=disp.device)
+        ma = torch.empty((h, w, d), dtype=torch.float32, device=disp.device) if octa else None
+        _check(lib().octmc_merge(self._h, _ptr(disp.contiguous()), _ptr(mo), _ptr(ma), _stream(stream)))
+        return mo, ma
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().octmc_pair_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
+
+
+def eval_batched(pairs, level: int, disp: torch.Tensor, *, grad: bool = True, eta_mode: int = 1, stream=None):
+    """One grouped evaluation over pairs sharing the level shape.
+    disp: [B][2][h][w][3] float32 cuda.  Returns terms [B][NTERMS], grad."""
+    B = len(pairs)
+    disp = disp.contiguous()
+    terms = torch.empty((B, NTERMS), dtype=torch.float64, device=disp.device)
+    g = torch.empty_like(disp) if grad else None
+    arr = (C.c_void_p * B)(*[p._h for p in pairs])
+    _check(lib().octmc_eval_batched(arr, B, level, _ptr(disp), _ptr(terms), _ptr(g), eta_mode, _stream(stream)))
+    return terms, g
+
+
+def terms_dict(terms: torch.Tensor) -> dict:
+    t = terms.detach().cpu().tolist()
+    return dict(zip(TERM_NAMES, t))

@@ -1,0 +1,658 @@
+// Hot-path kernels: one evaluation of the registration objective and its
+// gradient (Eqs. 1-10 of Ploner et al., without the stage-1 tilt term).
+//
+//   k_sum     sum of the displacements of both scans (mean term M)
+//   k_struct  per output A-scan: resample both structural volumes with
+//             their displacement (Eq. 2), residual, pseudo-Huber loss (Eq. 4)
+//             and the depth sums of the loss and of its gradient with respect
+//             to the A-scan's displacement
+//   k_combine per output A-scan: en face residual (Eq. 7), resampled
+//             validity (Eq. 5), weight delta (Eq. 8), combination with eta
+//             (Eq. 9), scan-order regulariser, mean term, gradient; and the
+//             float64 global sums in a fixed order
+#include <hip/hip_runtime.h>
+
+#include "octmc_internal.h"
+
+namespace octmc {
+
+namespace {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float uni(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Cubic Hermite spline with central-difference tangents (Catmull-Rom), the
+// C1 "Hermitian" interpolator of Eq. 2: weights of the samples at n-1 .. n+2
+// for the fraction t in [0, 1), and their derivatives.
+__device__ __forceinline__ void cr_taps(float t, float w[4], float dw[4])
+{
+    const float t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5f * (-t3 + 2.f * t2 - t);
+    w[1] = 0.5f * (3.f * t3 - 5.f * t2 + 2.f);
+    w[2] = 0.5f * (-3.f * t3 + 4.f * t2 + t);
+    w[3] = 0.5f * (t3 - t2);
+    dw[0] = 0.5f * (-3.f * t2 + 4.f * t - 1.f);
+    dw[1] = 0.5f * (9.f * t2 - 10.f * t);
+    dw[2] = 0.5f * (-9.f * t2 + 8.f * t + 1.f);
+    dw[3] = 0.5f * (3.f * t2 - 2.f * t);
+}
+
+// Split an integer grid coordinate plus a displacement into the integer base
+// and the fraction without rounding: dv = floor(dv) + frac exactly.
+__device__ __forceinline__ void split(int idx, float dv, int& n, float& t)
+{
+    const float f = floorf(dv);
+    t = dv - f;
+    n = idx + (int)f;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <typename T>
+__device__ __forceinline__ float ldv(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float ldv<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+struct bf16_t {};
+struct f16_t {};
+template <>
+__device__ __forceinline__ float ldv<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+template <>
+__device__ __forceinline__ float ldv<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+    return (float)__builtin_bit_cast(_Float16, b);
+}
+template <typename T> struct esize { static constexpr uint32_t v = 2; };
+template <> struct esize<float> { static constexpr uint32_t v = 4; };
+
+constexpr uint32_t kRsrcWord3 = 0x00020000u;
+
+// Per-scan stencil of one output A-scan: 16 lateral columns with their
+// (wave-uniform) byte offsets and blend weights, and the depth taps.  The
+// lateral derivative taps are recomputed from the fractions after the depth
+// loop, so they do not occupy registers during it.
+struct Stencil {
+    float w[16];
+    uint32_t off[16];
+    float wz[4], dwz[4];
+    float tx, ty;
+    int base;  // source sample of the first depth tap of output sample 0
+};
+
+template <typename T>
+__device__ __forceinline__ void make_stencil(Stencil& s, int i, int j, float dx, float dy, float dz, int w,
+                                             int h, int d)
+{
+    int nx, ny, nz;
+    float tx, ty, tz;
+    split(i, uni(dx), nx, tx);
+    split(j, uni(dy), ny, ty);
+    split(0, uni(dz), nz, tz);
+    nx = uni(nx);
+    ny = uni(ny);
+    nz = uni(nz);
+    float wx[4], dwx[4], wy[4], dwy[4];
+    cr_taps(uni(tx), wx, dwx);
+    cr_taps(uni(ty), wy, dwy);
+    cr_taps(uni(tz), s.wz, s.dwz);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        s.wz[c] = uni(s.wz[c]);
+        s.dwz[c] = uni(s.dwz[c]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int row = clampi(ny - 1 + b, 0, h - 1);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int col = clampi(nx - 1 + a, 0, w - 1);
+            s.off[b * 4 + a] = (uint32_t)uni((int)((uint32_t)(row * w + col) * (uint32_t)d * esize<T>::v));
+            s.w[b * 4 + a] = uni(wx[a] * wy[b]);
+        }
+    }
+    s.tx = uni(tx);
+    s.ty = uni(ty);
+    s.base = uni(nz - 1);
+}
+
+// Depth is processed in steps of 61 output samples on 64 lanes: lane l holds
+// source sample base + 61 n + l, output lane l (< 61) reads source lanes
+// l .. l+3, and the adjoint of output lane l goes to the same source lanes.
+// Every step is therefore self-contained (a source sample shared by two
+// steps receives each step's part of the adjoint separately).
+constexpr int kOutPerStep = 61;
+
+template <typename T>
+__device__ __forceinline__ void load_cols(float (&v)[16], __amdgpu_buffer_rsrc_t r, const Stencil& s, int step,
+                                          int lane, int d)
+{
+    const int m = clampi(s.base + step * kOutPerStep + lane, 0, d - 1);
+    const uint32_t voff = (uint32_t)m * esize<T>::v;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = ldv<T>(r, voff, s.off[q]);
+}
+
+__device__ __forceinline__ float blend(const float (&v)[16], const Stencil& s)
+{
+    float c = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) c = fmaf(s.w[q], v[q], c);
+    return c;
+}
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+    double v = x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return (float)v;
+}
+
+// LDS scratch of one wave: blended columns of both scans (with room for the
+// reads past lane 63) and the loss derivative (with 4 leading zeros).
+constexpr int kRingC = 72;
+constexpr int kRingG = 68;
+constexpr int kRing = 2 * kRingC + kRingG;
+
+// Logical block of a physical one: workgroups are dispatched to the 8 XCDs
+// round robin, so give every XCD a contiguous range of tiles (neighbouring
+// A-scans then share that XCD's L2).  The grid is a multiple of 8.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
+{
+    __shared__ float ring_all[kWavesPerBlock][kRing];
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    int jid = -1;
+    for (int q = 0; q < jobs.n; ++q)
+        if (lb >= jobs.j[q].blk_begin) jid = q;
+    if (jid < 0) return;
+    const StructJob& J = jobs.j[jid];
+    const int w = J.w, h = J.h, d = J.d;
+    // 2 x 2 tile of output A-scans per workgroup, one per wave
+    const int tpr = (w + 1) >> 1;
+    const int t = lb - J.blk_begin;
+    const int i = 2 * (t % tpr) + (wv & 1);
+    const int j = 2 * (t / tpr) + (wv >> 1);
+    if (t >= tpr * ((h + 1) >> 1) || i >= w || j >= h) return;  // whole wave; no block barrier below
+    const int a = uni(j * w + i);
+    const float* dX = J.disp + (size_t)a * 3;
+    const float* dY = J.disp + ((size_t)J.na + a) * 3;
+    Stencil SX, SY;
+    make_stencil<T>(SX, i, j, dX[0], dX[1], dX[2], w, h, d);
+    make_stencil<T>(SY, i, j, dY[0], dY[1], dY[2], w, h, d);
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t ry =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sy), (short)0, (int)J.vol_bytes, kRsrcWord3);
+    float* rcx = ring_all[wv];
+    float* rcy = rcx + kRingC;
+    float* rg = rcy + kRingC;
+    // padding read by the lanes that produce no output sample: zero, so that
+    // masked lanes never see uninitialised values
+    if (lane < kRingC - 64) {
+        rcx[64 + lane] = 0.f;
+        rcy[64 + lane] = 0.f;
+    }
+    if (lane < 4) rg[lane] = 0.f;
+    const float eps = J.eps_h;
+    const float inv_eps = 1.0f / J.eps_h;
+
+    float sx[16], sy[16];
+    float PX[16], PY[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) PX[q] = PY[q] = 0.f;
+    float lam = 0.f, gzx = 0.f, gzy = 0.f;
+    const int nsteps = (d + kOutPerStep - 1) / kOutPerStep;
+    for (int n = 0; n < nsteps; ++n) {
+        load_cols<T>(sx, rx, SX, n, lane, d);
+        load_cols<T>(sy, ry, SY, n, lane, d);
+        rcx[lane] = blend(sx, SX);
+        rcy[lane] = blend(sy, SY);
+        wave_sync();
+        float ix = 0.f, izx = 0.f, iy = 0.f, izy = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float vx = rcx[lane + c];
+            const float vy = rcy[lane + c];
+            ix = fmaf(SX.wz[c], vx, ix);
+            izx = fmaf(SX.dwz[c], vx, izx);
+            iy = fmaf(SY.wz[c], vy, iy);
+            izy = fmaf(SY.dwz[c], vy, izy);
+        }
+        // residual (Eq. 2) and pseudo-Huber loss (Eq. 4) in the form
+        // eps u^2 / (sqrt(1 + u^2) + 1), u = r / eps, and its derivative u / sqrt(1 + u^2)
+        const float r = ix - iy;
+        const float u = r * inv_eps;
+        const float q = u * u;
+        const float rs = __builtin_amdgcn_rsqf(1.f + q);
+        const float sq = (1.f + q) * rs;
+        const bool valid = lane < kOutPerStep && (n * kOutPerStep + lane) < d;
+        const float L = valid ? eps * q * __builtin_amdgcn_rcpf(sq + 1.f) : 0.f;
+        const float G = valid ? u * rs : 0.f;
+        lam += L;
+        gzx += valid ? G * izx : 0.f;
+        gzy += valid ? G * izy : 0.f;
+        rg[4 + lane] = G;
+        wave_sync();
+        float hx = 0.f, hy = 0.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float g = rg[4 + lane - c];
+            hx = fmaf(SX.wz[c], g, hx);
+            hy = fmaf(SY.wz[c], g, hy);
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < 16; ++q2) {
+            PX[q2] = fmaf(sx[q2], hx, PX[q2]);
+            PY[q2] = fmaf(sy[q2], hy, PY[q2]);
+        }
+        wave_sync();
+    }
+    // Gamma_x = sum_ab dwx_a wy_b P_ab, Gamma_y = sum_ab wx_a dwy_b P_ab
+    float wx[4], dwx[4], wy[4], dwy[4];
+    float gxx = 0.f, gyx = 0.f, gxy = 0.f, gyy = 0.f;
+    cr_taps(SX.tx, wx, dwx);
+    cr_taps(SX.ty, wy, dwy);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a2 = 0; a2 < 4; ++a2) {
+            gxx = fmaf(dwx[a2] * wy[b], PX[b * 4 + a2], gxx);
+            gyx = fmaf(wx[a2] * dwy[b], PX[b * 4 + a2], gyx);
+        }
+    cr_taps(SY.tx, wx, dwx);
+    cr_taps(SY.ty, wy, dwy);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a2 = 0; a2 < 4; ++a2) {
+            gxy = fmaf(dwx[a2] * wy[b], PY[b * 4 + a2], gxy);
+            gyy = fmaf(wx[a2] * dwy[b], PY[b * 4 + a2], gyy);
+        }
+    lam = wave_sum(lam);
+    gxx = wave_sum(gxx);
+    gyx = wave_sum(gyx);
+    gzx = wave_sum(gzx);
+    gxy = wave_sum(gxy);
+    gyy = wave_sum(gyy);
+    gzy = wave_sum(gzy);
+    if (lane == 0) {
+        float4* o = reinterpret_cast<float4*>(J.part + (size_t)a * 8);
+        o[0] = make_float4(lam, gxx, gyx, gzx);
+        o[1] = make_float4(gxy, gyy, gzy, 0.f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic block reduction helpers
+
+template <int N>
+__device__ __forceinline__ void block_reduce_store(double (&v)[N], double* blk_row)
+{
+    __shared__ double sh[N][kRedBlock];
+#pragma unroll
+    for (int q = 0; q < N; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < N) blk_row[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// After every block of a job has stored its row, the last one to finish sums
+// the rows in a fixed order (strided per thread, then a fixed tree).
+template <int N>
+__device__ __forceinline__ bool last_block(unsigned* counter, int nblk)
+{
+    __shared__ bool is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == (unsigned)(nblk - 1));
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+template <int N>
+__device__ __forceinline__ void sum_rows(const double* blk, int nblk, double (&out)[N])
+{
+    __shared__ double sh[N][kRedBlock];
+    double acc[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc[q] = 0.0;
+    for (int r = threadIdx.x; r < nblk; r += kRedBlock) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) acc[q] += blk[(size_t)r * N + q];
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = kRedBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = sh[q][0];
+}
+
+__device__ __forceinline__ int find_job(const int* begins, int n)
+{
+    int jid = 0;
+    for (int q = 1; q < n; ++q)
+        if ((int)blockIdx.x >= begins[q]) jid = q;
+    return jid;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kRedBlock) void k_sum(const SumJobs jobs)
+{
+    int jid = 0;
+    for (int q = 1; q < jobs.n; ++q)
+        if ((int)blockIdx.x >= jobs.j[q].blk_begin) jid = q;
+    const SumJob& J = jobs.j[jid];
+    const int b = blockIdx.x - J.blk_begin;
+    double v[4] = {0, 0, 0, 0};
+    const int total = 2 * J.na;
+    for (int q = b * kRedBlock + threadIdx.x; q < total; q += J.nblk * kRedBlock) {
+        v[0] += (double)J.disp[(size_t)q * 3 + 0];
+        v[1] += (double)J.disp[(size_t)q * 3 + 1];
+        v[2] += (double)J.disp[(size_t)q * 3 + 2];
+    }
+    block_reduce_store<4>(v, J.blk + (size_t)b * 4);
+    if (last_block<4>(J.counter, J.nblk)) {
+        double s[4];
+        sum_rows<4>(J.blk, J.nblk, s);
+        if (threadIdx.x < 3) J.out[threadIdx.x] = s[threadIdx.x];
+        if (threadIdx.x == 0) *J.counter = 0u;
+    }
+}
+
+// pseudo-Huber in float64 (regulariser and en face terms)
+__device__ __forceinline__ void huber_d(double x, double eps, double& L, double& dL)
+{
+    const double u = x / eps;
+    const double s = sqrt(1.0 + u * u);
+    L = eps * u * u / (s + 1.0);
+    dL = u / s;
+}
+
+// 2-D / 1-D Catmull-Rom samples (value and derivatives) in float32
+__device__ __forceinline__ void sample2(const float* img, int w, int h, int i, int j, float dx, float dy,
+                                        float out[3])
+{
+    int nx, ny;
+    float tx, ty;
+    split(i, dx, nx, tx);
+    split(j, dy, ny, ty);
+    float wx[4], dwx[4], wy[4], dwy[4];
+    cr_taps(tx, wx, dwx);
+    cr_taps(ty, wy, dwy);
+    float v = 0.f, gx = 0.f, gy = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float* row = img + (size_t)clampi(ny - 1 + b, 0, h - 1) * w;
+        float rv = 0.f, rd = 0.f;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const float s = row[clampi(nx - 1 + a, 0, w - 1)];
+            rv = fmaf(wx[a], s, rv);
+            rd = fmaf(dwx[a], s, rd);
+        }
+        v = fmaf(wy[b], rv, v);
+        gx = fmaf(wy[b], rd, gx);
+        gy = fmaf(dwy[b], rv, gy);
+    }
+    out[0] = v;
+    out[1] = gx;
+    out[2] = gy;
+}
+
+__device__ __forceinline__ void sample1(const float* vec, int n, int i, float dv, float out[2])
+{
+    int nx;
+    float t;
+    split(i, dv, nx, t);
+    float w[4], dw[4];
+    cr_taps(t, w, dw);
+    float v = 0.f, g = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const float s = vec[clampi(nx - 1 + a, 0, n - 1)];
+        v = fmaf(w[a], s, v);
+        g = fmaf(dw[a], s, g);
+    }
+    out[0] = v;
+    out[1] = g;
+}
+
+// Neighbours of output A-scan (i, j) in scan V's acquisition order (X-fast:
+// along rows, then to the next row; Y-fast: along columns).  Returns the
+// A-scan index or -1, and the link weight (1 inside a B-scan, wfb across the
+// flyback between B-scans).
+__device__ __forceinline__ int prev_ascan(int V, int i, int j, int w, int h, double wfb, double& om)
+{
+    if (V == 0) {
+        if (i > 0) { om = 1.0; return j * w + i - 1; }
+        if (j > 0) { om = wfb; return (j - 1) * w + (w - 1); }
+    } else {
+        if (j > 0) { om = 1.0; return (j - 1) * w + i; }
+        if (i > 0) { om = wfb; return (h - 1) * w + (i - 1); }
+    }
+    om = 0.0;
+    return -1;
+}
+__device__ __forceinline__ int next_ascan(int V, int i, int j, int w, int h, double wfb, double& om)
+{
+    if (V == 0) {
+        if (i < w - 1) { om = 1.0; return j * w + i + 1; }
+        if (j < h - 1) { om = wfb; return (j + 1) * w; }
+    } else {
+        if (j < h - 1) { om = 1.0; return (j + 1) * w + i; }
+        if (i < w - 1) { om = wfb; return i + 1; }
+    }
+    om = 0.0;
+    return -1;
+}
+
+__global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
+{
+    int jid = 0;
+    for (int q = 1; q < jobs.n; ++q)
+        if ((int)blockIdx.x >= jobs.j[q].blk_begin) jid = q;
+    const CombineJob& J = jobs.j[jid];
+    const int b = blockIdx.x - J.blk_begin;
+    const int a = b * kRedBlock + threadIdx.x;
+    // partial sums: data, str, ang, reg, (unused), str05, ang05, g.p
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (a < J.na) {
+        const int w = J.w, h = J.h, na = J.na;
+        const double dd = (double)J.d;
+        const int i = a % w, j = a / w;
+        const float4 p0 = reinterpret_cast<const float4*>(J.part)[(size_t)a * 2];
+        const float4 p1 = reinterpret_cast<const float4*>(J.part)[(size_t)a * 2 + 1];
+        const double lam = p0.x;
+        const float* dX = J.disp + (size_t)a * 3;
+        const float* dY = J.disp + ((size_t)na + a) * 3;
+        float jx[3], jy[3];
+        sample2(J.ax, w, h, i, j, dX[0], dX[1], jx);
+        sample2(J.ay, w, h, i, j, dY[0], dY[1], jy);
+        double LA, GA;
+        huber_d((double)jx[0] - (double)jy[0], J.eps_h, LA, GA);
+        float rx[2], ry[2];
+        sample1(J.vx, h, j, dX[1], rx);  // X-fast validity varies along y (Eq. 5)
+        sample1(J.vy, w, i, dY[0], ry);  // Y-fast along x
+        const double tvx = rx[0] <= 0.f ? 0.0 : (rx[0] >= 1.f ? 1.0 : (double)rx[0]);
+        const double dtvx = (rx[0] > 0.f && rx[0] < 1.f) ? (double)rx[1] : 0.0;
+        const double tvy = ry[0] <= 0.f ? 0.0 : (ry[0] >= 1.f ? 1.0 : (double)ry[0]);
+        const double dtvy = (ry[0] > 0.f && ry[0] < 1.f) ? (double)ry[1] : 0.0;
+        v[5] = (1.0 - 0.5 * tvx * tvy) * lam;
+        v[6] = 0.5 * tvx * tvy * dd * LA;
+        if (J.mode == 1) {
+            const double eta = *J.eta;
+            const double delta = J.delta0 * tvx * tvy;  // Eq. 8
+            const double ws = eta * (1.0 - delta);       // structural weight (Eqs. 6, 9)
+            const double wa = dd / eta * delta;          // angiographic weight (Eqs. 7, 9)
+            v[1] = (1.0 - delta) * lam;
+            v[2] = delta * dd * LA;
+            v[0] = eta * v[1] + v[2] / eta;
+            const double dpd = -eta * lam + dd / eta * LA;  // d(data)/d(delta)
+            double g[6];
+            g[0] = ws * p0.y + wa * GA * jx[1];
+            g[1] = ws * p0.z + wa * GA * jx[2] + dpd * J.delta0 * tvy * dtvx;
+            g[2] = ws * p0.w;
+            g[3] = -(ws * p1.x + wa * GA * jy[1]) + dpd * J.delta0 * tvx * dtvy;
+            g[4] = -(ws * p1.y + wa * GA * jy[2]);
+            g[5] = -(ws * p1.z);
+            // scan-order regulariser (gather form: this A-scan's two links)
+            double reg = 0.0;
+            for (int V = 0; V < 2; ++V) {
+                const float* DV = J.disp + (size_t)V * na * 3;
+                const float* da = DV + (size_t)a * 3;
+                double omp, omn;
+                const int pa = prev_ascan(V, i, j, w, h, J.wfb, omp);
+                const int nb = next_ascan(V, i, j, w, h, J.wfb, omn);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double Lr, dLr;
+                    if (pa >= 0) {
+                        huber_d((double)da[c] - (double)DV[(size_t)pa * 3 + c], J.eps_r, Lr, dLr);
+                        g[V * 3 + c] += J.alpha * dd * omp * dLr;
+                    }
+                    if (nb >= 0) {
+                        huber_d((double)DV[(size_t)nb * 3 + c] - (double)da[c], J.eps_r, Lr, dLr);
+                        g[V * 3 + c] -= J.alpha * dd * omn * dLr;
+                        reg += dd * omn * Lr;
+                    }
+                }
+            }
+            v[3] = reg;
+            // mean-displacement term: dM/dd_c = gamma d sum_c / N_A
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double gm = J.gamma * dd * J.sumd[c] / (double)na;
+                g[c] += gm;
+                g[3 + c] += gm;
+            }
+            if (J.grad) {
+                float* gX = J.grad + (size_t)a * 3;
+                float* gY = J.grad + ((size_t)na + a) * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    gX[c] = (float)g[c];
+                    gY[c] = (float)g[3 + c];
+                }
+            }
+            if (J.grad64) {
+                double* gX = J.grad64 + (size_t)a * 3;
+                double* gY = J.grad64 + ((size_t)na + a) * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    gX[c] = g[c];
+                    gY[c] = g[3 + c];
+                }
+            }
+            if (J.p) {  // directional derivative g . p (line search)
+                const double* pX = J.p + (size_t)a * 3;
+                const double* pY = J.p + ((size_t)na + a) * 3;
+                double gp = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gp += g[c] * pX[c] + g[3 + c] * pY[c];
+                v[7] = gp;
+            }
+        }
+    }
+    block_reduce_store<8>(v, J.blk + (size_t)b * 8);
+    if (last_block<8>(J.counter, J.nblk)) {
+        double s[8];
+        sum_rows<8>(J.blk, J.nblk, s);
+        if (threadIdx.x == 0) {
+            if (J.mode == 0) {
+                // Eq. 10; eta = 1 where a term vanishes (identical inputs)
+                *J.eta = (s[5] > 1e-300 && s[6] > 1e-300) ? sqrt(s[6] / s[5]) : 1.0;
+            } else {
+                const double eta = *J.eta;
+                double m = 0.0;
+                for (int c = 0; c < 3; ++c) m += J.sumd[c] * J.sumd[c];
+                m *= J.gamma * (double)J.d / (2.0 * (double)J.na);
+                double* t = J.terms;
+                t[OCTMC_TERM_DATA] = s[0];
+                t[OCTMC_TERM_STR] = s[1];
+                t[OCTMC_TERM_ANG] = s[2];
+                t[OCTMC_TERM_REG] = s[3];
+                t[OCTMC_TERM_MEAN] = m;
+                t[OCTMC_TERM_STR05] = s[5];
+                t[OCTMC_TERM_ANG05] = s[6];
+                t[OCTMC_TERM_ETA] = eta;
+                t[OCTMC_TERM_GP] = s[7];
+                t[OCTMC_TERM_F] = s[0] + J.alpha * s[3] + m;
+            }
+            *J.counter = 0u;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum, dim3(total_blocks), dim3(kRedBlock), 0, s, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s)
+{
+    switch (dt) {
+    case OCTMC_F32:
+        hipLaunchKernelGGL(k_struct<float>, dim3(total_blocks), dim3(256), 0, s, jobs);
+        break;
+    case OCTMC_BF16:
+        hipLaunchKernelGGL(k_struct<bf16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+        break;
+    case OCTMC_F16:
+        hipLaunchKernelGGL(k_struct<f16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_combine, dim3(total_blocks), dim3(kRedBlock), 0, s, jobs);
+    return hipGetLastError();
+}
+
+}  // namespace octmc

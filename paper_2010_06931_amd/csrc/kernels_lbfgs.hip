@@ -1,0 +1,170 @@
+// Vector kernels of the L-BFGS solve (float64 state on the device).
+//
+//   k_multidot  several dot products (and one max |.|) in one pass, block
+//               partials summed by the last block in a fixed order
+//   k_lincomb   out = sum_q c_q v_q (search direction from the compact
+//               representation of the L-BFGS matrix)
+//   k_trial     x_t = x + alpha p, also as float32 for the evaluation
+//   k_accept    s = x_t - x, y = g_t - g, then x = x_t, g = g_t
+#include <hip/hip_runtime.h>
+
+#include "octmc_internal.h"
+
+namespace octmc {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kMaxBlocks = 512;
+
+__global__ __launch_bounds__(kB) void k_multidot(const DotSpec spec, size_t n, double* __restrict__ blk,
+                                                 unsigned* counter, double* __restrict__ out)
+{
+    const int nd = spec.ndots;
+    double acc[kMaxDots];
+#pragma unroll
+    for (int q = 0; q < kMaxDots; ++q) acc[q] = 0.0;
+    double gmax = 0.0;
+    for (size_t t = (size_t)blockIdx.x * kB + threadIdx.x; t < n; t += (size_t)gridDim.x * kB) {
+#pragma unroll
+        for (int q = 0; q < kMaxDots; ++q)
+            if (q < nd) acc[q] += spec.v[spec.a[q]][t] * spec.v[spec.b[q]][t];
+        if (spec.gmax_vec >= 0) gmax = fmax(gmax, fabs(spec.v[spec.gmax_vec][t]));
+    }
+    __shared__ double sh[kB];
+    const int nrow = nd + 1;
+    for (int q = 0; q < nrow; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < kMaxDots; ++r)
+            if (r == q) v = acc[r];
+        if (q == nd) v = gmax;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = kB / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s)
+                sh[threadIdx.x] = (q == nd) ? fmax(sh[threadIdx.x], sh[threadIdx.x + s])
+                                            : sh[threadIdx.x] + sh[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) blk[(size_t)blockIdx.x * (kMaxDots + 1) + q] = sh[0];
+        __syncthreads();
+    }
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // fixed-order final sum: thread q sums column q over the blocks in order
+    for (int q = threadIdx.x; q < nrow; q += kB) {
+        double s = 0.0;
+        for (unsigned b = 0; b < gridDim.x; ++b) {
+            const double v = blk[(size_t)b * (kMaxDots + 1) + q];
+            s = (q == nd) ? fmax(s, v) : s + v;
+        }
+        out[q] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+__global__ void k_lincomb(const CombSpec spec, size_t n, double* __restrict__ out)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < spec.nv; ++q) s += spec.c[q] * spec.v[q][t];
+        out[t] = s;
+    }
+}
+
+__global__ void k_trial(const double* __restrict__ x, const double* __restrict__ p, double alpha, size_t n,
+                        double* __restrict__ xt, float* __restrict__ xt32)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const double v = x[t] + alpha * p[t];
+        xt[t] = v;
+        xt32[t] = (float)v;
+    }
+}
+
+__global__ void k_accept(double* __restrict__ x, double* __restrict__ g, const double* __restrict__ xt,
+                         const double* __restrict__ gt, double* __restrict__ s_out, double* __restrict__ y_out,
+                         size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const double xn = xt[t], gn = gt[t];
+        s_out[t] = xn - x[t];
+        y_out[t] = gn - g[t];
+        x[t] = xn;
+        g[t] = gn;
+    }
+}
+
+__global__ void k_to_f64(const float* __restrict__ in, double* __restrict__ out, size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        out[t] = (double)in[t];
+}
+
+__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        out[t] = (float)in[t];
+}
+
+__global__ void k_fill_u32(unsigned* p, unsigned v, size_t n)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        p[t] = v;
+}
+
+inline int grid_for(size_t n, int cap = 4096)
+{
+    size_t g = (n + 255) / 256;
+    if (g > (size_t)cap) g = cap;
+    return g < 1 ? 1 : (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_multidot(const DotSpec& spec, size_t n, double* blk, unsigned* counter, double* out,
+                           hipStream_t s)
+{
+    if (spec.ndots > kMaxDots) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_multidot, dim3(grid_for(n, kMaxBlocks)), dim3(kB), 0, s, spec, n, blk, counter, out);
+    return hipGetLastError();
+}
+hipError_t launch_lincomb(const CombSpec& spec, size_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n)), dim3(256), 0, s, spec, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_trial(const double* x, const double* p, double alpha, size_t n, double* xt, float* xt32,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_trial, dim3(grid_for(n)), dim3(256), 0, s, x, p, alpha, n, xt, xt32);
+    return hipGetLastError();
+}
+hipError_t launch_accept(double* x, double* g, const double* xt, const double* gt, double* s_out, double* y_out,
+                         size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_accept, dim3(grid_for(n)), dim3(256), 0, s, x, g, xt, gt, s_out, y_out, n);
+    return hipGetLastError();
+}
+hipError_t launch_to_f64(const float* in, double* out, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_f64, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace octmc

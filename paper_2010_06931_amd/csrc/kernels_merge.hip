@@ -1,0 +1,243 @@
+// Output kernels (Sec. 2.1 "merging", Sec. 2.5): sampling density, merge
+// weights and the weighted average of the two resampled scans.
+//
+//   k_density       every output A-scan splats its (clamped) sample position
+//                   bilinearly into a per-scan h x w grid; fixed-point 64-bit
+//                   integer atomics keep the sums independent of order
+//   k_merge_weights density read back at the sample position -> weight
+//                   exp(-kappa max(0, rho - 1)), clipped below tau, normalised;
+//                   the OCTA weights are further multiplied by the resampled
+//                   validity (Eq. 5); where both vanish, OCT keeps the scan with
+//                   the lower density and OCTA is 0
+//   k_merge_volume  resample both scans with their fields (Eq. 2 interpolator,
+//                   value only) and write the weighted sum
+#include <hip/hip_runtime.h>
+
+#include "octmc_internal.h"
+
+namespace octmc {
+namespace {
+
+constexpr double kFix = 4294967296.0;  // 2^32
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ void bilin(float x, float y, int w, int h, int& x0, int& y0, int& x1, int& y1, float& fx,
+                                      float& fy)
+{
+    x = fminf(fmaxf(x, 0.f), (float)(w - 1));
+    y = fminf(fmaxf(y, 0.f), (float)(h - 1));
+    x0 = (int)floorf(x);
+    y0 = (int)floorf(y);
+    x1 = min(x0 + 1, w - 1);
+    y1 = min(y0 + 1, h - 1);
+    fx = x - x0;
+    fy = y - y0;
+}
+
+__global__ void k_density(const float* __restrict__ disp, int w, int h, unsigned long long* __restrict__ grid)
+{
+    const int na = w * h;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < 2 * na; q += gridDim.x * blockDim.x) {
+        const int V = q / na, a = q % na;
+        const int i = a % w, j = a / w;
+        int x0, y0, x1, y1;
+        float fx, fy;
+        bilin(i + disp[(size_t)q * 3], j + disp[(size_t)q * 3 + 1], w, h, x0, y0, x1, y1, fx, fy);
+        unsigned long long* G = grid + (size_t)V * na;
+        atomicAdd(G + (size_t)y0 * w + x0, (unsigned long long)llrint((1.0 - fx) * (1.0 - fy) * kFix));
+        atomicAdd(G + (size_t)y0 * w + x1, (unsigned long long)llrint((double)fx * (1.0 - fy) * kFix));
+        atomicAdd(G + (size_t)y1 * w + x0, (unsigned long long)llrint((1.0 - fx) * (double)fy * kFix));
+        atomicAdd(G + (size_t)y1 * w + x1, (unsigned long long)llrint((double)fx * (double)fy * kFix));
+    }
+}
+
+__device__ __forceinline__ void cr_w(float t, float w[4])
+{
+    const float t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5f * (-t3 + 2.f * t2 - t);
+    w[1] = 0.5f * (3.f * t3 - 5.f * t2 + 2.f);
+    w[2] = 0.5f * (-3.f * t3 + 4.f * t2 + t);
+    w[3] = 0.5f * (t3 - t2);
+}
+
+__device__ __forceinline__ float valid_at(const float* v, int n, int idx, float dv)
+{
+    const float f = floorf(dv);
+    const int nx = idx + (int)f;
+    float w[4];
+    cr_w(dv - f, w);
+    float s = 0.f;
+    for (int a = 0; a < 4; ++a) s = fmaf(w[a], v[clampi(nx - 1 + a, 0, n - 1)], s);
+    return fminf(fmaxf(s, 0.f), 1.f);
+}
+
+__global__ void k_merge_weights(const float* __restrict__ disp, int w, int h,
+                                const unsigned long long* __restrict__ grid, const float* __restrict__ vx,
+                                const float* __restrict__ vy, double kappa, double tau, float4* __restrict__ wts)
+{
+    const int na = w * h;
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < na; a += gridDim.x * blockDim.x) {
+        const int i = a % w, j = a / w;
+        double rho[2];
+        for (int V = 0; V < 2; ++V) {
+            const float* dv = disp + ((size_t)V * na + a) * 3;
+            int x0, y0, x1, y1;
+            float fx, fy;
+            bilin(i + dv[0], j + dv[1], w, h, x0, y0, x1, y1, fx, fy);
+            const unsigned long long* G = grid + (size_t)V * na;
+            rho[V] = ((1.0 - fx) * (1.0 - fy) * (double)G[(size_t)y0 * w + x0] +
+                      (double)fx * (1.0 - fy) * (double)G[(size_t)y0 * w + x1] +
+                      (1.0 - fx) * (double)fy * (double)G[(size_t)y1 * w + x0] +
+                      (double)fx * (double)fy * (double)G[(size_t)y1 * w + x1]) / kFix;
+        }
+        double wx = exp(-kappa * fmax(0.0, rho[0] - 1.0)), wy = exp(-kappa * fmax(0.0, rho[1] - 1.0));
+        if (wx < tau) wx = 0.0;
+        if (wy < tau) wy = 0.0;
+        double ax, ay;
+        if (wx + wy > 0) {
+            ax = wx / (wx + wy);
+            ay = wy / (wx + wy);
+        } else if (rho[0] <= rho[1]) {
+            ax = 1.0;
+            ay = 0.0;
+        } else {
+            ax = 0.0;
+            ay = 1.0;
+        }
+        double ox = 0.0, oy = 0.0;
+        if (vx && vy) {
+            ox = wx * valid_at(vx, h, j, disp[(size_t)a * 3 + 1]);
+            oy = wy * valid_at(vy, w, i, disp[((size_t)na + a) * 3]);
+            const double s = ox + oy;
+            if (s > 0) {
+                ox /= s;
+                oy /= s;
+            }
+        }
+        wts[a] = make_float4((float)ax, (float)ay, (float)ox, (float)oy);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ float ld(const void* p, size_t q);
+template <>
+__device__ __forceinline__ float ld<float>(const void* p, size_t q) { return static_cast<const float*>(p)[q]; }
+struct bf16_t {};
+struct f16_t {};
+template <>
+__device__ __forceinline__ float ld<bf16_t>(const void* p, size_t q)
+{
+    return __builtin_bit_cast(float, (uint32_t) static_cast<const unsigned short*>(p)[q] << 16);
+}
+template <>
+__device__ __forceinline__ float ld<f16_t>(const void* p, size_t q)
+{
+    return (float)__builtin_bit_cast(_Float16, static_cast<const unsigned short*>(p)[q]);
+}
+
+// one wavefront per output A-scan, lanes along depth; which = 0 uses the OCT
+// weights (wts.x, wts.y), which = 1 the OCTA weights (wts.z, wts.w)
+template <typename T>
+__global__ __launch_bounds__(256) void k_merge_volume(const void* __restrict__ sx, const void* __restrict__ sy,
+                                                      const float* __restrict__ disp, const float4* __restrict__ wts,
+                                                      int which, int w, int h, int d, float* __restrict__ out)
+{
+    __shared__ float ring_all[4][2][128];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int na = w * h;
+    const int a = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+    if (a >= na) return;
+    const int i = a % w, j = a / w;
+    const float4 wt = wts[a];
+    const float wgt[2] = {which ? wt.z : wt.x, which ? wt.w : wt.y};
+    const void* vol[2] = {sx, sy};
+    size_t off[2][16];
+    float wl[2][16], wz[2][4];
+    int base[2];
+    for (int V = 0; V < 2; ++V) {
+        const float* dv = disp + ((size_t)V * na + a) * 3;
+        const float fxf = floorf(dv[0]), fyf = floorf(dv[1]), fzf = floorf(dv[2]);
+        const int nx = i + (int)fxf, ny = j + (int)fyf, nz = (int)fzf;
+        float wx[4], wy[4];
+        cr_w(dv[0] - fxf, wx);
+        cr_w(dv[1] - fyf, wy);
+        cr_w(dv[2] - fzf, wz[V]);
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c) {
+                off[V][b * 4 + c] = ((size_t)clampi(ny - 1 + b, 0, h - 1) * w + clampi(nx - 1 + c, 0, w - 1)) * d;
+                wl[V][b * 4 + c] = wx[c] * wy[b];
+            }
+        base[V] = nz - 1;
+    }
+    const int nch = (d + 63) / 64;
+    for (int n = 0; n < nch; ++n) {
+        float res = 0.f;
+        for (int V = 0; V < 2; ++V) {
+            float* ring = ring_all[wv][V];
+            for (int half = 0; half < 2; ++half) {
+                const int m = clampi(base[V] + (n + half) * 64 + lane, 0, d - 1);
+                float c = 0.f;
+                for (int q = 0; q < 16; ++q) c = fmaf(wl[V][q], ld<T>(vol[V], off[V][q] + m), c);
+                ring[half * 64 + lane] = c;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            float iv = 0.f;
+            for (int c = 0; c < 4; ++c) iv = fmaf(wz[V][c], ring[lane + c], iv);
+            res = fmaf(wgt[V], iv, res);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        const int k = n * 64 + lane;
+        if (k < d) out[(size_t)a * d + k] = res;
+    }
+}
+
+inline int grid_for(size_t n, int cap = 65536)
+{
+    size_t g = (n + 255) / 256;
+    if (g > (size_t)cap) g = cap;
+    return g < 1 ? 1 : (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_density(const float* disp, int w, int h, unsigned long long* grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_density, dim3(grid_for((size_t)2 * w * h)), dim3(256), 0, s, disp, w, h, grid);
+    return hipGetLastError();
+}
+hipError_t launch_merge_weights(const float* disp, int w, int h, const unsigned long long* grid, const float* vx,
+                                const float* vy, double kappa, double tau, float4* wts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_merge_weights, dim3(grid_for((size_t)w * h)), dim3(256), 0, s, disp, w, h, grid, vx, vy,
+                       kappa, tau, wts);
+    return hipGetLastError();
+}
+hipError_t launch_merge_volume(const void* vx_, const void* vy_, octmc_dtype dt, const float* disp,
+                               const float4* wts, int which, int w, int h, int d, float* out, hipStream_t s)
+{
+    const int blocks = (w * h + 3) / 4;
+    switch (dt) {
+    case OCTMC_F32:
+        hipLaunchKernelGGL(k_merge_volume<float>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h, d,
+                           out);
+        break;
+    case OCTMC_BF16:
+        hipLaunchKernelGGL(k_merge_volume<bf16_t>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h,
+                           d, out);
+        break;
+    case OCTMC_F16:
+        hipLaunchKernelGGL(k_merge_volume<f16_t>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h,
+                           d, out);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace octmc

@@ -1,0 +1,956 @@
+// Host runtime behind the C ABI (include/octmc.h): contexts, pair ingest and
+// pyramid, the evaluation sequence of the hot path, the L-BFGS level loop and
+// the merge.  All vectors stay in device memory; only float64 scalars cross
+// to the host (objective and directional derivative per line-search trial,
+// one set of dot products per L-BFGS iteration).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "octmc_internal.h"
+
+using namespace octmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? OCTMC_E_OOM : OCTMC_E_DEVICE,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+#define OCTMC_TRY(expr)                                                                            \
+    do {                                                                                           \
+        int r_ = (expr);                                                                           \
+        if (r_ != OCTMC_OK) return r_;                                                             \
+    } while (0)
+
+size_t esize(octmc_dtype dt) { return dt == OCTMC_F32 ? 4 : 2; }
+
+struct DevBuf {
+    std::vector<void*> ptrs;
+    ~DevBuf()
+    {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct octmc_ctx {
+    int device;
+};
+
+namespace octmc {
+
+struct Level {
+    int w = 0, h = 0, d = 0, na = 0;
+    void* sx = nullptr;
+    void* sy = nullptr;
+    float* ax = nullptr;
+    float* ay = nullptr;
+    float* vx = nullptr;
+    float* vy = nullptr;
+    uint32_t vol_bytes = 0;
+};
+
+}  // namespace octmc
+
+struct octmc_pair {
+    octmc_ctx* ctx = nullptr;
+    octmc_params params{};
+    octmc_dtype dtype = OCTMC_F32;
+    int nlev = 0;
+    Level lev[OCTMC_MAX_LEVELS];
+    float* octa[2] = {nullptr, nullptr};  // finest OCTA volumes (float32, invalid B-scans replaced)
+    // evaluation scratch, sized for the finest level
+    float* part = nullptr;      // [na0][8]
+    double* sum_blk = nullptr;  // [256][4]
+    unsigned* counters = nullptr;  // [0] sum, [1] combine, [2] multidot
+    double* sumd = nullptr;     // [3]
+    double* comb_blk = nullptr; // [nblk0][8]
+    double* eta = nullptr;      // [levels]
+    double* terms = nullptr;    // [OCTMC_NTERMS] solver scratch
+    double* dot_blk = nullptr;  // [512][kMaxDots + 1]
+    double* dot_out = nullptr;  // [kMaxDots + 1]
+    std::vector<void*> owned;
+    int busy = 0;
+
+    template <typename T>
+    hipError_t alloc(T** p, size_t bytes)
+    {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+        if (e == hipSuccess) {
+            owned.push_back(q);
+            *p = static_cast<T*>(q);
+        }
+        return e;
+    }
+    ~octmc_pair()
+    {
+        for (void* p : owned) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+constexpr int kSumBlocks = 256;
+
+int nblk_combine(int na) { return (na + kRedBlock - 1) / kRedBlock; }
+
+// ---------------------------------------------------------------------------
+// hot path: one grouped evaluation over up to kMaxJobs pairs at one level
+
+struct EvalArgs {
+    octmc_pair* pair;
+    const float* disp;
+    double* terms;
+    float* grad;
+    const double* p;         // search direction for the directional derivative (or null)
+    double* grad64 = nullptr;  // float64 gradient for the solver (or null)
+};
+
+int eval_group(const EvalArgs* ea, int n, int level, int eta_mode, hipStream_t s, hipEvent_t* ev = nullptr)
+{
+    SumJobs sj{};
+    StructJobs tj{};
+    CombineJobs cj{};
+    sj.n = tj.n = cj.n = n;
+    int sb = 0, tb = 0, cb = 0;
+    octmc_dtype dt = ea[0].pair->dtype;
+    for (int q = 0; q < n; ++q) {
+        octmc_pair* P = ea[q].pair;
+        const Level& L = P->lev[level];
+        const octmc_params& pr = P->params;
+        if (P->dtype != dt) return fail(OCTMC_E_DTYPE, "batched pairs must share the storage type");
+        const int nsum = std::min(kSumBlocks, (2 * L.na + kRedBlock - 1) / kRedBlock);
+        sj.j[q] = SumJob{ea[q].disp, P->sum_blk, P->counters + 0, P->sumd, L.na, sb, nsum};
+        sb += nsum;
+        tj.j[q] = StructJob{L.sx, L.sy, ea[q].disp, P->part, L.w, L.h, L.d, L.na, tb, L.vol_bytes,
+                            (float)pr.eps_huber};
+        tb += ((L.w + 1) / 2) * ((L.h + 1) / 2);  // one 2 x 2 tile of A-scans per block
+        const int nc = nblk_combine(L.na);
+        const int blen = L.w;  // square scans: every B-scan has w A-scans
+        const double f = std::floor(pr.flyback_frac * blen + 0.5);
+        CombineJob c{};
+        c.part = P->part;
+        c.disp = ea[q].disp;
+        c.grad = ea[q].grad;
+        c.grad64 = ea[q].grad64;
+        c.ax = L.ax;
+        c.ay = L.ay;
+        c.vx = L.vx;
+        c.vy = L.vy;
+        c.sumd = P->sumd;
+        c.eta = P->eta + level;
+        c.p = ea[q].p;
+        c.blk = P->comb_blk;
+        c.counter = P->counters + 1;
+        c.terms = ea[q].terms;
+        c.w = L.w;
+        c.h = L.h;
+        c.d = L.d;
+        c.na = L.na;
+        c.blk_begin = cb;
+        c.nblk = nc;
+        c.mode = 1;
+        c.delta0 = pr.delta0;
+        c.eps_h = pr.eps_huber;
+        c.eps_r = pr.eps_reg;
+        c.alpha = pr.alpha;
+        c.gamma = pr.mean_weight;
+        c.wfb = 1.0 / std::sqrt(1.0 + f);
+        cj.j[q] = c;
+        cb += nc;
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_sum(sj, sb, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(launch_struct(tj, (tb + 7) / 8 * 8, dt, s));  // multiple of the 8 XCDs
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    if (eta_mode == 0) {
+        CombineJobs c0 = cj;
+        for (int q = 0; q < n; ++q) {
+            c0.j[q].mode = 0;
+            c0.j[q].grad = nullptr;
+            c0.j[q].grad64 = nullptr;
+            c0.j[q].p = nullptr;
+        }
+        HIP_TRY(launch_combine(c0, cb, s));
+    }
+    HIP_TRY(launch_combine(cj, cb, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return OCTMC_OK;
+}
+
+int check_level(const octmc_pair* P, int level)
+{
+    if (!P) return fail(OCTMC_E_INVALID, "pair is NULL");
+    if (level < 0 || level >= P->nlev) return fail(OCTMC_E_INVALID, "level out of range");
+    return OCTMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// L-BFGS (textbook limited-memory BFGS with a strong Wolfe line search; the
+// search direction is formed from the compact representation of the inverse
+// Hessian approximation, which equals the two-loop recursion in exact
+// arithmetic and needs one pass of dot products per iteration)
+
+struct Solver {
+    size_t n = 0;
+    int m = 5;
+    double *x = nullptr, *g = nullptr, *p = nullptr, *xt = nullptr, *xprev = nullptr;
+    double *sc = nullptr, *yc = nullptr;  // candidate pair
+    double* gt = nullptr;                 // gradient at the trial point
+    double* S[8] = {};
+    double* Y[8] = {};
+    float* xt32 = nullptr;
+};
+
+struct LevelStats {
+    int iters = 0, evals = 0, ls_fail = 0;
+    double f_start = 0, f_end = 0;
+};
+
+// cubic interpolation step of the zoom phase, kept 10 % inside the bracket
+double cubic_min(double a0, double f0, double g0, double a1, double f1, double g1)
+{
+    const double lo = std::min(a0, a1), hi = std::max(a0, a1), span = hi - lo;
+    const double mid = 0.5 * (a0 + a1);
+    const double d1 = g0 + g1 - 3.0 * (f0 - f1) / (a0 - a1);
+    const double disc = d1 * d1 - g0 * g1;
+    if (!(disc >= 0)) return mid;
+    const double d2 = (a1 > a0 ? 1.0 : -1.0) * std::sqrt(disc);
+    const double den = g1 - g0 + 2.0 * d2;
+    if (den == 0) return mid;
+    const double a = a1 - (a1 - a0) * (g1 + d2 - d1) / den;
+    if (!std::isfinite(a) || a < lo + 0.1 * span || a > hi - 0.1 * span) return mid;
+    return a;
+}
+
+struct LevelRun {
+    octmc_pair* P;
+    int level;
+    Solver* sv;
+    hipStream_t s;
+    size_t n;
+    double* h_terms;  // pinned host [OCTMC_NTERMS]
+    double* h_dots;   // pinned host [kMaxDots + 1]
+    int evals = 0;
+
+    // phi(alpha) = F(x + alpha p), dphi = g(x + alpha p) . p
+    int trial(double alpha, double& f, double& dphi)
+    {
+        HIP_TRY(launch_trial(sv->x, sv->p, alpha, n, sv->xt, sv->xt32, s));
+        EvalArgs ea{P, sv->xt32, P->terms, nullptr, sv->p, sv->gt};
+        OCTMC_TRY(eval_group(&ea, 1, level, 1, s));
+        HIP_TRY(hipMemcpyAsync(h_terms, P->terms, sizeof(double) * OCTMC_NTERMS, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        f = h_terms[OCTMC_TERM_F];
+        dphi = h_terms[OCTMC_TERM_GP];
+        ++evals;
+        return OCTMC_OK;
+    }
+
+    // strong Wolfe line search; on success xt / gt hold the accepted point
+    int line_search(double f0, double g0, int max_evals, int start_evals, double c1, double c2, bool& ok,
+                    double& f_out)
+    {
+        ok = false;
+        double a_prev = 0, f_prev = f0, g_prev = g0, a = 1.0;
+        double lo, flo, glo, hi, fhi, ghi;
+        for (int i = 1;; ++i) {
+            if (evals - start_evals >= max_evals) return OCTMC_OK;
+            double fa, ga;
+            OCTMC_TRY(trial(a, fa, ga));
+            if (fa > f0 + c1 * a * g0 || (i > 1 && fa >= f_prev)) {
+                lo = a_prev; flo = f_prev; glo = g_prev;
+                hi = a; fhi = fa; ghi = ga;
+                break;
+            }
+            if (std::fabs(ga) <= -c2 * g0) {
+                ok = true;
+                f_out = fa;
+                return OCTMC_OK;
+            }
+            if (ga >= 0) {
+                lo = a; flo = fa; glo = ga;
+                hi = a_prev; fhi = f_prev; ghi = g_prev;
+                break;
+            }
+            a_prev = a; f_prev = fa; g_prev = ga;
+            a = 2.0 * a;
+        }
+        for (;;) {
+            if (evals - start_evals >= max_evals) return OCTMC_OK;
+            const double aj = cubic_min(lo, flo, glo, hi, fhi, ghi);
+            double fj, gj;
+            OCTMC_TRY(trial(aj, fj, gj));
+            if (fj > f0 + c1 * aj * g0 || fj >= flo) {
+                hi = aj; fhi = fj; ghi = gj;
+            } else {
+                if (std::fabs(gj) <= -c2 * g0) {
+                    ok = true;
+                    f_out = fj;
+                    return OCTMC_OK;
+                }
+                if (gj * (hi - lo) >= 0) {
+                    hi = lo; fhi = flo; ghi = glo;
+                }
+                lo = aj; flo = fj; glo = gj;
+            }
+        }
+    }
+
+    int run(const octmc_params& pr, LevelStats& st)
+    {
+        const int m = sv->m;
+        // initial evaluation: sets eta at the level's initial field (Eq. 10)
+        HIP_TRY(launch_to_f32(sv->x, sv->xt32, n, s));
+        {
+            EvalArgs ea{P, sv->xt32, P->terms, nullptr, nullptr, sv->g};
+            OCTMC_TRY(eval_group(&ea, 1, level, 0, s));
+        }
+        HIP_TRY(hipMemcpyAsync(h_terms, P->terms, sizeof(double) * OCTMC_NTERMS, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        evals = 1;
+        double f = h_terms[OCTMC_TERM_F];
+        st.f_start = f;
+        // history in chronological order (slot indices) and its dot products
+        std::deque<int> order;
+        double SY[8][8] = {}, YY[8][8] = {};  // SY[k][l] = s_k . y_l, YY[k][l] = y_k . y_l (slots)
+        bool cand = false;
+        int it = 0;
+        while (it < pr.iters_per_level) {
+            // one pass of dot products
+            DotSpec ds{};
+            int nv = 0;
+            const int vg = nv++;
+            ds.v[vg] = sv->g;
+            int vs = -1, vy = -1;
+            if (cand) {
+                vs = nv++;
+                ds.v[vs] = sv->sc;
+                vy = nv++;
+                ds.v[vy] = sv->yc;
+            }
+            int vS[8], vY[8];
+            for (size_t k = 0; k < order.size(); ++k) {
+                vS[k] = nv++;
+                ds.v[vS[k]] = sv->S[order[k]];
+                vY[k] = nv++;
+                ds.v[vY[k]] = sv->Y[order[k]];
+            }
+            int nd = 0;
+            auto dot = [&](int a, int b) {
+                ds.a[nd] = (unsigned char)a;
+                ds.b[nd] = (unsigned char)b;
+                return nd++;
+            };
+            const int i_gg = dot(vg, vg);
+            int i_sg[8], i_yg[8], i_syc[8], i_ycy[8];
+            for (size_t k = 0; k < order.size(); ++k) {
+                i_sg[k] = dot(vS[k], vg);
+                i_yg[k] = dot(vY[k], vg);
+                if (cand) {
+                    i_syc[k] = dot(vS[k], vy);
+                    i_ycy[k] = dot(vy, vY[k]);
+                }
+            }
+            int i_csg = -1, i_cyg = -1, i_csy = -1, i_cyy = -1;
+            if (cand) {
+                i_csg = dot(vs, vg);
+                i_cyg = dot(vy, vg);
+                i_csy = dot(vs, vy);
+                i_cyy = dot(vy, vy);
+            }
+            ds.ndots = nd;
+            ds.gmax_vec = vg;
+            HIP_TRY(launch_multidot(ds, n, P->dot_blk, P->counters + 2, P->dot_out, s));
+            HIP_TRY(hipMemcpyAsync(h_dots, P->dot_out, sizeof(double) * (kMaxDots + 1), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            const double gg = h_dots[i_gg], gmax = h_dots[nd];
+            // the new pair enters the memory only if it passes the curvature test
+            std::vector<double> a_s(order.size()), b_y(order.size());
+            for (size_t k = 0; k < order.size(); ++k) {
+                a_s[k] = h_dots[i_sg[k]];
+                b_y[k] = h_dots[i_yg[k]];
+            }
+            if (cand) {
+                const double sy = h_dots[i_csy], yy = h_dots[i_cyy];
+                if (sy > 1e-12 * yy && yy > 0) {
+                    int slot;
+                    if ((int)order.size() == m) {
+                        slot = order.front();
+                        order.pop_front();
+                        a_s.erase(a_s.begin());
+                        b_y.erase(b_y.begin());
+                        // keep the dots of the remaining pairs with the candidate
+                        for (size_t k = 0; k + 1 <= order.size(); ++k) {
+                            i_syc[k] = i_syc[k + 1];
+                            i_ycy[k] = i_ycy[k + 1];
+                        }
+                    } else {
+                        std::vector<bool> used(m, false);
+                        for (int q : order) used[q] = true;
+                        slot = 0;
+                        while (used[slot]) ++slot;
+                    }
+                    std::swap(sv->S[slot], sv->sc);
+                    std::swap(sv->Y[slot], sv->yc);
+                    for (size_t k = 0; k < order.size(); ++k) {
+                        SY[order[k]][slot] = h_dots[i_syc[k]];
+                        YY[order[k]][slot] = YY[slot][order[k]] = h_dots[i_ycy[k]];
+                    }
+                    SY[slot][slot] = sy;
+                    YY[slot][slot] = yy;
+                    order.push_back(slot);
+                    a_s.push_back(h_dots[i_csg]);
+                    b_y.push_back(h_dots[i_cyg]);
+                }
+                cand = false;
+            }
+            if (gmax <= 1e-10 * std::max(1.0, std::fabs(f))) break;
+            double gp;
+            const int c = (int)order.size();
+            auto steepest = [&]() -> int {
+                CombSpec cs{};
+                cs.nv = 1;
+                cs.v[0] = sv->g;
+                cs.c[0] = -1.0 / gmax;
+                HIP_TRY(launch_lincomb(cs, n, sv->p, s));
+                gp = -gg / gmax;
+                return OCTMC_OK;
+            };
+            if (c == 0) {
+                OCTMC_TRY(steepest());
+            } else {
+                // H g = gamma g + S u + gamma Y v with v = -R^-1 a and
+                // u = R^-T ((D + gamma Y'Y) R^-1 a - gamma b), R = upper(S'Y)
+                const int nw = order.back();
+                const double gamma = SY[nw][nw] / YY[nw][nw];
+                std::vector<double> R(c * c, 0.0), t1(c), rhs(c), u(c);
+                for (int k = 0; k < c; ++k)
+                    for (int l = k; l < c; ++l) R[k * c + l] = SY[order[k]][order[l]];
+                for (int k = c - 1; k >= 0; --k) {  // R t1 = a
+                    double v = a_s[k];
+                    for (int l = k + 1; l < c; ++l) v -= R[k * c + l] * t1[l];
+                    t1[k] = v / R[k * c + k];
+                }
+                for (int k = 0; k < c; ++k) {
+                    double v = SY[order[k]][order[k]] * t1[k];
+                    for (int l = 0; l < c; ++l) v += gamma * YY[order[k]][order[l]] * t1[l];
+                    rhs[k] = v - gamma * b_y[k];
+                }
+                for (int k = 0; k < c; ++k) {  // R' u = rhs
+                    double v = rhs[k];
+                    for (int l = 0; l < k; ++l) v -= R[l * c + k] * u[l];
+                    u[k] = v / R[k * c + k];
+                }
+                CombSpec cs{};
+                cs.nv = 1 + 2 * c;
+                cs.v[0] = sv->g;
+                cs.c[0] = -gamma;
+                double hg = gamma * gg;
+                for (int k = 0; k < c; ++k) {
+                    cs.v[1 + 2 * k] = sv->S[order[k]];
+                    cs.c[1 + 2 * k] = -u[k];
+                    cs.v[2 + 2 * k] = sv->Y[order[k]];
+                    cs.c[2 + 2 * k] = gamma * t1[k];
+                    hg += u[k] * a_s[k] - gamma * t1[k] * b_y[k];
+                }
+                HIP_TRY(launch_lincomb(cs, n, sv->p, s));
+                gp = -hg;
+            }
+            if (!(gp < 0)) {  // not a descent direction: drop the memory
+                order.clear();
+                OCTMC_TRY(steepest());
+            }
+            bool ok;
+            double fn;
+            const int start = evals;
+            OCTMC_TRY(line_search(f, gp, pr.ls_max_evals, start, pr.c1, pr.c2, ok, fn));
+            if (!ok) {
+                st.ls_fail = 1;
+                break;
+            }
+            HIP_TRY(launch_accept(sv->x, sv->g, sv->xt, sv->gt, sv->sc, sv->yc, n, s));
+            cand = true;
+            f = fn;
+            ++it;
+        }
+        st.iters = it;
+        st.evals = evals;
+        st.f_end = f;
+        return OCTMC_OK;
+    }
+};
+
+bool finite_param(double v) { return std::isfinite(v); }
+
+int validate_params(const octmc_params* p)
+{
+    if (!p) return fail(OCTMC_E_INVALID, "params is NULL");
+    const double vals[] = {p->alpha, p->delta0, p->eps_huber, p->eps_reg, p->flyback_frac, p->mean_weight,
+                           p->c1, p->c2, p->merge_kappa, p->merge_tau};
+    for (double v : vals)
+        if (!finite_param(v)) return fail(OCTMC_E_INVALID, "parameters must be finite");
+    if (p->alpha < 0) return fail(OCTMC_E_INVALID, "alpha must be >= 0");
+    if (p->delta0 < 0 || p->delta0 > 1) return fail(OCTMC_E_INVALID, "delta0 must lie in [0, 1]");
+    if (!(p->eps_huber > 0) || !(p->eps_reg > 0)) return fail(OCTMC_E_INVALID, "eps_huber and eps_reg must be > 0");
+    if (p->flyback_frac < 0 || p->mean_weight < 0) return fail(OCTMC_E_INVALID, "negative flyback or mean weight");
+    if (p->levels < 1 || p->levels > OCTMC_MAX_LEVELS) return fail(OCTMC_E_INVALID, "levels must lie in [1, 8]");
+    if (p->iters_per_level < 0) return fail(OCTMC_E_INVALID, "iters_per_level must be >= 0");
+    if (p->lbfgs_m < 1 || p->lbfgs_m > 8) return fail(OCTMC_E_INVALID, "lbfgs_m must lie in [1, 8]");
+    if (p->ls_max_evals < 1) return fail(OCTMC_E_INVALID, "ls_max_evals must be >= 1");
+    if (!(p->c1 > 0 && p->c1 < p->c2 && p->c2 < 1)) return fail(OCTMC_E_INVALID, "need 0 < c1 < c2 < 1");
+    return OCTMC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+const char* octmc_version(void) { return "octmc 0.1 (gfx950)"; }
+
+const char* octmc_last_error(void) { return g_err.c_str(); }
+
+int octmc_params_default(octmc_params* out)
+{
+    if (!out) return fail(OCTMC_E_INVALID, "out is NULL");
+    octmc_params p{};
+    p.alpha = 1.0;
+    p.delta0 = 0.5;
+    p.eps_huber = 1e-3;
+    p.eps_reg = 0.1;
+    p.flyback_frac = 0.25;
+    p.mean_weight = 1.0;
+    p.levels = 3;
+    p.iters_per_level = 100;
+    p.lbfgs_m = 5;
+    p.ls_max_evals = 20;
+    p.c1 = 1e-4;
+    p.c2 = 0.9;
+    p.merge_kappa = 1.0;
+    p.merge_tau = 0.05;
+    p.flags = 0;
+    *out = p;
+    return OCTMC_OK;
+}
+
+int octmc_create(int device_ordinal, octmc_ctx** out)
+{
+    if (!out) return fail(OCTMC_E_INVALID, "out is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device_ordinal < 0 || device_ordinal >= n) return fail(OCTMC_E_INVALID, "no such device");
+    HIP_TRY(hipSetDevice(device_ordinal));
+    *out = new octmc_ctx{device_ordinal};
+    return OCTMC_OK;
+}
+
+int octmc_destroy(octmc_ctx* ctx)
+{
+    delete ctx;
+    return OCTMC_OK;
+}
+
+int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, const float* oct_x,
+                      const float* oct_y, const float* octa_x, const float* octa_y, const float* enface_x,
+                      const float* enface_y, const float* valid_x, const float* valid_y, void* stream,
+                      octmc_pair** out)
+{
+    if (!ctx || !shape || !out || !oct_x || !oct_y) return fail(OCTMC_E_INVALID, "NULL argument");
+    OCTMC_TRY(validate_params(params));
+    const int w = shape->w, h = shape->h, d = shape->d;
+    if (shape->dtype != OCTMC_F32 && shape->dtype != OCTMC_BF16 && shape->dtype != OCTMC_F16)
+        return fail(OCTMC_E_DTYPE, "unknown storage type");
+    if (shape->mem != OCTMC_MEM_HOST && shape->mem != OCTMC_MEM_DEVICE)
+        return fail(OCTMC_E_INVALID, "unknown memory kind");
+    if (w != h) return fail(OCTMC_E_SHAPE, "only square scans (w == h) are supported");
+    if (w < 4 || d < 4) return fail(OCTMC_E_SHAPE, "scans must be at least 4 x 4 x 4");
+    if ((size_t)w * h * d * 4 >= (1ull << 31)) return fail(OCTMC_E_SHAPE, "volume larger than 2^31 bytes");
+    int wl = w, dl = d;
+    for (int l = 1; l < params->levels; ++l) {
+        wl = (wl + 1) / 2;
+        dl = (dl + 1) / 2;
+    }
+    if (wl < 4 || dl < 4) return fail(OCTMC_E_SHAPE, "too many pyramid levels for this size");
+    const bool have_octa = octa_x && octa_y;
+    const bool have_enface = enface_x && enface_y;
+    if (!have_octa && !have_enface) return fail(OCTMC_E_INVALID, "need both OCTA volumes or both en face images");
+    if ((octa_x != nullptr) != (octa_y != nullptr) || (enface_x != nullptr) != (enface_y != nullptr))
+        return fail(OCTMC_E_INVALID, "OCTA inputs must be given for both scans");
+    if ((valid_x != nullptr) != (valid_y != nullptr)) return fail(OCTMC_E_INVALID, "give both validity vectors or none");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto* P = new octmc_pair();
+    std::unique_ptr<octmc_pair> guard(P);
+    P->ctx = ctx;
+    P->params = *params;
+    P->dtype = shape->dtype;
+    P->nlev = params->levels;
+    const size_t na = (size_t)w * h, nv = na * d;
+    const bool host = shape->mem == OCTMC_MEM_HOST;
+    const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    DevBuf tmp;
+    auto talloc = [&](size_t bytes) -> void* {
+        void* q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+        tmp.ptrs.push_back(q);
+        return q;
+    };
+    // float32 copies of the inputs
+    float* f32[2] = {(float*)talloc(nv * 4), (float*)talloc(nv * 4)};
+    if (!f32[0] || !f32[1]) return fail(OCTMC_E_OOM, "out of device memory (input staging)");
+    HIP_TRY(hipMemcpyAsync(f32[0], oct_x, nv * 4, kind, s));
+    HIP_TRY(hipMemcpyAsync(f32[1], oct_y, nv * 4, kind, s));
+    std::vector<float> hvx(h, 1.0f), hvy(w, 1.0f);
+    if (valid_x) {
+        HIP_TRY(hipMemcpyAsync(hvx.data(), valid_x, h * 4, host ? hipMemcpyHostToHost : hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hvy.data(), valid_y, w * 4, host ? hipMemcpyHostToHost : hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    unsigned* ctr = nullptr;
+    HIP_TRY(P->alloc(&ctr, 64));
+    HIP_TRY(launch_fill_u32(ctr, 0u, 16, s));
+    P->counters = ctr;
+    if (params->flags & OCTMC_CHECK_NAN) {
+        HIP_TRY(launch_count_nonfinite(f32[0], nv, ctr + 8, s));
+        HIP_TRY(launch_count_nonfinite(f32[1], nv, ctr + 8, s));
+        unsigned bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, ctr + 8, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return fail(OCTMC_E_NAN, "non-finite values in the structural volumes");
+    }
+    // OCTA volumes: keep for the merge, replace invalid B-scans by their
+    // nearest valid neighbour (Sec. 2.3, 2.5), then project
+    float* enf[2] = {nullptr, nullptr};
+    HIP_TRY(P->alloc(&enf[0], na * 4));
+    HIP_TRY(P->alloc(&enf[1], na * 4));
+    if (have_octa) {
+        const float* src[2] = {octa_x, octa_y};
+        for (int V = 0; V < 2; ++V) {
+            HIP_TRY(P->alloc(&P->octa[V], nv * 4));
+            HIP_TRY(hipMemcpyAsync(P->octa[V], src[V], nv * 4, kind, s));
+            const std::vector<float>& val = V == 0 ? hvx : hvy;
+            const int nb = V == 0 ? h : w;
+            std::vector<int> from(nb);
+            bool any_valid = false, any_invalid = false;
+            for (int b = 0; b < nb; ++b) {
+                any_valid |= val[b] > 0.5f;
+                any_invalid |= !(val[b] > 0.5f);
+            }
+            if (any_valid && any_invalid) {
+                for (int b = 0; b < nb; ++b) {
+                    if (val[b] > 0.5f) {
+                        from[b] = b;
+                        continue;
+                    }
+                    int best = -1;
+                    for (int dist = 1; dist < nb && best < 0; ++dist) {
+                        if (b - dist >= 0 && val[b - dist] > 0.5f) best = b - dist;
+                        else if (b + dist < nb && val[b + dist] > 0.5f) best = b + dist;
+                    }
+                    from[b] = best;
+                }
+                int* dfrom = (int*)talloc(nb * 4);
+                if (!dfrom) return fail(OCTMC_E_OOM, "out of device memory");
+                HIP_TRY(hipMemcpyAsync(dfrom, from.data(), nb * 4, hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_copy_bscans(P->octa[V], w, h, d, dfrom, V, s));
+                HIP_TRY(hipStreamSynchronize(s));  // `from` is host memory
+            }
+            if (!have_enface) HIP_TRY(launch_enface_mean(P->octa[V], (int)na, d, enf[V], s));
+        }
+    }
+    if (have_enface) {
+        HIP_TRY(hipMemcpyAsync(enf[0], enface_x, na * 4, kind, s));
+        HIP_TRY(hipMemcpyAsync(enf[1], enface_y, na * 4, kind, s));
+    }
+    // pyramid: float32 at every level, stored in the storage type
+    float* cur[2] = {f32[0], f32[1]};
+    float* cen[2] = {enf[0], enf[1]};
+    float *cvx = nullptr, *cvy = nullptr;
+    HIP_TRY(P->alloc(&cvx, h * 4));
+    HIP_TRY(P->alloc(&cvy, w * 4));
+    HIP_TRY(hipMemcpyAsync(cvx, hvx.data(), h * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(cvy, hvy.data(), w * 4, hipMemcpyHostToDevice, s));
+    int lw = w, lh = h, ld = d;
+    for (int l = 0; l < P->nlev; ++l) {
+        Level& L = P->lev[l];
+        L.w = lw;
+        L.h = lh;
+        L.d = ld;
+        L.na = lw * lh;
+        const size_t lnv = (size_t)L.na * ld;
+        L.vol_bytes = (uint32_t)(lnv * esize(P->dtype));
+        void* st[2];
+        for (int V = 0; V < 2; ++V) {
+            HIP_TRY(P->alloc(&st[V], lnv * esize(P->dtype)));
+            HIP_TRY(launch_to_storage(cur[V], st[V], lnv, P->dtype, s));
+        }
+        L.sx = st[0];
+        L.sy = st[1];
+        L.ax = cen[0];
+        L.ay = cen[1];
+        L.vx = cvx;
+        L.vy = cvy;
+        if (l + 1 < P->nlev) {
+            const int w2 = (lw + 1) / 2, h2 = (lh + 1) / 2, d2 = (ld + 1) / 2;
+            float* nxt[2];
+            for (int V = 0; V < 2; ++V) {
+                nxt[V] = (float*)talloc((size_t)w2 * h2 * d2 * 4);
+                if (!nxt[V]) return fail(OCTMC_E_OOM, "out of device memory (pyramid)");
+                HIP_TRY(launch_pyr3(cur[V], lw, lh, ld, nxt[V], s));
+            }
+            float* ne[2];
+            for (int V = 0; V < 2; ++V) {
+                HIP_TRY(P->alloc(&ne[V], (size_t)w2 * h2 * 4));
+                HIP_TRY(launch_pyr2(cen[V], lw, lh, ne[V], s));
+            }
+            float *nvx, *nvy;
+            HIP_TRY(P->alloc(&nvx, h2 * 4));
+            HIP_TRY(P->alloc(&nvy, w2 * 4));
+            HIP_TRY(launch_pyr1(cvx, lh, nvx, s));
+            HIP_TRY(launch_pyr1(cvy, lw, nvy, s));
+            cur[0] = nxt[0];
+            cur[1] = nxt[1];
+            cen[0] = ne[0];
+            cen[1] = ne[1];
+            cvx = nvx;
+            cvy = nvy;
+            lw = w2;
+            lh = h2;
+            ld = d2;
+        }
+    }
+    // evaluation scratch
+    HIP_TRY(P->alloc(&P->part, na * 8 * 4));
+    HIP_TRY(P->alloc(&P->sum_blk, kSumBlocks * 4 * 8));
+    HIP_TRY(P->alloc(&P->sumd, 4 * 8));
+    HIP_TRY(P->alloc(&P->comb_blk, (size_t)nblk_combine((int)na) * 8 * 8));
+    HIP_TRY(P->alloc(&P->eta, OCTMC_MAX_LEVELS * 8));
+    HIP_TRY(P->alloc(&P->terms, OCTMC_NTERMS * 8));
+    HIP_TRY(P->alloc(&P->dot_blk, (size_t)512 * (kMaxDots + 1) * 8));
+    HIP_TRY(P->alloc(&P->dot_out, (kMaxDots + 1) * 8));
+    std::vector<double> ones(OCTMC_MAX_LEVELS, 1.0);
+    HIP_TRY(hipMemcpyAsync(P->eta, ones.data(), OCTMC_MAX_LEVELS * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // temporaries are freed on return
+    *out = guard.release();
+    return OCTMC_OK;
+}
+
+int octmc_pair_destroy(octmc_pair* pair)
+{
+    if (pair) {
+        (void)hipSetDevice(pair->ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    delete pair;
+    return OCTMC_OK;
+}
+
+int octmc_pair_level_shape(const octmc_pair* pair, int32_t level, int32_t* w, int32_t* h, int32_t* d)
+{
+    OCTMC_TRY(check_level(pair, level));
+    if (w) *w = pair->lev[level].w;
+    if (h) *h = pair->lev[level].h;
+    if (d) *d = pair->lev[level].d;
+    return OCTMC_OK;
+}
+
+int octmc_eval(octmc_pair* pair, int32_t level, const float* disp, double* terms, float* grad, int32_t eta_mode,
+               void* stream)
+{
+    OCTMC_TRY(check_level(pair, level));
+    if (!disp || !terms) return fail(OCTMC_E_INVALID, "disp and terms are required");
+    if (eta_mode != 0 && eta_mode != 1) return fail(OCTMC_E_INVALID, "eta_mode must be 0 or 1");
+    HIP_TRY(hipSetDevice(pair->ctx->device));
+    EvalArgs ea{pair, disp, terms, grad, nullptr};
+    return eval_group(&ea, 1, level, eta_mode, static_cast<hipStream_t>(stream));
+}
+
+int octmc_eval_profile(octmc_pair* pair, int32_t level, const float* disp, double* terms, float* grad,
+                       int32_t eta_mode, float* stage_ms, void* stream)
+{
+    OCTMC_TRY(check_level(pair, level));
+    if (!disp || !terms || !stage_ms) return fail(OCTMC_E_INVALID, "disp, terms and stage_ms are required");
+    if (eta_mode != 0 && eta_mode != 1) return fail(OCTMC_E_INVALID, "eta_mode must be 0 or 1");
+    HIP_TRY(hipSetDevice(pair->ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[4] = {};
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    struct Ev {
+        hipEvent_t* e;
+        ~Ev()
+        {
+            for (int k = 0; k < 4; ++k) (void)hipEventDestroy(e[k]);
+        }
+    } guard{ev};
+    EvalArgs ea{pair, disp, terms, grad, nullptr};
+    OCTMC_TRY(eval_group(&ea, 1, level, eta_mode, s, ev));
+    HIP_TRY(hipEventSynchronize(ev[3]));
+    for (int k = 0; k < 3; ++k) HIP_TRY(hipEventElapsedTime(stage_ms + k, ev[k], ev[k + 1]));
+    return OCTMC_OK;
+}
+
+int octmc_eval_batched(octmc_pair* const* pairs, int32_t npairs, int32_t level, const float* disp, double* terms,
+                       float* grad, int32_t eta_mode, void* stream)
+{
+    if (!pairs || npairs < 1 || !disp || !terms) return fail(OCTMC_E_INVALID, "bad batched arguments");
+    if (eta_mode != 0 && eta_mode != 1) return fail(OCTMC_E_INVALID, "eta_mode must be 0 or 1");
+    for (int q = 0; q < npairs; ++q) {
+        OCTMC_TRY(check_level(pairs[q], level));
+        for (int r = 0; r < q; ++r)
+            if (pairs[r] == pairs[q]) return fail(OCTMC_E_INVALID, "a pair appears twice in the batch");
+    }
+    const Level& L0 = pairs[0]->lev[level];
+    for (int q = 1; q < npairs; ++q) {
+        const Level& L = pairs[q]->lev[level];
+        if (L.w != L0.w || L.h != L0.h || L.d != L0.d) return fail(OCTMC_E_SHAPE, "batched pairs differ in shape");
+    }
+    HIP_TRY(hipSetDevice(pairs[0]->ctx->device));
+    const size_t nd = (size_t)2 * L0.na * 3;
+    for (int q0 = 0; q0 < npairs; q0 += kMaxJobs) {
+        const int cnt = std::min(kMaxJobs, npairs - q0);
+        EvalArgs ea[kMaxJobs];
+        for (int q = 0; q < cnt; ++q)
+            ea[q] = EvalArgs{pairs[q0 + q], disp + (q0 + q) * nd, terms + (size_t)(q0 + q) * OCTMC_NTERMS,
+                             grad ? grad + (q0 + q) * nd : nullptr, nullptr};
+        OCTMC_TRY(eval_group(ea, cnt, level, eta_mode, static_cast<hipStream_t>(stream)));
+    }
+    return OCTMC_OK;
+}
+
+int octmc_merge(octmc_pair* pair, const float* disp, float* merged_oct, float* merged_octa, void* stream)
+{
+    if (!pair || !disp || !merged_oct) return fail(OCTMC_E_INVALID, "NULL argument");
+    if (merged_octa && !pair->octa[0]) return fail(OCTMC_E_INVALID, "no OCTA volumes were given at creation");
+    HIP_TRY(hipSetDevice(pair->ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Level& L = pair->lev[0];
+    DevBuf tmp;
+    unsigned long long* grid = nullptr;
+    float4* wts = nullptr;
+    HIP_TRY(hipMalloc(&grid, (size_t)2 * L.na * 8));
+    tmp.ptrs.push_back(grid);
+    HIP_TRY(hipMalloc(&wts, (size_t)L.na * 16));
+    tmp.ptrs.push_back(wts);
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(grid), 0u, (size_t)4 * L.na, s));
+    HIP_TRY(launch_density(disp, L.w, L.h, grid, s));
+    HIP_TRY(launch_merge_weights(disp, L.w, L.h, grid, merged_octa ? L.vx : nullptr, merged_octa ? L.vy : nullptr,
+                                 pair->params.merge_kappa, pair->params.merge_tau, wts, s));
+    HIP_TRY(launch_merge_volume(L.sx, L.sy, pair->dtype, disp, wts, 0, L.w, L.h, L.d, merged_oct, s));
+    if (merged_octa)
+        HIP_TRY(launch_merge_volume(pair->octa[0], pair->octa[1], OCTMC_F32, disp, wts, 1, L.w, L.h, L.d, merged_octa,
+                                    s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return OCTMC_OK;
+}
+
+int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oct, float* merged_octa, octmc_report* rep,
+                   void* stream)
+{
+    if (!pair || !disp_out) return fail(OCTMC_E_INVALID, "NULL argument");
+    if (merged_octa && !pair->octa[0]) return fail(OCTMC_E_INVALID, "no OCTA volumes were given at creation");
+    if (pair->busy) return fail(OCTMC_E_BUSY, "pair is in use");
+    HIP_TRY(hipSetDevice(pair->ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const octmc_params& pr = pair->params;
+    const size_t n0 = (size_t)6 * pair->lev[0].na;
+    Solver sv;
+    sv.m = pr.lbfgs_m;
+    DevBuf mem;
+    auto dalloc = [&](double** p) -> int {
+        HIP_TRY(hipMalloc(p, n0 * 8));
+        mem.ptrs.push_back(*p);
+        return OCTMC_OK;
+    };
+    OCTMC_TRY(dalloc(&sv.x));
+    OCTMC_TRY(dalloc(&sv.g));
+    OCTMC_TRY(dalloc(&sv.p));
+    OCTMC_TRY(dalloc(&sv.xt));
+    OCTMC_TRY(dalloc(&sv.xprev));
+    OCTMC_TRY(dalloc(&sv.sc));
+    OCTMC_TRY(dalloc(&sv.gt));
+    OCTMC_TRY(dalloc(&sv.yc));
+    for (int k = 0; k < sv.m; ++k) {
+        OCTMC_TRY(dalloc(&sv.S[k]));
+        OCTMC_TRY(dalloc(&sv.Y[k]));
+    }
+    HIP_TRY(hipMalloc(&sv.xt32, n0 * 4));
+    mem.ptrs.push_back(sv.xt32);
+    double *h_terms = nullptr, *h_dots = nullptr;
+    HIP_TRY(hipHostMalloc(&h_terms, OCTMC_NTERMS * 8, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&h_dots, (kMaxDots + 1) * 8, hipHostMallocDefault));
+    struct HostFree {
+        double *a, *b;
+        ~HostFree()
+        {
+            (void)hipHostFree(a);
+            (void)hipHostFree(b);
+        }
+    } hf{h_terms, h_dots};
+    pair->busy = 1;
+    struct Unbusy {
+        octmc_pair* p;
+        ~Unbusy() { p->busy = 0; }
+    } ub{pair};
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->nlevels = pair->nlev;
+    }
+    for (int l = pair->nlev - 1; l >= 0; --l) {
+        const Level& L = pair->lev[l];
+        const size_t n = (size_t)6 * L.na;
+        if (l == pair->nlev - 1) {
+            HIP_TRY(hipMemsetAsync(sv.x, 0, n * 8, s));
+        } else {
+            const Level& C = pair->lev[l + 1];
+            HIP_TRY(hipMemcpyAsync(sv.xprev, sv.x, (size_t)6 * C.na * 8, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(launch_upsample(sv.xprev, C.w, C.h, sv.x, L.w, L.h, s));
+        }
+        sv.n = n;
+        LevelRun run{pair, l, &sv, s, n, h_terms, h_dots};
+        LevelStats st;
+        OCTMC_TRY(run.run(pr, st));
+        if (rep) {
+            const int r = pair->nlev - 1 - l;
+            rep->iters[r] = st.iters;
+            rep->evals[r] = st.evals;
+            rep->ls_fail[r] = st.ls_fail;
+            rep->f_start[r] = st.f_start;
+            rep->f_end[r] = st.f_end;
+            double eta = 1.0;
+            HIP_TRY(hipMemcpy(&eta, pair->eta + l, 8, hipMemcpyDeviceToHost));
+            rep->eta[r] = eta;
+        }
+    }
+    HIP_TRY(launch_to_f32(sv.x, disp_out, n0, s));
+    if (merged_oct) OCTMC_TRY(octmc_merge(pair, disp_out, merged_oct, merged_octa, stream));
+    HIP_TRY(hipStreamSynchronize(s));
+    return OCTMC_OK;
+}
+
+}  // extern "C"

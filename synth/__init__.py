@@ -200,15 +200,22 @@ def _inverse_field(pos, iters: int = 30):
 
 
 def _gauss_smooth3(x: torch.Tensor, sigma: float):
+    """Separable Gaussian smoothing with edge replication, as sums of shifted
+    slices (no convolution library; works for any tensor size)."""
     r = int(math.ceil(3 * sigma))
-    t = torch.arange(-r, r + 1, dtype=torch.float32, device=x.device)
+    t = torch.arange(-r, r + 1, dtype=torch.float64)
     k = torch.exp(-0.5 * (t / sigma) ** 2)
-    k = k / k.sum()
-    y = x[None, None]
-    y = F.conv3d(F.pad(y, (r, r, 0, 0, 0, 0), mode="replicate"), k.view(1, 1, 1, 1, -1))
-    y = F.conv3d(F.pad(y, (0, 0, r, r, 0, 0), mode="replicate"), k.view(1, 1, 1, -1, 1))
-    y = F.conv3d(F.pad(y, (0, 0, 0, 0, r, r), mode="replicate"), k.view(1, 1, -1, 1, 1))
-    return y[0, 0]
+    k = (k / k.sum()).tolist()
+    for dim in range(3):
+        n = x.shape[dim]
+        idx = torch.clamp(torch.arange(-r, n + r, device=x.device), 0, n - 1)
+        xp = torch.index_select(x, dim, idx)
+        y = torch.zeros_like(x)
+        for q, kq in enumerate(k):
+            y.add_(xp.narrow(dim, q, n), alpha=kq)
+        del xp
+        x = y
+    return x
 
 
 def _quantile(x: torch.Tensor, q: float) -> float:
@@ -310,21 +317,26 @@ def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = N
 
     def sample(vol, pos):
         """Trilinear sample of the fine truth volume at output voxels
-        (i + m_x, j + m_y, k + m_z), processed in row slabs."""
+        (i + m_x, j + m_y, k + m_z), in row slabs; each slab reads only the
+        truth rows it can reach."""
         out = torch.empty((n, n, d), dtype=torch.float32, device=device)
-        inp = vol[None, None]  # (N, C, D=rows y, H=cols x, W=depth z)
         post = torch.as_tensor(pos, dtype=torch.float32, device=device)
         kk = torch.arange(d, dtype=torch.float32, device=device)
+        ii = torch.arange(n, dtype=torch.float32, device=device)
         rs = max(1, int(2**23 // (n * d)))
         for j0 in range(0, n, rs):
             j1 = min(n, j0 + rs)
             jj = torch.arange(j0, j1, dtype=torch.float32, device=device)
-            ii = torch.arange(n, dtype=torch.float32, device=device)
             P = post[j0:j1]
-            yy = (2 * (jj[:, None] + P[..., 1] + margin))[..., None].expand(-1, -1, d)
+            yf = 2 * (jj[:, None] + P[..., 1] + margin)          # fine row coordinate
+            r0 = max(0, int(math.floor(float(yf.min()))) - 1)
+            r1 = min(G - 1, int(math.ceil(float(yf.max()))) + 1)
+            inp = vol[r0:r1 + 1][None, None]  # (N, C, D=rows y, H=cols x, W=depth z)
+            yy = (yf - r0)[..., None].expand(-1, -1, d)
             xx = (2 * (ii[None, :] + P[..., 0] + margin))[..., None].expand(-1, -1, d)
             zq = 2 * (kk[None, None, :] + P[..., 2:3] + mz)
-            grid = torch.stack([2 * zq / (Dz - 1) - 1, 2 * xx / (G - 1) - 1, 2 * yy / (G - 1) - 1], dim=-1)
+            ny = max(r1 - r0, 1)
+            grid = torch.stack([2 * zq / (Dz - 1) - 1, 2 * xx / (G - 1) - 1, 2 * yy / ny - 1], dim=-1)
             out[j0:j1] = F.grid_sample(inp, grid[None], mode="bilinear", padding_mode="border",
                                        align_corners=True)[0, 0]
         return out

@@ -1,0 +1,157 @@
+"""GPU parity of the hot path (one objective + gradient evaluation) against
+the FP64 oracle, through the C ABI.
+
+Tolerance: 1e-4 relative on the objective terms and 1e-4 relative (norm-wise)
+on the gradient, FP32 kernels against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import grad_rel, log, make_field, rel, round_storage
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def octmc():
+    import paper_2010_06931_amd as m
+    m.lib()
+    return m
+
+
+def _gpu_pair(octmc, pair, dtype="f32", **kw):
+    return octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=dtype, **kw)
+
+
+def _orc_params(P):
+    p = P.params
+    return oracle.Params(alpha=p.alpha, delta0=p.delta0, eps_h=p.eps_huber, eps_r=p.eps_reg,
+                         flyback_frac=p.flyback_frac, mean_weight=p.mean_weight)
+
+
+def _compare(octmc, P, lv, level, D, tag, tol=TOL, eta_mode=0):
+    log(f"eval {tag} level={level} shape={lv.whd}")
+    Dg = D.to(device="cuda", dtype=torch.float32)
+    terms, g = P.eval(level, Dg, eta_mode=eta_mode)
+    torch.cuda.synchronize()
+    assert torch.isfinite(terms).all() and torch.isfinite(g).all(), tag
+    t = octmc.terms_dict(terms)
+    prm = _orc_params(P)
+    # the oracle sees exactly the float32 displacement the GPU saw
+    D32 = Dg.double().cpu().numpy()
+    eta = oracle.eta_at(lv, D32, prm) if eta_mode == 0 else t["eta"]
+    assert rel(t["eta"], eta) < tol, (tag, t["eta"], eta)
+    ref, gref = oracle.evaluate(lv, D32, prm, eta)
+    for k in ("F", "data", "str", "ang", "reg", "str05", "ang05"):
+        assert rel(t[k], ref[k]) < tol or abs(t[k] - ref[k]) < 1e-9 * max(1.0, abs(ref["F"])), (tag, k, t[k], ref[k])
+    assert abs(t["mean"] - ref["mean"]) <= tol * max(abs(ref["mean"]), 1e-6 * abs(ref["F"])), (tag, t["mean"], ref["mean"])
+    e = grad_rel(g.double().cpu().numpy(), gref)
+    assert e < tol, (tag, e)
+    return t, g
+
+
+@pytest.mark.parametrize("case", ["zero", "gt", "gt_noise", "smooth", "uniform"])
+def test_eval_parity_tiny(octmc, case):
+    pair = synth.make_pair("tiny")
+    P = _gpu_pair(octmc, pair, levels=3)
+    lv = oracle.level_from_pair(pair)
+    _compare(octmc, P, lv, 0, make_field(pair, case, seed=3), f"tiny/{case}")
+
+
+def test_eval_parity_ragged_all_levels(octmc):
+    # 40 x 40 A-scans (several blocks, ragged last block), 150 samples
+    # (two full depth chunks and a ragged tail); every pyramid level
+    pair = synth.make_pair("tiny", n=40, d=150)
+    P = _gpu_pair(octmc, pair, levels=3)
+    pyr = oracle.pyramid(oracle.level_from_pair(pair), 3)
+    for level in range(3):
+        w, h, d = P.level_shape(level)
+        assert (w, h, d) == pyr[level].whd
+        D = synth.smooth_random_field(w, h, 1.5, seed=10 + level)
+        _compare(octmc, P, pyr[level], level, D, f"ragged/L{level}")
+
+
+def test_eval_parity_validity_and_white_lines(octmc):
+    pair = synth.make_pair("tiny", n=48, d=64, white_lines=True)
+    assert (pair.vx == 0).any() and (pair.vy == 0).any()
+    P = _gpu_pair(octmc, pair, levels=2)
+    lv = oracle.level_from_pair(pair)
+    for case in ("gt", "gt_noise"):
+        _compare(octmc, P, lv, 0, make_field(pair, case, seed=5), f"white/{case}")
+
+
+def test_eval_parity_delta0_zero_and_params(octmc):
+    pair = synth.make_pair("tiny", n=32, d=48)
+    P = _gpu_pair(octmc, pair, levels=2, delta0=0.0, alpha=0.3, eps_reg=0.05, mean_weight=2.5)
+    lv = oracle.level_from_pair(pair)
+    t, _ = _compare(octmc, P, lv, 0, make_field(pair, "gt_noise", seed=2), "delta0=0")
+    assert t["ang"] == 0.0
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_eval_parity_storage_types(octmc, dtype):
+    pair = synth.make_pair("tiny")
+    P = _gpu_pair(octmc, pair, dtype=dtype, levels=3)
+    # compute error: the oracle reads the volumes rounded to the storage type
+    lv = oracle.level_from(round_storage(pair.sx, dtype), round_storage(pair.sy, dtype), pair.ax, pair.ay,
+                           pair.vx, pair.vy)
+    _compare(octmc, P, lv, 0, make_field(pair, "gt_noise", seed=4), f"{dtype}/compute")
+
+
+def test_eval_is_deterministic_and_eta_mode(octmc):
+    pair = synth.make_pair("tiny", n=40, d=96)
+    P = _gpu_pair(octmc, pair, levels=2)
+    D = make_field(pair, "gt_noise", 1).float().cuda()
+    t1, g1 = P.eval(0, D, eta_mode=0)
+    t1, g1 = t1.clone(), g1.clone()
+    t2, g2 = P.eval(0, D, eta_mode=1)
+    torch.cuda.synchronize()
+    assert torch.equal(t1, t2)
+    assert torch.equal(g1, g2)
+    # eta_mode 1 keeps the stored eta when the field changes
+    D2 = make_field(pair, "smooth", 2).float().cuda()
+    t3, _ = P.eval(0, D2, eta_mode=1)
+    assert t3[octmc.TERM_ETA].item() == t1[octmc.TERM_ETA].item()
+
+
+def test_eval_batched_matches_single(octmc):
+    pairs = [synth.make_pair("batch", p, n=40, d=64) for p in range(3)]
+    Ps = [_gpu_pair(octmc, q, levels=2) for q in pairs]
+    D = torch.stack([make_field(q, "gt_noise", k) for k, q in enumerate(pairs)]).float().cuda()
+    log("batched eval 3 pairs")
+    tb, gb = octmc.eval_batched(Ps, 0, D, eta_mode=0)
+    for k, P in enumerate(Ps):
+        t, g = P.eval(0, D[k], eta_mode=0)
+        torch.cuda.synchronize()
+        assert torch.equal(t, tb[k])
+        assert torch.equal(g, gb[k])
+    lv = oracle.level_from_pair(pairs[1])
+    _compare(octmc, Ps[1], lv, 0, D[1].double().cpu(), "batched/oracle")
+
+
+@pytest.mark.slow
+def test_eval_parity_full_size_sampled(octmc):
+    """500 x 500 A-scans x 800 samples, generated on the GPU, in the launch
+    configuration the benchmark times: the data gradient of 192 sampled
+    A-scans (incl. corners and edges) against the oracle."""
+    log("generate dense 500x500x800 on cuda")
+    pair = synth.make_pair("dense", device="cuda", octa_volumes=False)
+    P = _gpu_pair(octmc, pair, levels=4, alpha=0.0, mean_weight=0.0)
+    D = make_field(pair, "gt_noise", seed=7)
+    Dg = D.float().cuda()
+    log("eval dense level 0")
+    terms, g = P.eval(0, Dg, eta_mode=1)  # stored eta = 1
+    torch.cuda.synchronize()
+    assert octmc.terms_dict(terms)["eta"] == 1.0
+    n = 500
+    rng = np.random.default_rng(0)
+    sample = np.concatenate([[0, n - 1, n * (n - 1), n * n - 1, n * 250 + 250], rng.integers(0, n * n, 187)])
+    lv = oracle.Level(*(oracle._f64(t) for t in (pair.sx, pair.sy, pair.ax, pair.ay, pair.vx, pair.vy)))
+    _, gref = oracle.data_ascans(lv, Dg.double().cpu().numpy(), sample, _orc_params(P), 1.0)
+    gg = g.double().cpu().numpy().reshape(2, -1, 3)
+    got = np.concatenate([gg[0][sample], gg[1][sample]], axis=1)
+    assert grad_rel(got, gref) < TOL

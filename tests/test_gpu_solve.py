@@ -1,0 +1,85 @@
+"""GPU parity of the full solve (pyramid, eta per level, L-BFGS, level
+transitions) and of the merge against the FP64 oracle, through the C ABI.
+
+Final displacements: <= 0.05 px RMS against the oracle's FP64 solve."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def octmc():
+    import paper_2010_06931_amd as m
+    m.lib()
+    return m
+
+
+def _orc_params(p):
+    return oracle.Params(alpha=p.alpha, delta0=p.delta0, eps_h=p.eps_huber, eps_r=p.eps_reg,
+                         flyback_frac=p.flyback_frac, mean_weight=p.mean_weight, levels=p.levels,
+                         iters=p.iters_per_level, lbfgs_m=p.lbfgs_m, ls_max_evals=p.ls_max_evals, c1=p.c1, c2=p.c2,
+                         merge_kappa=p.merge_kappa, merge_tau=p.merge_tau)
+
+
+@pytest.mark.parametrize("iters", [100])
+def test_register_matches_oracle_tiny(octmc, iters):
+    pair = synth.make_pair("tiny")
+    P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, levels=3,
+                   iters_per_level=iters)
+    log(f"register tiny iters={iters}")
+    D, _, _, rep = P.register()
+    torch.cuda.synchronize()
+    Dg = D.double().cpu().numpy()
+    Do, orep = oracle.register(oracle.level_from_pair(pair), _orc_params(P.params))
+    diff = np.sqrt(((Dg - Do) ** 2).mean())
+    print("levels gpu", rep, "oracle", orep, "rms diff", diff)
+    assert len(rep) == 3
+    assert abs(rep[0]["eta"] - orep[0]["eta"]) < 1e-6 * orep[0]["eta"]
+    for r, o in zip(rep, orep):
+        assert r["f_end"] < r["f_start"]
+        assert abs(r["f_end"] - o["f_end"]) < 0.05 * o["f_end"]
+    assert diff <= 0.05, diff
+
+
+def test_register_recovers_motion(octmc):
+    # pair 1 needs more than 100 steps per level to converge (so does the oracle)
+    pair = synth.make_pair("tiny", pair=1)
+    P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, levels=3, iters_per_level=300)
+    D, _, _, _ = P.register()
+    from test_oracle_pins import recovery_mask
+    m = recovery_mask(pair)
+    e = D.double().cpu().numpy() - pair.d_gt.numpy()
+    e -= e[m].mean(axis=0)
+    rms = np.sqrt((e[m] ** 2).mean(axis=0))
+    assert np.all(rms < 0.3), rms
+
+
+def test_merge_matches_oracle(octmc):
+    pair = synth.make_pair("tiny", n=40, d=72, white_lines=True)
+    P = octmc.Pair(pair.sx, pair.sy, ox=pair.ox, oy=pair.oy, vx=pair.vx, vy=pair.vy, levels=2)
+    D = synth.perturbed_field(pair.d_gt, 0.2, 3).float()
+    log("merge 40x40x72")
+    mo, ma = P.merge(D.cuda(), octa=True)
+    torch.cuda.synchronize()
+    ox = oracle.substitute_invalid(pair.ox, pair.vx, 0)
+    oy = oracle.substitute_invalid(pair.oy, pair.vy, 1)
+    ro, ra, _, _ = oracle.merge(pair.sx, pair.sy, D.double(), ox, oy, pair.vx, pair.vy,
+                                P.params.merge_kappa, P.params.merge_tau)
+    assert np.abs(mo.double().cpu().numpy() - ro).max() < 1e-4 * max(1.0, np.abs(ro).max())
+    assert np.abs(ma.double().cpu().numpy() - ra).max() < 1e-4 * max(1.0, np.abs(ra).max())
+
+
+def test_register_with_merge_and_enface_from_octa(octmc):
+    pair = synth.make_pair("tiny", n=32, d=40)
+    P = octmc.Pair(pair.sx, pair.sy, ox=pair.ox, oy=pair.oy, levels=2, iters_per_level=10)
+    D, mo, ma, rep = P.register(merged=True)
+    torch.cuda.synchronize()
+    assert mo.shape == (32, 32, 40) and ma.shape == (32, 32, 40)
+    assert torch.isfinite(mo).all() and torch.isfinite(ma).all()
+    assert all(r["iters"] <= 10 for r in rep)
