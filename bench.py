@@ -62,6 +62,59 @@ def load_traffic(dtype):
         return None
 
 
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per copy
+COPY_REPEATS = 3
+
+
+def calibration_copies(torch):
+    """Plain device-to-device copies of known size, run after the timed
+    evaluations of a profile-only run so that the same counter pass sees them."""
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(COPY_REPEATS):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def _counter_rows(path, counter):
+    import csv
+    rows = [r for r in csv.DictReader(open(path)) if r.get("Counter_Name", "").startswith(counter)]
+    if not rows:
+        raise SystemExit(f"{path}: no {counter} rows")
+    return rows
+
+
+def traffic_summary(fetch_csv, write_csv, dtype, out_path, command):
+    """HBM bytes per launch of the structural kernel from two rocprofv3
+    counter passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by
+    the ratio of known bytes to counted bytes of the calibration copies."""
+    res = {}
+    for name, path, known in (("FETCH_SIZE", fetch_csv, COPY_BYTES), ("WRITE_SIZE", write_csv, COPY_BYTES)):
+        rows = _counter_rows(path, name)
+        ks = [float(r["Counter_Value"]) for r in rows if "k_struct" in r["Kernel_Name"]]
+        # the calibration copies are the last copy dispatches of the run
+        cp = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"])) for r in rows
+                    if "copyBuffer" in r["Kernel_Name"])
+        cp = [v for _, v in cp[-COPY_REPEATS:]]
+        if not ks or not cp:
+            raise SystemExit(f"{path}: k_struct dispatches {len(ks)}, copy dispatches {len(cp)}")
+        factor = known * COPY_REPEATS / (sum(cp) * 1024.0)
+        res[name] = {"kib_per_dispatch": round(sum(ks) / len(ks), 1), "dispatches": len(ks),
+                     "copy_kib_total": round(sum(cp), 1), "copy_factor": round(factor, 4),
+                     "bytes_per_launch": sum(ks) / len(ks) * 1024.0 * factor}
+    rec = {}
+    if os.path.exists(out_path):
+        rec = json.load(open(out_path))
+        if rec.get("source_sha") != source_sha():
+            rec = {}
+    rec["source_sha"] = source_sha()
+    rec[dtype] = {"bytes_per_launch": round(res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]),
+                  "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"], "command": command}
+    json.dump(rec, open(out_path, "w"), indent=1)
+    print(json.dumps(rec[dtype]))
+
+
 def cpu_baseline(pair, D, target_s=15.0):
     """The FP64 oracle (as it stands) on the host: data term of a bounded
     sample of A-scans, scaled to evaluations per second."""
@@ -100,8 +153,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--profile-only", action="store_true", help="only the timed evaluations (for rocprofv3)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the timed evaluations and the calibration copies (for rocprofv3)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic of the structural kernel from two rocprofv3 counter passes")
+    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_struct_dense_counters.json"))
+    ap.add_argument("--summary-command", default="")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.dtype, args.summary_out, args.summary_command)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (pairs are independent: a multi-GPU "
               f"deployment runs one process per GPU)", file=sys.stderr)
@@ -140,6 +201,7 @@ def main():
     evals_s = 1000.0 / ms
     log(f"{ms:.4f} ms/eval ({evals_s:.1f} evals/s), wall {wall:.2f} s")
     if args.profile_only:
+        calibration_copies(torch)
         print(json.dumps({"ms_per_eval": ms}))
         return
 

@@ -192,12 +192,19 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     if (jid < 0) return;
     const StructJob& J = jobs.j[jid];
     const int w = J.w, h = J.h, d = J.d;
-    // 2 x 2 tile of output A-scans per workgroup, one per wave
+    // 2 x 2 tile of output A-scans per workgroup, one per wave.  The tile
+    // rows form 8 bands (one per XCD when the job fills the grid); a band is
+    // swept column by column, so the rows a tile reads are still in that
+    // XCD's L2 when the neighbouring column of tiles reads them again.
     const int tpr = (w + 1) >> 1;
+    const int trows = (h + 1) >> 1;
+    const int rpb = (trows + 7) >> 3;
     const int t = lb - J.blk_begin;
-    const int i = 2 * (t % tpr) + (wv & 1);
-    const int j = 2 * (t / tpr) + (wv >> 1);
-    if (t >= tpr * ((h + 1) >> 1) || i >= w || j >= h) return;  // whole wave; no block barrier below
+    const int band = t / (rpb * tpr), tb = t - band * (rpb * tpr);
+    const int trow = band * rpb + tb % rpb;
+    const int i = 2 * (tb / rpb) + (wv & 1);
+    const int j = 2 * trow + (wv >> 1);
+    if (t >= 8 * rpb * tpr || trow >= trows || i >= w || j >= h) return;  // whole wave; no block barrier below
     const int a = uni(j * w + i);
     const float* dX = J.disp + (size_t)a * 3;
     const float* dY = J.disp + ((size_t)J.na + a) * 3;

@@ -146,7 +146,8 @@ int eval_group(const EvalArgs* ea, int n, int level, int eta_mode, hipStream_t s
         sb += nsum;
         tj.j[q] = StructJob{L.sx, L.sy, ea[q].disp, P->part, L.w, L.h, L.d, L.na, tb, L.vol_bytes,
                             (float)pr.eps_huber};
-        tb += ((L.w + 1) / 2) * ((L.h + 1) / 2);  // one 2 x 2 tile of A-scans per block
+        // one 2 x 2 tile of A-scans per block; 8 bands of whole tile rows
+        tb += 8 * (((L.h + 1) / 2 + 7) / 8) * ((L.w + 1) / 2);
         const int nc = nblk_combine(L.na);
         const int blen = L.w;  // square scans: every B-scan has w A-scans
         const double f = std::floor(pr.flyback_frac * blen + 0.5);
