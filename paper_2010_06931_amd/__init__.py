@@ -265,6 +265,11 @@ def eval_batched(pairs, level: int, disp: torch.Tensor, *, grad: bool = True, et
     """One grouped evaluation over pairs sharing the level shape.
     disp: [B][2][h][w][3] float32 cuda.  Returns terms [B][NTERMS], grad."""
     B = len(pairs)
+    if B < 1:
+        raise ValueError("need at least one pair")
+    w, h, d = pairs[0].level_shape(level)
+    if disp.shape != (B, 2, h, w, 3) or disp.dtype != torch.float32 or not disp.is_cuda:
+        raise ValueError(f"disp must be a float32 cuda tensor of shape ({B}, 2, {h}, {w}, 3)")
     disp = disp.contiguous()
     terms = torch.empty((B, NTERMS), dtype=torch.float64, device=disp.device)
     g = torch.empty_like(disp) if grad else None
@@ -276,3 +281,53 @@ def eval_batched(pairs, level: int, disp: torch.Tensor, *, grad: bool = True, et
 def terms_dict(terms: torch.Tensor) -> dict:
     t = terms.detach().cpu().tolist()
     return dict(zip(TERM_NAMES, t))
+
+
+class OctmcObjective(torch.autograd.Function):
+    """F(D) of B pairs as a differentiable function of their displacements.
+
+    forward(D, pairs, level) evaluates the objective (Eq. 1 without the tilt
+    term) of every pair in one grouped launch and returns F as float64 [B];
+    the gradient the same launch computes (the hand-written adjoint of the
+    resampling, loss and regulariser) is kept, and backward returns it scaled
+    by the incoming dF.  eta of each pair's level is used as stored (Eq. 10
+    fixes it per level; it carries no gradient): set it first with
+    eval(..., eta_mode=0) or eval_batched(..., eta_mode=0).
+
+        F = OctmcObjective.apply(D, pairs, level)   # D: [B][2][h][w][3] float32 cuda
+        F.sum().backward()                           # D.grad = dF/dD
+    """
+
+    @staticmethod
+    def forward(ctx, D, pairs, level):
+        terms, g = eval_batched(list(pairs), int(level), D.detach(), grad=True, eta_mode=1)
+        ctx.save_for_backward(g)
+        return terms[:, TERM_F].clone()
+
+    @staticmethod
+    def backward(ctx, gF):
+        (g,) = ctx.saved_tensors
+        scale = gF.to(device=g.device, dtype=torch.float32).reshape(-1, *([1] * (g.dim() - 1)))
+        return scale * g, None, None
+
+
+def objective(D: torch.Tensor, pairs, level: int = 0) -> torch.Tensor:
+    """F of every pair (float64 [B]), differentiable with respect to D."""
+    return OctmcObjective.apply(D, tuple(pairs), level)
+
+
+def register(x_oct, y_oct, x_octa=None, y_octa=None, *, enface_x=None, enface_y=None, valid_x=None, valid_y=None,
+             params: Params | None = None, dtype: str = "f32", merged: bool = True, **param_overrides):
+    """Register one orthogonal scan pair and merge it.
+
+    x_oct, y_oct: structural volumes [h][w][d] in the common frame (the Y-fast
+    scan transposed by the caller); x_octa, y_octa: OCTA volumes or None;
+    enface_*: en face images [h][w] (needed when no OCTA volumes are given);
+    valid_*: B-scan validity.  Returns (disp [2][h][w][3], merged_oct,
+    merged_octa, per-level report)."""
+    P = Pair(x_oct, y_oct, ox=x_octa, oy=y_octa, ax=enface_x, ay=enface_y, vx=valid_x, vy=valid_y, params=params,
+             dtype=dtype, **param_overrides)
+    try:
+        return P.register(merged=merged)
+    finally:
+        P.close()
