@@ -39,7 +39,7 @@ class _Params(C.Structure):
                 ("eps_r", C.c_double), ("flyback_frac", C.c_double), ("mean_weight", C.c_double),
                 ("levels", C.c_int), ("iters", C.c_int), ("lbfgs_m", C.c_int), ("ls_max_evals", C.c_int),
                 ("c1", C.c_double), ("c2", C.c_double), ("merge_kappa", C.c_double),
-                ("merge_tau", C.c_double)]
+                ("merge_tau", C.c_double), ("store", C.c_int)]
 
 
 @dataclass
@@ -58,6 +58,7 @@ class Params:
     c2: float = 0.9
     merge_kappa: float = 1.0
     merge_tau: float = 0.05
+    store: int = 0  # structural storage in the solve: 0 exact, 1 bfloat16, 2 binary16
 
     def c(self) -> _Params:
         return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
@@ -103,6 +104,8 @@ def lib():
         L.orc_merge.argtypes = [dp] * 6 + [C.c_int] * 3 + [dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_enface_mean.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
         L.orc_substitute_invalid.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_int]
+        L.orc_round_storage.argtypes = [dp, C.c_size_t, C.c_int]
+        L.orc_round_storage.restype = None
         _lib = L
     return _lib
 
@@ -350,3 +353,11 @@ def substitute_invalid(vol, valid, V: int):
     h, w, d = vol.shape
     lib().orc_substitute_invalid(_p(vol), w, h, d, _p(valid), int(V))
     return vol
+
+
+def round_storage(v, store: int):
+    """v rounded to bfloat16 (store = 1) or binary16 (store = 2), to nearest
+    with ties to even, as float64."""
+    v = _f64(v).copy()
+    lib().orc_round_storage(_p(v), v.size, int(store))
+    return v

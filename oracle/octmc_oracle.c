@@ -43,12 +43,17 @@
  *   mean_weight  gamma_M of the mean-displacement term M (reading)
  *   levels, iters, lbfgs_m, ls_max_evals, c1, c2: the L-BFGS solve
  *   merge_kappa, merge_tau: the density-based merge weights (Sec. 2.1,
- *                "merging"; reading) */
+ *                "merging"; reading)
+ *   store        storage type of the structural volumes in the solve: 0 =
+ *                exact, 1 = bfloat16, 2 = IEEE binary16; every pyramid level
+ *                is built from the unrounded level above it and then rounded
+ *                to nearest, ties to even (see orc_round_storage) */
 typedef struct {
     double alpha, delta0, eps_h, eps_r, flyback_frac, mean_weight;
     int levels, iters, lbfgs_m, ls_max_evals;
     double c1, c2;
     double merge_kappa, merge_tau;
+    int store;
 } orc_params;
 
 /* Terms returned by orc_eval (indices). */
@@ -686,6 +691,38 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Rounding to a narrower binary floating-point format, to nearest with ties
+ * to even, from the definition: a format with p significant bits and
+ * smallest normal exponent emin represents, near |x| = m 2^e (m in
+ * [1/2, 1)), exactly the multiples of the quantum 2^max(e - p, emin - p + 1);
+ * x is divided by the quantum (exact: a power of two), rounded to an integer
+ * in the default rounding mode (nearest, ties to even) and scaled back.
+ * Results beyond the largest finite value become infinite.
+ *   bfloat16: p = 8,  emin = -126, largest finite (2 - 2^-7) 2^127
+ *   binary16: p = 11, emin = -14,  largest finite 65504 */
+static double round_format(double x, int p, int emin, double maxf)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    frexp(x, &e);
+    int qe = e - p;
+    if (qe < emin - p + 1) qe = emin - p + 1;
+    const double r = ldexp(nearbyint(ldexp(x, -qe)), qe);
+    if (fabs(r) > maxf) return r > 0 ? INFINITY : -INFINITY;
+    return r;
+}
+
+EXPORT void orc_round_storage(double* v, size_t n, int store)
+{
+    if (store == 1) {
+        const double maxf = ldexp(2.0 - ldexp(1.0, -7), 127);
+        for (size_t i = 0; i < n; i++) v[i] = round_format(v[i], 8, -126, maxf);
+    } else if (store == 2) {
+        for (size_t i = 0; i < n; i++) v[i] = round_format(v[i], 11, -14, 65504.0);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Multi-resolution 3-D registration (Sec. 2.1, "optimization"): a factor-2
  * pyramid, zero displacement at the coarsest level, eta fixed per level at
  * the level's initial field (Eq. 10), L-BFGS per level, upsampling between
@@ -737,6 +774,22 @@ EXPORT int orc_register(const double* sx, const double* sy, const double* ax, co
         orc_pyr_down1(VX[l - 1], H[l - 1], VX[l]);
         orc_pyr_down1(VY[l - 1], W[l - 1], VY[l]);
     }
+    /* storage rounding after the whole pyramid is built from exact values */
+    double *sx0 = NULL, *sy0 = NULL;
+    if (p->store) {
+        const size_t nv0 = (size_t)w * h * d;
+        sx0 = (double*)malloc(nv0 * sizeof(double));
+        sy0 = (double*)malloc(nv0 * sizeof(double));
+        memcpy(sx0, sx, nv0 * sizeof(double));
+        memcpy(sy0, sy, nv0 * sizeof(double));
+        SX[0] = sx0;
+        SY[0] = sy0;
+        for (int l = 0; l < L; l++) {
+            const size_t nv = (size_t)W[l] * H[l] * Dd[l];
+            orc_round_storage(SX[l], nv, p->store);
+            orc_round_storage(SY[l], nv, p->store);
+        }
+    }
     int rc = 0;
     double* Dc = NULL;
     for (int l = L - 1; l >= 0; l--) {
@@ -764,6 +817,8 @@ EXPORT int orc_register(const double* sx, const double* sy, const double* ax, co
     for (int l = 1; l < L; l++) {
         free(SX[l]); free(SY[l]); free(AX[l]); free(AY[l]); free(VX[l]); free(VY[l]);
     }
+    free(sx0);
+    free(sy0);
     return rc;
 }
 

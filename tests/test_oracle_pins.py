@@ -9,6 +9,7 @@ import math
 
 import numpy as np
 import pytest
+import torch
 from scipy.interpolate import CubicHermiteSpline
 
 import synth
@@ -541,3 +542,24 @@ def test_synthetic_recovery_tiny(orc):
     assert np.all(rms < 0.25), rms
     assert np.all(np.sqrt((zero ** 2).mean(axis=0)) > 1.0)  # the motion was real
     assert reps[-1]["f_end"] < reps[-1]["f_start"]
+
+
+def test_round_storage_matches_library_conversions(orc):
+    """Storage rounding against numpy's binary16 and torch's bfloat16
+    conversions (both round to nearest, ties to even), on random values over
+    many binades, exact ties, subnormals and overflow."""
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal(20000) * np.exp2(rng.integers(-30, 20, 20000))).astype(np.float32)
+    halfway = np.float32(1.0 + 2.0 ** -8)   # exactly between two bfloat16 values
+    halfway16 = np.float32(1.0 + 2.0 ** -11)  # exactly between two binary16 values
+    extra = np.array([0.0, -0.0, 1.0, halfway, -halfway, halfway16, 3 * 2.0 ** -25, 2.0 ** -140, 65519.0, 65520.0,
+                      1e6, -1e6, 3.0e38], np.float32)
+    x = np.concatenate([x, extra])
+    got16 = orc.round_storage(x, 2)
+    with np.errstate(over="ignore"):
+        ref16 = x.astype(np.float16).astype(np.float64)
+    assert np.array_equal(got16, ref16)
+    gotbf = orc.round_storage(x, 1)
+    refbf = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
+    assert np.array_equal(gotbf, refbf)
+    assert orc.round_storage(np.array([halfway]), 1)[0] == 1.0  # tie to even
