@@ -204,6 +204,85 @@ OCTMC_API int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oc
  * displacement field disp (device).  merged_octa may be NULL. */
 OCTMC_API int octmc_merge(octmc_pair* pair, const float* disp, float* merged_oct, float* merged_octa, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: registration requests of mixed sizes solved concurrently on one
+ * device (the full solve of Sec. 2.1 per request).  A server owns one range
+ * of device memory (hbm_budget_bytes) and admits queued requests in arrival
+ * order as soon as their footprint (octmc_request_footprint) fits in it and
+ * fewer than max_active requests are being solved.  An admitted request keeps
+ * its pyramid, float64 solver state and scratch in its part of that range
+ * until it completes.  The evaluations of the active requests, each at its
+ * own pyramid level and size, run either as grouped launches (one launch per
+ * kernel covers every request waiting for an evaluation; OCTMC_SERVE_GROUPED)
+ * or each on its request's own stream (OCTMC_SERVE_STREAMS).  A request's
+ * result is the same in both modes and equals octmc_register's for the same
+ * inputs: every reduction runs in a fixed order per request.
+ */
+typedef struct octmc_server octmc_server;
+
+#define OCTMC_SERVE_GROUPED 0
+#define OCTMC_SERVE_STREAMS 1
+
+/* One request.  Inputs as for octmc_pair_create (shape.mem says where they
+ * live); they are read when the request is admitted, so they must stay valid
+ * until its completion has been returned by octmc_server_poll.  Outputs are
+ * device buffers of the caller: disp_out [2][h][w][3] float32 (required),
+ * merged_oct / merged_octa [h][w][d] float32 or NULL. */
+typedef struct {
+    octmc_params params;
+    octmc_shape shape;
+    const float *oct_x, *oct_y, *octa_x, *octa_y, *enface_x, *enface_y, *valid_x, *valid_y;
+    float* disp_out;
+    float* merged_oct;
+    float* merged_octa;
+    uint64_t tag; /* returned unchanged in the completion */
+} octmc_request;
+
+/* Completion record of one request.  Times are seconds since the server was
+ * created (steady clock). */
+typedef struct {
+    uint64_t id;
+    uint64_t tag;
+    int32_t status; /* octmc_status of the request's solve */
+    int32_t reserved;
+    double t_submit, t_admit, t_done;
+    uint64_t bytes_reserved; /* footprint taken from the server's memory */
+    uint64_t bytes_used;     /* of which the request actually used */
+    octmc_report report;
+    char error[160];         /* octmc_last_error() text when status != 0 */
+} octmc_completion;
+
+/* Device bytes one request occupies while it is active (pyramid, solver
+ * state, scratch, and the merge buffers if it asks for a merged volume).
+ * Errors: as octmc_pair_create's validation. */
+OCTMC_API int octmc_request_footprint(const octmc_request* req, uint64_t* bytes);
+
+/* Create a server on ctx's device.  hbm_budget_bytes of device memory are
+ * allocated at once; max_active (1..64) requests are solved concurrently;
+ * mode is OCTMC_SERVE_GROUPED or OCTMC_SERVE_STREAMS.  Errors: OCTMC_E_INVALID,
+ * OCTMC_E_OOM (the budget cannot be allocated). */
+OCTMC_API int octmc_server_create(octmc_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_active, int32_t mode,
+                                  octmc_server** out);
+
+/* Queue a request; *id identifies its completion.  The call validates the
+ * request and returns at once.  Errors: OCTMC_E_INVALID / SHAPE / DTYPE,
+ * OCTMC_E_OOM if its footprint exceeds the whole budget (it could never be
+ * admitted). */
+OCTMC_API int octmc_server_submit(octmc_server* srv, const octmc_request* req, uint64_t* id);
+
+/* Move up to max completions into out (in completion order), waiting up to
+ * wait_ms milliseconds for the first one (0: do not wait, < 0: wait until one
+ * is available or nothing is pending).  *n receives the count. */
+OCTMC_API int octmc_server_poll(octmc_server* srv, octmc_completion* out, int32_t max, int32_t wait_ms,
+                                int32_t* n);
+
+/* Counts of queued, active and completed-but-not-polled requests. */
+OCTMC_API int octmc_server_status(const octmc_server* srv, int32_t* queued, int32_t* active, int32_t* done);
+
+/* Finish every submitted request, then release the server's threads, streams
+ * and memory.  Unpolled completions are discarded. */
+OCTMC_API int octmc_server_destroy(octmc_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

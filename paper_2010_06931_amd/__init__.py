@@ -33,7 +33,10 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_DTYPE", -4: "E_OOM", -
 # exported symbols of include/octmc.h (checked by the CPU test suite)
 SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_create", "octmc_destroy",
            "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_eval",
-           "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge")
+           "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge",
+           "octmc_request_footprint", "octmc_server_create", "octmc_server_submit", "octmc_server_poll",
+           "octmc_server_status", "octmc_server_destroy")
+SERVE_GROUPED, SERVE_STREAMS = 0, 1
 
 
 class Params(C.Structure):
@@ -60,6 +63,25 @@ class Report(C.Structure):
         n = self.nlevels
         return [dict(iters=self.iters[k], evals=self.evals[k], ls_fail=self.ls_fail[k], eta=self.eta[k],
                      f_start=self.f_start[k], f_end=self.f_end[k]) for k in range(n)]
+
+
+class Request(C.Structure):
+    _fields_ = [("params", Params), ("shape", Shape)] + \
+               [(n, C.c_void_p) for n in ("oct_x", "oct_y", "octa_x", "octa_y", "enface_x", "enface_y", "valid_x",
+                                          "valid_y", "disp_out", "merged_oct", "merged_octa")] + \
+               [("tag", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("bytes_reserved", C.c_uint64), ("bytes_used", C.c_uint64), ("report", Report),
+                ("error", C.c_char * 160)]
+
+    def as_dict(self):
+        return dict(id=self.id, tag=self.tag, status=self.status, t_submit=self.t_submit, t_admit=self.t_admit,
+                    t_done=self.t_done, bytes_reserved=self.bytes_reserved, bytes_used=self.bytes_used,
+                    report=self.report.as_list(), error=self.error.decode(errors="replace"))
 
 
 class OctmcError(RuntimeError):
@@ -92,6 +114,12 @@ def lib():
         L.octmc_eval_batched.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.octmc_register.argtypes = [vp, vp, vp, vp, C.POINTER(Report), vp]
         L.octmc_merge.argtypes = [vp, vp, vp, vp, vp]
+        L.octmc_request_footprint.argtypes = [C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.octmc_server_create.argtypes = [vp, C.c_uint64, C.c_int32, C.c_int32, C.POINTER(vp)]
+        L.octmc_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.octmc_server_poll.argtypes = [vp, C.POINTER(Completion), C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+        L.octmc_server_status.argtypes = [vp] + [C.POINTER(C.c_int32)] * 3
+        L.octmc_server_destroy.argtypes = [vp]
         for name in SYMBOLS:
             if name not in ("octmc_version", "octmc_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -331,3 +359,85 @@ def register(x_oct, y_oct, x_octa=None, y_octa=None, *, enface_x=None, enface_y=
         return P.register(merged=merged)
     finally:
         P.close()
+
+
+class Server:
+    """Continuous-batching registration server on one device (see
+    octmc_server_create).  Tensors passed to submit() are kept alive until
+    their completion has been polled."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 8, mode: int = SERVE_GROUPED,
+                 ctx: Context | None = None):
+        self.ctx = ctx or context(0)
+        self._h = C.c_void_p()
+        _check(lib().octmc_server_create(self.ctx._h, int(hbm_budget_bytes), int(max_active), int(mode),
+                                         C.byref(self._h)))
+        self._keep = {}
+
+    @staticmethod
+    def _request(sx, sy, disp_out, *, ox=None, oy=None, ax=None, ay=None, vx=None, vy=None, merged_oct=None,
+                 merged_octa=None, params: Params | None = None, dtype: str = "f32", tag: int = 0,
+                 **param_overrides):
+        dev = disp_out.device
+        sx, sy = _f32(sx, dev), _f32(sy, dev)
+        h, w, d = sx.shape
+        if disp_out.shape != (2, h, w, 3) or disp_out.dtype != torch.float32 or not disp_out.is_cuda:
+            raise ValueError(f"disp_out must be a float32 cuda tensor of shape (2, {h}, {w}, 3)")
+        prm = params if params is not None else default_params()
+        for k, v in param_overrides.items():
+            setattr(prm, k, v)
+        keep = [sx, sy, _f32(ox, dev), _f32(oy, dev), _f32(ax, dev), _f32(ay, dev), _f32(vx, dev), _f32(vy, dev),
+                disp_out, merged_oct, merged_octa]
+        r = Request()
+        r.params = prm
+        r.shape = Shape(w, h, d, _DTYPES[dtype], MEM_DEVICE)
+        for name, t in zip(("oct_x", "oct_y", "octa_x", "octa_y", "enface_x", "enface_y", "valid_x", "valid_y",
+                            "disp_out", "merged_oct", "merged_octa"), keep):
+            setattr(r, name, None if t is None else t.data_ptr())
+        r.tag = int(tag)
+        return r, keep
+
+    @staticmethod
+    def footprint(sx, sy, disp_out, **kw) -> int:
+        r, _ = Server._request(sx, sy, disp_out, **kw)
+        b = C.c_uint64()
+        _check(lib().octmc_request_footprint(C.byref(r), C.byref(b)))
+        return b.value
+
+    def submit(self, sx, sy, disp_out, **kw) -> int:
+        """Queue one request (keywords as Pair plus disp_out / merged_oct /
+        merged_octa device outputs and a tag); returns its id."""
+        r, keep = self._request(sx, sy, disp_out, **kw)
+        rid = C.c_uint64()
+        torch.cuda.current_stream().synchronize()  # inputs written on torch's stream are complete
+        _check(lib().octmc_server_submit(self._h, C.byref(r), C.byref(rid)))
+        self._keep[rid.value] = keep
+        return rid.value
+
+    def poll(self, max_n: int = 64, wait_ms: int = 0):
+        out = (Completion * max_n)()
+        n = C.c_int32()
+        _check(lib().octmc_server_poll(self._h, out, max_n, int(wait_ms), C.byref(n)))
+        res = []
+        for k in range(n.value):
+            c = out[k].as_dict()
+            self._keep.pop(c["id"], None)
+            res.append(c)
+        return res
+
+    def status(self):
+        q, a, d = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().octmc_server_status(self._h, C.byref(q), C.byref(a), C.byref(d)))
+        return dict(queued=q.value, active=a.value, done=d.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().octmc_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass

@@ -13,9 +13,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liboctmc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_eval.hip", "kernels_prep.hip", "kernels_lbfgs.hip", "kernels_merge.hip", "runtime.hip"]
+SOURCES = ["kernels_eval.hip", "kernels_prep.hip", "kernels_lbfgs.hip", "kernels_merge.hip", "runtime.hip",
+           "server.hip"]
 ARCH = os.environ.get("OCTMC_ARCH", "gfx950")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fvisibility=hidden", "-DOCTMC_BUILD",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-fvisibility=hidden", "-DOCTMC_BUILD",
          # no packed FP32 instructions in generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
@@ -35,7 +36,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = ["hipcc", "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -4,9 +4,90 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/octmc.h"
 
 namespace octmc {
+
+// Error reporting: set the calling thread's last error (octmc_last_error) and
+// return `code`.
+int fail(int code, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return ::octmc::fail(e_ == hipErrorOutOfMemory ? OCTMC_E_OOM : OCTMC_E_DEVICE,         \
+                                 std::string(#expr) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+#define OCTMC_TRY(expr)                                                                            \
+    do {                                                                                           \
+        int r_ = (expr);                                                                           \
+        if (r_ != OCTMC_OK) return r_;                                                             \
+    } while (0)
+
+// A contiguous range of device memory handed out by bumping an offset (every
+// allocation 256-byte aligned); nothing is freed before the whole range is.
+struct Slab {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    void* take(size_t bytes)
+    {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off > size || bytes > size - off) return nullptr;
+        used = off + bytes;
+        return base + off;
+    }
+};
+inline size_t slab_bytes(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+
+// One evaluation job: a pair at one of its pyramid levels.
+struct EvalArgs {
+    octmc_pair* pair;
+    const float* disp;
+    double* terms;
+    float* grad;
+    const double* p = nullptr;       // search direction for the directional derivative (or null)
+    double* grad64 = nullptr;        // float64 gradient for the solver (or null)
+    int level = 0;
+    int eta_mode = 1;                // 0: set the level's eta first (Eq. 10)
+};
+
+// The hot path over up to kMaxJobs jobs (distinct pairs, one storage type,
+// any levels and sizes) in one launch per kernel, on stream s.  ev (4 events
+// or null) brackets the three stages for timing.
+int eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev = nullptr);
+
+// How the solver gets its evaluations: directly on its stream, or through a
+// scheduler that groups the evaluations of several solvers.  eval() returns
+// once the evaluation is ordered before any later work on s.
+struct Evaluator {
+    virtual ~Evaluator() = default;
+    virtual int eval(const EvalArgs& ea, hipStream_t s) = 0;
+};
+
+octmc_dtype pair_dtype(const octmc_pair* pair);
+int validate_params(const octmc_params* p);
+int validate_shape(const octmc_params* params, const octmc_shape* shape);
+
+// Device bytes a pair (and its solve and merge) takes from a Slab.
+size_t pair_footprint(const octmc_params& params, const octmc_shape& shape, bool have_octa, bool have_valid,
+                      bool merged);
+
+// The C-ABI operations with an optional slab (all device memory, including
+// temporaries, comes from it), an evaluator and host scratch.
+int pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, const float* oct_x,
+                     const float* oct_y, const float* octa_x, const float* octa_y, const float* enface_x,
+                     const float* enface_y, const float* valid_x, const float* valid_y, hipStream_t s, Slab* slab,
+                     octmc_pair** out);
+int register_impl(octmc_pair* pair, float* disp_out, float* merged_oct, float* merged_octa, octmc_report* rep,
+                  hipStream_t s, Evaluator* ev, Slab* slab, double* h_terms, double* h_dots);
+int merge_impl(octmc_pair* pair, const float* disp, float* merged_oct, float* merged_octa, hipStream_t s,
+               Slab* slab);
+int ctx_device(const octmc_ctx* ctx);
 
 constexpr int kMaxJobs = 8;     // jobs (pairs) per grouped launch
 constexpr int kWavesPerBlock = 4;

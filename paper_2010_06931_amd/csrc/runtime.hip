@@ -19,28 +19,16 @@
 using namespace octmc;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const std::string& msg)
+int octmc::fail(int code, const std::string& msg)
 {
     g_err = msg;
     return code;
 }
 
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess)                                                                      \
-            return fail(e_ == hipErrorOutOfMemory ? OCTMC_E_OOM : OCTMC_E_DEVICE,                  \
-                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
-    } while (0)
-
-#define OCTMC_TRY(expr)                                                                            \
-    do {                                                                                           \
-        int r_ = (expr);                                                                           \
-        if (r_ != OCTMC_OK) return r_;                                                             \
-    } while (0)
+namespace {
 
 size_t esize(octmc_dtype dt) { return dt == OCTMC_F32 ? 4 : 2; }
 
@@ -91,12 +79,19 @@ struct octmc_pair {
     double* dot_blk = nullptr;  // [512][kMaxDots + 1]
     double* dot_out = nullptr;  // [kMaxDots + 1]
     std::vector<void*> owned;
+    Slab* slab = nullptr;  // when set, all device memory comes from it
     int busy = 0;
 
     template <typename T>
     hipError_t alloc(T** p, size_t bytes)
     {
         void* q = nullptr;
+        if (slab) {
+            q = slab->take(bytes ? bytes : 16);
+            if (!q) return hipErrorOutOfMemory;
+            *p = static_cast<T*>(q);
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
         if (e == hipSuccess) {
             owned.push_back(q);
@@ -119,16 +114,9 @@ int nblk_combine(int na) { return (na + kRedBlock - 1) / kRedBlock; }
 // ---------------------------------------------------------------------------
 // hot path: one grouped evaluation over up to kMaxJobs pairs at one level
 
-struct EvalArgs {
-    octmc_pair* pair;
-    const float* disp;
-    double* terms;
-    float* grad;
-    const double* p;         // search direction for the directional derivative (or null)
-    double* grad64 = nullptr;  // float64 gradient for the solver (or null)
-};
+}  // namespace
 
-int eval_group(const EvalArgs* ea, int n, int level, int eta_mode, hipStream_t s, hipEvent_t* ev = nullptr)
+int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev)
 {
     SumJobs sj{};
     StructJobs tj{};
@@ -136,9 +124,12 @@ int eval_group(const EvalArgs* ea, int n, int level, int eta_mode, hipStream_t s
     sj.n = tj.n = cj.n = n;
     int sb = 0, tb = 0, cb = 0;
     octmc_dtype dt = ea[0].pair->dtype;
+    bool any_eta = false;
     for (int q = 0; q < n; ++q) {
         octmc_pair* P = ea[q].pair;
+        const int level = ea[q].level;
         const Level& L = P->lev[level];
+        any_eta |= ea[q].eta_mode == 0;
         const octmc_params& pr = P->params;
         if (P->dtype != dt) return fail(OCTMC_E_DTYPE, "batched pairs must share the storage type");
         const int nsum = std::min(kSumBlocks, (2 * L.na + kRedBlock - 1) / kRedBlock);
@@ -187,20 +178,28 @@ int eval_group(const EvalArgs* ea, int n, int level, int eta_mode, hipStream_t s
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(launch_struct(tj, (tb + 7) / 8 * 8, dt, s));  // multiple of the 8 XCDs
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-    if (eta_mode == 0) {
-        CombineJobs c0 = cj;
+    if (any_eta) {  // eta of the jobs that ask for it, before their evaluation
+        CombineJobs c0{};
+        int b0 = 0;
         for (int q = 0; q < n; ++q) {
-            c0.j[q].mode = 0;
-            c0.j[q].grad = nullptr;
-            c0.j[q].grad64 = nullptr;
-            c0.j[q].p = nullptr;
+            if (ea[q].eta_mode != 0) continue;
+            CombineJob c = cj.j[q];
+            c.mode = 0;
+            c.grad = nullptr;
+            c.grad64 = nullptr;
+            c.p = nullptr;
+            c.blk_begin = b0;
+            b0 += c.nblk;
+            c0.j[c0.n++] = c;
         }
-        HIP_TRY(launch_combine(c0, cb, s));
+        HIP_TRY(launch_combine(c0, b0, s));
     }
     HIP_TRY(launch_combine(cj, cb, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return OCTMC_OK;
 }
+
+namespace {
 
 int check_level(const octmc_pair* P, int level)
 {
@@ -255,14 +254,15 @@ struct LevelRun {
     size_t n;
     double* h_terms;  // pinned host [OCTMC_NTERMS]
     double* h_dots;   // pinned host [kMaxDots + 1]
+    Evaluator* ev;
     int evals = 0;
 
     // phi(alpha) = F(x + alpha p), dphi = g(x + alpha p) . p
     int trial(double alpha, double& f, double& dphi)
     {
         HIP_TRY(launch_trial(sv->x, sv->p, alpha, n, sv->xt, sv->xt32, s));
-        EvalArgs ea{P, sv->xt32, P->terms, nullptr, sv->p, sv->gt};
-        OCTMC_TRY(eval_group(&ea, 1, level, 1, s));
+        EvalArgs ea{P, sv->xt32, P->terms, nullptr, sv->p, sv->gt, level, 1};
+        OCTMC_TRY(ev->eval(ea, s));
         HIP_TRY(hipMemcpyAsync(h_terms, P->terms, sizeof(double) * OCTMC_NTERMS, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         f = h_terms[OCTMC_TERM_F];
@@ -327,8 +327,8 @@ struct LevelRun {
         // initial evaluation: sets eta at the level's initial field (Eq. 10)
         HIP_TRY(launch_to_f32(sv->x, sv->xt32, n, s));
         {
-            EvalArgs ea{P, sv->xt32, P->terms, nullptr, nullptr, sv->g};
-            OCTMC_TRY(eval_group(&ea, 1, level, 0, s));
+            EvalArgs ea{P, sv->xt32, P->terms, nullptr, nullptr, sv->g, level, 0};
+            OCTMC_TRY(ev->eval(ea, s));
         }
         HIP_TRY(hipMemcpyAsync(h_terms, P->terms, sizeof(double) * OCTMC_NTERMS, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -507,7 +507,17 @@ struct LevelRun {
 
 bool finite_param(double v) { return std::isfinite(v); }
 
-int validate_params(const octmc_params* p)
+struct DirectEvaluator final : Evaluator {
+    int eval(const EvalArgs& ea, hipStream_t s) override { return eval_group(&ea, 1, s); }
+};
+
+}  // namespace
+
+octmc_dtype octmc::pair_dtype(const octmc_pair* pair) { return pair->dtype; }
+
+int octmc::ctx_device(const octmc_ctx* ctx) { return ctx->device; }
+
+int octmc::validate_params(const octmc_params* p)
 {
     if (!p) return fail(OCTMC_E_INVALID, "params is NULL");
     const double vals[] = {p->alpha, p->delta0, p->eps_huber, p->eps_reg, p->flyback_frac, p->mean_weight,
@@ -526,7 +536,63 @@ int validate_params(const octmc_params* p)
     return OCTMC_OK;
 }
 
-}  // namespace
+int octmc::validate_shape(const octmc_params* params, const octmc_shape* shape)
+{
+    if (!shape) return fail(OCTMC_E_INVALID, "shape is NULL");
+    const int w = shape->w, h = shape->h, d = shape->d;
+    if (shape->dtype != OCTMC_F32 && shape->dtype != OCTMC_BF16 && shape->dtype != OCTMC_F16)
+        return fail(OCTMC_E_DTYPE, "unknown storage type");
+    if (shape->mem != OCTMC_MEM_HOST && shape->mem != OCTMC_MEM_DEVICE)
+        return fail(OCTMC_E_INVALID, "unknown memory kind");
+    if (w != h) return fail(OCTMC_E_SHAPE, "only square scans (w == h) are supported");
+    if (w < 4 || d < 4) return fail(OCTMC_E_SHAPE, "scans must be at least 4 x 4 x 4");
+    if ((size_t)w * h * d * 4 >= (1ull << 31)) return fail(OCTMC_E_SHAPE, "volume larger than 2^31 bytes");
+    int wl = w, dl = d;
+    for (int l = 1; l < params->levels; ++l) {
+        wl = (wl + 1) / 2;
+        dl = (dl + 1) / 2;
+    }
+    if (wl < 4 || dl < 4) return fail(OCTMC_E_SHAPE, "too many pyramid levels for this size");
+    return OCTMC_OK;
+}
+
+// Every device allocation pair_create_impl, register_impl and merge_impl make
+// for one pair, each rounded up to the slab alignment.
+size_t octmc::pair_footprint(const octmc_params& pr, const octmc_shape& sh, bool have_octa, bool have_valid,
+                             bool merged)
+{
+    const size_t w = sh.w, h = sh.h, d = sh.d, na = w * h, nv = na * d;
+    const size_t es = esize(sh.dtype);
+    size_t t = 0;
+    t += 2 * slab_bytes(nv * 4);  // float32 staging
+    t += slab_bytes(64);          // counters
+    t += 2 * slab_bytes(na * 4);  // en face
+    if (have_octa) {
+        t += 2 * slab_bytes(nv * 4);
+        if (have_valid) t += slab_bytes(h * 4) + slab_bytes(w * 4);  // substitution tables
+    }
+    t += slab_bytes(h * 4) + slab_bytes(w * 4);  // validity
+    size_t lw = w, lh = h, ld = d;
+    for (int l = 0; l < pr.levels; ++l) {
+        t += 2 * slab_bytes(lw * lh * ld * es);
+        if (l + 1 < pr.levels) {
+            const size_t w2 = (lw + 1) / 2, h2 = (lh + 1) / 2, d2 = (ld + 1) / 2;
+            t += 2 * slab_bytes(w2 * h2 * d2 * 4) + 2 * slab_bytes(w2 * h2 * 4) + slab_bytes(h2 * 4) +
+                 slab_bytes(w2 * 4);
+            lw = w2;
+            lh = h2;
+            ld = d2;
+        }
+    }
+    t += slab_bytes(na * 8 * 4) + slab_bytes(kSumBlocks * 4 * 8) + slab_bytes(4 * 8) +
+         slab_bytes((size_t)nblk_combine((int)na) * 8 * 8) + slab_bytes(OCTMC_MAX_LEVELS * 8) +
+         slab_bytes(OCTMC_NTERMS * 8) + slab_bytes((size_t)512 * (kMaxDots + 1) * 8) +
+         slab_bytes((kMaxDots + 1) * 8);
+    const size_t n0 = 6 * na;
+    t += (size_t)(8 + 2 * pr.lbfgs_m) * slab_bytes(n0 * 8) + slab_bytes(n0 * 4);  // solver
+    if (merged) t += slab_bytes(2 * na * 8) + slab_bytes(na * 16);                 // merge
+    return t;
+}
 
 // ===========================================================================
 // C ABI
@@ -577,27 +643,17 @@ int octmc_destroy(octmc_ctx* ctx)
     return OCTMC_OK;
 }
 
-int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, const float* oct_x,
-                      const float* oct_y, const float* octa_x, const float* octa_y, const float* enface_x,
-                      const float* enface_y, const float* valid_x, const float* valid_y, void* stream,
-                      octmc_pair** out)
+}  // extern "C"
+
+int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape,
+                            const float* oct_x, const float* oct_y, const float* octa_x, const float* octa_y,
+                            const float* enface_x, const float* enface_y, const float* valid_x, const float* valid_y,
+                            hipStream_t s, Slab* slab, octmc_pair** out)
 {
     if (!ctx || !shape || !out || !oct_x || !oct_y) return fail(OCTMC_E_INVALID, "NULL argument");
     OCTMC_TRY(validate_params(params));
+    OCTMC_TRY(validate_shape(params, shape));
     const int w = shape->w, h = shape->h, d = shape->d;
-    if (shape->dtype != OCTMC_F32 && shape->dtype != OCTMC_BF16 && shape->dtype != OCTMC_F16)
-        return fail(OCTMC_E_DTYPE, "unknown storage type");
-    if (shape->mem != OCTMC_MEM_HOST && shape->mem != OCTMC_MEM_DEVICE)
-        return fail(OCTMC_E_INVALID, "unknown memory kind");
-    if (w != h) return fail(OCTMC_E_SHAPE, "only square scans (w == h) are supported");
-    if (w < 4 || d < 4) return fail(OCTMC_E_SHAPE, "scans must be at least 4 x 4 x 4");
-    if ((size_t)w * h * d * 4 >= (1ull << 31)) return fail(OCTMC_E_SHAPE, "volume larger than 2^31 bytes");
-    int wl = w, dl = d;
-    for (int l = 1; l < params->levels; ++l) {
-        wl = (wl + 1) / 2;
-        dl = (dl + 1) / 2;
-    }
-    if (wl < 4 || dl < 4) return fail(OCTMC_E_SHAPE, "too many pyramid levels for this size");
     const bool have_octa = octa_x && octa_y;
     const bool have_enface = enface_x && enface_y;
     if (!have_octa && !have_enface) return fail(OCTMC_E_INVALID, "need both OCTA volumes or both en face images");
@@ -605,9 +661,9 @@ int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_sh
         return fail(OCTMC_E_INVALID, "OCTA inputs must be given for both scans");
     if ((valid_x != nullptr) != (valid_y != nullptr)) return fail(OCTMC_E_INVALID, "give both validity vectors or none");
     HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     auto* P = new octmc_pair();
     std::unique_ptr<octmc_pair> guard(P);
+    P->slab = slab;
     P->ctx = ctx;
     P->params = *params;
     P->dtype = shape->dtype;
@@ -618,6 +674,7 @@ int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_sh
     DevBuf tmp;
     auto talloc = [&](size_t bytes) -> void* {
         void* q = nullptr;
+        if (slab) return slab->take(bytes);  // temporaries stay in the slab until the pair is released
         if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
         tmp.ptrs.push_back(q);
         return q;
@@ -762,9 +819,20 @@ int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_sh
     return OCTMC_OK;
 }
 
+extern "C" {
+
+int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, const float* oct_x,
+                      const float* oct_y, const float* octa_x, const float* octa_y, const float* enface_x,
+                      const float* enface_y, const float* valid_x, const float* valid_y, void* stream,
+                      octmc_pair** out)
+{
+    return pair_create_impl(ctx, params, shape, oct_x, oct_y, octa_x, octa_y, enface_x, enface_y, valid_x, valid_y,
+                            static_cast<hipStream_t>(stream), nullptr, out);
+}
+
 int octmc_pair_destroy(octmc_pair* pair)
 {
-    if (pair) {
+    if (pair && !pair->slab) {  // a slab's owner orders its release after the pair's work
         (void)hipSetDevice(pair->ctx->device);
         (void)hipDeviceSynchronize();
     }
@@ -788,8 +856,8 @@ int octmc_eval(octmc_pair* pair, int32_t level, const float* disp, double* terms
     if (!disp || !terms) return fail(OCTMC_E_INVALID, "disp and terms are required");
     if (eta_mode != 0 && eta_mode != 1) return fail(OCTMC_E_INVALID, "eta_mode must be 0 or 1");
     HIP_TRY(hipSetDevice(pair->ctx->device));
-    EvalArgs ea{pair, disp, terms, grad, nullptr};
-    return eval_group(&ea, 1, level, eta_mode, static_cast<hipStream_t>(stream));
+    EvalArgs ea{pair, disp, terms, grad, nullptr, nullptr, level, eta_mode};
+    return eval_group(&ea, 1, static_cast<hipStream_t>(stream));
 }
 
 int octmc_eval_profile(octmc_pair* pair, int32_t level, const float* disp, double* terms, float* grad,
@@ -809,8 +877,8 @@ int octmc_eval_profile(octmc_pair* pair, int32_t level, const float* disp, doubl
             for (int k = 0; k < 4; ++k) (void)hipEventDestroy(e[k]);
         }
     } guard{ev};
-    EvalArgs ea{pair, disp, terms, grad, nullptr};
-    OCTMC_TRY(eval_group(&ea, 1, level, eta_mode, s, ev));
+    EvalArgs ea{pair, disp, terms, grad, nullptr, nullptr, level, eta_mode};
+    OCTMC_TRY(eval_group(&ea, 1, s, ev));
     HIP_TRY(hipEventSynchronize(ev[3]));
     for (int k = 0; k < 3; ++k) HIP_TRY(hipEventElapsedTime(stage_ms + k, ev[k], ev[k + 1]));
     return OCTMC_OK;
@@ -838,26 +906,34 @@ int octmc_eval_batched(octmc_pair* const* pairs, int32_t npairs, int32_t level, 
         EvalArgs ea[kMaxJobs];
         for (int q = 0; q < cnt; ++q)
             ea[q] = EvalArgs{pairs[q0 + q], disp + (q0 + q) * nd, terms + (size_t)(q0 + q) * OCTMC_NTERMS,
-                             grad ? grad + (q0 + q) * nd : nullptr, nullptr};
-        OCTMC_TRY(eval_group(ea, cnt, level, eta_mode, static_cast<hipStream_t>(stream)));
+                             grad ? grad + (q0 + q) * nd : nullptr, nullptr, nullptr, level, eta_mode};
+        OCTMC_TRY(eval_group(ea, cnt, static_cast<hipStream_t>(stream)));
     }
     return OCTMC_OK;
 }
 
-int octmc_merge(octmc_pair* pair, const float* disp, float* merged_oct, float* merged_octa, void* stream)
+}  // extern "C"
+
+int octmc::merge_impl(octmc_pair* pair, const float* disp, float* merged_oct, float* merged_octa, hipStream_t s,
+                      Slab* slab)
 {
     if (!pair || !disp || !merged_oct) return fail(OCTMC_E_INVALID, "NULL argument");
     if (merged_octa && !pair->octa[0]) return fail(OCTMC_E_INVALID, "no OCTA volumes were given at creation");
     HIP_TRY(hipSetDevice(pair->ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const Level& L = pair->lev[0];
     DevBuf tmp;
     unsigned long long* grid = nullptr;
     float4* wts = nullptr;
-    HIP_TRY(hipMalloc(&grid, (size_t)2 * L.na * 8));
-    tmp.ptrs.push_back(grid);
-    HIP_TRY(hipMalloc(&wts, (size_t)L.na * 16));
-    tmp.ptrs.push_back(wts);
+    if (slab) {
+        grid = static_cast<unsigned long long*>(slab->take((size_t)2 * L.na * 8));
+        wts = static_cast<float4*>(slab->take((size_t)L.na * 16));
+        if (!grid || !wts) return fail(OCTMC_E_OOM, "slab exhausted (merge)");
+    } else {
+        HIP_TRY(hipMalloc(&grid, (size_t)2 * L.na * 8));
+        tmp.ptrs.push_back(grid);
+        HIP_TRY(hipMalloc(&wts, (size_t)L.na * 16));
+        tmp.ptrs.push_back(wts);
+    }
     HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(grid), 0u, (size_t)4 * L.na, s));
     HIP_TRY(launch_density(disp, L.w, L.h, grid, s));
     HIP_TRY(launch_merge_weights(disp, L.w, L.h, grid, merged_octa ? L.vx : nullptr, merged_octa ? L.vy : nullptr,
@@ -870,20 +946,26 @@ int octmc_merge(octmc_pair* pair, const float* disp, float* merged_oct, float* m
     return OCTMC_OK;
 }
 
-int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oct, float* merged_octa, octmc_report* rep,
-                   void* stream)
+int octmc::register_impl(octmc_pair* pair, float* disp_out, float* merged_oct, float* merged_octa, octmc_report* rep,
+                         hipStream_t s, Evaluator* ev, Slab* slab, double* h_terms_in, double* h_dots_in)
 {
     if (!pair || !disp_out) return fail(OCTMC_E_INVALID, "NULL argument");
     if (merged_octa && !pair->octa[0]) return fail(OCTMC_E_INVALID, "no OCTA volumes were given at creation");
     if (pair->busy) return fail(OCTMC_E_BUSY, "pair is in use");
     HIP_TRY(hipSetDevice(pair->ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    DirectEvaluator direct;
+    if (!ev) ev = &direct;
     const octmc_params& pr = pair->params;
     const size_t n0 = (size_t)6 * pair->lev[0].na;
     Solver sv;
     sv.m = pr.lbfgs_m;
     DevBuf mem;
     auto dalloc = [&](double** p) -> int {
+        if (slab) {
+            *p = static_cast<double*>(slab->take(n0 * 8));
+            if (!*p) return fail(OCTMC_E_OOM, "slab exhausted (solver)");
+            return OCTMC_OK;
+        }
         HIP_TRY(hipMalloc(p, n0 * 8));
         mem.ptrs.push_back(*p);
         return OCTMC_OK;
@@ -900,19 +982,30 @@ int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oct, float* 
         OCTMC_TRY(dalloc(&sv.S[k]));
         OCTMC_TRY(dalloc(&sv.Y[k]));
     }
-    HIP_TRY(hipMalloc(&sv.xt32, n0 * 4));
-    mem.ptrs.push_back(sv.xt32);
-    double *h_terms = nullptr, *h_dots = nullptr;
-    HIP_TRY(hipHostMalloc(&h_terms, OCTMC_NTERMS * 8, hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(&h_dots, (kMaxDots + 1) * 8, hipHostMallocDefault));
+    if (slab) {
+        sv.xt32 = static_cast<float*>(slab->take(n0 * 4));
+        if (!sv.xt32) return fail(OCTMC_E_OOM, "slab exhausted (solver)");
+    } else {
+        HIP_TRY(hipMalloc(&sv.xt32, n0 * 4));
+        mem.ptrs.push_back(sv.xt32);
+    }
+    double *h_terms = h_terms_in, *h_dots = h_dots_in;
     struct HostFree {
-        double *a, *b;
+        double *a = nullptr, *b = nullptr;
         ~HostFree()
         {
-            (void)hipHostFree(a);
-            (void)hipHostFree(b);
+            if (a) (void)hipHostFree(a);
+            if (b) (void)hipHostFree(b);
         }
-    } hf{h_terms, h_dots};
+    } hf;
+    if (!h_terms) {
+        HIP_TRY(hipHostMalloc(&h_terms, OCTMC_NTERMS * 8, hipHostMallocDefault));
+        hf.a = h_terms;
+    }
+    if (!h_dots) {
+        HIP_TRY(hipHostMalloc(&h_dots, (kMaxDots + 1) * 8, hipHostMallocDefault));
+        hf.b = h_dots;
+    }
     pair->busy = 1;
     struct Unbusy {
         octmc_pair* p;
@@ -933,7 +1026,7 @@ int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oct, float* 
             HIP_TRY(launch_upsample(sv.xprev, C.w, C.h, sv.x, L.w, L.h, s));
         }
         sv.n = n;
-        LevelRun run{pair, l, &sv, s, n, h_terms, h_dots};
+        LevelRun run{pair, l, &sv, s, n, h_terms, h_dots, ev};
         LevelStats st;
         OCTMC_TRY(run.run(pr, st));
         if (rep) {
@@ -943,15 +1036,29 @@ int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oct, float* 
             rep->ls_fail[r] = st.ls_fail;
             rep->f_start[r] = st.f_start;
             rep->f_end[r] = st.f_end;
-            double eta = 1.0;
-            HIP_TRY(hipMemcpy(&eta, pair->eta + l, 8, hipMemcpyDeviceToHost));
-            rep->eta[r] = eta;
+            HIP_TRY(hipMemcpyAsync(h_terms, pair->eta + l, 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            rep->eta[r] = h_terms[0];
         }
     }
     HIP_TRY(launch_to_f32(sv.x, disp_out, n0, s));
-    if (merged_oct) OCTMC_TRY(octmc_merge(pair, disp_out, merged_oct, merged_octa, stream));
+    if (merged_oct) OCTMC_TRY(merge_impl(pair, disp_out, merged_oct, merged_octa, s, slab));
     HIP_TRY(hipStreamSynchronize(s));
     return OCTMC_OK;
+}
+
+extern "C" {
+
+int octmc_merge(octmc_pair* pair, const float* disp, float* merged_oct, float* merged_octa, void* stream)
+{
+    return merge_impl(pair, disp, merged_oct, merged_octa, static_cast<hipStream_t>(stream), nullptr);
+}
+
+int octmc_register(octmc_pair* pair, float* disp_out, float* merged_oct, float* merged_octa, octmc_report* rep,
+                   void* stream)
+{
+    return register_impl(pair, disp_out, merged_oct, merged_octa, rep, static_cast<hipStream_t>(stream), nullptr,
+                         nullptr, nullptr, nullptr);
 }
 
 }  // extern "C"

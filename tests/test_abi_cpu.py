@@ -3,6 +3,7 @@ declares; argument checks that need no GPU return the documented codes."""
 import ctypes as C
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -51,7 +52,69 @@ def test_invalid_arguments_are_reported(m):
     assert L.octmc_register(None, None, None, None, None, None) == -1
 
 
-def test_structs_match_header(m):
-    # octmc_params: 6 doubles, 4 int32, 4 doubles, 1 uint32 (+ padding)
-    assert C.sizeof(m.Params) == 6 * 8 + 4 * 4 + 4 * 8 + 8
-    assert C.sizeof(m.Shape) == 5 * 4
+def _c_layout(tmp_path, structs):
+    """sizeof and offsetof of header structs, from a host C compiler."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "octmc.h"', "int main(void) {"]
+    for name, fields in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {a: int(b) for a, b in (ln.split() for ln in out.splitlines())}
+
+
+def test_structs_match_header(m, tmp_path):
+    mirrors = {"octmc_params": m.Params, "octmc_shape": m.Shape, "octmc_report": m.Report,
+               "octmc_request": m.Request, "octmc_completion": m.Completion}
+    structs = {name: [f for f, _ in cls._fields_] for name, cls in mirrors.items()}
+    lay = _c_layout(tmp_path, structs)
+    for name, cls in mirrors.items():
+        assert C.sizeof(cls) == lay[name], name
+        for f, _ in cls._fields_:
+            assert getattr(cls, f).offset == lay[f"{name}.{f}"], (name, f)
+
+
+def _request(m, w=64, d=128, levels=3, dtype=0, octa=False, merged=False):
+    r = m.Request()
+    m.lib().octmc_params_default(C.byref(r.params))
+    r.params.levels = levels
+    r.shape = m.Shape(w, w, d, dtype, m.MEM_DEVICE)
+    dummy = 0x1000  # never dereferenced: footprint and validation only
+    r.oct_x = r.oct_y = r.disp_out = dummy
+    if octa:
+        r.octa_x = r.octa_y = dummy
+    else:
+        r.enface_x = r.enface_y = dummy
+    if merged:
+        r.merged_oct = dummy
+    return r
+
+
+def test_request_footprint_and_validation(m):
+    L = m.lib()
+    b = C.c_uint64()
+    r = _request(m)
+    assert L.octmc_request_footprint(C.byref(r), C.byref(b)) == 0
+    f32 = b.value
+    w, d = 64, 128
+    pyramid = sum(2 * (w >> l) ** 2 * (d >> l) * 4 for l in range(3))
+    assert f32 > pyramid + 2 * w * w * d * 4  # pyramid + float32 staging + solver
+    assert f32 < 3 * pyramid + 16 * 6 * w * w * 8 + (1 << 21)
+    L.octmc_request_footprint(C.byref(_request(m, dtype=1)), C.byref(b))
+    assert b.value < f32  # 16-bit storage
+    L.octmc_request_footprint(C.byref(_request(m, octa=True, merged=True)), C.byref(b))
+    assert b.value > f32 + 2 * w * w * d * 4  # OCTA volumes and merge buffers
+    bad = _request(m, w=64, d=128, levels=6)  # coarsest level below 4
+    assert L.octmc_request_footprint(C.byref(bad), C.byref(b)) == -2
+    bad = _request(m)
+    bad.disp_out = None
+    assert L.octmc_request_footprint(C.byref(bad), C.byref(b)) == -1
+    assert L.octmc_server_create(None, 1 << 30, 4, 0, None) == -1
+    assert L.octmc_server_submit(None, C.byref(r), None) == -1
+    n = C.c_int32()
+    assert L.octmc_server_poll(None, None, 0, 0, C.byref(n)) == -1

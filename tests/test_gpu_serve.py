@@ -1,0 +1,131 @@
+"""The serving API (octmc_server_*) through the C ABI: requests of mixed
+sizes, pyramid depths and storage types solved concurrently give the same
+displacements (bitwise) and merged volumes as each request solved alone with
+octmc_register; admission follows arrival order and the memory budget."""
+import pytest
+import torch
+
+import synth
+from gpu_util import log
+
+pytestmark = pytest.mark.gpu
+
+# (n, d, levels, dtype, iterations per level)
+MIX = [(40, 64, 2, "f32", 30), (48, 80, 3, "bf16", 30), (32, 48, 2, "f32", 40), (56, 64, 3, "f16", 25),
+       (36, 40, 2, "bf16", 30)]
+
+
+@pytest.fixture(scope="module")
+def octmc():
+    import paper_2010_06931_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def mix():
+    return [synth.make_pair("serving", k, n=n, d=d, octa_volumes=(k == 0)) for k, (n, d, *_) in enumerate(MIX)]
+
+
+def _alone(octmc, pairs):
+    out = []
+    for k, (q, (n, d, lv, dt, it)) in enumerate(zip(pairs, MIX)):
+        kw = dict(ox=q.ox, oy=q.oy) if k == 0 else dict(ax=q.ax, ay=q.ay)
+        P = octmc.Pair(q.sx, q.sy, vx=q.vx, vy=q.vy, dtype=dt, levels=lv, iters_per_level=it, **kw)
+        D, mo, ma, rep = P.register(merged=(k == 0))
+        torch.cuda.synchronize()
+        out.append((D, mo, ma, rep))
+        P.close()
+    return out
+
+
+def _serve(octmc, srv, pairs):
+    outs = {}
+    for k, (q, (n, d, lv, dt, it)) in enumerate(zip(pairs, MIX)):
+        disp = torch.empty((2, n, n, 3), dtype=torch.float32, device="cuda")
+        mo = torch.empty((n, n, d), dtype=torch.float32, device="cuda") if k == 0 else None
+        ma = torch.empty_like(mo) if k == 0 else None
+        kw = dict(ox=q.ox, oy=q.oy, merged_oct=mo, merged_octa=ma) if k == 0 else dict(ax=q.ax, ay=q.ay)
+        rid = srv.submit(q.sx, q.sy, disp, vx=q.vx, vy=q.vy, dtype=dt, levels=lv, iters_per_level=it, tag=k, **kw)
+        outs[rid] = (k, disp, mo, ma)
+    done = []
+    while len(done) < len(MIX):
+        got = srv.poll(16, wait_ms=60000)
+        assert got, "no completion within 60 s"
+        done += got
+    return outs, done
+
+
+@pytest.mark.parametrize("mode", ["grouped", "streams"])
+def test_serve_results_equal_alone_and_in_mix(octmc, mix, mode):
+    log(f"serve: {len(MIX)} requests alone")
+    ref = _alone(octmc, mix)
+    m = octmc.SERVE_GROUPED if mode == "grouped" else octmc.SERVE_STREAMS
+    srv = octmc.Server(4 << 30, max_active=len(MIX), mode=m)
+    log(f"serve: {len(MIX)} requests in the mix ({mode})")
+    outs, done = _serve(octmc, srv, mix)
+    srv.close()
+    assert len(done) == len(MIX)
+    overlap = 0
+    for c in done:
+        assert c["status"] == 0, c["error"]
+        assert c["bytes_used"] <= c["bytes_reserved"], c
+        k, disp, mo, ma = outs[c["id"]]
+        assert c["tag"] == k
+        D, rmo, rma, rep = ref[k]
+        assert torch.equal(disp, D), (mode, k)
+        assert [r["evals"] for r in c["report"]] == [r["evals"] for r in rep]
+        if k == 0:
+            assert torch.equal(mo, rmo) and torch.equal(ma, rma)
+        overlap += sum(1 for o in done if o["id"] != c["id"] and o["t_admit"] < c["t_done"] and
+                       c["t_admit"] < o["t_done"])
+    assert overlap > 0  # the requests really ran concurrently
+
+
+def test_serve_admission_follows_budget(octmc, mix):
+    fps = []
+    for k, (q, (n, d, lv, dt, it)) in enumerate(zip(mix, MIX)):
+        disp = torch.empty((2, n, n, 3), dtype=torch.float32, device="cuda")
+        kw = dict(ox=q.ox, oy=q.oy, merged_oct=torch.empty((n, n, d), device="cuda"),
+                  merged_octa=torch.empty((n, n, d), device="cuda")) if k == 0 else dict(ax=q.ax, ay=q.ay)
+        fps.append(octmc.Server.footprint(q.sx, q.sy, disp, vx=q.vx, vy=q.vy, dtype=dt, levels=lv, **kw))
+    # the largest request never fits beside any other one
+    budget = max(fps) + min(fps) - 256
+    srv = octmc.Server(budget, max_active=4)
+    log(f"serve: budget {budget} bytes, footprints {fps}")
+    _, done = _serve(octmc, srv, mix)
+    n, d = 400, 512  # footprint far above the budget: refused at submission
+    x = torch.zeros((n, n, d), device="cuda")
+    with pytest.raises(octmc.OctmcError) as e:
+        srv.submit(x, x, torch.empty((2, n, n, 3), device="cuda"), ax=x[:, :, 0], ay=x[:, :, 0], levels=3)
+    assert e.value.code == -4
+    srv.close()
+    done.sort(key=lambda c: c["id"])
+    for c in done:
+        assert c["status"] == 0, c["error"]
+        assert c["bytes_reserved"] == fps[c["tag"]]
+    for a, b in zip(done, done[1:]):  # admitted in arrival order
+        assert b["t_admit"] >= a["t_admit"]
+    big = max(done, key=lambda c: c["bytes_reserved"])
+    for c in done:
+        if c is not big:
+            assert c["t_done"] <= big["t_admit"] or c["t_admit"] >= big["t_done"], (c, big)
+    events = sorted([(c["t_admit"], c["bytes_reserved"]) for c in done] +
+                    [(c["t_done"], -c["bytes_reserved"]) for c in done], key=lambda e: (e[0], e[1]))
+    used = 0
+    for _, delta in events:
+        used += delta
+        assert used <= budget
+
+
+def test_serve_rejects_invalid_requests(octmc, mix):
+    srv = octmc.Server(1 << 30, max_active=2)
+    q = mix[2]
+    n = MIX[2][0]
+    with pytest.raises(octmc.OctmcError) as e:
+        srv.submit(q.sx, q.sy, torch.empty((2, n, n, 3), device="cuda"), ax=q.ax, ay=q.ay, levels=5)
+    assert e.value.code == -2
+    with pytest.raises(octmc.OctmcError):
+        srv.submit(q.sx, q.sy, torch.empty((2, n, n, 3), device="cuda"), ax=q.ax, ay=q.ay, alpha=-1.0)
+    assert srv.status() == dict(queued=0, active=0, done=0)
+    srv.close()
