@@ -142,6 +142,124 @@ def cpu_baseline(pair, D, target_s=15.0):
                       f"{na}/{nsample}"}
 
 
+SERVE_SIZES = (300, 400, 500, 600)
+SERVE_DEPTHS = (512, 640, 800)
+UM_PER_PX = (12.0, 12.0, 3.0)  # transverse x, y and axial spacing of the dense / serving scans
+
+
+def _interior_rms(D, gt, border=8):
+    """Per-component RMS of D - gt over A-scans away from the border, after
+    removing the common mean (the gauge the mean term fixes)."""
+    import numpy as np
+    e = D.double().cpu().numpy() - gt.double().cpu().numpy()
+    h, w = e.shape[1:3]
+    m = np.zeros((2, h, w), bool)
+    m[:, border:h - border, border:w - border] = True
+    e -= e[m].mean(axis=0)
+    return np.sqrt((e[m] ** 2).mean(axis=0))
+
+
+def serving(octmc, torch, nreq, budget_gib, max_active, log):
+    """Mixed-size requests through the server (BF16 storage) against
+    sequential FP32 solves of the same trace on the same GPU."""
+    import numpy as np
+    import synth
+    classes = [(n, d) for n in SERVE_SIZES for d in SERVE_DEPTHS]
+    log(f"serving: generating {len(classes)} size classes on cuda")
+    pairs = [synth.make_pair("serving", c, n=n, d=d, device="cuda", octa_volumes=False)
+             for c, (n, d) in enumerate(classes)]
+    rng = np.random.default_rng(np.random.SeedSequence([20100693104, 999]))
+    cls = rng.integers(0, len(classes), nreq)
+    arrival = np.cumsum(rng.exponential(0.25, nreq))
+    arrival -= arrival[0]
+    torch.cuda.synchronize()
+
+    def out_of(c):
+        n = classes[c][0]
+        return torch.empty((2, n, n, 3), dtype=torch.float32, device="cuda")
+
+    # sequential plain FP32 solves, first-come first-served on the trace
+    log(f"serving: {nreq} sequential FP32 solves")
+    seq_t, seq_D = [], {}
+    for r in range(nreq):
+        q = pairs[cls[r]]
+        t0 = time.perf_counter()
+        P = octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, dtype="f32", levels=4)
+        D, _, _, _ = P.register()
+        torch.cuda.synchronize()
+        P.close()
+        seq_t.append(time.perf_counter() - t0)
+        if cls[r] not in seq_D:
+            seq_D[cls[r]] = D
+    done = 0.0
+    seq_lat = []
+    for r in range(nreq):
+        done = max(done, arrival[r]) + seq_t[r]
+        seq_lat.append(done - arrival[r])
+    seq = {"pairs_per_s_burst": round(nreq / sum(seq_t), 3),
+           "pairs_per_s_trace": round(nreq / done, 3),
+           "latency_p50_s": round(float(np.percentile(seq_lat, 50)), 3),
+           "latency_p99_s": round(float(np.percentile(seq_lat, 99)), 3),
+           "solve_s_mean": round(float(np.mean(seq_t)), 4)}
+
+    torch.cuda.empty_cache()  # return the generator's cached blocks to the device
+    del_free, _ = torch.cuda.mem_get_info()
+    budget = int(min(budget_gib * (1 << 30), 0.6 * del_free))
+    log(f"serving: memory budget {budget / 2**30:.1f} GiB")
+
+    def served(mode, times):
+        srv = octmc.Server(budget, max_active=max_active, mode=mode)
+        outs = {}
+        t0 = time.perf_counter()
+        for r in range(nreq):
+            wait = times[r] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            q = pairs[cls[r]]
+            disp = out_of(cls[r])
+            rid = srv.submit(q.sx, q.sy, disp, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, dtype="bf16", levels=4, tag=r)
+            outs[rid] = (r, disp)
+        comp = []
+        while len(comp) < nreq:
+            comp += srv.poll(nreq, wait_ms=120000)
+        t_end = time.perf_counter() - t0
+        srv.close()
+        bad = [c for c in comp if c["status"] != 0]
+        if bad:
+            raise RuntimeError(f"served request failed: {bad[0]['error']}")
+        lat = [c["t_done"] - c["t_submit"] for c in comp]
+        res = {"pairs_per_s": round(nreq / t_end, 3),
+               "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
+               "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+               "max_reserved_GiB": round(max(c["bytes_reserved"] for c in comp) / (1 << 30), 3)}
+        return res, {outs[c["id"]][0]: outs[c["id"]][1] for c in comp}
+
+    log("serving: Poisson trace, grouped launches")
+    poisson, got = served(octmc.SERVE_GROUPED, arrival)
+    log("serving: burst, grouped launches")
+    burst, _ = served(octmc.SERVE_GROUPED, np.zeros(nreq))
+    log("serving: burst, one stream per request")
+    burst_streams, _ = served(octmc.SERVE_STREAMS, np.zeros(nreq))
+    # accuracy: served BF16 against ground truth and against the FP32 solve of the same input
+    acc_gt_bf16, acc_gt_f32, acc_vs_f32 = [], [], []
+    for r, D in got.items():
+        c = cls[r]
+        gt = pairs[c].d_gt
+        acc_gt_bf16.append(_interior_rms(D, gt))
+        acc_gt_f32.append(_interior_rms(seq_D[c], gt))
+        acc_vs_f32.append(np.sqrt(((D - seq_D[c]).double().cpu().numpy() ** 2).reshape(-1, 3).mean(axis=0)))
+    med = lambda a: [round(float(x), 3) for x in np.median(np.array(a), axis=0)]
+    return {"requests": nreq, "size_classes": [f"{n}x{n}x{d}" for n, d in classes],
+            "arrivals": "Poisson, mean inter-arrival 0.25 s", "max_active": max_active, "storage": "bf16",
+            "budget_GiB": round(budget / 2**30, 2),
+            "levels": 4, "iters_per_level": 100,
+            "served_poisson_grouped": poisson, "served_burst_grouped": burst,
+            "served_burst_streams": burst_streams, "sequential_fp32": seq,
+            "accuracy_median_rms_px": {"served_bf16_vs_ground_truth": med(acc_gt_bf16),
+                                       "sequential_fp32_vs_ground_truth": med(acc_gt_f32),
+                                       "served_bf16_vs_sequential_fp32": med(acc_vs_f32)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +271,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=float, default=48.0)
+    ap.add_argument("--serve-max-active", type=int, default=8)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed evaluations and the calibration copies (for rocprofv3)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -175,6 +297,10 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    props = torch.cuda.get_device_properties(0)
+    free, total = torch.cuda.mem_get_info()
+    log(f"device {props.name}: {props.multi_processor_count} CUs, {total / 2**30:.1f} GiB "
+        f"({free / 2**30:.1f} GiB free)")
     log(f"generating the dense pair {args.n}x{args.n}x{args.d} on cuda")
     pair = synth.make_pair("dense", n=args.n, d=args.d, device="cuda", octa_volumes=False)
     log("ingest")
@@ -252,6 +378,12 @@ def main():
             vb = 2 * w * h * d * (4 if dt == "f32" else 2) + w * h * EXTRA_BYTES_PER_ASCAN
             var[dt] = {"evals_per_s": round(1000 / vms, 2), "struct_ms": round(vst[1], 5),
                        "hbm_GBps_algorithmic": round(vb / (vst[1] * 1e-3) / 1e9, 1)}
+            if not args.no_solve:
+                t0 = time.perf_counter()
+                Dq, _, _, _ = Q.register()
+                torch.cuda.synchronize()
+                var[dt]["solve_s"] = round(time.perf_counter() - t0, 4)
+                var[dt]["solution"] = Dq
             Q.close()
             del Q
         out["storage_variants"] = var
@@ -266,15 +398,26 @@ def main():
             Dsol, _, _, rep = P.register()
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - t0)
-        m = np.ones((2, h, w), bool)
-        m[:, :8] = m[:, -8:] = False
-        m[:, :, :8] = m[:, :, -8:] = False
-        e = Dsol.double().cpu().numpy() - pair.d_gt.numpy()
-        e -= e[m].mean(axis=0)
+        rms32 = _interior_rms(Dsol, pair.d_gt)
         out["solve"] = {"seconds_median": round(float(np.median(lat)), 4), "pairs_per_s": round(1 / float(np.median(lat)), 3),
                         "levels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in rep],
                         "evals_total": int(sum(r["evals"] for r in rep)),
-                        "rms_vs_ground_truth_px": [round(float(x), 4) for x in np.sqrt((e[m] ** 2).mean(axis=0))]}
+                        "rms_vs_ground_truth_px": [round(float(x), 4) for x in rms32],
+                        "rms_vs_ground_truth_um": [round(float(x * s), 2) for x, s in zip(rms32, UM_PER_PX)]}
+        for dt, v in out.get("storage_variants", {}).items():
+            Dq = v.pop("solution", None)
+            if Dq is None:
+                continue
+            r = _interior_rms(Dq, pair.d_gt)
+            v["solve_rms_vs_ground_truth_px"] = [round(float(x), 4) for x in r]
+            v["solve_rms_vs_ground_truth_um"] = [round(float(x * s), 2) for x, s in zip(r, UM_PER_PX)]
+            v["solve_rms_vs_fp32_solve_px"] = [round(float(x), 4) for x in
+                                               np.sqrt(((Dq - Dsol).double().cpu().numpy() ** 2).reshape(-1, 3).mean(axis=0))]
+
+    for v in out.get("storage_variants", {}).values():
+        v.pop("solution", None)
+    if not args.no_serve:
+        out["serving"] = serving(octmc, torch, args.serve_requests, args.serve_budget_gib, args.serve_max_active, log)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

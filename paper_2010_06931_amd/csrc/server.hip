@@ -11,8 +11,9 @@
 //              merge)
 //   batcher    (grouped mode) collects the evaluations the workers are
 //              waiting for and runs each set of up to kMaxJobs as one launch
-//              per kernel, every job at its own level and size; the next set
-//              forms while the current one runs on the device
+//              per kernel, every job at its own level and size; sets
+//              alternate between two streams, and the next set forms while
+//              up to two run on the device
 //
 // The solver of a request is the same code as octmc_register's and every
 // reduction runs in a fixed order per job, so a request's result does not
@@ -134,8 +135,8 @@ struct octmc_server {
     std::vector<Worker*> workers;
     std::vector<Ticket*> pending;
     std::thread batcher;
-    hipStream_t bs = nullptr;
-    hipEvent_t last = nullptr;
+    hipStream_t bs[2] = {nullptr, nullptr};  // grouped launches alternate between two streams
+    hipEvent_t last[2] = {nullptr, nullptr};
 
     double now() const { return std::chrono::duration<double>(Clock::now() - start).count(); }
 };
@@ -172,15 +173,15 @@ struct GroupEval final : Evaluator {
 };
 
 // Launch one set of waiting evaluations (one storage type, distinct pairs).
-int launch_set(octmc_server* S, Ticket* const* t, int n)
+int launch_set(hipStream_t bs, Ticket* const* t, int n)
 {
     EvalArgs ea[kMaxJobs];
     for (int q = 0; q < n; ++q) {
-        HIP_TRY(hipStreamWaitEvent(S->bs, t[q]->ready, 0));
+        HIP_TRY(hipStreamWaitEvent(bs, t[q]->ready, 0));
         ea[q] = t[q]->ea;
     }
-    OCTMC_TRY(eval_group(ea, n, S->bs));
-    for (int q = 0; q < n; ++q) HIP_TRY(hipEventRecord(t[q]->done, S->bs));
+    OCTMC_TRY(eval_group(ea, n, bs));
+    for (int q = 0; q < n; ++q) HIP_TRY(hipEventRecord(t[q]->done, bs));
     return OCTMC_OK;
 }
 
@@ -188,7 +189,9 @@ void batcher_main(octmc_server* S)
 {
     (void)hipSetDevice(S->device);
     std::vector<Ticket*> take;
-    for (;;) {
+    bool launched_before[2] = {false, false};
+    for (int step = 0;; step ^= 1) {
+        hipStream_t bs = S->bs[step];
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_batch.wait(lk, [&] { return S->stop_batcher || !S->pending.empty(); });
@@ -203,7 +206,7 @@ void batcher_main(octmc_server* S)
             size_t q1 = q0 + 1;
             const octmc_dtype dt = pair_dtype(take[q0]->ea.pair);
             while (q1 < take.size() && q1 - q0 < (size_t)kMaxJobs && pair_dtype(take[q1]->ea.pair) == dt) ++q1;
-            const int rc = launch_set(S, take.data() + q0, (int)(q1 - q0));
+            const int rc = launch_set(bs, take.data() + q0, (int)(q1 - q0));
             if (rc != OCTMC_OK) {
                 const std::string msg = octmc_last_error();
                 for (size_t q = q0; q < q1; ++q) {
@@ -213,14 +216,16 @@ void batcher_main(octmc_server* S)
             }
             q0 = q1;
         }
-        const hipError_t e = hipEventRecord(S->last, S->bs);
+        const hipError_t e = hipEventRecord(S->last[step], bs);
+        launched_before[step] = e == hipSuccess;
         {
             std::lock_guard<std::mutex> lk(S->mu);
             for (Ticket* t : take) t->launched = true;
         }
         S->cv_ticket.notify_all();
-        // the next set forms while this one runs
-        if (e == hipSuccess) (void)hipEventSynchronize(S->last);
+        // at most two sets in flight: the next one forms while this one and
+        // the one before it run; wait for the one before it
+        if (launched_before[step ^ 1]) (void)hipEventSynchronize(S->last[step ^ 1]);
         take.clear();
     }
 }
@@ -311,8 +316,10 @@ size_t request_footprint(const octmc_request* req)
 
 void destroy_server(octmc_server* S)
 {
-    if (S->bs) (void)hipStreamDestroy(S->bs);
-    if (S->last) (void)hipEventDestroy(S->last);
+    for (int q = 0; q < 2; ++q) {
+        if (S->bs[q]) (void)hipStreamDestroy(S->bs[q]);
+        if (S->last[q]) (void)hipEventDestroy(S->last[q]);
+    }
     for (Worker* W : S->workers) {
         if (W->s) (void)hipStreamDestroy(W->s);
         if (W->ready) (void)hipEventDestroy(W->ready);
@@ -363,8 +370,10 @@ int octmc_server_create(octmc_ctx* ctx, uint64_t hbm_budget_bytes, int32_t max_a
     HIP_TRY(hipMalloc(&mem, S->budget));
     S->base = static_cast<char*>(mem);
     S->arena.reset(S->budget);
-    HIP_TRY(hipStreamCreateWithFlags(&S->bs, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&S->last, hipEventDisableTiming));
+    for (int q = 0; q < 2; ++q) {
+        HIP_TRY(hipStreamCreateWithFlags(&S->bs[q], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&S->last[q], hipEventDisableTiming));
+    }
     for (int k = 0; k < max_active; ++k) {
         auto* W = new Worker();
         S->workers.push_back(W);
