@@ -18,13 +18,6 @@ namespace octmc {
 
 namespace {
 
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ __forceinline__ float uni(float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
@@ -157,19 +150,40 @@ __device__ __forceinline__ float blend(const float (&v)[16], const Stencil& s)
     return c;
 }
 
-__device__ __forceinline__ float wave_sum(float x)
+// Whole-wave lane shifts (DPP): shl1 gives lane l the value of lane l + 1,
+// shr1 that of lane l - 1; a lane whose source lies outside the wave reads 0
+// (bound control), so the shift can fold into the instruction that uses it.
+__device__ __forceinline__ float shl1(float v)
 {
-    double v = x;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return (float)v;
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float shr1(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
 }
 
-// LDS scratch of one wave: blended columns of both scans (with room for the
-// reads past lane 63) and the loss derivative (with 4 leading zeros).
-constexpr int kRingC = 72;
-constexpr int kRingG = 68;
-constexpr int kRing = 2 * kRingC + kRingG;
+// Sum over the wave: float32 within each row of 16 lanes (DPP row shifts; the
+// last lane of a row ends with the row's sum), float64 over the four rows.
+// Returns the sum in every lane.
+template <int S>
+__device__ __forceinline__ float row_shr_add(float v)
+{
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 | S, 0xF,
+                                                                     0xF, true));
+}
+__device__ __forceinline__ float wave_sum(float x)
+{
+    float v = row_shr_add<1>(x);
+    v = row_shr_add<2>(v);
+    v = row_shr_add<4>(v);
+    v = row_shr_add<8>(v);
+    const int b = __builtin_bit_cast(int, v);
+    const double s = (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 15)) +
+                     (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 31)) +
+                     (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 47)) +
+                     (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 63));
+    return (float)s;
+}
 
 // Logical block of a physical one: workgroups are dispatched to the 8 XCDs
 // round robin, so give every XCD a contiguous range of tiles (neighbouring
@@ -182,14 +196,13 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 template <typename T>
 __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
 {
-    __shared__ float ring_all[kWavesPerBlock][kRing];
-    const int wv = threadIdx.x >> 6;
+    const int wv = uni((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     int jid = -1;
     for (int q = 0; q < jobs.n; ++q)
         if (lb >= jobs.j[q].blk_begin) jid = q;
-    if (jid < 0) return;
+    if (jid < 0) return;  // whole block
     const StructJob& J = jobs.j[jid];
     const int w = J.w, h = J.h, d = J.d;
     // 2 x 2 tile of output A-scans per workgroup, one per wave.  The tile
@@ -202,10 +215,15 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     const int t = lb - J.blk_begin;
     const int band = t / (rpb * tpr), tb = t - band * (rpb * tpr);
     const int trow = band * rpb + tb % rpb;
+    if (t >= 8 * rpb * tpr || trow >= trows) return;  // whole block
     const int i = 2 * (tb / rpb) + (wv & 1);
     const int j = 2 * trow + (wv >> 1);
-    if (t >= 8 * rpb * tpr || trow >= trows || i >= w || j >= h) return;  // whole wave; no block barrier below
-    const int a = uni(j * w + i);
+    // With float32 storage the waves of a tile step through depth together
+    // (one barrier per step), so the columns they share are still in the L1
+    // cache when the others read them (measured: no gain for 16-bit
+    // storage).  A wave outside the scan only takes part in the barriers.
+    const bool active = i < w && j < h;  // wave-uniform
+    const int a = uni(active ? j * w + i : 0);
     const float* dX = J.disp + (size_t)a * 3;
     const float* dY = J.disp + ((size_t)J.na + a) * 3;
     Stencil SX, SY;
@@ -215,16 +233,6 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
     const __amdgpu_buffer_rsrc_t ry =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sy), (short)0, (int)J.vol_bytes, kRsrcWord3);
-    float* rcx = ring_all[wv];
-    float* rcy = rcx + kRingC;
-    float* rg = rcy + kRingC;
-    // padding read by the lanes that produce no output sample: zero, so that
-    // masked lanes never see uninitialised values
-    if (lane < kRingC - 64) {
-        rcx[64 + lane] = 0.f;
-        rcy[64 + lane] = 0.f;
-    }
-    if (lane < 4) rg[lane] = 0.f;
     const float eps = J.eps_h;
     const float inv_eps = 1.0f / J.eps_h;
 
@@ -235,71 +243,84 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     float lam = 0.f, gzx = 0.f, gzy = 0.f;
     const int nsteps = (d + kOutPerStep - 1) / kOutPerStep;
     for (int n = 0; n < nsteps; ++n) {
-        load_cols<T>(sx, rx, SX, n, lane, d);
-        load_cols<T>(sy, ry, SY, n, lane, d);
-        rcx[lane] = blend(sx, SX);
-        rcy[lane] = blend(sy, SY);
-        wave_sync();
-        float ix = 0.f, izx = 0.f, iy = 0.f, izy = 0.f;
+        if (active) {
+            load_cols<T>(sx, rx, SX, n, lane, d);
+            load_cols<T>(sy, ry, SY, n, lane, d);
+            // blended columns, then the depth interpolation of Eq. 2 and its
+            // depth derivative: output lane l reads source lanes l .. l + 3
+            float ix = 0.f, izx = 0.f, iy = 0.f, izy = 0.f;
+            float vx = blend(sx, SX), vy = blend(sy, SY);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float vx = rcx[lane + c];
-            const float vy = rcy[lane + c];
-            ix = fmaf(SX.wz[c], vx, ix);
-            izx = fmaf(SX.dwz[c], vx, izx);
-            iy = fmaf(SY.wz[c], vy, iy);
-            izy = fmaf(SY.dwz[c], vy, izy);
-        }
-        // residual (Eq. 2) and pseudo-Huber loss (Eq. 4) in the form
-        // eps u^2 / (sqrt(1 + u^2) + 1), u = r / eps, and its derivative u / sqrt(1 + u^2)
-        const float r = ix - iy;
-        const float u = r * inv_eps;
-        const float q = u * u;
-        const float rs = __builtin_amdgcn_rsqf(1.f + q);
-        const float sq = (1.f + q) * rs;
-        const bool valid = lane < kOutPerStep && (n * kOutPerStep + lane) < d;
-        const float L = valid ? eps * q * __builtin_amdgcn_rcpf(sq + 1.f) : 0.f;
-        const float G = valid ? u * rs : 0.f;
-        lam += L;
-        gzx += valid ? G * izx : 0.f;
-        gzy += valid ? G * izy : 0.f;
-        rg[4 + lane] = G;
-        wave_sync();
-        float hx = 0.f, hy = 0.f;
+            for (int c = 0; c < 4; ++c) {
+                ix = fmaf(SX.wz[c], vx, ix);
+                izx = fmaf(SX.dwz[c], vx, izx);
+                iy = fmaf(SY.wz[c], vy, iy);
+                izy = fmaf(SY.dwz[c], vy, izy);
+                if (c < 3) {
+                    vx = shl1(vx);
+                    vy = shl1(vy);
+                }
+            }
+            // residual (Eq. 2) and pseudo-Huber loss (Eq. 4) in the form
+            // eps u^2 / (sqrt(1 + u^2) + 1), u = r / eps, and its derivative u / sqrt(1 + u^2)
+            const float r = ix - iy;
+            const float u = r * inv_eps;
+            const float q = u * u;
+            const float rs = __builtin_amdgcn_rsqf(1.f + q);
+            const float sq = (1.f + q) * rs;
+            const bool valid = lane < kOutPerStep && (n * kOutPerStep + lane) < d;
+            const float L = valid ? eps * q * __builtin_amdgcn_rcpf(sq + 1.f) : 0.f;
+            const float G = valid ? u * rs : 0.f;
+            lam += L;
+            gzx += valid ? G * izx : 0.f;
+            gzy += valid ? G * izy : 0.f;
+            // adjoint of the depth interpolation: source lane l collects the
+            // derivatives of output lanes l - 3 .. l (invalid lanes carry 0)
+            float hx = 0.f, hy = 0.f, g = G;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float g = rg[4 + lane - c];
-            hx = fmaf(SX.wz[c], g, hx);
-            hy = fmaf(SY.wz[c], g, hy);
-        }
+            for (int c = 0; c < 4; ++c) {
+                hx = fmaf(SX.wz[c], g, hx);
+                hy = fmaf(SY.wz[c], g, hy);
+                if (c < 3) g = shr1(g);
+            }
 #pragma unroll
-        for (int q2 = 0; q2 < 16; ++q2) {
-            PX[q2] = fmaf(sx[q2], hx, PX[q2]);
-            PY[q2] = fmaf(sy[q2], hy, PY[q2]);
+            for (int q2 = 0; q2 < 16; ++q2) {
+                PX[q2] = fmaf(sx[q2], hx, PX[q2]);
+                PY[q2] = fmaf(sy[q2], hy, PY[q2]);
+            }
         }
-        wave_sync();
+        if constexpr (esize<T>::v == 4) __builtin_amdgcn_s_barrier();
     }
-    // Gamma_x = sum_ab dwx_a wy_b P_ab, Gamma_y = sum_ab wx_a dwy_b P_ab
+    if (!active) return;
+    // Gamma_x = sum_b wy_b sum_a dwx_a P_ab, Gamma_y = sum_b dwy_b sum_a wx_a P_ab
     float wx[4], dwx[4], wy[4], dwy[4];
     float gxx = 0.f, gyx = 0.f, gxy = 0.f, gyy = 0.f;
     cr_taps(SX.tx, wx, dwx);
     cr_taps(SX.ty, wy, dwy);
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 4; ++b) {
+        float rv = 0.f, rd = 0.f;
 #pragma unroll
         for (int a2 = 0; a2 < 4; ++a2) {
-            gxx = fmaf(dwx[a2] * wy[b], PX[b * 4 + a2], gxx);
-            gyx = fmaf(wx[a2] * dwy[b], PX[b * 4 + a2], gyx);
+            rv = fmaf(wx[a2], PX[b * 4 + a2], rv);
+            rd = fmaf(dwx[a2], PX[b * 4 + a2], rd);
         }
+        gxx = fmaf(wy[b], rd, gxx);
+        gyx = fmaf(dwy[b], rv, gyx);
+    }
     cr_taps(SY.tx, wx, dwx);
     cr_taps(SY.ty, wy, dwy);
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 4; ++b) {
+        float rv = 0.f, rd = 0.f;
 #pragma unroll
         for (int a2 = 0; a2 < 4; ++a2) {
-            gxy = fmaf(dwx[a2] * wy[b], PY[b * 4 + a2], gxy);
-            gyy = fmaf(wx[a2] * dwy[b], PY[b * 4 + a2], gyy);
+            rv = fmaf(wx[a2], PY[b * 4 + a2], rv);
+            rd = fmaf(dwx[a2], PY[b * 4 + a2], rd);
         }
+        gxy = fmaf(wy[b], rd, gxy);
+        gyy = fmaf(dwy[b], rv, gyy);
+    }
     lam = wave_sum(lam);
     gxx = wave_sum(gxx);
     gyx = wave_sum(gyx);
