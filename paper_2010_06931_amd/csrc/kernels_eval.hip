@@ -8,8 +8,11 @@
 //             to the A-scan's displacement
 //   k_combine per output A-scan: en face residual (Eq. 7), resampled
 //             validity (Eq. 5), weight delta (Eq. 8), combination with eta
-//             (Eq. 9), scan-order regulariser, mean term, gradient; and the
-//             float64 global sums in a fixed order
+//             (Eq. 9), scan-order regulariser, mean term, gradient; float64
+//             block partials
+//   k_finalize the float64 global sums in a fixed order (one block per job;
+//             a kernel boundary, not a device-scope fence per block, makes
+//             the partials visible)
 #include <hip/hip_runtime.h>
 
 #include "octmc_internal.h"
@@ -355,20 +358,9 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[N], double* blk_r
     if ((int)threadIdx.x < N) blk_row[threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// After every block of a job has stored its row, the last one to finish sums
-// the rows in a fixed order (strided per thread, then a fixed tree).
-template <int N>
-__device__ __forceinline__ bool last_block(unsigned* counter, int nblk)
-{
-    __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = (atomicAdd(counter, 1u) == (unsigned)(nblk - 1));
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last;
-}
-
+// Fixed-order sum of the rows of block partials (strided per thread, then a
+// fixed tree); every thread of the block receives the result, and every block
+// that sums the same rows gets the same bits.
 template <int N>
 __device__ __forceinline__ void sum_rows(const double* blk, int nblk, double (&out)[N])
 {
@@ -419,12 +411,6 @@ __global__ __launch_bounds__(kRedBlock) void k_sum(const SumJobs jobs)
         v[2] += (double)J.disp[(size_t)q * 3 + 2];
     }
     block_reduce_store<4>(v, J.blk + (size_t)b * 4);
-    if (last_block<4>(J.counter, J.nblk)) {
-        double s[4];
-        sum_rows<4>(J.blk, J.nblk, s);
-        if (threadIdx.x < 3) J.out[threadIdx.x] = s[threadIdx.x];
-        if (threadIdx.x == 0) *J.counter = 0u;
-    }
 }
 
 // pseudo-Huber in float64 (regulariser and en face terms)
@@ -522,6 +508,9 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
     const CombineJob& J = jobs.j[jid];
     const int b = blockIdx.x - J.blk_begin;
     const int a = b * kRedBlock + threadIdx.x;
+    // sum of all displacements (mean term), from the partials of k_sum
+    double sumd[4] = {0, 0, 0, 0};
+    if (J.mode == 1) sum_rows<4>(J.sum_blk, J.nsum, sumd);  // block-uniform
     // partial sums: data, str, ang, reg, (unused), str05, ang05, g.p
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (a < J.na) {
@@ -589,7 +578,7 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
             // mean-displacement term: dM/dd_c = gamma d sum_c / N_A
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double gm = J.gamma * dd * J.sumd[c] / (double)na;
+                const double gm = J.gamma * dd * sumd[c] / (double)na;
                 g[c] += gm;
                 g[3 + c] += gm;
             }
@@ -622,32 +611,38 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
         }
     }
     block_reduce_store<8>(v, J.blk + (size_t)b * 8);
-    if (last_block<8>(J.counter, J.nblk)) {
-        double s[8];
-        sum_rows<8>(J.blk, J.nblk, s);
-        if (threadIdx.x == 0) {
-            if (J.mode == 0) {
-                // Eq. 10; eta = 1 where a term vanishes (identical inputs)
-                *J.eta = (s[5] > 1e-300 && s[6] > 1e-300) ? sqrt(s[6] / s[5]) : 1.0;
-            } else {
-                const double eta = *J.eta;
-                double m = 0.0;
-                for (int c = 0; c < 3; ++c) m += J.sumd[c] * J.sumd[c];
-                m *= J.gamma * (double)J.d / (2.0 * (double)J.na);
-                double* t = J.terms;
-                t[OCTMC_TERM_DATA] = s[0];
-                t[OCTMC_TERM_STR] = s[1];
-                t[OCTMC_TERM_ANG] = s[2];
-                t[OCTMC_TERM_REG] = s[3];
-                t[OCTMC_TERM_MEAN] = m;
-                t[OCTMC_TERM_STR05] = s[5];
-                t[OCTMC_TERM_ANG05] = s[6];
-                t[OCTMC_TERM_ETA] = eta;
-                t[OCTMC_TERM_GP] = s[7];
-                t[OCTMC_TERM_F] = s[0] + J.alpha * s[3] + m;
-            }
-            *J.counter = 0u;
-        }
+}
+
+// Final sums of one evaluation per job (one block each), after k_combine:
+// the objective terms (mode 1) or the level's eta (mode 0, Eq. 10).
+__global__ __launch_bounds__(kRedBlock) void k_finalize(const CombineJobs jobs)
+{
+    const CombineJob& J = jobs.j[blockIdx.x];
+    double s[8];
+    sum_rows<8>(J.blk, J.nblk, s);
+    if (J.mode == 0) {
+        // eta = 1 where a term vanishes (identical inputs)
+        if (threadIdx.x == 0) *J.eta = (s[5] > 1e-300 && s[6] > 1e-300) ? sqrt(s[6] / s[5]) : 1.0;
+        return;
+    }
+    double sumd[4];
+    sum_rows<4>(J.sum_blk, J.nsum, sumd);
+    if (threadIdx.x == 0) {
+        const double eta = *J.eta;
+        double m = 0.0;
+        for (int c = 0; c < 3; ++c) m += sumd[c] * sumd[c];
+        m *= J.gamma * (double)J.d / (2.0 * (double)J.na);
+        double* t = J.terms;
+        t[OCTMC_TERM_DATA] = s[0];
+        t[OCTMC_TERM_STR] = s[1];
+        t[OCTMC_TERM_ANG] = s[2];
+        t[OCTMC_TERM_REG] = s[3];
+        t[OCTMC_TERM_MEAN] = m;
+        t[OCTMC_TERM_STR05] = s[5];
+        t[OCTMC_TERM_ANG05] = s[6];
+        t[OCTMC_TERM_ETA] = eta;
+        t[OCTMC_TERM_GP] = s[7];
+        t[OCTMC_TERM_F] = s[0] + J.alpha * s[3] + m;
     }
 }
 
@@ -680,6 +675,7 @@ hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype d
 hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s)
 {
     hipLaunchKernelGGL(k_combine, dim3(total_blocks), dim3(kRedBlock), 0, s, jobs);
+    hipLaunchKernelGGL(k_finalize, dim3(jobs.n), dim3(kRedBlock), 0, s, jobs);
     return hipGetLastError();
 }
 

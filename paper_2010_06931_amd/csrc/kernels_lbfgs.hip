@@ -1,7 +1,7 @@
 // Vector kernels of the L-BFGS solve (float64 state on the device).
 //
 //   k_multidot  several dot products (and one max |.|) in one pass, block
-//               partials summed by the last block in a fixed order
+//               partials; k_multidot_final sums them in a fixed order
 //   k_lincomb   out = sum_q c_q v_q (search direction from the compact
 //               representation of the L-BFGS matrix)
 //   k_trial     x_t = x + alpha p, also as float32 for the evaluation
@@ -16,8 +16,7 @@ namespace {
 constexpr int kB = 256;
 constexpr int kMaxBlocks = 512;
 
-__global__ __launch_bounds__(kB) void k_multidot(const DotSpec spec, size_t n, double* __restrict__ blk,
-                                                 unsigned* counter, double* __restrict__ out)
+__global__ __launch_bounds__(kB) void k_multidot(const DotSpec spec, size_t n, double* __restrict__ blk)
 {
     const int nd = spec.ndots;
     double acc[kMaxDots];
@@ -49,23 +48,20 @@ __global__ __launch_bounds__(kB) void k_multidot(const DotSpec spec, size_t n, d
         if (threadIdx.x == 0) blk[(size_t)blockIdx.x * (kMaxDots + 1) + q] = sh[0];
         __syncthreads();
     }
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // fixed-order final sum: thread q sums column q over the blocks in order
+}
+
+// fixed-order final sum: thread q sums column q over the blocks in order
+__global__ __launch_bounds__(kB) void k_multidot_final(int nrow, int gmax_row, int nblk,
+                                                       const double* __restrict__ blk, double* __restrict__ out)
+{
     for (int q = threadIdx.x; q < nrow; q += kB) {
         double s = 0.0;
-        for (unsigned b = 0; b < gridDim.x; ++b) {
+        for (int b = 0; b < nblk; ++b) {
             const double v = blk[(size_t)b * (kMaxDots + 1) + q];
-            s = (q == nd) ? fmax(s, v) : s + v;
+            s = (q == gmax_row) ? fmax(s, v) : s + v;
         }
         out[q] = s;
     }
-    if (threadIdx.x == 0) *counter = 0u;
 }
 
 __global__ void k_lincomb(const CombSpec spec, size_t n, double* __restrict__ out)
@@ -127,11 +123,12 @@ inline int grid_for(size_t n, int cap = 4096)
 
 }  // namespace
 
-hipError_t launch_multidot(const DotSpec& spec, size_t n, double* blk, unsigned* counter, double* out,
-                           hipStream_t s)
+hipError_t launch_multidot(const DotSpec& spec, size_t n, double* blk, double* out, hipStream_t s)
 {
     if (spec.ndots > kMaxDots) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_multidot, dim3(grid_for(n, kMaxBlocks)), dim3(kB), 0, s, spec, n, blk, counter, out);
+    const int nb = grid_for(n, kMaxBlocks);
+    hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(kB), 0, s, spec, n, blk);
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(kB), 0, s, spec.ndots + 1, spec.ndots, nb, blk, out);
     return hipGetLastError();
 }
 hipError_t launch_lincomb(const CombSpec& spec, size_t n, double* out, hipStream_t s)

@@ -111,12 +111,11 @@ struct StructJobs {
     int n;
 };
 
-// Hot path, step 0: sum of the displacements (for the mean term M).
+// Hot path, step 0: sum of the displacements (for the mean term M), as one
+// row of block partials per block (summed in a fixed order by its readers).
 struct SumJob {
     const float* disp;  // [2][na][3]
     double* blk;        // [nblk][4] block partials
-    unsigned* counter;  // last-block counter (0 between launches)
-    double* out;        // [3]
     int na, blk_begin, nblk;
 };
 struct SumJobs {
@@ -135,13 +134,12 @@ struct CombineJob {
     const float* ay;
     const float* vx;     // validity [h]
     const float* vy;     // validity [w]
-    const double* sumd;  // [3]
+    const double* sum_blk;  // [nsum][4] displacement-sum partials of step 0
     double* eta;         // level constant (read in mode 1, written in mode 0)
     const double* p;     // [2][na][3] search direction (float64) or nullptr
-    double* blk;         // [nblk][8]
-    unsigned* counter;
+    double* blk;         // [nblk][8] block partials
     double* terms;       // [OCTMC_NTERMS] (mode 1)
-    int w, h, d, na, blk_begin, nblk;
+    int w, h, d, na, blk_begin, nblk, nsum;
     int mode;            // 0: only set eta (Eq. 10); 1: full evaluation
     double delta0, eps_h, eps_r, alpha, gamma, wfb;
 };
@@ -154,6 +152,8 @@ struct CombineJobs {
 // launchers (kernels_eval.hip)
 hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s);
 hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s);
+// per-A-scan combination (total_blocks) followed by the fixed-order final
+// sums, one block per job
 hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s);
 
 // preparation (kernels_prep.hip)
@@ -175,8 +175,9 @@ struct DotSpec {
     int ndots;
     int gmax_vec;  // index of the vector whose max |.| is also reduced (-1: none)
 };
-hipError_t launch_multidot(const DotSpec& spec, size_t n, double* blk, unsigned* counter, double* out,
-                           hipStream_t s);
+// dot products (and the max |.|) in one pass: block partials, then a
+// fixed-order sum of the partials in a second launch
+hipError_t launch_multidot(const DotSpec& spec, size_t n, double* blk, double* out, hipStream_t s);
 constexpr int kMaxComb = 20;
 struct CombSpec {
     const double* v[kMaxComb];

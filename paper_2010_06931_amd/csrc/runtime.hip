@@ -71,8 +71,7 @@ struct octmc_pair {
     // evaluation scratch, sized for the finest level
     float* part = nullptr;      // [na0][8]
     double* sum_blk = nullptr;  // [256][4]
-    unsigned* counters = nullptr;  // [0] sum, [1] combine, [2] multidot
-    double* sumd = nullptr;     // [3]
+    unsigned* counters = nullptr;  // [8] non-finite input count
     double* comb_blk = nullptr; // [nblk0][8]
     double* eta = nullptr;      // [levels]
     double* terms = nullptr;    // [OCTMC_NTERMS] solver scratch
@@ -133,7 +132,7 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev)
         const octmc_params& pr = P->params;
         if (P->dtype != dt) return fail(OCTMC_E_DTYPE, "batched pairs must share the storage type");
         const int nsum = std::min(kSumBlocks, (2 * L.na + kRedBlock - 1) / kRedBlock);
-        sj.j[q] = SumJob{ea[q].disp, P->sum_blk, P->counters + 0, P->sumd, L.na, sb, nsum};
+        sj.j[q] = SumJob{ea[q].disp, P->sum_blk, L.na, sb, nsum};
         sb += nsum;
         tj.j[q] = StructJob{L.sx, L.sy, ea[q].disp, P->part, L.w, L.h, L.d, L.na, tb, L.vol_bytes,
                             (float)pr.eps_huber};
@@ -151,11 +150,11 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev)
         c.ay = L.ay;
         c.vx = L.vx;
         c.vy = L.vy;
-        c.sumd = P->sumd;
+        c.sum_blk = P->sum_blk;
+        c.nsum = nsum;
         c.eta = P->eta + level;
         c.p = ea[q].p;
         c.blk = P->comb_blk;
-        c.counter = P->counters + 1;
         c.terms = ea[q].terms;
         c.w = L.w;
         c.h = L.h;
@@ -385,7 +384,7 @@ struct LevelRun {
             }
             ds.ndots = nd;
             ds.gmax_vec = vg;
-            HIP_TRY(launch_multidot(ds, n, P->dot_blk, P->counters + 2, P->dot_out, s));
+            HIP_TRY(launch_multidot(ds, n, P->dot_blk, P->dot_out, s));
             HIP_TRY(hipMemcpyAsync(h_dots, P->dot_out, sizeof(double) * (kMaxDots + 1), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             const double gg = h_dots[i_gg], gmax = h_dots[nd];
@@ -584,7 +583,7 @@ size_t octmc::pair_footprint(const octmc_params& pr, const octmc_shape& sh, bool
             ld = d2;
         }
     }
-    t += slab_bytes(na * 8 * 4) + slab_bytes(kSumBlocks * 4 * 8) + slab_bytes(4 * 8) +
+    t += slab_bytes(na * 8 * 4) + slab_bytes(kSumBlocks * 4 * 8) +
          slab_bytes((size_t)nblk_combine((int)na) * 8 * 8) + slab_bytes(OCTMC_MAX_LEVELS * 8) +
          slab_bytes(OCTMC_NTERMS * 8) + slab_bytes((size_t)512 * (kMaxDots + 1) * 8) +
          slab_bytes((kMaxDots + 1) * 8);
@@ -806,7 +805,6 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
     // evaluation scratch
     HIP_TRY(P->alloc(&P->part, na * 8 * 4));
     HIP_TRY(P->alloc(&P->sum_blk, kSumBlocks * 4 * 8));
-    HIP_TRY(P->alloc(&P->sumd, 4 * 8));
     HIP_TRY(P->alloc(&P->comb_blk, (size_t)nblk_combine((int)na) * 8 * 8));
     HIP_TRY(P->alloc(&P->eta, OCTMC_MAX_LEVELS * 8));
     HIP_TRY(P->alloc(&P->terms, OCTMC_NTERMS * 8));
