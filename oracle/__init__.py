@@ -104,6 +104,8 @@ def lib():
         L.orc_merge.argtypes = [dp] * 6 + [C.c_int] * 3 + [dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_enface_mean.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
         L.orc_substitute_invalid.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_int]
+        L.orc_validity.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
+        L.orc_validity.restype = None
         L.orc_round_storage.argtypes = [dp, C.c_size_t, C.c_int]
         L.orc_round_storage.restype = None
         _lib = L
@@ -361,3 +363,13 @@ def round_storage(v, store: int):
     v = _f64(v).copy()
     lib().orc_round_storage(_p(v), v.size, int(store))
     return v
+
+
+def validity(vol, V: int):
+    """Input validity of one OCTA volume [h][w][d] (Sec. 2.2): one value per
+    B-scan (rows j for V = 0, columns i for V = 1)."""
+    vol = _f64(vol)
+    h, w, d = vol.shape
+    out = np.zeros(h if V == 0 else w)
+    lib().orc_validity(_p(vol), w, h, d, int(V), _p(out))
+    return out

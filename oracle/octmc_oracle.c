@@ -985,3 +985,48 @@ EXPORT void orc_substitute_invalid(double* vol, int w, int h, int d, const doubl
     }
     free(src);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Input validity of one OCTA volume (Sec. 2.2, "input validity").  A
+ * saccade saturates the decorrelation of a whole B-scan; such B-scans are
+ * found from their mean decorrelation and excluded together with two
+ * neighbours on each side:
+ *   m_b   mean of the OCTA volume over B-scan b (every A-scan and sample);
+ *   flag  m_b > mu + 3 sigma, with mu and sigma the mean and standard
+ *         deviation of m over all B-scans of the volume.  Reading: the
+ *         population standard deviation (divisor = number of B-scans);
+ *   v_b   1 if none of the B-scans b-2 .. b+2 (those inside the volume) is
+ *         flagged, else 0.
+ * B-scans of the X-fast scan are the rows j of the common-frame volume
+ * [h][w][d] (nb = h); those of the Y-fast scan are the columns i (nb = w).
+ * v receives nb values. */
+EXPORT void orc_validity(const double* vol, int w, int h, int d, int V, double* v)
+{
+    const int nb = (V == 0) ? h : w;
+    const int na = (V == 0) ? w : h; /* A-scans per B-scan */
+    double* m = (double*)malloc(nb * sizeof(double));
+    int* flag = (int*)malloc(nb * sizeof(int));
+    for (int b = 0; b < nb; b++) {
+        double s = 0.0;
+        for (int o = 0; o < na; o++) {
+            const size_t a = (V == 0) ? ((size_t)b * w + o) : ((size_t)o * w + b);
+            for (int k = 0; k < d; k++) s += vol[a * d + k];
+        }
+        m[b] = s / ((double)na * d);
+    }
+    double mu = 0.0;
+    for (int b = 0; b < nb; b++) mu += m[b];
+    mu /= nb;
+    double var = 0.0;
+    for (int b = 0; b < nb; b++) var += (m[b] - mu) * (m[b] - mu);
+    const double sigma = sqrt(var / nb);
+    for (int b = 0; b < nb; b++) flag[b] = m[b] > mu + 3.0 * sigma;
+    for (int b = 0; b < nb; b++) {
+        int bad = 0;
+        for (int q = b - 2; q <= b + 2; q++)
+            if (q >= 0 && q < nb && flag[q]) bad = 1;
+        v[b] = bad ? 0.0 : 1.0;
+    }
+    free(m);
+    free(flag);
+}

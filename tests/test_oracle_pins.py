@@ -563,3 +563,54 @@ def test_round_storage_matches_library_conversions(orc):
     refbf = torch.from_numpy(x).to(torch.bfloat16).double().numpy()
     assert np.array_equal(gotbf, refbf)
     assert orc.round_storage(np.array([halfway]), 1)[0] == 1.0  # tie to even
+
+
+def test_validity_hand_example(orc):
+    """Sec. 2.2 input validity on a hand-worked case: 20 B-scans, 19 with mean
+    decorrelation 0.1 and B-scan 7 with 1.0.  Mean 0.145, population standard
+    deviation sqrt(0.038475) = 0.19615, threshold 0.7335: only B-scan 7 is
+    flagged, and B-scans 5..9 are invalid."""
+    rng = np.random.default_rng(3)
+    h, w, d = 20, 6, 8
+    vol = np.full((h, w, d), 0.1)
+    # rows with the same mean but varying content
+    noise = rng.uniform(-0.05, 0.05, (h, w, d))
+    noise -= noise.mean(axis=(1, 2), keepdims=True)
+    vol += noise
+    vol[7] = 1.0
+    v = orc.validity(vol, 0)
+    expect = np.ones(h)
+    expect[5:10] = 0.0
+    assert np.array_equal(v, expect)
+    # the Y-fast scan's B-scans are columns: the transposed volume gives the same
+    assert np.array_equal(orc.validity(np.ascontiguousarray(vol.transpose(1, 0, 2)), 1), expect)
+
+
+def test_validity_borders_and_constant(orc):
+    h, w, d = 16, 4, 4
+    vol = np.full((h, w, d), 0.2)
+    assert np.array_equal(orc.validity(vol, 0), np.ones(h))  # sigma = 0: nothing above the mean
+    vol[0] = 3.0
+    vol[15] = 3.0
+    v = orc.validity(vol, 0)
+    # mean 0.55, sigma sqrt(0.8575) = 0.9260: threshold 3.328 > 3.0, so two outliers in 16 hide each other
+    assert np.array_equal(v, np.ones(h))
+    vol = np.full((40, w, d), 0.2)
+    vol[0] = 3.0
+    vol[39] = 3.0
+    v = orc.validity(vol, 0)
+    # 40 B-scans: mean 0.34, sigma sqrt(0.3724) = 0.6102, threshold 2.171: both flagged
+    expect = np.ones(40)
+    expect[:3] = 0.0
+    expect[37:] = 0.0
+    assert np.array_equal(v, expect)
+
+
+def test_validity_recovers_synthetic_white_lines(orc):
+    """The generator saturates the OCTA B-scan of every saccade and marks it and
+    its two neighbours on each side invalid; the detection finds exactly those."""
+    for p in range(3):
+        pair = synth.make_pair("tiny", p, white_lines=True)
+        assert (pair.vx == 0).any() or (pair.vy == 0).any()
+        assert np.array_equal(orc.validity(pair.ox, 0), pair.vx.numpy())
+        assert np.array_equal(orc.validity(pair.oy, 1), pair.vy.numpy())
