@@ -65,7 +65,9 @@ typedef enum { OCTMC_F32 = 0, OCTMC_BF16 = 1, OCTMC_F16 = 2 } octmc_dtype;
 typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
 
 /* flags */
-#define OCTMC_CHECK_NAN 0x1u /* scan the inputs for NaN/Inf at pair creation */
+#define OCTMC_CHECK_NAN 0x1u      /* scan the inputs for NaN/Inf at pair creation */
+#define OCTMC_DETECT_INVALID 0x2u /* derive the B-scan validity from the OCTA volumes (Sec. 2.2) when
+                                     octmc_pair_create gets OCTA volumes and no validity vectors */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
  * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
@@ -84,7 +86,7 @@ typedef struct {
     double c1, c2;       /* strong Wolfe constants                                [R: 1e-4, 0.9] */
     double merge_kappa;  /* density weight decay exp(-kappa (rho - 1))            [R: 1.0]  */
     double merge_tau;    /* weights below tau are clipped to 0                    [R: 0.05] */
-    uint32_t flags;      /* OCTMC_CHECK_NAN */
+    uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID */
 } octmc_params;
 
 typedef struct {
@@ -146,8 +148,11 @@ OCTMC_API int octmc_destroy(octmc_ctx* ctx);
  *                      given, and invalid B-scans are replaced by their
  *                      nearest valid neighbour for the OCTA merge (Sec. 2.5);
  *   enface_x, enface_y en face OCTA images [h][w] float32, or NULL;
- *   valid_x[h], valid_y[w] B-scan validity (Sec. 2.2, 1 = valid), or NULL for
- *                      all valid.  X-fast B-scans are rows, Y-fast columns.
+ *   valid_x[h], valid_y[w] B-scan validity (Sec. 2.2, 1 = valid), or NULL:
+ *                      all valid, or with OCTMC_DETECT_INVALID and OCTA
+ *                      volumes, derived from them as by
+ *                      octmc_validity_from_octa.  X-fast B-scans are rows,
+ *                      Y-fast columns.
  * Either both OCTA volumes or both en face images must be given.  All input
  * pointers live in shape->mem memory.  The library copies every input into
  * its own device memory; the caller may free them once the call returns.
@@ -159,6 +164,21 @@ OCTMC_API int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, cons
                       const float* enface_x, const float* enface_y, const float* valid_x,
                       const float* valid_y, void* stream, octmc_pair** out);
 OCTMC_API int octmc_pair_destroy(octmc_pair* pair);
+
+/* Input validity of one OCTA volume (Sec. 2.2): saccades saturate the
+ * decorrelation of whole B-scans.  With m_b the mean of the volume over
+ * B-scan b, and mu, sigma the mean and population standard deviation of m
+ * over all B-scans, B-scan b is flagged if m_b > mu + 3 sigma; valid_out[b]
+ * is 1 if none of the B-scans b-2 .. b+2 is flagged, else 0.
+ *   shape      w, h, d of the volume and where `octa` lives (shape->mem);
+ *              shape->dtype is ignored (the volume is float32);
+ *   octa       [h][w][d] float32 in the common frame;
+ *   scan       0: X-fast (B-scans are rows j, nb = h), 1: Y-fast (columns i, nb = w);
+ *   valid_out  device float32[nb].
+ * Synchronises `stream`.  Errors: OCTMC_E_INVALID, OCTMC_E_SHAPE (volume >
+ * 2^31 bytes), OCTMC_E_OOM, OCTMC_E_DEVICE. */
+OCTMC_API int octmc_validity_from_octa(octmc_ctx* ctx, const octmc_shape* shape, const float* octa, int32_t scan,
+                                       float* valid_out, void* stream);
 
 /* Shape (w, h, d) of pyramid level `level` (0 = finest). */
 OCTMC_API int octmc_pair_level_shape(const octmc_pair* pair, int32_t level, int32_t* w, int32_t* h, int32_t* d);

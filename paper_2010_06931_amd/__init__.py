@@ -21,6 +21,7 @@ F32, BF16, F16 = 0, 1, 2
 _DTYPES = {"f32": F32, "float32": F32, "bf16": BF16, "bfloat16": BF16, "f16": F16, "float16": F16}
 MEM_HOST, MEM_DEVICE = 0, 1
 CHECK_NAN = 0x1
+DETECT_INVALID = 0x2
 MAX_LEVELS = 8
 
 TERM_F, TERM_DATA, TERM_STR, TERM_ANG, TERM_REG, TERM_MEAN, TERM_STR05, TERM_ANG05, TERM_ETA, TERM_GP = range(10)
@@ -32,7 +33,8 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_DTYPE", -4: "E_OOM", -
 
 # exported symbols of include/octmc.h (checked by the CPU test suite)
 SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_create", "octmc_destroy",
-           "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_eval",
+           "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_validity_from_octa",
+           "octmc_eval",
            "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge",
            "octmc_request_footprint", "octmc_server_create", "octmc_server_submit", "octmc_server_poll",
            "octmc_server_status", "octmc_server_destroy")
@@ -109,6 +111,7 @@ def lib():
         L.octmc_pair_create.argtypes = [vp, C.POINTER(Params), C.POINTER(Shape)] + [vp] * 8 + [vp, C.POINTER(vp)]
         L.octmc_pair_destroy.argtypes = [vp]
         L.octmc_pair_level_shape.argtypes = [vp, C.c_int32] + [C.POINTER(C.c_int32)] * 3
+        L.octmc_validity_from_octa.argtypes = [vp, C.POINTER(Shape), vp, C.c_int32, vp, vp]
         L.octmc_eval.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.octmc_eval_profile.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), vp]
         L.octmc_eval_batched.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
@@ -203,12 +206,15 @@ class Pair:
     the library copies them."""
 
     def __init__(self, sx, sy, *, ox=None, oy=None, ax=None, ay=None, vx=None, vy=None, params: Params | None = None,
-                 dtype: str = "f32", ctx: Context | None = None, stream=None, **param_overrides):
+                 dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,
+                 **param_overrides):
         self.ctx = ctx or context(0)
         dev = torch.device("cuda", self.ctx.device)
         self.params = params if params is not None else default_params()
         for k, v in param_overrides.items():
             setattr(self.params, k, v)
+        if detect_invalid:  # validity from the OCTA volumes (Sec. 2.2) when vx, vy are not given
+            self.params.flags |= DETECT_INVALID
         sx, sy = _f32(sx, dev), _f32(sy, dev)
         h, w, d = sx.shape
         if sy.shape != sx.shape:
@@ -287,6 +293,20 @@ class Pair:
             self.close()
         except Exception:  # noqa: BLE001 - interpreter shutdown
             pass
+
+
+def validity_from_octa(vol: torch.Tensor, scan: int, *, ctx: Context | None = None, stream=None) -> torch.Tensor:
+    """Input validity of one OCTA volume [h][w][d] (Sec. 2.2): one 0/1 value per
+    B-scan, rows j for the X-fast scan (scan 0), columns i for the Y-fast scan
+    (scan 1)."""
+    ctx = ctx or context(0)
+    dev = torch.device("cuda", ctx.device)
+    vol = _f32(vol, dev)
+    h, w, d = vol.shape
+    out = torch.empty(h if scan == 0 else w, dtype=torch.float32, device=dev)
+    shape = Shape(w, h, d, F32, MEM_DEVICE)
+    _check(lib().octmc_validity_from_octa(ctx._h, C.byref(shape), _ptr(vol), int(scan), _ptr(out), _stream(stream)))
+    return out
 
 
 def eval_batched(pairs, level: int, disp: torch.Tensor, *, grad: bool = True, eta_mode: int = 1, stream=None):

@@ -146,7 +146,75 @@ inline int grid_for(size_t n, int block = 256, int cap = 65536)
     return g < 1 ? 1 : (int)g;
 }
 
+// Input validity of an OCTA volume (Sec. 2.2).  Step 1: mean decorrelation
+// of every B-scan (one block per B-scan, float64, fixed-order sum): rows j
+// of the X-fast scan (V = 0), columns i of the Y-fast scan (V = 1).
+constexpr int kVB = 256;
+
+__device__ __forceinline__ double block_sum_d(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kVB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kVB) void k_bscan_mean(const float* __restrict__ vol, int w, int h, int d, int V,
+                                                    double* __restrict__ m)
+{
+    __shared__ double sh[kVB];
+    const int b = blockIdx.x;
+    const int na = V == 0 ? w : h;
+    double s = 0.0;
+    if (V == 0) {  // one contiguous run of w * d samples
+        const float* p = vol + (size_t)b * w * d;
+        const size_t n = (size_t)w * d;
+        for (size_t q = threadIdx.x; q < n; q += kVB) s += (double)p[q];
+    } else {  // h A-scans of d samples, w * d apart
+        for (int o = 0; o < h; ++o) {
+            const float* p = vol + ((size_t)o * w + b) * d;
+            for (int k = threadIdx.x; k < d; k += kVB) s += (double)p[k];
+        }
+    }
+    s = block_sum_d(s, sh);
+    if (threadIdx.x == 0) m[b] = s / ((double)na * (double)d);
+}
+
+// Step 2 (one block): mean mu and population standard deviation sigma of the
+// B-scan means; B-scan b is flagged if m_b > mu + 3 sigma, and valid (1) if
+// none of b - 2 .. b + 2 is flagged.
+__global__ __launch_bounds__(kVB) void k_validity(const double* __restrict__ m, int nb, float* __restrict__ v)
+{
+    __shared__ double sh[kVB];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kVB) s += m[b];
+    const double mu = block_sum_d(s, sh) / nb;
+    double q = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kVB) q += (m[b] - mu) * (m[b] - mu);
+    const double thr = mu + 3.0 * sqrt(block_sum_d(q, sh) / nb);
+    for (int b = threadIdx.x; b < nb; b += kVB) {
+        bool bad = false;
+        for (int o = b - 2; o <= b + 2; ++o)
+            if (o >= 0 && o < nb && m[o] > thr) bad = true;
+        v[b] = bad ? 0.f : 1.f;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_validity(const float* vol, int w, int h, int d, int V, double* means, float* valid,
+                           hipStream_t s)
+{
+    const int nb = V == 0 ? h : w;
+    hipLaunchKernelGGL(k_bscan_mean, dim3(nb), dim3(kVB), 0, s, vol, w, h, d, V, means);
+    hipLaunchKernelGGL(k_validity, dim3(1), dim3(kVB), 0, s, means, nb, valid);
+    return hipGetLastError();
+}
 
 hipError_t launch_to_storage(const float* in, void* out, size_t n, octmc_dtype dt, hipStream_t s)
 {

@@ -165,6 +165,10 @@ hipError_t launch_enface_mean(const float* vol, int na, int d, float* out, hipSt
 hipError_t launch_count_nonfinite(const float* v, size_t n, unsigned* counter, hipStream_t s);
 hipError_t launch_copy_bscans(float* vol, int w, int h, int d, const int* src, int V, hipStream_t s);
 hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf, hipStream_t s);
+// input validity of one OCTA volume (Sec. 2.2): means[nb] float64 scratch,
+// valid[nb] float32 output, nb = h (V = 0) or w (V = 1)
+hipError_t launch_validity(const float* vol, int w, int h, int d, int V, double* means, float* valid,
+                           hipStream_t s);
 
 // L-BFGS vector kernels (kernels_lbfgs.hip)
 constexpr int kMaxDotVecs = 16;

@@ -532,6 +532,7 @@ int octmc::validate_params(const octmc_params* p)
     if (p->lbfgs_m < 1 || p->lbfgs_m > 8) return fail(OCTMC_E_INVALID, "lbfgs_m must lie in [1, 8]");
     if (p->ls_max_evals < 1) return fail(OCTMC_E_INVALID, "ls_max_evals must be >= 1");
     if (!(p->c1 > 0 && p->c1 < p->c2 && p->c2 < 1)) return fail(OCTMC_E_INVALID, "need 0 < c1 < c2 < 1");
+    if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID)) return fail(OCTMC_E_INVALID, "unknown flags");
     return OCTMC_OK;
 }
 
@@ -567,8 +568,10 @@ size_t octmc::pair_footprint(const octmc_params& pr, const octmc_shape& sh, bool
     t += slab_bytes(64);          // counters
     t += 2 * slab_bytes(na * 4);  // en face
     if (have_octa) {
+        const bool detect = !have_valid && (pr.flags & OCTMC_DETECT_INVALID);
         t += 2 * slab_bytes(nv * 4);
-        if (have_valid) t += slab_bytes(h * 4) + slab_bytes(w * 4);  // substitution tables
+        if (have_valid || detect) t += slab_bytes(h * 4) + slab_bytes(w * 4);  // substitution tables
+        if (detect) t += slab_bytes(h * 8) + slab_bytes(h * 4) + slab_bytes(w * 8) + slab_bytes(w * 4);
     }
     t += slab_bytes(h * 4) + slab_bytes(w * 4);  // validity
     size_t lw = w, lh = h, ld = d;
@@ -655,6 +658,7 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
     const int w = shape->w, h = shape->h, d = shape->d;
     const bool have_octa = octa_x && octa_y;
     const bool have_enface = enface_x && enface_y;
+    const bool detect = have_octa && !valid_x && (params->flags & OCTMC_DETECT_INVALID);
     if (!have_octa && !have_enface) return fail(OCTMC_E_INVALID, "need both OCTA volumes or both en face images");
     if ((octa_x != nullptr) != (octa_y != nullptr) || (enface_x != nullptr) != (enface_y != nullptr))
         return fail(OCTMC_E_INVALID, "OCTA inputs must be given for both scans");
@@ -711,6 +715,15 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
         for (int V = 0; V < 2; ++V) {
             HIP_TRY(P->alloc(&P->octa[V], nv * 4));
             HIP_TRY(hipMemcpyAsync(P->octa[V], src[V], nv * 4, kind, s));
+            if (detect) {  // B-scan validity from the OCTA volume (Sec. 2.2)
+                std::vector<float>& hv = V == 0 ? hvx : hvy;
+                double* means = (double*)talloc(hv.size() * 8);
+                float* dv = (float*)talloc(hv.size() * 4);
+                if (!means || !dv) return fail(OCTMC_E_OOM, "out of device memory (validity)");
+                HIP_TRY(launch_validity(P->octa[V], w, h, d, V, means, dv, s));
+                HIP_TRY(hipMemcpyAsync(hv.data(), dv, hv.size() * 4, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+            }
             const std::vector<float>& val = V == 0 ? hvx : hvy;
             const int nb = V == 0 ? h : w;
             std::vector<int> from(nb);
@@ -826,6 +839,36 @@ int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_sh
 {
     return pair_create_impl(ctx, params, shape, oct_x, oct_y, octa_x, octa_y, enface_x, enface_y, valid_x, valid_y,
                             static_cast<hipStream_t>(stream), nullptr, out);
+}
+
+int octmc_validity_from_octa(octmc_ctx* ctx, const octmc_shape* shape, const float* octa, int32_t scan,
+                             float* valid_out, void* stream)
+{
+    if (!ctx || !shape || !octa || !valid_out) return fail(OCTMC_E_INVALID, "NULL argument");
+    if (scan != 0 && scan != 1) return fail(OCTMC_E_INVALID, "scan must be 0 (X-fast) or 1 (Y-fast)");
+    if (shape->mem != OCTMC_MEM_HOST && shape->mem != OCTMC_MEM_DEVICE)
+        return fail(OCTMC_E_INVALID, "unknown memory kind");
+    const int w = shape->w, h = shape->h, d = shape->d;
+    if (w < 1 || h < 1 || d < 1) return fail(OCTMC_E_SHAPE, "empty volume");
+    const size_t nv = (size_t)w * h * d;
+    if (nv * 4 >= (1ull << 31)) return fail(OCTMC_E_SHAPE, "volume larger than 2^31 bytes");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf tmp;
+    const float* vol = octa;
+    if (shape->mem == OCTMC_MEM_HOST) {
+        void* q = nullptr;
+        HIP_TRY(hipMalloc(&q, nv * 4));
+        tmp.ptrs.push_back(q);
+        HIP_TRY(hipMemcpyAsync(q, octa, nv * 4, hipMemcpyHostToDevice, s));
+        vol = static_cast<const float*>(q);
+    }
+    void* means = nullptr;
+    HIP_TRY(hipMalloc(&means, (size_t)(scan == 0 ? h : w) * 8));
+    tmp.ptrs.push_back(means);
+    HIP_TRY(launch_validity(vol, w, h, d, scan, static_cast<double*>(means), valid_out, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the temporaries are freed on return
+    return OCTMC_OK;
 }
 
 int octmc_pair_destroy(octmc_pair* pair)
