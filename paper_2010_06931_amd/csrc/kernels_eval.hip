@@ -338,6 +338,206 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     }
 }
 
+// Two depth samples per lane (16-bit storage).  A step covers outputs o = 122 n + p - sx,
+// p = 2 l + e in [sx, 121 + sx] (lane l, e in {0, 1}), sx = parity of the
+// X-fast scan's first depth tap.  Pair position p of scan V holds the
+// sample base_V + o of output o's first tap, so the depth interpolation of
+// output p reads positions p .. p + 3 (this lane and the next one or two, by
+// DPP).  Each scan loads even-aligned pairs (q0, q1) = samples (E + 2l,
+// E + 2l + 1) with one 32-bit load per column; a
+// scan whose positions start one sample after an even boundary (r = 1) uses
+// c0 = q1 and c1 = the next lane's q0 (so the taps of every output, up to
+// position 125, lie inside the 128 loaded samples).  Samples outside the A-scan take the
+// edge value (clamp), applied to the blended columns and, for the adjoint, to
+// the weights of q0 and q1.  Every step is self-contained as in k_struct.
+constexpr int kOutPerStep2 = 122;
+
+// A pair of 16-bit samples is one 32-bit load.  (Float32 storage keeps one
+// sample per lane: 64-bit loads measured slower per byte than 32-bit ones on
+// this path, so pairs would not pay.)
+template <typename T>
+__device__ __forceinline__ void ld2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float& a, float& b);
+template <>
+__device__ __forceinline__ void ld2<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float& a, float& b)
+{
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    a = __builtin_bit_cast(float, v << 16);
+    b = __builtin_bit_cast(float, v & 0xFFFF0000u);
+}
+template <>
+__device__ __forceinline__ void ld2<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float& a, float& b)
+{
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    a = (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xFFFFu));
+    b = (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
+}
+
+template <typename T>
+__device__ __forceinline__ void load_pairs(float (&q0)[16], float (&q1)[16], __amdgpu_buffer_rsrc_t rs,
+                                           const Stencil& S, int m, int d)
+{
+    const int mc = clampi(m, 0, d - 2);
+    const uint32_t voff = (uint32_t)mc * esize<T>::v;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ld2<T>(rs, voff, S.off[q], q0[q], q1[q]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
+{
+    const int wv = uni((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    int jid = -1;
+    for (int q = 0; q < jobs.n; ++q)
+        if (lb >= jobs.j[q].blk_begin) jid = q;
+    if (jid < 0) return;  // whole block
+    const StructJob& J = jobs.j[jid];
+    const int w = J.w, h = J.h, d = J.d;
+    // 2 x 2 tiles in 8 bands of tile rows, swept column by column (as k_struct)
+    const int tpr = (w + 1) >> 1;
+    const int trows = (h + 1) >> 1;
+    const int rpb = (trows + 7) >> 3;
+    const int t = lb - J.blk_begin;
+    const int band = t / (rpb * tpr), tb = t - band * (rpb * tpr);
+    const int trow = band * rpb + tb % rpb;
+    if (t >= 8 * rpb * tpr || trow >= trows) return;  // whole block
+    const int i = 2 * (tb / rpb) + (wv & 1);
+    const int j = 2 * trow + (wv >> 1);
+    const bool active = i < w && j < h;  // wave-uniform
+    const int a = uni(active ? j * w + i : 0);
+    const float* dX = J.disp + (size_t)a * 3;
+    const float* dY = J.disp + ((size_t)J.na + a) * 3;
+    Stencil SX, SY;
+    make_stencil<T>(SX, i, j, dX[0], dX[1], dX[2], w, h, d);
+    make_stencil<T>(SY, i, j, dY[0], dY[1], dY[2], w, h, d);
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t ry =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sy), (short)0, (int)J.vol_bytes, kRsrcWord3);
+    const float eps = J.eps_h;
+    const float inv_eps = 1.0f / J.eps_h;
+    // position 0 of step 0 holds sample base_V - sx of scan V
+    const int sx = SX.base & 1;
+    const int rY = uni((SY.base - sx) & 1);
+    const int EX = SX.base - sx, EY = SY.base - sx - rY;  // even
+
+    float x0[16], x1[16], y0[16], y1[16];
+    float PX[16], PY[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) PX[q] = PY[q] = 0.f;
+    float lam = 0.f, gzx = 0.f, gzy = 0.f;
+    const int nsteps = (d + kOutPerStep2 - 1) / kOutPerStep2;
+    for (int n = 0; n < nsteps; ++n) {
+        if (active) {
+            const int mX = EX + kOutPerStep2 * n + 2 * lane;
+            const int mY = EY + kOutPerStep2 * n + 2 * lane;
+            load_pairs<T>(x0, x1, rx, SX, mX, d);
+            load_pairs<T>(y0, y1, ry, SY, mY, d);
+            // clamp: a pair below the A-scan holds sample 0 twice, one above it sample d - 1 twice
+            const bool loX = mX < 0, hiX = mX > d - 2, loY = mY < 0, hiY = mY > d - 2;
+            float bx0 = blend(x0, SX), bx1 = blend(x1, SX), by0 = blend(y0, SY), by1 = blend(y1, SY);
+            const float cx0 = hiX ? bx1 : bx0, cx1 = loX ? bx0 : bx1;
+            const float ty0 = hiY ? by1 : by0, ty1 = loY ? by0 : by1;
+            // Y positions start one sample after the pair boundary when rY = 1
+            const float ty0n = shl1(ty0);
+            const float cy0 = rY ? ty1 : ty0, cy1 = rY ? ty0n : ty1;
+            // depth interpolation (Eq. 2) of outputs at positions 2l and 2l + 1
+            const float cx0n = shl1(cx0), cx1n = shl1(cx1), cx0nn = shl1(cx0n);
+            const float cy0n = shl1(cy0), cy1n = shl1(cy1), cy0nn = shl1(cy0n);
+            const float ix0 = SX.wz[0] * cx0 + SX.wz[1] * cx1 + SX.wz[2] * cx0n + SX.wz[3] * cx1n;
+            const float ix1 = SX.wz[0] * cx1 + SX.wz[1] * cx0n + SX.wz[2] * cx1n + SX.wz[3] * cx0nn;
+            const float zx0 = SX.dwz[0] * cx0 + SX.dwz[1] * cx1 + SX.dwz[2] * cx0n + SX.dwz[3] * cx1n;
+            const float zx1 = SX.dwz[0] * cx1 + SX.dwz[1] * cx0n + SX.dwz[2] * cx1n + SX.dwz[3] * cx0nn;
+            const float iy0 = SY.wz[0] * cy0 + SY.wz[1] * cy1 + SY.wz[2] * cy0n + SY.wz[3] * cy1n;
+            const float iy1 = SY.wz[0] * cy1 + SY.wz[1] * cy0n + SY.wz[2] * cy1n + SY.wz[3] * cy0nn;
+            const float zy0 = SY.dwz[0] * cy0 + SY.dwz[1] * cy1 + SY.dwz[2] * cy0n + SY.dwz[3] * cy1n;
+            const float zy1 = SY.dwz[0] * cy1 + SY.dwz[1] * cy0n + SY.dwz[2] * cy1n + SY.dwz[3] * cy0nn;
+            // residual and pseudo-Huber loss (Eq. 4), eps u^2 / (sqrt(1 + u^2) + 1), and u / sqrt(1 + u^2)
+            const int p0 = 2 * lane;
+            const int o0 = kOutPerStep2 * n + p0 - sx;
+            const bool v0 = p0 >= sx && p0 <= 121 + sx && o0 < d;
+            const bool v1 = p0 + 1 <= 121 + sx && o0 + 1 < d;
+            float L0, G0, L1, G1;
+            {
+                const float u = (ix0 - iy0) * inv_eps, q = u * u;
+                const float rs = __builtin_amdgcn_rsqf(1.f + q), sq = (1.f + q) * rs;
+                L0 = v0 ? eps * q * __builtin_amdgcn_rcpf(sq + 1.f) : 0.f;
+                G0 = v0 ? u * rs : 0.f;
+            }
+            {
+                const float u = (ix1 - iy1) * inv_eps, q = u * u;
+                const float rs = __builtin_amdgcn_rsqf(1.f + q), sq = (1.f + q) * rs;
+                L1 = v1 ? eps * q * __builtin_amdgcn_rcpf(sq + 1.f) : 0.f;
+                G1 = v1 ? u * rs : 0.f;
+            }
+            lam += L0 + L1;
+            gzx += G0 * zx0 + G1 * zx1;
+            gzy += G0 * zy0 + G1 * zy1;
+            // adjoint of the depth interpolation: position q collects the
+            // derivatives of the outputs at q, q - 1, q - 2, q - 3
+            const float G0p = shr1(G0), G1p = shr1(G1), G1pp = shr1(G1p);
+            const float hx0 = SX.wz[0] * G0 + SX.wz[1] * G1p + SX.wz[2] * G0p + SX.wz[3] * G1pp;
+            const float hx1 = SX.wz[0] * G1 + SX.wz[1] * G0 + SX.wz[2] * G1p + SX.wz[3] * G0p;
+            const float hy0 = SY.wz[0] * G0 + SY.wz[1] * G1p + SY.wz[2] * G0p + SY.wz[3] * G1pp;
+            const float hy1 = SY.wz[0] * G1 + SY.wz[1] * G0 + SY.wz[2] * G1p + SY.wz[3] * G0p;
+            // back to the loaded samples q0, q1: alignment shift, then clamp
+            const float hy1p = shr1(hy1);
+            const float uy0 = rY ? hy1p : hy0, uy1 = rY ? hy0 : hy1;
+            const float wx0 = loX ? hx0 + hx1 : (hiX ? 0.f : hx0);
+            const float wx1 = hiX ? hx0 + hx1 : (loX ? 0.f : hx1);
+            const float wy0 = loY ? uy0 + uy1 : (hiY ? 0.f : uy0);
+            const float wy1 = hiY ? uy0 + uy1 : (loY ? 0.f : uy1);
+#pragma unroll
+            for (int q2 = 0; q2 < 16; ++q2) {
+                PX[q2] = fmaf(x0[q2], wx0, fmaf(x1[q2], wx1, PX[q2]));
+                PY[q2] = fmaf(y0[q2], wy0, fmaf(y1[q2], wy1, PY[q2]));
+            }
+        }
+    }
+    if (!active) return;
+    float wx[4], dwx[4], wy[4], dwy[4];
+    float gxx = 0.f, gyx = 0.f, gxy = 0.f, gyy = 0.f;
+    cr_taps(SX.tx, wx, dwx);
+    cr_taps(SX.ty, wy, dwy);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        float rv = 0.f, rd = 0.f;
+#pragma unroll
+        for (int a2 = 0; a2 < 4; ++a2) {
+            rv = fmaf(wx[a2], PX[b * 4 + a2], rv);
+            rd = fmaf(dwx[a2], PX[b * 4 + a2], rd);
+        }
+        gxx = fmaf(wy[b], rd, gxx);
+        gyx = fmaf(dwy[b], rv, gyx);
+    }
+    cr_taps(SY.tx, wx, dwx);
+    cr_taps(SY.ty, wy, dwy);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        float rv = 0.f, rd = 0.f;
+#pragma unroll
+        for (int a2 = 0; a2 < 4; ++a2) {
+            rv = fmaf(wx[a2], PY[b * 4 + a2], rv);
+            rd = fmaf(dwx[a2], PY[b * 4 + a2], rd);
+        }
+        gxy = fmaf(wy[b], rd, gxy);
+        gyy = fmaf(dwy[b], rv, gyy);
+    }
+    lam = wave_sum(lam);
+    gxx = wave_sum(gxx);
+    gyx = wave_sum(gyx);
+    gzx = wave_sum(gzx);
+    gxy = wave_sum(gxy);
+    gyy = wave_sum(gyy);
+    gzy = wave_sum(gzy);
+    if (lane == 0) {
+        float4* o = reinterpret_cast<float4*>(J.part + (size_t)a * 8);
+        o[0] = make_float4(lam, gxx, gyx, gzx);
+        o[1] = make_float4(gxy, gyy, gzy, 0.f);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // deterministic block reduction helpers
 
@@ -656,6 +856,22 @@ hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s)
 
 hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s)
 {
+    // 16-bit storage: two samples per lane, unless a depth is odd (the last
+    // pair of an A-scan would then start at an odd sample, not 32-bit aligned)
+    bool pairs = dt != OCTMC_F32;
+    for (int q = 0; q < jobs.n; ++q) pairs &= (jobs.j[q].d % 2) == 0;
+    if (pairs) {
+        switch (dt) {
+        case OCTMC_BF16:
+            hipLaunchKernelGGL(k_struct2<bf16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+            return hipGetLastError();
+        case OCTMC_F16:
+            hipLaunchKernelGGL(k_struct2<f16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+            return hipGetLastError();
+        default:
+            return hipErrorInvalidValue;
+        }
+    }
     switch (dt) {
     case OCTMC_F32:
         hipLaunchKernelGGL(k_struct<float>, dim3(total_blocks), dim3(256), 0, s, jobs);

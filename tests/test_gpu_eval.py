@@ -75,6 +75,26 @@ def test_eval_parity_ragged_all_levels(octmc):
         _compare(octmc, P, pyr[level], level, D, f"ragged/L{level}")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_eval_parity_odd_depth(octmc, dtype):
+    """Odd depth at every level (151, 76, 38): the last sample pair of an
+    A-scan starts at an odd sample (float32) or takes the one-sample-per-lane
+    kernel (16-bit storage); random fields give both parities of the first
+    depth tap in both scans."""
+    pair = synth.make_pair("tiny", n=36, d=151)
+    # the library builds every level from the exact level above and stores it rounded
+    pyr = oracle.pyramid(oracle.level_from_pair(pair), 2)
+    if dtype != "f32":
+        pyr = [oracle.Level(oracle.round_storage(lv.sx, 1), oracle.round_storage(lv.sy, 1), lv.ax, lv.ay, lv.vx,
+                            lv.vy) for lv in pyr]
+    P = _gpu_pair(octmc, pair, dtype=dtype, levels=2)
+    for level in range(2):
+        w, h, d = P.level_shape(level)
+        for case, seed in (("uniform", 1), ("smooth", 2)):
+            D = synth.random_field(w, h, 3.0, seed) if case == "uniform" else synth.smooth_random_field(w, h, 2.5, seed)
+            _compare(octmc, P, pyr[level], level, D, f"odd/{dtype}/{level}/{case}", tol=TOL if dtype == "f32" else 2e-4)
+
+
 def test_eval_parity_validity_and_white_lines(octmc):
     pair = synth.make_pair("tiny", n=48, d=64, white_lines=True)
     assert (pair.vx == 0).any() and (pair.vy == 0).any()
