@@ -104,6 +104,14 @@ def lib():
         L.orc_merge.argtypes = [dp] * 6 + [C.c_int] * 3 + [dp, C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_enface_mean.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
         L.orc_substitute_invalid.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, C.c_int]
+        L.orc_median3.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
+        L.orc_median3.restype = None
+        L.orc_rank_line.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp]
+        L.orc_rank_line.restype = None
+        L.orc_quantile_valid.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_double]
+        L.orc_quantile_valid.restype = C.c_double
+        L.orc_enface_project.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
+        L.orc_enface_project.restype = None
         L.orc_validity.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.orc_validity.restype = None
         L.orc_round_storage.argtypes = [dp, C.c_size_t, C.c_int]
@@ -372,4 +380,37 @@ def validity(vol, V: int):
     h, w, d = vol.shape
     out = np.zeros(h if V == 0 else w)
     lib().orc_validity(_p(vol), w, h, d, int(V), _p(out))
+    return out
+
+
+def median3(vol):
+    vol = _f64(vol)
+    h, w, d = vol.shape
+    out = np.empty_like(vol)
+    lib().orc_median3(_p(vol), w, h, d, _p(out))
+    return out
+
+
+def rank_line(vol, axis: int, half: int = 7, rank: int = 2):
+    """Rank filter along x (axis 0) or y (axis 1) of a [h][w][d] volume."""
+    vol = _f64(vol)
+    h, w, d = vol.shape
+    out = np.empty_like(vol)
+    lib().orc_rank_line(_p(vol), w, h, d, int(axis), int(half), int(rank), _p(out))
+    return out
+
+
+def quantile_valid(vol, V: int, valid, q: float) -> float:
+    vol = _f64(vol)
+    h, w, d = vol.shape
+    return lib().orc_quantile_valid(_p(vol), w, h, d, int(V), _p(_f64(valid)), float(q))
+
+
+def enface_project(oct_vol, octa_vol, V: int, valid=None):
+    """Segmentation-free en face projection (Sec. 2.3) of scan V: [h][w]."""
+    o, a = _f64(oct_vol), _f64(octa_vol)
+    h, w, d = a.shape
+    valid = np.ones(h if V == 0 else w) if valid is None else _f64(valid)
+    out = np.zeros((h, w))
+    lib().orc_enface_project(_p(o), _p(a), w, h, d, int(V), _p(valid), _p(out))
     return out

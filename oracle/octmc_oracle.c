@@ -937,9 +937,9 @@ EXPORT void orc_merge(const double* sx, const double* sy, const double* ox, cons
     free(rho);
 }
 
-/* Plain depth mean of an OCTA volume: the en face image used in place of the
- * paper's segmentation-free projection (Sec. 2.3), which is not part of this
- * oracle. */
+/* Plain depth mean of an OCTA volume: the simple en face image, used when
+ * the segmentation-free projection of Sec. 2.3 (orc_enface_project) is not
+ * asked for. */
 EXPORT void orc_enface_mean(const double* vol, int w, int h, int d, double* out)
 {
     for (size_t a = 0; a < (size_t)w * h; a++) {
@@ -1029,4 +1029,155 @@ EXPORT void orc_validity(const double* vol, int w, int h, int d, int V, double* 
     }
     free(m);
     free(flag);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Segmentation-free en face OCTA projection (Sec. 2.3).  Volumes are
+ * [h][w][d] in the common frame; the fast scan axis of scan V is x (i) for
+ * the X-fast scan (V = 0) and y (j) for the Y-fast scan (V = 1).  Readings of
+ * the points the paper leaves open are listed with each step. */
+
+static int cmp_double(const void* a, const void* b)
+{
+    const double x = *(const double*)a, y = *(const double*)b;
+    return (x > y) - (x < y);
+}
+
+static size_t vidx(int i, int j, int k, int w, int h, int d)
+{
+    i = i < 0 ? 0 : (i >= w ? w - 1 : i);
+    j = j < 0 ? 0 : (j >= h ? h - 1 : j);
+    k = k < 0 ? 0 : (k >= d ? d - 1 : k);
+    return ((size_t)j * w + i) * d + k;
+}
+
+/* 3-D median filter of radius 1: the 14th smallest of the 27 samples of the
+ * 3 x 3 x 3 neighbourhood, indices clamped to the volume (reading). */
+EXPORT void orc_median3(const double* in, int w, int h, int d, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < h; j++)
+        for (int i = 0; i < w; i++)
+            for (int k = 0; k < d; k++) {
+                double v[27];
+                int n = 0;
+                for (int dj = -1; dj <= 1; dj++)
+                    for (int di = -1; di <= 1; di++)
+                        for (int dk = -1; dk <= 1; dk++) v[n++] = in[vidx(i + di, j + dj, k + dk, w, h, d)];
+                qsort(v, 27, sizeof(double), cmp_double);
+                out[((size_t)j * w + i) * d + k] = v[13];
+            }
+}
+
+/* 1-D rank filter along x (axis 0) or y (axis 1): the (rank + 1)-th smallest
+ * of the 2 half + 1 samples centred on the voxel, indices clamped. */
+EXPORT void orc_rank_line(const double* in, int w, int h, int d, int axis, int half, int rank, double* out)
+{
+    const int n = 2 * half + 1;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < h; j++) {
+        double* v = (double*)malloc(n * sizeof(double));
+        for (int i = 0; i < w; i++)
+            for (int k = 0; k < d; k++) {
+                for (int o = -half; o <= half; o++)
+                    v[o + half] = axis == 0 ? in[vidx(i + o, j, k, w, h, d)] : in[vidx(i, j + o, k, w, h, d)];
+                qsort(v, n, sizeof(double), cmp_double);
+                out[((size_t)j * w + i) * d + k] = v[rank];
+            }
+        free(v);
+    }
+}
+
+/* q-quantile (q in [0, 1]) of the voxels of the valid B-scans of scan V
+ * (all voxels if no B-scan is valid), by linear interpolation between the
+ * order statistics at position q (N - 1) (reading). */
+EXPORT double orc_quantile_valid(const double* vol, int w, int h, int d, int V, const double* valid, double q)
+{
+    const int nb = V == 0 ? h : w;
+    int any = 0;
+    for (int b = 0; b < nb; b++) any |= valid[b] > 0.5;
+    size_t n = 0;
+    double* x = (double*)malloc((size_t)w * h * d * sizeof(double));
+    for (int j = 0; j < h; j++)
+        for (int i = 0; i < w; i++) {
+            const int b = V == 0 ? j : i;
+            if (any && !(valid[b] > 0.5)) continue;
+            for (int k = 0; k < d; k++) x[n++] = vol[((size_t)j * w + i) * d + k];
+        }
+    qsort(x, n, sizeof(double), cmp_double);
+    const double pos = q * (double)(n - 1);
+    size_t lo = (size_t)floor(pos);
+    if (lo >= n - 1) lo = n - 1;
+    const double frac = pos - (double)lo;
+    const double r = lo + 1 < n ? x[lo] + frac * (x[lo + 1] - x[lo]) : x[lo];
+    free(x);
+    return r;
+}
+
+/* The projection, step by step:
+ *   1. M = 3-D median of radius 1 of the OCTA volume;
+ *   2. R = rank filters of width 15 keeping the 3rd smallest value, first
+ *      along the fast axis of the scan, then along its slow axis;
+ *   3. p5, p95 = 5th and 95th percentile of R over the valid B-scans; the
+ *      normalised value (R - p5) / (p95 - p5) is compared with 0.1, as
+ *      R < p5 + 0.1 (p95 - p5) (reading: the mask keeps the low values, the
+ *      retina between vessels, where the filtered volume is low);
+ *   4. OCT mask (reading, the threshold is not given: a noise threshold as
+ *      used for amplitude decorrelation): OCT intensity above mean + 2
+ *      standard deviations (population) of the first nz = max(1,
+ *      floor(0.05 d + 0.5)) samples of every A-scan;
+ *   5. en face value = mean of the OCTA samples in both masks along depth
+ *      (0 where none is);
+ *   6. each B-scan's median (numpy convention: mean of the two middle values
+ *      for an even count) is subtracted from it;
+ *   7. invalid B-scans are replaced by their nearest valid neighbour.
+ * out: [h][w]. */
+EXPORT void orc_enface_project(const double* oct, const double* octa, int w, int h, int d, int V,
+                               const double* valid, double* out)
+{
+    const size_t nv = (size_t)w * h * d;
+    double* m = (double*)malloc(nv * sizeof(double));
+    double* r = (double*)malloc(nv * sizeof(double));
+    orc_median3(octa, w, h, d, m);
+    orc_rank_line(m, w, h, d, V == 0 ? 0 : 1, 7, 2, r);
+    orc_rank_line(r, w, h, d, V == 0 ? 1 : 0, 7, 2, m);
+    const double p5 = orc_quantile_valid(m, w, h, d, V, valid, 0.05);
+    const double p95 = orc_quantile_valid(m, w, h, d, V, valid, 0.95);
+    const double thr_r = p5 + 0.1 * (p95 - p5);
+    const int nz = (int)floor(0.05 * d + 0.5) < 1 ? 1 : (int)floor(0.05 * d + 0.5);
+    double s = 0.0, s2 = 0.0;
+    for (size_t a = 0; a < (size_t)w * h; a++)
+        for (int k = 0; k < nz; k++) s += oct[a * d + k];
+    const double cnt = (double)w * h * nz;
+    const double mu = s / cnt;
+    for (size_t a = 0; a < (size_t)w * h; a++)
+        for (int k = 0; k < nz; k++) s2 += (oct[a * d + k] - mu) * (oct[a * d + k] - mu);
+    const double thr_s = mu + 2.0 * sqrt(s2 / cnt);
+    for (size_t a = 0; a < (size_t)w * h; a++) {
+        double acc = 0.0;
+        int c = 0;
+        for (int k = 0; k < d; k++) {
+            const size_t q = a * d + k;
+            if (m[q] < thr_r && oct[q] > thr_s) {
+                acc += octa[q];
+                c++;
+            }
+        }
+        out[a] = c ? acc / c : 0.0;
+    }
+    const int nb = V == 0 ? h : w, na = V == 0 ? w : h;
+    double* line = (double*)malloc(na * sizeof(double));
+    for (int b = 0; b < nb; b++) {
+        for (int o = 0; o < na; o++) line[o] = V == 0 ? out[(size_t)b * w + o] : out[(size_t)o * w + b];
+        qsort(line, na, sizeof(double), cmp_double);
+        const double med = (na & 1) ? line[na / 2] : 0.5 * (line[na / 2 - 1] + line[na / 2]);
+        for (int o = 0; o < na; o++) {
+            if (V == 0) out[(size_t)b * w + o] -= med;
+            else out[(size_t)o * w + b] -= med;
+        }
+    }
+    free(line);
+    orc_substitute_invalid(out, w, h, 1, valid, V);
+    free(m);
+    free(r);
 }

@@ -614,3 +614,131 @@ def test_validity_recovers_synthetic_white_lines(orc):
         assert (pair.vx == 0).any() or (pair.vy == 0).any()
         assert np.array_equal(orc.validity(pair.ox, 0), pair.vx.numpy())
         assert np.array_equal(orc.validity(pair.oy, 1), pair.vy.numpy())
+
+
+# ---------------------------------------------------------------------------
+# Segmentation-free en face projection (Sec. 2.3).
+
+def _np_nearest_valid(img, valid, V):
+    """Brute force: each invalid B-scan copies the valid one at the smallest
+    distance, the lower index on a tie."""
+    out = img.copy()
+    nb = len(valid)
+    ok = np.flatnonzero(valid > 0.5)
+    if len(ok) == 0:
+        return out
+    for b in range(nb):
+        if valid[b] > 0.5:
+            continue
+        src = ok[np.argmin(np.abs(ok - b) * 2 + (ok > b))]
+        if V == 0:
+            out[b] = img[src]
+        else:
+            out[:, b] = img[:, src]
+    return out
+
+
+def _scipy_projection(oct_vol, octa, V, valid):
+    """The projection composed from library routines: scipy's median and rank
+    filters (clamped borders), numpy's percentile, mean, standard deviation
+    and median."""
+    from scipy import ndimage
+    m = ndimage.median_filter(octa, size=3, mode="nearest")
+    fast, slow = ((1, 15, 1), (15, 1, 1)) if V == 0 else ((15, 1, 1), (1, 15, 1))
+    r = ndimage.rank_filter(m, rank=2, size=fast, mode="nearest")
+    r = ndimage.rank_filter(r, rank=2, size=slow, mode="nearest")
+    sel = valid > 0.5 if (valid > 0.5).any() else np.ones_like(valid, bool)
+    rv = r[sel] if V == 0 else r[:, sel]
+    p5, p95 = np.percentile(rv, [5, 95])
+    mask = r < p5 + 0.1 * (p95 - p5)
+    d = octa.shape[2]
+    nz = max(1, int(np.floor(0.05 * d + 0.5)))
+    noise = oct_vol[:, :, :nz]
+    mask &= oct_vol > noise.mean() + 2.0 * noise.std()
+    cnt = mask.sum(axis=2)
+    e = np.where(cnt > 0, (octa * mask).sum(axis=2) / np.maximum(cnt, 1), 0.0)
+    e = e - (np.median(e, axis=1, keepdims=True) if V == 0 else np.median(e, axis=0, keepdims=True))
+    return _np_nearest_valid(e, valid, V)
+
+
+def test_median3_matches_scipy(orc):
+    from scipy import ndimage
+    for shape in [(9, 11, 7), (1, 5, 4), (6, 1, 1), (13, 10, 33)]:
+        vol = RNG.standard_normal(shape)
+        vol[vol > 1.0] = 1.0  # ties
+        assert np.array_equal(orc.median3(vol), ndimage.median_filter(vol, size=3, mode="nearest")), shape
+
+
+def test_rank_line_matches_scipy(orc):
+    from scipy import ndimage
+    for shape in [(20, 23, 6), (3, 40, 2), (31, 4, 5)]:
+        vol = RNG.random(shape)
+        vol[vol < 0.2] = 0.2
+        for axis, size in ((0, (1, 15, 1)), (1, (15, 1, 1))):
+            got = orc.rank_line(vol, axis, 7, 2)
+            assert np.array_equal(got, ndimage.rank_filter(vol, rank=2, size=size, mode="nearest")), (shape, axis)
+        # rank 0 of width 3 is the minimum filter
+        assert np.array_equal(orc.rank_line(vol, 0, 1, 0), ndimage.minimum_filter(vol, size=(1, 3, 1), mode="nearest"))
+
+
+def test_quantile_valid_matches_numpy(orc):
+    vol = RNG.standard_normal((12, 9, 5))
+    valid = np.ones(12)
+    valid[[0, 4, 5]] = 0.0
+    for q in (0.0, 0.05, 0.5, 0.95, 1.0):
+        assert math.isclose(orc.quantile_valid(vol, 0, valid, q), np.percentile(vol[valid > 0.5], 100 * q),
+                            rel_tol=1e-15, abs_tol=1e-15)
+    vy = np.ones(9)
+    vy[8] = 0.0
+    assert math.isclose(orc.quantile_valid(vol, 1, vy, 0.05), np.percentile(vol[:, :8], 5), rel_tol=1e-15)
+    # no valid B-scan: every voxel counts
+    assert math.isclose(orc.quantile_valid(vol, 0, np.zeros(12), 0.95), np.percentile(vol, 95), rel_tol=1e-15)
+
+
+@pytest.mark.parametrize("V", [0, 1])
+def test_enface_projection_matches_library_composition(orc, V):
+    h, w, d = 26, 23, 40
+    rng = np.random.default_rng(11 + V)
+    octa = rng.random((h, w, d))
+    octa[:, :, 12:22] *= 0.15  # a low-decorrelation band, as the retina between vessels
+    octv = rng.random((h, w, d)) * 0.2
+    octv[:, :, 10:24] += 1.0
+    nb = h if V == 0 else w
+    valid = np.ones(nb)
+    valid[[0, 7, 8, nb - 1]] = 0.0
+    got = orc.enface_project(octv, octa, V, valid)
+    ref = _scipy_projection(octv, octa, V, valid)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12)
+
+
+def test_enface_projection_layered_closed_form(orc):
+    """A flat retina: decorrelation 0.1 in depths 10..19 and 1.0 elsewhere, one
+    vessel one voxel wide (decorrelation 0.9) at x = 5, depth 13, running along
+    y.  OCT is bright only in depths 10..15.  The median filter removes the
+    vessel, the rank filters keep the layers, the percentile mask is exactly
+    the band, the OCT mask keeps its upper six samples: the en face image is
+    0.1 + 0.8 / 6 on the vessel column and 0.1 elsewhere, and after the B-scan
+    median 0.8 / 6 and 0.  A mask of the high values would give 0 everywhere."""
+    h, w, d = 12, 16, 40
+    octa = np.ones((h, w, d))
+    octa[:, :, 10:20] = 0.1
+    octa[:, 5, 13] = 0.9
+    octv = np.zeros((h, w, d))
+    octv[:, :, 10:16] = 1.0
+    e = orc.enface_project(octv, octa, 0)
+    expect = np.zeros((h, w))
+    expect[:, 5] = 0.8 / 6
+    assert np.allclose(e, expect, atol=1e-14)
+    # the Y-fast scan subtracts column medians: the vessel column is the whole B-scan, removed
+    ey = orc.enface_project(octv, octa, 1)
+    assert np.allclose(ey, 0.0, atol=1e-14)
+    # an invalid B-scan takes its nearest valid neighbour's values
+    vol2 = octa.copy()
+    vol2[:, 9, 14] = 0.5  # a second vessel, seen by the X-fast image at x = 9
+    vol2[4, 9, 14] = 0.1  # ... missing in B-scan 4
+    valid = np.ones(h)
+    valid[4] = 0.0
+    e2 = orc.enface_project(octv, vol2, 0, valid)
+    assert np.allclose(e2[:, 9], 0.4 / 6, atol=1e-14)
+    e3 = orc.enface_project(octv, vol2, 0)
+    assert math.isclose(e3[4, 9], 0.0, abs_tol=1e-14)
