@@ -110,7 +110,7 @@ def lib():
         L.orc_rank_line.restype = None
         L.orc_quantile_valid.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, C.c_double]
         L.orc_quantile_valid.restype = C.c_double
-        L.orc_enface_project.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
+        L.orc_enface_project.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp]
         L.orc_enface_project.restype = None
         L.orc_validity.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.orc_validity.restype = None
@@ -406,11 +406,17 @@ def quantile_valid(vol, V: int, valid, q: float) -> float:
     return lib().orc_quantile_valid(_p(vol), w, h, d, int(V), _p(_f64(valid)), float(q))
 
 
-def enface_project(oct_vol, octa_vol, V: int, valid=None):
-    """Segmentation-free en face projection (Sec. 2.3) of scan V: [h][w]."""
+def enface_project(oct_vol, octa_vol, V: int, valid=None, fixed=None, details=False):
+    """Segmentation-free en face projection (Sec. 2.3) of scan V: [h][w].
+    fixed: optional (p5, p95) normalisation mapping.  With details=True also
+    returns the per-A-scan voxel counts and (p5, p95, thr_r, thr_s)."""
     o, a = _f64(oct_vol), _f64(octa_vol)
     h, w, d = a.shape
     valid = np.ones(h if V == 0 else w) if valid is None else _f64(valid)
     out = np.zeros((h, w))
-    lib().orc_enface_project(_p(o), _p(a), w, h, d, int(V), _p(valid), _p(out))
-    return out
+    cnt = np.zeros((h, w))
+    st = np.zeros(4)
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.float64)
+    lib().orc_enface_project(_p(o), _p(a), w, h, d, int(V), _p(valid), None if fx is None else _p(fx), _p(out),
+                             _p(cnt), _p(st))
+    return (out, cnt, st) if details else out

@@ -1131,9 +1131,13 @@ EXPORT double orc_quantile_valid(const double* vol, int w, int h, int d, int V, 
  *   6. each B-scan's median (numpy convention: mean of the two middle values
  *      for an even count) is subtracted from it;
  *   7. invalid B-scans are replaced by their nearest valid neighbour.
- * out: [h][w]. */
+ * fixed (NULL or {p5, p95}) replaces the percentiles of step 3 by a fixed
+ * normalisation mapping, as the paper does for its wide-field runs.
+ * out: [h][w]; count (NULL or [h][w]): number of voxels averaged in step 5,
+ * before step 7; stats (NULL or 4 values): p5, p95, the threshold on the
+ * filtered volume and the OCT threshold. */
 EXPORT void orc_enface_project(const double* oct, const double* octa, int w, int h, int d, int V,
-                               const double* valid, double* out)
+                               const double* valid, const double* fixed, double* out, double* count, double* stats)
 {
     const size_t nv = (size_t)w * h * d;
     double* m = (double*)malloc(nv * sizeof(double));
@@ -1141,8 +1145,8 @@ EXPORT void orc_enface_project(const double* oct, const double* octa, int w, int
     orc_median3(octa, w, h, d, m);
     orc_rank_line(m, w, h, d, V == 0 ? 0 : 1, 7, 2, r);
     orc_rank_line(r, w, h, d, V == 0 ? 1 : 0, 7, 2, m);
-    const double p5 = orc_quantile_valid(m, w, h, d, V, valid, 0.05);
-    const double p95 = orc_quantile_valid(m, w, h, d, V, valid, 0.95);
+    const double p5 = fixed ? fixed[0] : orc_quantile_valid(m, w, h, d, V, valid, 0.05);
+    const double p95 = fixed ? fixed[1] : orc_quantile_valid(m, w, h, d, V, valid, 0.95);
     const double thr_r = p5 + 0.1 * (p95 - p5);
     const int nz = (int)floor(0.05 * d + 0.5) < 1 ? 1 : (int)floor(0.05 * d + 0.5);
     double s = 0.0, s2 = 0.0;
@@ -1164,6 +1168,13 @@ EXPORT void orc_enface_project(const double* oct, const double* octa, int w, int
             }
         }
         out[a] = c ? acc / c : 0.0;
+        if (count) count[a] = c;
+    }
+    if (stats) {
+        stats[0] = p5;
+        stats[1] = p95;
+        stats[2] = thr_r;
+        stats[3] = thr_s;
     }
     const int nb = V == 0 ? h : w, na = V == 0 ? w : h;
     double* line = (double*)malloc(na * sizeof(double));

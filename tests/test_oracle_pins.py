@@ -742,3 +742,26 @@ def test_enface_projection_layered_closed_form(orc):
     assert np.allclose(e2[:, 9], 0.4 / 6, atol=1e-14)
     e3 = orc.enface_project(octv, vol2, 0)
     assert math.isclose(e3[4, 9], 0.0, abs_tol=1e-14)
+
+
+def test_enface_projection_fixed_mapping_and_details(orc):
+    """With the fixed mapping equal to the measured percentiles the image is
+    unchanged; the reported counts and thresholds are those of the closed
+    form above (band of 6 OCT-bright samples, thresholds 0.19 and 0)."""
+    h, w, d = 12, 16, 40
+    octa = np.ones((h, w, d))
+    octa[:, :, 10:20] = 0.1
+    octv = np.zeros((h, w, d))
+    octv[:, :, 10:16] = 1.0
+    e, cnt, st = orc.enface_project(octv, octa, 0, details=True)
+    assert np.array_equal(cnt, np.full((h, w), 6.0))
+    assert math.isclose(st[0], 0.1, rel_tol=1e-15) and st[1] == 1.0
+    assert math.isclose(st[2], 0.1 + 0.1 * 0.9, rel_tol=1e-15) and st[3] == 0.0
+    rng = np.random.default_rng(5)
+    octa = rng.random((h, w, d))
+    octv = rng.random((h, w, d))
+    e, cnt, st = orc.enface_project(octv, octa, 1, details=True)
+    assert np.array_equal(orc.enface_project(octv, octa, 1, fixed=st[:2]), e)
+    # a mapping whose threshold lies below every value keeps no voxel
+    e0, cnt0, _ = orc.enface_project(octv, octa, 1, fixed=(-2.0, -1.0), details=True)
+    assert not cnt0.any() and not e0.any()
