@@ -68,6 +68,9 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
 #define OCTMC_CHECK_NAN 0x1u      /* scan the inputs for NaN/Inf at pair creation */
 #define OCTMC_DETECT_INVALID 0x2u /* derive the B-scan validity from the OCTA volumes (Sec. 2.2) when
                                      octmc_pair_create gets OCTA volumes and no validity vectors */
+#define OCTMC_ENFACE_PROJECT 0x4u /* form the en face OCTA images by the segmentation-free projection
+                                     of Sec. 2.3 (octmc_enface_project) instead of the depth mean when
+                                     octmc_pair_create gets OCTA volumes and no en face images */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
  * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
@@ -86,7 +89,7 @@ typedef struct {
     double c1, c2;       /* strong Wolfe constants                                [R: 1e-4, 0.9] */
     double merge_kappa;  /* density weight decay exp(-kappa (rho - 1))            [R: 1.0]  */
     double merge_tau;    /* weights below tau are clipped to 0                    [R: 0.05] */
-    uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID */
+    uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT */
 } octmc_params;
 
 typedef struct {
@@ -143,10 +146,12 @@ OCTMC_API int octmc_destroy(octmc_ctx* ctx);
  * "optimization"; validity of Sec. 2.2; en face images of Sec. 2.3/2.4).
  *   oct_x, oct_y       structural volumes [h][w][d] float32 (required);
  *   octa_x, octa_y     OCTA volumes [h][w][d] float32, or NULL; when given,
- *                      the en face images are their depth means (a stand-in
- *                      for the projection of Sec. 2.3) unless enface_* are
- *                      given, and invalid B-scans are replaced by their
- *                      nearest valid neighbour for the OCTA merge (Sec. 2.5);
+ *                      the en face images are their projections (Sec. 2.3,
+ *                      with OCTMC_ENFACE_PROJECT, using oct_* for the OCT
+ *                      mask and the validity below) or else their depth
+ *                      means, unless enface_* are given; invalid B-scans are
+ *                      replaced by their nearest valid neighbour for the
+ *                      OCTA merge (Sec. 2.5);
  *   enface_x, enface_y en face OCTA images [h][w] float32, or NULL;
  *   valid_x[h], valid_y[w] B-scan validity (Sec. 2.2, 1 = valid), or NULL:
  *                      all valid, or with OCTMC_DETECT_INVALID and OCTA
@@ -179,6 +184,53 @@ OCTMC_API int octmc_pair_destroy(octmc_pair* pair);
  * 2^31 bytes), OCTMC_E_OOM, OCTMC_E_DEVICE. */
 OCTMC_API int octmc_validity_from_octa(octmc_ctx* ctx, const octmc_shape* shape, const float* octa, int32_t scan,
                                        float* valid_out, void* stream);
+
+/* Segmentation-free en face OCTA projection (Sec. 2.3) of one scan:
+ *   1. 3-D median filter of radius 1 of the OCTA volume;
+ *   2. rank filters of width 15 keeping the 3rd smallest value, along the
+ *      fast then the slow scan axis (x then y for X-fast, y then x for Y-fast);
+ *   3. p5, p95 = 5th and 95th percentile of that filtered volume over the
+ *      valid B-scans (all B-scans if none is valid; linear interpolation
+ *      between order statistics), voxel mask: filtered < p5 + 0.1 (p95 - p5);
+ *   4. OCT mask: oct > mean + 2 (population) standard deviations of the first
+ *      max(1, round(0.05 d)) samples of every A-scan;
+ *   5. en face value: mean of the OCTA samples in both masks along depth
+ *      (0 where there is none);
+ *   6. every B-scan's median is subtracted from it;
+ *   7. invalid B-scans take the values of their nearest valid neighbour
+ *      (the lower one on a tie).
+ * Borders are clamped in every filter.  Selections are exact; thresholds and
+ * means are formed in float64.
+ *   shape      w, h, d of both volumes and where oct, octa and valid live
+ *              (shape->mem); shape->dtype is ignored (float32 volumes);
+ *              w, h <= 8192;
+ *   oct, octa  [h][w][d] float32 in the common frame: structural and OCTA;
+ *   scan       0: X-fast (B-scans are rows j), 1: Y-fast (columns i);
+ *   valid      float32[nb] (nb = h for X-fast, w for Y-fast; 1 = valid) or
+ *              NULL: all valid;
+ *   fixed      host double[2] {p5, p95}, a fixed normalisation mapping used
+ *              in place of the percentiles of step 3, or NULL;
+ *   enface_out device float32 [h][w];
+ *   count_out  device int32 [h][w] or NULL: voxels averaged in step 5;
+ *   stats_out  host double[4] or NULL: p5, p95, the threshold of step 3 and
+ *              the OCT threshold of step 4;
+ *   workspace  device memory of workspace_bytes >= octmc_enface_workspace_size
+ *              bytes (about 8 w h d), owned by the caller and not used by
+ *              anything else until the stream has passed this call, or NULL:
+ *              the library allocates and frees it.
+ * With a workspace, device inputs and no stats_out the call is asynchronous
+ * on `stream`; otherwise it synchronises `stream`.  Errors: OCTMC_E_INVALID
+ * (also a workspace smaller than needed), OCTMC_E_SHAPE (empty, a B-scan
+ * longer than 8192 A-scans, volume > 2^31 bytes), OCTMC_E_OOM,
+ * OCTMC_E_DEVICE. */
+OCTMC_API int octmc_enface_project(octmc_ctx* ctx, const octmc_shape* shape, const float* oct, const float* octa,
+                                   int32_t scan, const float* valid, const double* fixed, float* enface_out,
+                                   int32_t* count_out, double* stats_out, void* workspace, uint64_t workspace_bytes,
+                                   void* stream);
+
+/* Device bytes of the workspace octmc_enface_project needs for w x h x d
+ * volumes.  Errors: OCTMC_E_INVALID (NULL), OCTMC_E_SHAPE (empty). */
+OCTMC_API int octmc_enface_workspace_size(int32_t w, int32_t h, int32_t d, uint64_t* bytes);
 
 /* Shape (w, h, d) of pyramid level `level` (0 = finest). */
 OCTMC_API int octmc_pair_level_shape(const octmc_pair* pair, int32_t level, int32_t* w, int32_t* h, int32_t* d);

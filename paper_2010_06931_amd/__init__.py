@@ -22,6 +22,7 @@ _DTYPES = {"f32": F32, "float32": F32, "bf16": BF16, "bfloat16": BF16, "f16": F1
 MEM_HOST, MEM_DEVICE = 0, 1
 CHECK_NAN = 0x1
 DETECT_INVALID = 0x2
+ENFACE_PROJECT = 0x4
 MAX_LEVELS = 8
 
 TERM_F, TERM_DATA, TERM_STR, TERM_ANG, TERM_REG, TERM_MEAN, TERM_STR05, TERM_ANG05, TERM_ETA, TERM_GP = range(10)
@@ -34,7 +35,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_DTYPE", -4: "E_OOM", -
 # exported symbols of include/octmc.h (checked by the CPU test suite)
 SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_create", "octmc_destroy",
            "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_validity_from_octa",
-           "octmc_eval",
+           "octmc_enface_project", "octmc_enface_workspace_size", "octmc_eval",
            "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge",
            "octmc_request_footprint", "octmc_server_create", "octmc_server_submit", "octmc_server_poll",
            "octmc_server_status", "octmc_server_destroy")
@@ -112,6 +113,9 @@ def lib():
         L.octmc_pair_destroy.argtypes = [vp]
         L.octmc_pair_level_shape.argtypes = [vp, C.c_int32] + [C.POINTER(C.c_int32)] * 3
         L.octmc_validity_from_octa.argtypes = [vp, C.POINTER(Shape), vp, C.c_int32, vp, vp]
+        L.octmc_enface_project.argtypes = [vp, C.POINTER(Shape), vp, vp, C.c_int32, vp, C.POINTER(C.c_double), vp, vp,
+                                           C.POINTER(C.c_double), vp, C.c_uint64, vp]
+        L.octmc_enface_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint64)]
         L.octmc_eval.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.octmc_eval_profile.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), vp]
         L.octmc_eval_batched.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
@@ -207,7 +211,7 @@ class Pair:
 
     def __init__(self, sx, sy, *, ox=None, oy=None, ax=None, ay=None, vx=None, vy=None, params: Params | None = None,
                  dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,
-                 **param_overrides):
+                 project_enface: bool = False, **param_overrides):
         self.ctx = ctx or context(0)
         dev = torch.device("cuda", self.ctx.device)
         self.params = params if params is not None else default_params()
@@ -215,6 +219,8 @@ class Pair:
             setattr(self.params, k, v)
         if detect_invalid:  # validity from the OCTA volumes (Sec. 2.2) when vx, vy are not given
             self.params.flags |= DETECT_INVALID
+        if project_enface:  # en face images by the projection of Sec. 2.3 when ax, ay are not given
+            self.params.flags |= ENFACE_PROJECT
         sx, sy = _f32(sx, dev), _f32(sy, dev)
         h, w, d = sx.shape
         if sy.shape != sx.shape:
@@ -307,6 +313,47 @@ def validity_from_octa(vol: torch.Tensor, scan: int, *, ctx: Context | None = No
     shape = Shape(w, h, d, F32, MEM_DEVICE)
     _check(lib().octmc_validity_from_octa(ctx._h, C.byref(shape), _ptr(vol), int(scan), _ptr(out), _stream(stream)))
     return out
+
+
+def enface_workspace_size(w: int, h: int, d: int) -> int:
+    n = C.c_uint64()
+    _check(lib().octmc_enface_workspace_size(int(w), int(h), int(d), C.byref(n)))
+    return n.value
+
+
+def enface_project(oct_vol: torch.Tensor, octa_vol: torch.Tensor, scan: int, valid: torch.Tensor | None = None, *,
+                   fixed=None, details: bool = False, workspace: torch.Tensor | None = None, out=None,
+                   ctx: Context | None = None, stream=None):
+    """Segmentation-free en face projection (Sec. 2.3) of one scan: float32
+    [h][w] on the device.  oct_vol, octa_vol: [h][w][d]; valid: one value per
+    B-scan (rows for scan 0, columns for scan 1) or None; fixed: (p5, p95) in
+    place of the percentiles.  With details=True also returns the per-A-scan
+    voxel counts (int32 [h][w]) and (p5, p95, threshold, OCT threshold).
+    workspace: a device tensor of at least enface_workspace_size bytes; with
+    it (and details=False) the call is asynchronous on the stream."""
+    ctx = ctx or context(0)
+    dev = torch.device("cuda", ctx.device)
+    o, a = _f32(oct_vol, dev), _f32(octa_vol, dev)
+    if o.dim() != 3 or o.shape != a.shape:
+        raise ValueError("oct_vol and octa_vol must be [h][w][d] volumes of one shape")
+    h, w, d = a.shape
+    v = _f32(valid, dev)
+    if v is not None and v.numel() != (h if scan == 0 else w):
+        raise ValueError("valid needs one value per B-scan")
+    if out is None:
+        out = torch.empty((h, w), dtype=torch.float32, device=dev)
+    elif out.shape != (h, w) or out.dtype != torch.float32 or out.device != dev or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [h][w] tensor on the context's device")
+    cnt = torch.empty((h, w), dtype=torch.int32, device=dev) if details else None
+    stats = (C.c_double * 4)() if details else None
+    fx = None if fixed is None else (C.c_double * 2)(float(fixed[0]), float(fixed[1]))
+    shape = Shape(w, h, d, F32, MEM_DEVICE)
+    wb = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    if workspace is not None and (not workspace.is_cuda or not workspace.is_contiguous()):
+        raise ValueError("workspace must be a contiguous device tensor")
+    _check(lib().octmc_enface_project(ctx._h, C.byref(shape), _ptr(o), _ptr(a), int(scan), _ptr(v), fx, _ptr(out),
+                                      _ptr(cnt), stats, _ptr(workspace), wb, _stream(stream)))
+    return (out, cnt, tuple(stats)) if details else out
 
 
 def eval_batched(pairs, level: int, disp: torch.Tensor, *, grad: bool = True, eta_mode: int = 1, stream=None):

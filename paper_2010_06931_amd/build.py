@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liboctmc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels_eval.hip", "kernels_prep.hip", "kernels_lbfgs.hip", "kernels_merge.hip", "runtime.hip",
-           "server.hip"]
+SOURCES = ["kernels_eval.hip", "kernels_prep.hip", "kernels_lbfgs.hip", "kernels_merge.hip", "kernels_enface.hip",
+           "runtime.hip", "server.hip"]
 ARCH = os.environ.get("OCTMC_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-fvisibility=hidden", "-DOCTMC_BUILD",
          # no packed FP32 instructions in generated code

@@ -167,6 +167,17 @@ hipError_t launch_copy_bscans(float* vol, int w, int h, int d, const int* src, i
 hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf, hipStream_t s);
 // input validity of one OCTA volume (Sec. 2.2): means[nb] float64 scratch,
 // valid[nb] float32 output, nb = h (V = 0) or w (V = 1)
+// Segmentation-free en face projection (Sec. 2.3) of one scan; `scratch`
+// holds enface_scratch_bytes(w, h, d) device bytes; `valid` is a device
+// vector of nb = (V == 0 ? h : w) floats or NULL (all valid); `fixed` a host
+// {p5, p95} or NULL; `count` device int[h*w] or NULL; `stats_host` host
+// double[4] or NULL (p5, p95, threshold on the filtered volume, OCT
+// threshold; valid once the stream has reached this point).
+size_t enface_scratch_bytes(int w, int h, int d);
+int enface_max_bscan();
+hipError_t launch_enface_project(const float* oct, const float* octa, int w, int h, int d, int V,
+                                 const float* valid, const double* fixed, float* out, int* count, double* stats_host,
+                                 void* scratch, hipStream_t s);
 hipError_t launch_validity(const float* vol, int w, int h, int d, int V, double* means, float* valid,
                            hipStream_t s);
 

@@ -532,7 +532,8 @@ int octmc::validate_params(const octmc_params* p)
     if (p->lbfgs_m < 1 || p->lbfgs_m > 8) return fail(OCTMC_E_INVALID, "lbfgs_m must lie in [1, 8]");
     if (p->ls_max_evals < 1) return fail(OCTMC_E_INVALID, "ls_max_evals must be >= 1");
     if (!(p->c1 > 0 && p->c1 < p->c2 && p->c2 < 1)) return fail(OCTMC_E_INVALID, "need 0 < c1 < c2 < 1");
-    if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID)) return fail(OCTMC_E_INVALID, "unknown flags");
+    if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT))
+        return fail(OCTMC_E_INVALID, "unknown flags");
     return OCTMC_OK;
 }
 
@@ -572,6 +573,8 @@ size_t octmc::pair_footprint(const octmc_params& pr, const octmc_shape& sh, bool
         t += 2 * slab_bytes(nv * 4);
         if (have_valid || detect) t += slab_bytes(h * 4) + slab_bytes(w * 4);  // substitution tables
         if (detect) t += slab_bytes(h * 8) + slab_bytes(h * 4) + slab_bytes(w * 8) + slab_bytes(w * 4);
+        if (pr.flags & OCTMC_ENFACE_PROJECT)
+            t += slab_bytes(enface_scratch_bytes(sh.w, sh.h, sh.d)) + slab_bytes(h * 4) + slab_bytes(w * 4);
     }
     t += slab_bytes(h * 4) + slab_bytes(w * 4);  // validity
     size_t lw = w, lh = h, ld = d;
@@ -659,7 +662,11 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
     const bool have_octa = octa_x && octa_y;
     const bool have_enface = enface_x && enface_y;
     const bool detect = have_octa && !valid_x && (params->flags & OCTMC_DETECT_INVALID);
+    const bool project = have_octa && !have_enface && (params->flags & OCTMC_ENFACE_PROJECT);
+    void* pscratch = nullptr;
     if (!have_octa && !have_enface) return fail(OCTMC_E_INVALID, "need both OCTA volumes or both en face images");
+    if (project && (w > enface_max_bscan() || h > enface_max_bscan()))
+        return fail(OCTMC_E_SHAPE, "B-scans longer than 8192 A-scans for the projection");
     if ((octa_x != nullptr) != (octa_y != nullptr) || (enface_x != nullptr) != (enface_y != nullptr))
         return fail(OCTMC_E_INVALID, "OCTA inputs must be given for both scans");
     if ((valid_x != nullptr) != (valid_y != nullptr)) return fail(OCTMC_E_INVALID, "give both validity vectors or none");
@@ -726,6 +733,15 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
             }
             const std::vector<float>& val = V == 0 ? hvx : hvy;
             const int nb = V == 0 ? h : w;
+            if (project) {  // Sec. 2.3, from the OCTA volume before substitution
+                if (!pscratch) pscratch = talloc(enface_scratch_bytes(w, h, d));
+                float* dv = (float*)talloc((size_t)nb * 4);
+                if (!pscratch || !dv) return fail(OCTMC_E_OOM, "out of device memory (projection)");
+                HIP_TRY(hipMemcpyAsync(dv, val.data(), (size_t)nb * 4, hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_enface_project(f32[V], P->octa[V], w, h, d, V, dv, nullptr, enf[V], nullptr, nullptr,
+                                              pscratch, s));
+                HIP_TRY(hipStreamSynchronize(s));  // `val` is host memory
+            }
             std::vector<int> from(nb);
             bool any_valid = false, any_invalid = false;
             for (int b = 0; b < nb; ++b) {
@@ -751,7 +767,7 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
                 HIP_TRY(launch_copy_bscans(P->octa[V], w, h, d, dfrom, V, s));
                 HIP_TRY(hipStreamSynchronize(s));  // `from` is host memory
             }
-            if (!have_enface) HIP_TRY(launch_enface_mean(P->octa[V], (int)na, d, enf[V], s));
+            if (!have_enface && !project) HIP_TRY(launch_enface_mean(P->octa[V], (int)na, d, enf[V], s));
         }
     }
     if (have_enface) {
@@ -868,6 +884,60 @@ int octmc_validity_from_octa(octmc_ctx* ctx, const octmc_shape* shape, const flo
     tmp.ptrs.push_back(means);
     HIP_TRY(launch_validity(vol, w, h, d, scan, static_cast<double*>(means), valid_out, s));
     HIP_TRY(hipStreamSynchronize(s));  // the temporaries are freed on return
+    return OCTMC_OK;
+}
+
+int octmc_enface_workspace_size(int32_t w, int32_t h, int32_t d, uint64_t* bytes)
+{
+    if (!bytes) return fail(OCTMC_E_INVALID, "NULL argument");
+    if (w < 1 || h < 1 || d < 1) return fail(OCTMC_E_SHAPE, "empty volume");
+    *bytes = enface_scratch_bytes(w, h, d);
+    return OCTMC_OK;
+}
+
+int octmc_enface_project(octmc_ctx* ctx, const octmc_shape* shape, const float* oct, const float* octa,
+                         int32_t scan, const float* valid, const double* fixed, float* enface_out,
+                         int32_t* count_out, double* stats_out, void* workspace, uint64_t workspace_bytes,
+                         void* stream)
+{
+    if (!ctx || !shape || !oct || !octa || !enface_out) return fail(OCTMC_E_INVALID, "NULL argument");
+    if (scan != 0 && scan != 1) return fail(OCTMC_E_INVALID, "scan must be 0 (X-fast) or 1 (Y-fast)");
+    if (shape->mem != OCTMC_MEM_HOST && shape->mem != OCTMC_MEM_DEVICE)
+        return fail(OCTMC_E_INVALID, "unknown memory kind");
+    const int w = shape->w, h = shape->h, d = shape->d;
+    if (w < 1 || h < 1 || d < 1) return fail(OCTMC_E_SHAPE, "empty volume");
+    if (w > enface_max_bscan() || h > enface_max_bscan()) return fail(OCTMC_E_SHAPE, "B-scans longer than 8192 A-scans");
+    const size_t nv = (size_t)w * h * d, nb = scan == 0 ? h : w;
+    if (nv * 4 >= (1ull << 31)) return fail(OCTMC_E_SHAPE, "volume larger than 2^31 bytes");
+    if (fixed && !(fixed[0] == fixed[0] && fixed[1] == fixed[1])) return fail(OCTMC_E_INVALID, "fixed mapping is NaN");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DevBuf tmp;
+    auto dalloc = [&](size_t bytes) -> void* {
+        void* q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+        tmp.ptrs.push_back(q);
+        return q;
+    };
+    if (workspace && workspace_bytes < enface_scratch_bytes(w, h, d))
+        return fail(OCTMC_E_INVALID, "workspace smaller than octmc_enface_workspace_size");
+    void* scratch = workspace ? workspace : dalloc(enface_scratch_bytes(w, h, d));
+    if (!scratch) return fail(OCTMC_E_OOM, "out of device memory (projection scratch)");
+    const float *o = oct, *a = octa, *v = valid;
+    if (shape->mem == OCTMC_MEM_HOST) {
+        float* q = (float*)dalloc(2 * nv * 4 + nb * 4);
+        if (!q) return fail(OCTMC_E_OOM, "out of device memory (input copies)");
+        HIP_TRY(hipMemcpyAsync(q, oct, nv * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(q + nv, octa, nv * 4, hipMemcpyHostToDevice, s));
+        o = q;
+        a = q + nv;
+        if (valid) {
+            HIP_TRY(hipMemcpyAsync(q + 2 * nv, valid, nb * 4, hipMemcpyHostToDevice, s));
+            v = q + 2 * nv;
+        }
+    }
+    HIP_TRY(launch_enface_project(o, a, w, h, d, scan, v, fixed, enface_out, count_out, stats_out, scratch, s));
+    if (!tmp.ptrs.empty() || stats_out) HIP_TRY(hipStreamSynchronize(s));  // temporaries are freed on return
     return OCTMC_OK;
 }
 

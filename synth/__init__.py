@@ -226,7 +226,8 @@ def _quantile(x: torch.Tensor, q: float) -> float:
 
 def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = None, d: int | None = None,
               device: str | torch.device = "cpu", octa_volumes: bool = True, white_lines: bool = False,
-              drift: float | None = None, saccades=None, amp: float | None = None) -> Pair:
+              drift: float | None = None, saccades=None, amp: float | None = None,
+              decorrelation: bool = False) -> Pair:
     """Generate one scan pair of a workload (see WORKLOADS) on `device`.
 
     n, d, drift, saccades and amp override the workload's values (tests use
@@ -234,7 +235,11 @@ def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = N
     face OCTA images are returned (they are still the depth mean of the
     sampled OCTA volume).  With white_lines=True the OCTA B-scans that contain
     a saccade are saturated and the validity vectors mark them and their two
-    neighbours on each side invalid."""
+    neighbours on each side invalid.  With decorrelation=True the OCTA
+    volumes also carry the background of amplitude-decorrelation angiography:
+    0.5 exp(-s / 0.1) for the structural reflectivity s, attenuated below the
+    deepest layer boundary (e-folding depth 0.05 d), so that the vitreous and
+    the deep choroid are bright and the retina between vessels is dark."""
     cfg = dict(WORKLOADS[workload]) if isinstance(workload, str) else dict(workload)
     if n is not None:
         cfg["n"] = n
@@ -314,6 +319,12 @@ def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = N
     vmap = torch.from_numpy(_vessel_map(r_ve, G, 2 * n)).to(device)
     octa_truth = slab * vmap[:, :, None]
     del slab
+    if decorrelation:
+        for r0 in range(0, G, rows):
+            r1 = min(G, r0 + rows)
+            zz = z.view(1, 1, -1)
+            att = torch.exp(-torch.clamp(zz - bnd[5, r0:r1, :, None], min=0.0) / (0.05 * d))
+            octa_truth[r0:r1] += 0.5 * torch.exp(-truth[r0:r1] * att / 0.1)
 
     def sample(vol, pos):
         """Trilinear sample of the fine truth volume at output voxels
