@@ -262,6 +262,49 @@ def serving(octmc, torch, nreq, budget_gib, max_active, log):
                                        "served_bf16_vs_sequential_fp32": med(acc_vs_f32)}}
 
 
+def enface_bench(octmc, torch, log, reps=20):
+    """The segmentation-free en face projection (Sec. 2.3) of one OCTA volume,
+    with its percentile normalisation and with a fixed mapping, at the
+    paper's 500^2 x 465 volume size and at the dense 500^2 x 800 size.  The
+    workspace and inputs are resident; each projection is one stream-ordered
+    sequence of kernels, timed with events over `reps` back-to-back runs."""
+    import synth
+    res = {}
+    for n, d in ((500, 465), (500, 800)):
+        log(f"en face projection {n}x{n}x{d}: generating OCT and decorrelation OCTA")
+        q = synth.make_pair("dense", 1, n=n, d=d, device="cuda", decorrelation=True, white_lines=True)
+        s, a, v = q.sx, q.ox, q.vx
+        del q
+        torch.cuda.empty_cache()
+        ws = torch.empty(octmc.enface_workspace_size(n, n, d), dtype=torch.uint8, device="cuda")
+        out = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        _, _, st = octmc.enface_project(s, a, 0, v, details=True, workspace=ws)
+        row = {}
+        for mode, fixed in (("percentiles", None), ("fixed_mapping", (st[0], st[1]))):
+            for _ in range(3):
+                octmc.enface_project(s, a, 0, v, fixed=fixed, workspace=ws, out=out)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                octmc.enface_project(s, a, 0, v, fixed=fixed, workspace=ws, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row[mode] = {"ms_per_volume": round(ms, 4), "volumes_per_s": round(1000.0 / ms, 1)}
+        nv = n * n * d
+        # the projection must read the OCTA volume and the OCT volume at least once
+        row["min_traffic_GBps"] = round(8 * nv / (row["percentiles"]["ms_per_volume"] * 1e-3) / 1e9, 1)
+        row["workload"] = f"X-fast OCTA volume {n}x{n} A-scans x {d} samples, float32, white lines"
+        log(f"  {row}")
+        res[f"{n}x{n}x{d}"] = row
+        del s, a, v, ws, out
+        torch.cuda.empty_cache()
+    res["paper_context"] = "about 209 ms per 500^2 x 465 volume, 66 ms with a fixed mapping (GTX 960)"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +317,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-enface", action="store_true", help="skip the en face projection timing")
+    ap.add_argument("--enface-only", action="store_true", help="time only the en face projection")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=48.0)
     ap.add_argument("--serve-max-active", type=int, default=8)
@@ -303,6 +348,9 @@ def main():
     free, total = torch.cuda.mem_get_info()
     log(f"device {props.name}: {props.multi_processor_count} CUs, {total / 2**30:.1f} GiB "
         f"({free / 2**30:.1f} GiB free)")
+    if args.enface_only:
+        print(json.dumps({"enface_projection": enface_bench(octmc, torch, log)}), flush=True)
+        return
     log(f"generating the dense pair {args.n}x{args.n}x{args.d} on cuda")
     pair = synth.make_pair("dense", n=args.n, d=args.d, device="cuda", octa_volumes=False)
     log("ingest")
@@ -432,6 +480,11 @@ def main():
         v.pop("solution", None)
     if not args.no_serve:
         out["serving"] = serving(octmc, torch, args.serve_requests, args.serve_budget_gib, args.serve_max_active, log)
+
+    if not args.no_enface:
+        del P
+        torch.cuda.empty_cache()
+        out["enface_projection"] = enface_bench(octmc, torch, log)
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -6,9 +6,10 @@
 //   k_median3      3-D median of radius 1 (clamped borders)
 //   k_rank15       width-15 rank filter keeping the 3rd smallest value, along
 //                  one lateral axis (run for the fast, then the slow axis)
-//   k_radix_hist   three radix passes (11, 11, 10 bits) that select the two
-//   k_radix_select order statistics on each side of the 5th and 95th
-//                  percentile of the filtered volume over the valid B-scans
+//   k_radix_hist   three radix passes (11, 11, 10 bits; the first counted by
+//   k_radix_select the slow-axis rank filter) that select the two order
+//                  statistics on each side of the 5th and 95th percentile
+//                  of the filtered volume over the valid B-scans
 //   k_noise_sum    mean and standard deviation of the OCT noise samples
 //   k_mask_mean    both masks and the masked depth mean per A-scan
 //   k_bscan_median per-B-scan median
@@ -28,8 +29,8 @@ namespace {
 constexpr int kMedTile = 62;   // depth outputs per wave (64 lanes, one halo lane each side)
 constexpr int kMedSeg = 30;    // x positions per wave, a multiple of 3
 constexpr int kHistBins = 2048;
-constexpr int kHistBlocks = 1024;
-constexpr int kNoiseBlocks = 256;
+constexpr int kHistBlocks = 2048;
+constexpr int kNoiseBlocks = 2048;
 constexpr int kMaxBscan = 8192;  // A-scans per B-scan (LDS sort of the B-scan median)
 
 __device__ __forceinline__ float shl1(float v)  // lane l gets lane l + 1 (lane 63 gets 0)
@@ -157,75 +158,6 @@ __global__ __launch_bounds__(256) void k_median3(const float* __restrict__ in, f
 }
 
 // ---------------------------------------------------------------------------
-// Rank filter: the 3rd smallest of the 15 samples p-7 .. p+7 along one
-// lateral axis, clamped at the ends.
-//
-// A wave owns one line (64 consecutive depths) and walks it in chunks of 15
-// positions aligned so that chunk c spans p = 15c-7 .. 15c+7.  The window of
-// output p = 15c + t is the tail of chunk c from offset t joined with the
-// head of chunk c+1 up to offset t-1: the three smallest of each part are
-// kept sorted (suffix triples of chunk c, a running prefix triple of chunk
-// c+1), and the 3rd smallest of the union of two sorted triples a, b is
-// min(a3, b3, max(a1, b2), max(a2, b1)).  Inserting v into a sorted triple
-// gives (min(a1, v), med3(a1, a2, v), med3(a2, a3, v)).  Every sample is
-// loaded once per line.
-struct Tri {
-    float a, b, c;
-};
-__device__ __forceinline__ Tri insert(Tri t, float v)
-{
-    return Tri{__builtin_fminf(t.a, v), med3f(t.a, t.b, v), med3f(t.b, t.c, v)};
-}
-__device__ __forceinline__ float third_of_union(Tri s, Tri p)
-{
-    return min3f(__builtin_fminf(s.c, p.c), __builtin_fmaxf(s.a, p.b), __builtin_fmaxf(s.b, p.a));
-}
-
-__global__ __launch_bounds__(256) void k_rank15(const float* __restrict__ in, float* __restrict__ out, int w, int h,
-                                                int d, int axis)
-{
-    const int lane = threadIdx.x & 63;
-    const int ktiles = (d + 63) >> 6;
-    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int nlines = axis == 0 ? h : w;
-    if (wid >= nlines * ktiles) return;  // uniform per wave; no barrier in this kernel
-    const int o = wid / ktiles, kt = wid - o * ktiles;
-    const int k = kt * 64 + lane;
-    const int kc = k < d ? k : d - 1;
-    const bool store = k < d;
-    const int n = axis == 0 ? w : h;
-    const size_t stride = axis == 0 ? (size_t)d : (size_t)w * d;
-    const size_t base = (axis == 0 ? (size_t)o * w * d : (size_t)o * d) + kc;
-    const float* __restrict__ p = in + base;
-    float* __restrict__ q = out + base;
-    auto ld = [&](int pos) {
-        pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos);
-        return p[(size_t)pos * stride];
-    };
-    constexpr float inf = __builtin_inff();
-    float u[15];
-    Tri s[15];
-#pragma unroll
-    for (int t = 0; t < 15; ++t) u[t] = ld(t - 7);
-    s[14] = Tri{u[14], inf, inf};
-#pragma unroll
-    for (int t = 13; t >= 0; --t) s[t] = insert(s[t + 1], u[t]);
-    for (int c0 = 0; c0 < n; c0 += 15) {
-#pragma unroll
-        for (int t = 0; t < 15; ++t) u[t] = ld(c0 + 8 + t);
-        Tri pre{inf, inf, inf};
-#pragma unroll
-        for (int t = 0; t < 15; ++t) {
-            if (c0 + t < n && store) q[(size_t)(c0 + t) * stride] = third_of_union(s[t], pre);
-            pre = insert(pre, u[t]);
-        }
-        s[14] = Tri{u[14], inf, inf};
-#pragma unroll
-        for (int t = 13; t >= 0; --t) s[t] = insert(s[t + 1], u[t]);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Order statistics by radix selection on the order-preserving integer image
 // of the float values.  State lives in device memory so that the passes run
 // back to back on the stream.
@@ -234,7 +166,10 @@ struct SelState {
     unsigned any_valid;    // 0: no B-scan valid, every sample counts
     unsigned prefix[4];    // selected high bits of each target
     unsigned rank[4];      // rank of each target among the samples with that prefix
-    unsigned pad[2];
+    unsigned uprefix[4];   // the distinct prefixes, one histogram each in the next pass
+    unsigned slot[4];      // index of each target's prefix in uprefix
+    unsigned nu;           // number of distinct prefixes
+    unsigned pad;
     double value[4];       // the four order statistics
     double p5, p95, thr_r; // percentiles and the threshold on the filtered volume
     double mu, thr_s;      // OCT noise mean and threshold
@@ -248,6 +183,115 @@ __device__ __forceinline__ unsigned ord_key(float v)
 __device__ __forceinline__ float from_key(unsigned k)
 {
     return __builtin_bit_cast(float, (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// ---------------------------------------------------------------------------
+// Rank filter: the 3rd smallest of the 15 samples p-7 .. p+7 along one
+// lateral axis, clamped at the ends.
+//
+// A wave owns 64 consecutive depths of one line and a segment of kRankSeg
+// positions, which it walks in chunks of 15 aligned so that chunk c spans
+// p0-7+15c .. p0+7+15c.  The window of output p = p0+15c+t is the tail of
+// chunk c from offset t joined with the head of chunk c+1 up to offset t-1:
+// the three smallest of each part are kept sorted (suffix triples of chunk
+// c, a running prefix triple of chunk c+1), and the 3rd smallest of the
+// union of two sorted triples a, b is min(a3, b3, max(a1, b2), max(a2, b1)).
+// Inserting v into a sorted triple gives (min(a1, v), med3(a1, a2, v),
+// med3(a2, a3, v)).  Every sample is loaded once per segment.
+//
+// With kHist (the slow-axis pass, whose positions are the B-scans) the
+// kernel also counts bits 31..21 of every output of a valid B-scan: the
+// first radix pass of the percentile selection.  Along the walk a lane's
+// outputs change bin rarely, so each lane adds runs of equal bins.
+constexpr int kRankSeg = 120;  // a multiple of 15
+
+struct Tri {
+    float a, b, c;
+};
+__device__ __forceinline__ Tri insert(Tri t, float v)
+{
+    return Tri{__builtin_fminf(t.a, v), med3f(t.a, t.b, v), med3f(t.b, t.c, v)};
+}
+__device__ __forceinline__ float third_of_union(Tri s, Tri p)
+{
+    return min3f(__builtin_fminf(s.c, p.c), __builtin_fmaxf(s.a, p.b), __builtin_fmaxf(s.b, p.a));
+}
+
+template <bool kHist>
+__global__ __launch_bounds__(256) void k_rank15(const float* __restrict__ in, float* __restrict__ out, int w, int h,
+                                                int d, int axis, const float* __restrict__ valid,
+                                                const SelState* __restrict__ st, unsigned* __restrict__ hist)
+{
+    __shared__ unsigned lh[kHist ? kHistBins : 1];
+    if (kHist) {
+        for (int t = threadIdx.x; t < kHistBins; t += blockDim.x) lh[t] = 0u;
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & 63;
+    const int ktiles = (d + 63) >> 6;
+    const int n = axis == 0 ? w : h;
+    const int nseg = (n + kRankSeg - 1) / kRankSeg;
+    const int nlines = axis == 0 ? h : w;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid < nlines * ktiles * nseg) {  // uniform per wave
+        const int seg = wid % nseg, rest = wid / nseg;
+        const int kt = rest % ktiles, o = rest / ktiles;
+        const int k = kt * 64 + lane;
+        const int kc = k < d ? k : d - 1;
+        const bool store = k < d;
+        const int p0 = seg * kRankSeg, p1 = min(p0 + kRankSeg, n);
+        const size_t stride = axis == 0 ? (size_t)d : (size_t)w * d;
+        const size_t base = (axis == 0 ? (size_t)o * w * d : (size_t)o * d) + kc;
+        const float* __restrict__ p = in + base;
+        float* __restrict__ q = out + base;
+        const unsigned anyv = kHist ? st->any_valid : 0u;
+        int cur = -1;       // bin of the current run of this lane's outputs
+        unsigned run = 0u;  // and its length
+        auto ld = [&](int pos) {
+            pos = pos < 0 ? 0 : (pos >= n ? n - 1 : pos);
+            return p[(size_t)pos * stride];
+        };
+        constexpr float inf = __builtin_inff();
+        float u[15];
+        Tri s[15];
+#pragma unroll
+        for (int t = 0; t < 15; ++t) u[t] = ld(p0 - 7 + t);
+        s[14] = Tri{u[14], inf, inf};
+#pragma unroll
+        for (int t = 13; t >= 0; --t) s[t] = insert(s[t + 1], u[t]);
+        for (int c0 = p0; c0 < p1; c0 += 15) {
+#pragma unroll
+            for (int t = 0; t < 15; ++t) u[t] = ld(c0 + 8 + t);
+            Tri pre{inf, inf, inf};
+#pragma unroll
+            for (int t = 0; t < 15; ++t) {
+                if (c0 + t < p1) {  // uniform
+                    const float r = third_of_union(s[t], pre);
+                    if (store) q[(size_t)(c0 + t) * stride] = r;
+                    if (kHist) {
+                        const bool ok = store && (!anyv || valid[c0 + t] > 0.5f);
+                        const int bin = ok ? (int)(ord_key(r) >> 21) : -1;
+                        if (bin != cur) {
+                            if (cur >= 0) atomicAdd(&lh[cur], run);
+                            cur = bin;
+                            run = 0u;
+                        }
+                        ++run;
+                    }
+                }
+                pre = insert(pre, u[t]);
+            }
+            s[14] = Tri{u[14], inf, inf};
+#pragma unroll
+            for (int t = 13; t >= 0; --t) s[t] = insert(s[t + 1], u[t]);
+        }
+        if (kHist && cur >= 0) atomicAdd(&lh[cur], run);
+    }
+    if (kHist) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < kHistBins; t += blockDim.x)
+            if (lh[t]) atomicAdd(&hist[t], lh[t]);
+    }
 }
 
 // Nearest valid B-scan of each B-scan (the lower index on a tie; itself when
@@ -279,67 +323,91 @@ __global__ __launch_bounds__(256) void k_enface_init(const float* __restrict__ v
     }
 }
 
-// pass 0: bits 31..21 of every sample; pass 1: bits 20..10 of the samples
-// whose bits 31..21 equal a target's prefix; pass 2: bits 9..0 of those whose
-// bits 31..10 do.  One LDS histogram of kHistBins counters per target.
+// Radix passes 1 and 2 over the filtered volume: pass 1 counts bits 20..10
+// of the samples whose bits 31..21 equal one of the distinct target
+// prefixes, pass 2 bits 9..0 of those whose bits 31..10 do; one histogram of
+// kHistBins counters per distinct prefix.  Few samples match, so each adds
+// its own count.  A wave walks A-scans with eight loads in flight per lane.
+// Pass 0 is counted by the slow-axis rank filter.
 __global__ __launch_bounds__(256) void k_radix_hist(const float* __restrict__ vol, int w, int h, int d, int V,
                                                     const float* __restrict__ valid, const SelState* __restrict__ st,
                                                     int pass, unsigned* __restrict__ hist)
 {
     __shared__ unsigned lh[4 * kHistBins];
-    const int nt = pass == 0 ? 1 : 4;
-    for (int t = threadIdx.x; t < nt * kHistBins; t += blockDim.x) lh[t] = 0u;
+    const int nu = (int)st->nu;
+    for (int t = threadIdx.x; t < nu * kHistBins; t += blockDim.x) lh[t] = 0u;
     __syncthreads();
     const unsigned any = st->any_valid;
     unsigned pre[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) pre[t] = st->prefix[t];
+    for (int t = 0; t < 4; ++t) pre[t] = t < nu ? st->uprefix[t] : 0xFFFFFFFFu;
+    const int shift = pass == 1 ? 21 : 10;
+    const unsigned dmask = pass == 1 ? 2047u : 1023u;
+    const int dshift = pass == 1 ? 10 : 0;
     const int lane = threadIdx.x & 63;
-    const int nwaves = gridDim.x * (blockDim.x >> 6);
-    const size_t na = (size_t)w * h;
-    for (size_t a = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < na; a += nwaves) {
-        const int i = (int)(a % w), j = (int)(a / w);
-        const int b = V == 0 ? j : i;
+    const unsigned nwaves = gridDim.x * (blockDim.x >> 6);
+    const unsigned na = (unsigned)w * (unsigned)h;
+    for (unsigned a = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < na; a += nwaves) {
+        const unsigned j = a / (unsigned)w, i = a - j * (unsigned)w;
+        const unsigned b = V == 0 ? j : i;
         if (any && !(valid[b] > 0.5f)) continue;  // uniform per wave
-        const float* __restrict__ col = vol + a * d;
-        for (int k = lane; k < d; k += 64) {
-            const unsigned key = ord_key(col[k]);
-            if (pass == 0) {
-                atomicAdd(&lh[key >> 21], 1u);
-            } else if (pass == 1) {
+        const float* __restrict__ col = vol + (size_t)a * d;
+        for (int k0 = 0; k0 < d; k0 += 512) {
+            float v[8];
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if ((key >> 21) == pre[t]) atomicAdd(&lh[t * kHistBins + ((key >> 10) & 2047u)], 1u);
-            } else {
+            for (int e = 0; e < 8; ++e) {
+                const int kk = k0 + e * 64 + lane;
+                v[e] = kk < d ? col[kk] : 0.0f;
+            }
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if ((key >> 10) == pre[t]) atomicAdd(&lh[t * kHistBins + (key & 1023u)], 1u);
+            for (int e = 0; e < 8; ++e) {
+                if (k0 + e * 64 + lane < d) {
+                    const unsigned key = ord_key(v[e]);
+                    const unsigned hi = key >> shift;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (hi == pre[t]) atomicAdd(&lh[t * kHistBins + ((key >> dshift) & dmask)], 1u);
+                }
             }
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nt * kHistBins; t += blockDim.x)
+    for (int t = threadIdx.x; t < nu * kHistBins; t += blockDim.x)
         if (lh[t]) atomicAdd(&hist[t], lh[t]);
 }
 
-// One block: find, for each target, the bin holding its rank; after the last
-// pass form the order statistics, the percentiles and the threshold.  Clears
-// the histogram for the next pass.
+// One block: for each target, the bin whose counts cross its rank (a block
+// scan of the histogram); after the last pass the order statistics, the
+// percentiles and the threshold.  Clears the histograms it read.
 __global__ __launch_bounds__(256) void k_radix_select(unsigned* __restrict__ hist, SelState* st, int pass)
 {
 #pragma clang fp contract(off)
-    __shared__ unsigned sh[4][kHistBins];
+    __shared__ unsigned scan[256];
     __shared__ unsigned target[4];
-    const int nt = pass == 0 ? 1 : 4;
-    for (int t = threadIdx.x; t < nt * kHistBins; t += blockDim.x) {
-        sh[t / kHistBins][t % kHistBins] = hist[t];
-        hist[t] = 0u;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (pass == 0) {
-            unsigned n = 0;
-            for (int b = 0; b < kHistBins; ++b) n += sh[0][b];
+    const int nbins = pass == 2 ? 1024 : kHistBins;
+    const int per = nbins / 256;
+    const int nslot = pass == 0 ? 1 : (int)st->nu;
+    const int tid = threadIdx.x;
+    for (int u = 0; u < nslot; ++u) {
+        const unsigned* hh = hist + (size_t)u * kHistBins;
+        unsigned c[8];
+        unsigned local = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            c[e] = e < per ? hh[tid * per + e] : 0u;
+            local += c[e];
+        }
+        scan[tid] = local;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {  // inclusive scan
+            const unsigned v = tid >= off ? scan[tid - off] : 0u;
+            __syncthreads();
+            scan[tid] += v;
+            __syncthreads();
+        }
+        const unsigned excl = scan[tid] - local;
+        if (pass == 0 && tid == 0) {
+            const unsigned n = scan[255];
             st->n = n;
             const double q[2] = {0.05, 0.95};
             for (int e = 0; e < 2; ++e) {
@@ -349,55 +417,65 @@ __global__ __launch_bounds__(256) void k_radix_select(unsigned* __restrict__ his
                 target[2 * e] = lo;
                 target[2 * e + 1] = lo + 1 < n ? lo + 1 : n - 1;
             }
-        } else {
-            for (int t = 0; t < 4; ++t) target[t] = st->rank[t];
+        } else if (pass > 0 && tid < 4) {
+            target[tid] = st->rank[tid];
         }
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        const int t = threadIdx.x;
-        const unsigned* hh = sh[pass == 0 ? 0 : t];
-        const int nbins = pass == 2 ? 1024 : kHistBins;
-        unsigned r = target[t], cum = 0;
-        int bin = 0;
-        for (; bin < nbins; ++bin) {
-            if (r < cum + hh[bin]) break;
-            cum += hh[bin];
-        }
-        if (pass == 0) {
-            st->prefix[t] = (unsigned)bin;
-        } else if (pass == 1) {
-            st->prefix[t] = (st->prefix[t] << 11) | (unsigned)bin;
-        } else {
-            st->value[t] = (double)from_key((st->prefix[t] << 10) | (unsigned)bin);
-        }
-        st->rank[t] = r - cum;
-    }
-    __syncthreads();
-    if (pass == 2 && threadIdx.x == 0) {
-        const unsigned n = st->n;
-        const double q[2] = {0.05, 0.95};
-        double p[2];
-        for (int e = 0; e < 2; ++e) {
-            const double pos = q[e] * (double)(n - 1);
-            unsigned lo = (unsigned)floor(pos);
-            if (lo >= n - 1) lo = n - 1;
-            const double frac = pos - (double)lo;
-            const double x0 = st->value[2 * e], x1 = st->value[2 * e + 1];
-            if (lo + 1 < n) {
-                const double dx = x1 - x0;
-                const double step = frac * dx;
-                p[e] = x0 + step;
-            } else {
-                p[e] = x0;
+        __syncthreads();
+        for (int t = 0; t < 4; ++t) {
+            if (pass > 0 && (int)st->slot[t] != u) continue;
+            const unsigned r = target[t];
+            if (r >= excl && r < excl + local) {
+                unsigned cum = excl;
+                int e = 0;
+                for (; e < per - 1; ++e) {
+                    if (r < cum + c[e]) break;
+                    cum += c[e];
+                }
+                const unsigned bin = (unsigned)(tid * per + e);
+                if (pass == 0) st->prefix[t] = bin;
+                else if (pass == 1) st->prefix[t] = (st->prefix[t] << 11) | bin;
+                else st->value[t] = (double)from_key((st->prefix[t] << 10) | bin);
+                st->rank[t] = r - cum;
             }
         }
-        st->p5 = p[0];
-        st->p95 = p[1];
-        const double span = p[1] - p[0];
-        const double off = 0.1 * span;
-        st->thr_r = p[0] + off;
+        __syncthreads();
     }
+    for (int t = tid; t < nslot * kHistBins; t += blockDim.x) hist[t] = 0u;
+    __syncthreads();
+    if (tid != 0) return;
+    if (pass < 2) {
+        unsigned nu = 0;
+        for (int t = 0; t < 4; ++t) {
+            unsigned u = 0;
+            while (u < nu && st->uprefix[u] != st->prefix[t]) ++u;
+            if (u == nu) st->uprefix[nu++] = st->prefix[t];
+            st->slot[t] = u;
+        }
+        st->nu = nu;
+        return;
+    }
+    const unsigned n = st->n;
+    const double q[2] = {0.05, 0.95};
+    double p[2];
+    for (int e = 0; e < 2; ++e) {
+        const double pos = q[e] * (double)(n - 1);
+        unsigned lo = (unsigned)floor(pos);
+        if (lo >= n - 1) lo = n - 1;
+        const double frac = pos - (double)lo;
+        const double x0 = st->value[2 * e], x1 = st->value[2 * e + 1];
+        if (lo + 1 < n) {
+            const double dx = x1 - x0;
+            const double step = frac * dx;
+            p[e] = x0 + step;
+        } else {
+            p[e] = x0;
+        }
+    }
+    st->p5 = p[0];
+    st->p95 = p[1];
+    const double span = p[1] - p[0];
+    const double off = 0.1 * span;
+    st->thr_r = p[0] + off;
 }
 
 // A fixed normalisation mapping in place of the percentiles.
@@ -412,45 +490,60 @@ __global__ void k_set_fixed(SelState* st, double p5, double p95)
 }
 
 // OCT noise statistics over the first nz samples of every A-scan: pass 0
-// sums the samples, pass 1 the squared deviations from their mean.  Partial
-// sums per block, combined in a fixed order by k_noise_final.
+// sums the samples, pass 1 the squared deviations from their mean.  One wave
+// per A-scan; partial sums per block, combined in a fixed order by
+// k_noise_final.
+__device__ __forceinline__ double block_sum(double v, double* red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
 __global__ __launch_bounds__(256) void k_noise_sum(const float* __restrict__ oct, size_t na, int d, int nz,
                                                    const SelState* __restrict__ st, int pass,
                                                    double* __restrict__ partial)
 {
     __shared__ double red[256];
     const double mu = pass ? st->mu : 0.0;
+    const int lane = threadIdx.x & 63;
+    const size_t nwaves = (size_t)gridDim.x * (blockDim.x >> 6);
     double acc = 0.0;
-    const size_t n = na * nz;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const size_t a = e / nz, k = e - a * nz;
-        const double x = oct[a * d + k];
-        if (pass == 0) {
-            acc += x;
-        } else {
-            const double t = x - mu;
-            acc += t * t;
+#pragma unroll 4
+    for (size_t a = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); a < na; a += nwaves) {
+        for (int k = lane; k < nz; k += 64) {
+            const double x = oct[a * d + k];
+            if (pass == 0) {
+                acc += x;
+            } else {
+                const double t = x - mu;
+                acc += t * t;
+            }
         }
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ void k_noise_final(const double* __restrict__ partial, int nblk, double cnt, int pass, SelState* st)
+__global__ __launch_bounds__(256) void k_noise_final(const double* __restrict__ partial, int nblk, double cnt,
+                                                     int pass, SelState* st)
 {
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) v += partial[b];
+    const double s = block_sum(v, red);
     if (threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[b];
     if (pass == 0) st->mu = s / cnt;
     else st->thr_s = st->mu + 2.0 * sqrt(s / cnt);
 }
 
-// Both masks and the masked depth mean; one wave per A-scan.
+// Both masks and the masked depth mean; one wave per A-scan.  kVec: four
+// depths per lane with 16-byte loads (d a multiple of 4, aligned volumes).
+template <bool kVec>
 __global__ __launch_bounds__(256) void k_mask_mean(const float* __restrict__ filt, const float* __restrict__ oct,
                                                    const float* __restrict__ octa, size_t na, int d,
                                                    const SelState* __restrict__ st, double* __restrict__ E,
@@ -463,11 +556,26 @@ __global__ __launch_bounds__(256) void k_mask_mean(const float* __restrict__ fil
         const size_t o = a * d;
         double acc = 0.0;
         int c = 0;
-        for (int k = lane; k < d; k += 64) {
-            const double r = filt[o + k], s = oct[o + k];
-            if (r < thr_r && s > thr_s) {
-                acc += (double)octa[o + k];
-                ++c;
+        if (kVec) {
+            const float4* __restrict__ r4 = reinterpret_cast<const float4*>(filt + o);
+            const float4* __restrict__ s4 = reinterpret_cast<const float4*>(oct + o);
+            const float4* __restrict__ a4 = reinterpret_cast<const float4*>(octa + o);
+            const int d4 = d >> 2;
+#pragma unroll 4
+            for (int k = lane; k < d4; k += 64) {
+                const float4 r = r4[k], s = s4[k], v = a4[k];
+                if ((double)r.x < thr_r && (double)s.x > thr_s) { acc += (double)v.x; ++c; }
+                if ((double)r.y < thr_r && (double)s.y > thr_s) { acc += (double)v.y; ++c; }
+                if ((double)r.z < thr_r && (double)s.z > thr_s) { acc += (double)v.z; ++c; }
+                if ((double)r.w < thr_r && (double)s.w > thr_s) { acc += (double)v.w; ++c; }
+            }
+        } else {
+            for (int k = lane; k < d; k += 64) {
+                const double r = filt[o + k], s = oct[o + k];
+                if (r < thr_r && s > thr_s) {
+                    acc += (double)octa[o + k];
+                    ++c;
+                }
             }
         }
 #pragma unroll
@@ -571,19 +679,26 @@ hipError_t launch_enface_project(const float* oct, const float* octa, int w, int
         valid = vd;
     }
     hipLaunchKernelGGL(k_enface_init, dim3(1), dim3(256), 0, s, valid, (int)nb, from, st, hist);
-    // filtering
+    // filtering; the slow-axis pass also counts the first radix digit
     const dim3 gm((d + kMedTile - 1) / kMedTile, (w + kMedSeg - 1) / kMedSeg, (h + 3) / 4);
     hipLaunchKernelGGL(k_median3, gm, dim3(256), 0, s, octa, v0, w, h, d);
     const int ktiles = (d + 63) / 64;
     const int fast = V == 0 ? 0 : 1, slow = 1 - fast;
-    const int wf = (fast == 0 ? h : w) * ktiles, ws = (slow == 0 ? h : w) * ktiles;
-    hipLaunchKernelGGL(k_rank15, dim3((wf + 3) / 4), dim3(256), 0, s, v0, v1, w, h, d, fast);
-    hipLaunchKernelGGL(k_rank15, dim3((ws + 3) / 4), dim3(256), 0, s, v1, v0, w, h, d, slow);
-    // normalisation
+    auto waves = [&](int axis) {
+        const int n = axis == 0 ? w : h, lines = axis == 0 ? h : w;
+        return lines * ktiles * ((n + kRankSeg - 1) / kRankSeg);
+    };
+    hipLaunchKernelGGL(k_rank15<false>, dim3((waves(fast) + 3) / 4), dim3(256), 0, s, v0, v1, w, h, d, fast, valid,
+                       st, hist);
     if (fixed) {
+        hipLaunchKernelGGL(k_rank15<false>, dim3((waves(slow) + 3) / 4), dim3(256), 0, s, v1, v0, w, h, d, slow,
+                           valid, st, hist);
         hipLaunchKernelGGL(k_set_fixed, dim3(1), dim3(1), 0, s, st, fixed[0], fixed[1]);
     } else {
-        for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(k_rank15<true>, dim3((waves(slow) + 3) / 4), dim3(256), 0, s, v1, v0, w, h, d, slow,
+                           valid, st, hist);
+        hipLaunchKernelGGL(k_radix_select, dim3(1), dim3(256), 0, s, hist, st, 0);
+        for (int pass = 1; pass < 3; ++pass) {
             hipLaunchKernelGGL(k_radix_hist, dim3(kHistBlocks), dim3(256), 0, s, v0, w, h, d, V, valid, st, pass,
                                hist);
             hipLaunchKernelGGL(k_radix_select, dim3(1), dim3(256), 0, s, hist, st, pass);
@@ -593,11 +708,15 @@ hipError_t launch_enface_project(const float* oct, const float* octa, int w, int
     const int nz = (int)floor(0.05 * d + 0.5) < 1 ? 1 : (int)floor(0.05 * d + 0.5);
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_noise_sum, dim3(kNoiseBlocks), dim3(256), 0, s, oct, na, d, nz, st, pass, part);
-        hipLaunchKernelGGL(k_noise_final, dim3(1), dim3(64), 0, s, part, kNoiseBlocks, (double)na * nz, pass, st);
+        hipLaunchKernelGGL(k_noise_final, dim3(1), dim3(256), 0, s, part, kNoiseBlocks, (double)na * nz, pass, st);
     }
     // masks, depth mean, B-scan median, substitution
-    hipLaunchKernelGGL(k_mask_mean, dim3((unsigned)std::min<size_t>((na + 3) / 4, 65536)), dim3(256), 0, s, v0, oct,
-                       octa, na, d, st, E, count ? count : cnt);
+    const bool vec = (d & 3) == 0 && ((uintptr_t)oct & 15) == 0 && ((uintptr_t)octa & 15) == 0;
+    const dim3 gmm((unsigned)std::min<size_t>((na + 3) / 4, 65536));
+    if (vec)
+        hipLaunchKernelGGL(k_mask_mean<true>, gmm, dim3(256), 0, s, v0, oct, octa, na, d, st, E, count ? count : cnt);
+    else
+        hipLaunchKernelGGL(k_mask_mean<false>, gmm, dim3(256), 0, s, v0, oct, octa, na, d, st, E, count ? count : cnt);
     hipLaunchKernelGGL(k_bscan_median, dim3((unsigned)nb), dim3(512), 0, s, E, w, h, V, med);
     hipLaunchKernelGGL(k_enface_finish, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, E, med, from, w, h, V,
                        out);
