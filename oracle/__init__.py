@@ -112,6 +112,22 @@ def lib():
         L.orc_quantile_valid.restype = C.c_double
         L.orc_enface_project.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp]
         L.orc_enface_project.restype = None
+        L.orc_tilt_expand.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.orc_tilt_expand.restype = None
+        L.orc_tilt_reduce.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.orc_tilt_reduce.restype = None
+        L.orc_tilt_term.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_double, dp]
+        L.orc_tilt_term.restype = C.c_double
+        L.orc_prealign_eval.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, dp, C.POINTER(_Params), C.c_double, dp,
+                                        dp]
+        L.orc_prealign_eval.restype = C.c_double
+        L.orc_tilt_upsample.argtypes = [dp, C.c_int, C.c_int, dp, C.c_int, C.c_int]
+        L.orc_tilt_upsample.restype = None
+        L.orc_prealign.argtypes = [dp, dp, C.c_int, C.c_int, C.c_int, C.POINTER(_Params), C.c_double, C.c_int, dp,
+                                   dp]
+        L.orc_prealign.restype = C.c_int
+        L.orc_resample_z.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, dp]
+        L.orc_resample_z.restype = None
         L.orc_validity.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.orc_validity.restype = None
         L.orc_round_storage.argtypes = [dp, C.c_size_t, C.c_int]
@@ -420,3 +436,74 @@ def enface_project(oct_vol, octa_vol, V: int, valid=None, fixed=None, details=Fa
     lib().orc_enface_project(_p(o), _p(a), w, h, d, int(V), _p(valid), None if fx is None else _p(fx), _p(out),
                              _p(cnt), _p(st))
     return (out, cnt, st) if details else out
+
+
+# ----------------------------------------------------------------------------
+# Stage 1, rough axial prealignment.  theta: X-fast B-scans (h rows) then
+# Y-fast B-scans (w columns), (z_b, t_b) each: 2 (h + w) values.
+
+def tilt_expand(theta, w: int, h: int):
+    th = _f64(theta)
+    D = np.zeros((2, h, w, 3))
+    lib().orc_tilt_expand(_p(th), w, h, _p(D))
+    return D
+
+
+def tilt_reduce(G):
+    G = _f64(G)
+    _, h, w, _ = G.shape
+    out = np.zeros(2 * (w + h))
+    lib().orc_tilt_reduce(_p(G), w, h, _p(out))
+    return out
+
+
+def tilt_term(theta, w: int, h: int, d: int, gamma_t: float = 1.0):
+    th = _f64(theta)
+    g = np.zeros(2 * (w + h))
+    T = lib().orc_tilt_term(_p(th), w, h, d, float(gamma_t), _p(g))
+    return T, g
+
+
+def prealign_eval(sx, sy, theta, params: Params | None = None, gamma_t: float = 1.0):
+    """Stage-1 objective F + T at theta: (terms dict with "T" and "F1", gradient)."""
+    params = params or Params()
+    sx, sy, th = _f64(sx), _f64(sy), _f64(theta)
+    h, w, d = sx.shape
+    terms = np.zeros(9)
+    g = np.zeros(2 * (w + h))
+    pc = params.c()
+    f1 = lib().orc_prealign_eval(_p(sx), _p(sy), w, h, d, _p(th), C.byref(pc), float(gamma_t), _p(terms), _p(g))
+    t = dict(zip(TERM_NAMES, terms[:8].tolist()))
+    t["T"] = float(terms[8])
+    t["F1"] = float(f1)
+    return t, g
+
+
+def tilt_upsample(theta_c, wc: int, hc: int, wf: int, hf: int):
+    tc = _f64(theta_c)
+    out = np.zeros(2 * (wf + hf))
+    lib().orc_tilt_upsample(_p(tc), wc, hc, _p(out), wf, hf)
+    return out
+
+
+def prealign(sx, sy, params: Params | None = None, gamma_t: float = 1.0, iters: int = 100):
+    """The stage-1 solve on the pyramid: theta at the finest level and
+    per-level reports (coarsest first)."""
+    params = params or Params()
+    sx, sy = _f64(sx), _f64(sy)
+    h, w, d = sx.shape
+    th = np.zeros(2 * (w + h))
+    rep = np.zeros((params.levels, 4))
+    pc = params.c()
+    rc = lib().orc_prealign(_p(sx), _p(sy), w, h, d, C.byref(pc), float(gamma_t), int(iters), _p(th), _p(rep))
+    if rc:
+        raise RuntimeError(f"orc_prealign failed ({rc})")
+    return th, [dict(f_start=r[0], f_end=r[1], iters=int(r[2]), evals=int(r[3])) for r in rep]
+
+
+def resample_z(vol, dz):
+    vol, dz = _f64(vol), _f64(dz)
+    h, w, d = vol.shape
+    out = np.zeros_like(vol)
+    lib().orc_resample_z(_p(vol), w, h, d, _p(dz), _p(out))
+    return out

@@ -1192,3 +1192,227 @@ EXPORT void orc_enface_project(const double* oct, const double* octa, int w, int
     free(m);
     free(r);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Stage 1, rough axial prealignment (Fig. 1, Sec. 2.1 "optimization"): the
+ * same objective, with displacements restricted to the axial direction at
+ * B-scan granularity plus a tilt within each B-scan, on the factor-2 pyramid.
+ * The en face OCTA term is not used (Sec. 2.4), so delta0 = 0 and eta = 1.
+ *
+ * Parameters theta: for the X-fast scan h B-scans (rows j, fast axis x, w
+ * A-scans each), then for the Y-fast scan w B-scans (columns i, fast axis y,
+ * h A-scans); per B-scan (z_b, t_b).  The field is
+ *   dz(f, b) = z_b + t_b (f - (n_f - 1) / 2),  dx = dy = 0,
+ * f the index along the fast axis, n_f the B-scan length.
+ *
+ * T, the tilt normalisation (Eq. 1), is defined only in earlier work that is
+ * not available; reading (parity unpinned): a quadratic penalty on the sum of
+ * each scan's tilts, which fixes the two degrees of freedom the data term
+ * cannot see (a common plane a x + b y added to both scans' fields), as M
+ * fixes the translations:
+ *   T = sum_V gamma_t d n_f (n_f^2 - 1) / (24 n_b) (sum_b t_b)^2,
+ * scaled so that a uniform tilt tau costs gamma_t d N_A var_f tau^2 / 2. */
+static void tilt_dims(int V, int w, int h, int* nb, int* nf, int* off)
+{
+    *nb = V == 0 ? h : w;
+    *nf = V == 0 ? w : h;
+    *off = V == 0 ? 0 : 2 * h;
+}
+
+EXPORT void orc_tilt_expand(const double* th, int w, int h, double* D)
+{
+    memset(D, 0, (size_t)2 * w * h * 3 * sizeof(double));
+    for (int V = 0; V < 2; V++) {
+        int nb, nf, off;
+        tilt_dims(V, w, h, &nb, &nf, &off);
+        const double c = 0.5 * (nf - 1);
+        for (int j = 0; j < h; j++)
+            for (int i = 0; i < w; i++) {
+                const int f = V == 0 ? i : j, b = V == 0 ? j : i;
+                D[(((size_t)V * h + j) * w + i) * 3 + 2] = th[off + 2 * b] + th[off + 2 * b + 1] * (f - c);
+            }
+    }
+}
+
+/* Adjoint of orc_tilt_expand: gradient with respect to theta from the
+ * gradient G ([2][h][w][3]) with respect to the field. */
+EXPORT void orc_tilt_reduce(const double* G, int w, int h, double* gth)
+{
+    memset(gth, 0, (size_t)2 * (w + h) * sizeof(double));
+    for (int V = 0; V < 2; V++) {
+        int nb, nf, off;
+        tilt_dims(V, w, h, &nb, &nf, &off);
+        const double c = 0.5 * (nf - 1);
+        for (int j = 0; j < h; j++)
+            for (int i = 0; i < w; i++) {
+                const int f = V == 0 ? i : j, b = V == 0 ? j : i;
+                const double g = G[(((size_t)V * h + j) * w + i) * 3 + 2];
+                gth[off + 2 * b] += g;
+                gth[off + 2 * b + 1] += g * (f - c);
+            }
+    }
+}
+
+/* T and, if gth != NULL, its gradient added into gth. */
+EXPORT double orc_tilt_term(const double* th, int w, int h, int d, double gamma_t, double* gth)
+{
+    double T = 0;
+    for (int V = 0; V < 2; V++) {
+        int nb, nf, off;
+        tilt_dims(V, w, h, &nb, &nf, &off);
+        double s = 0;
+        for (int b = 0; b < nb; b++) s += th[off + 2 * b + 1];
+        const double kap = gamma_t * d * (double)nf * ((double)nf * nf - 1.0) / (24.0 * nb);
+        T += kap * s * s;
+        if (gth)
+            for (int b = 0; b < nb; b++) gth[off + 2 * b + 1] += 2.0 * kap * s;
+    }
+    return T;
+}
+
+/* Stage-1 objective at theta: terms[T_COUNT] as orc_eval (delta0 = 0, no en
+ * face images) plus terms[T_COUNT] = T; returns F + T.  gth may be NULL. */
+EXPORT double orc_prealign_eval(const double* sx, const double* sy, int w, int h, int d, const double* th,
+                                const orc_params* p, double gamma_t, double* terms, double* gth)
+{
+    const size_t na = (size_t)w * h;
+    double* D = (double*)malloc(2 * na * 3 * sizeof(double));
+    double* G = gth ? (double*)calloc(2 * na * 3, sizeof(double)) : NULL;
+    double* zero = (double*)calloc(na, sizeof(double));
+    double* ones = (double*)malloc((size_t)(w > h ? w : h) * sizeof(double));
+    for (int q = 0; q < (w > h ? w : h); q++) ones[q] = 1.0;
+    orc_params p1 = *p;
+    p1.delta0 = 0.0;
+    orc_tilt_expand(th, w, h, D);
+    orc_eval(sx, sy, zero, zero, ones, ones, w, h, d, D, &p1, 1.0, terms, G);
+    if (gth) orc_tilt_reduce(G, w, h, gth);
+    const double T = orc_tilt_term(th, w, h, d, gamma_t, gth);
+    terms[T_COUNT] = T;
+    free(D);
+    free(G);
+    free(zero);
+    free(ones);
+    return terms[T_F] + T;
+}
+
+/* Level transition of theta (reading): the fine field is twice the coarse
+ * field at the coarse position ((f - 0.5)/2, (b - 0.5)/2), linear along the
+ * fast axis as the field is, interpolated linearly between B-scans and
+ * clamped to the first and last.  Per fine B-scan this gives
+ *   t = t_c(u),  z = 2 z_c(u) + t (n_f - 2 n_fc) / 2,  u = (b - 0.5)/2. */
+EXPORT void orc_tilt_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf)
+{
+    for (int V = 0; V < 2; V++) {
+        int nbc, nfc, offc, nbf, nff, offf;
+        tilt_dims(V, wc, hc, &nbc, &nfc, &offc);
+        tilt_dims(V, wf, hf, &nbf, &nff, &offf);
+        for (int b = 0; b < nbf; b++) {
+            double u = (b - 0.5) / 2.0;
+            if (u < 0) u = 0;
+            if (u > nbc - 1) u = nbc - 1;
+            const int b0 = (int)floor(u), b1 = b0 + 1 < nbc ? b0 + 1 : nbc - 1;
+            const double fr = u - b0;
+            const double zc = (1 - fr) * coarse[offc + 2 * b0] + fr * coarse[offc + 2 * b1];
+            const double tc = (1 - fr) * coarse[offc + 2 * b0 + 1] + fr * coarse[offc + 2 * b1 + 1];
+            fine[offf + 2 * b + 1] = tc;
+            fine[offf + 2 * b] = 2.0 * zc + tc * 0.5 * (nff - 2.0 * nfc);
+        }
+    }
+}
+
+typedef struct {
+    const double *sx, *sy;
+    int w, h, d;
+    const orc_params* p;
+    double gamma_t;
+    double terms[T_COUNT + 1];
+} pre_ctx;
+
+static int pre_fg(void* vctx, const double* x, double* f, double* g)
+{
+    pre_ctx* c = (pre_ctx*)vctx;
+    *f = orc_prealign_eval(c->sx, c->sy, c->w, c->h, c->d, x, c->p, c->gamma_t, c->terms, g);
+    return 0;
+}
+
+/* The stage-1 solve: pyramid of the structural volumes (as orc_register,
+ * with the same storage rounding), theta = 0 at the coarsest level, L-BFGS
+ * with `iters` steps per level, orc_tilt_upsample between levels.  th_out:
+ * 2 (h + w) values at the finest level; levels_rep (may be NULL): per level,
+ * coarsest first, f_start, f_end, iters, evals. */
+EXPORT int orc_prealign(const double* sx, const double* sy, int w, int h, int d, const orc_params* p,
+                        double gamma_t, int iters, double* th_out, double* levels_rep)
+{
+    int L = p->levels;
+    if (L < 1 || L > 8) return -1;
+    int W[8], H[8], Dd[8];
+    double *SX[8], *SY[8];
+    W[0] = w; H[0] = h; Dd[0] = d;
+    SX[0] = (double*)sx; SY[0] = (double*)sy;
+    for (int l = 1; l < L; l++) {
+        W[l] = (W[l - 1] + 1) / 2; H[l] = (H[l - 1] + 1) / 2; Dd[l] = (Dd[l - 1] + 1) / 2;
+        const size_t nv = (size_t)W[l] * H[l] * Dd[l];
+        SX[l] = (double*)malloc(nv * sizeof(double));
+        SY[l] = (double*)malloc(nv * sizeof(double));
+        orc_pyr_down3(SX[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SX[l]);
+        orc_pyr_down3(SY[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SY[l]);
+    }
+    double *sx0 = NULL, *sy0 = NULL;
+    if (p->store) {
+        const size_t nv0 = (size_t)w * h * d;
+        sx0 = (double*)malloc(nv0 * sizeof(double));
+        sy0 = (double*)malloc(nv0 * sizeof(double));
+        memcpy(sx0, sx, nv0 * sizeof(double));
+        memcpy(sy0, sy, nv0 * sizeof(double));
+        SX[0] = sx0;
+        SY[0] = sy0;
+        for (int l = 0; l < L; l++) {
+            const size_t nv = (size_t)W[l] * H[l] * Dd[l];
+            orc_round_storage(SX[l], nv, p->store);
+            orc_round_storage(SY[l], nv, p->store);
+        }
+    }
+    int rc = 0;
+    double* tc = NULL;
+    for (int l = L - 1; l >= 0; l--) {
+        const int n = 2 * (W[l] + H[l]);
+        double* tl = (double*)calloc(n, sizeof(double));
+        if (tc) {
+            orc_tilt_upsample(tc, W[l + 1], H[l + 1], tl, W[l], H[l]);
+            free(tc);
+        }
+        pre_ctx ctx = {SX[l], SY[l], W[l], H[l], Dd[l], p, gamma_t, {0}};
+        orc_lbfgs_report rep;
+        rc = orc_lbfgs(n, tl, pre_fg, &ctx, p->lbfgs_m, iters, p->ls_max_evals, p->c1, p->c2, &rep);
+        if (levels_rep) {
+            double* r = levels_rep + (size_t)(L - 1 - l) * 4;
+            r[0] = rep.f_start; r[1] = rep.f_end; r[2] = rep.iters; r[3] = rep.evals;
+        }
+        tc = tl;
+        if (rc) break;
+    }
+    if (rc == 0) memcpy(th_out, tc, (size_t)2 * (w + h) * sizeof(double));
+    free(tc);
+    for (int l = 1; l < L; l++) {
+        free(SX[l]);
+        free(SY[l]);
+    }
+    free(sx0);
+    free(sy0);
+    return rc;
+}
+
+/* Axial resampling of a volume by a per-A-scan field (the prealigned volumes
+ * of Fig. 1): out(i, j, k) = I(vol, i, j, k + dz(i, j)), the interpolator of
+ * Eq. 2 at integer lateral positions, i.e. the 1-D Catmull-Rom spline along
+ * depth with constant extension. */
+EXPORT void orc_resample_z(const double* vol, int w, int h, int d, const double* dz, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (long a = 0; a < (long)w * h; a++)
+        for (int k = 0; k < d; k++) {
+            double v[2];
+            orc_sample1(vol + (size_t)a * d, d, k + dz[a], v);
+            out[(size_t)a * d + k] = v[0];
+        }
+}
