@@ -71,6 +71,8 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
 #define OCTMC_ENFACE_PROJECT 0x4u /* form the en face OCTA images by the segmentation-free projection
                                      of Sec. 2.3 (octmc_enface_project) instead of the depth mean when
                                      octmc_pair_create gets OCTA volumes and no en face images */
+#define OCTMC_PREALIGN 0x8u       /* octmc_pair_create first runs the stage-1 rough axial prealignment
+                                     (octmc_prealign) and ingests the prealigned volumes */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
  * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
@@ -89,7 +91,9 @@ typedef struct {
     double c1, c2;       /* strong Wolfe constants                                [R: 1e-4, 0.9] */
     double merge_kappa;  /* density weight decay exp(-kappa (rho - 1))            [R: 1.0]  */
     double merge_tau;    /* weights below tau are clipped to 0                    [R: 0.05] */
-    uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT */
+    uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN */
+    int32_t prealign_iters; /* stage-1 L-BFGS steps per level                     [100]     */
+    double gamma_tilt;   /* weight of the tilt normalisation T (Eq. 1, stage 1)   [R: 1.0]  */
 } octmc_params;
 
 typedef struct {
@@ -158,7 +162,13 @@ OCTMC_API int octmc_destroy(octmc_ctx* ctx);
  *                      volumes, derived from them as by
  *                      octmc_validity_from_octa.  X-fast B-scans are rows,
  *                      Y-fast columns.
- * Either both OCTA volumes or both en face images must be given.  All input
+ * Either both OCTA volumes or both en face images must be given.  With
+ * OCTMC_PREALIGN the stage-1 prealignment (octmc_prealign, with delta0 = 0
+ * and no en face images) runs first on the structural volumes; both
+ * structural and both OCTA volumes are resampled axially with its field
+ * (octmc_resample_axial) and the pair holds the prealigned volumes, so that
+ * validity detection, projection, registration and merge work on them;
+ * octmc_pair_prealignment returns the stage-1 result.  All input
  * pointers live in shape->mem memory.  The library copies every input into
  * its own device memory; the caller may free them once the call returns.
  * Errors: OCTMC_E_SHAPE (w != h, min(w, d) at the coarsest level < 4,
@@ -231,6 +241,57 @@ OCTMC_API int octmc_enface_project(octmc_ctx* ctx, const octmc_shape* shape, con
 /* Device bytes of the workspace octmc_enface_project needs for w x h x d
  * volumes.  Errors: OCTMC_E_INVALID (NULL), OCTMC_E_SHAPE (empty). */
 OCTMC_API int octmc_enface_workspace_size(int32_t w, int32_t h, int32_t d, uint64_t* bytes);
+
+/* Stage 1, rough axial prealignment (Fig. 1; Sec. 2.1 "optimization"):
+ * the objective of Eq. 1 restricted to axial displacements with one offset
+ * z_b and one tilt t_b per B-scan,
+ *   dz(f, b) = z_b + t_b (f - (n_f - 1) / 2),  dx = dy = 0,
+ * f the A-scan index along the fast axis, n_f the B-scan length, plus the
+ * tilt normalisation T.  T is defined only in earlier work; this library
+ * reads it as T = sum_V gamma_tilt d n_f (n_f^2 - 1) / (24 n_b) (sum_b t_b)^2,
+ * which fixes the two plane degrees of freedom the data term cannot see.
+ * theta layout (float64): the X-fast scan's h B-scans (rows j, n_f = w)
+ * then the Y-fast scan's w B-scans (columns i, n_f = h), (z_b, t_b) each:
+ * 2 (h + w) values at a level of w x h A-scans, in level pixels.
+ *
+ * octmc_prealign_eval: the stage-1 objective at level `level` and theta
+ * (host): terms (host float64[OCTMC_NTERMS]) as octmc_eval at the expanded
+ * field (the pair's parameters and stored eta; the paper's stage 1 has
+ * delta0 = 0, as the pair OCTMC_PREALIGN creates), T (host, may be NULL) and
+ * d(F + T)/d(theta) (host float64[2 (h + w)], may be NULL).  Synchronises
+ * `stream`.  Errors: OCTMC_E_INVALID, OCTMC_E_OOM, OCTMC_E_NAN, OCTMC_E_DEVICE. */
+OCTMC_API int octmc_prealign_eval(octmc_pair* pair, int32_t level, const double* theta, double gamma_tilt,
+                                  double* terms, double* tilt_term, double* grad_theta, void* stream);
+
+/* octmc_prealign: the stage-1 solve on the pair's pyramid: theta = 0 at the
+ * coarsest level, iters_per_level L-BFGS steps per level (the pair's lbfgs_m,
+ * line search constants), between levels the fine field is twice the coarse
+ * field at the fine A-scan's coarse position, linear along the fast axis and
+ * interpolated linearly between B-scans.  theta_out: host float64[2 (h + w)]
+ * at the finest level; rep (may be NULL) as octmc_register (eta = 1).
+ * Synchronises `stream`.  Errors: as octmc_prealign_eval. */
+OCTMC_API int octmc_prealign(octmc_pair* pair, double gamma_tilt, int32_t iters_per_level, double* theta_out,
+                             octmc_report* rep, void* stream);
+
+/* The stage-1 result of a pair created with OCTMC_PREALIGN: theta_out (host
+ * float64[2 (h + w)], may be NULL) and the axial field dz_out (device float32
+ * [2][h][w], may be NULL).  The displacements octmc_register returns for such
+ * a pair are relative to the prealigned volumes; the field to apply to the
+ * original scan V at output A-scan (i, j) is d^V plus (0, 0, dz^V) taken at
+ * (i + dx^V, j + dy^V).  Synchronises `stream` when dz_out is given.
+ * Errors: OCTMC_E_INVALID (no prealignment), OCTMC_E_OOM, OCTMC_E_DEVICE. */
+OCTMC_API int octmc_pair_prealignment(const octmc_pair* pair, double* theta_out, float* dz_out, void* stream);
+
+/* Axial resampling (the "prealigned volumes" of Fig. 1):
+ * out(i, j, k) = I(vol, i, j, k + dz(i, j)), the interpolator of Eq. 2 at
+ * integer lateral positions, i.e. the Catmull-Rom spline along depth with tap
+ * indices clamped to the A-scan.  vol [h][w][d] and dz [h][w] float32 live in
+ * shape->mem memory (shape->dtype is ignored); out is device float32
+ * [h][w][d].  Asynchronous for device inputs; host inputs are copied and the
+ * stream synchronised.  Errors: OCTMC_E_INVALID, OCTMC_E_SHAPE, OCTMC_E_OOM,
+ * OCTMC_E_DEVICE. */
+OCTMC_API int octmc_resample_axial(octmc_ctx* ctx, const octmc_shape* shape, const float* vol, const float* dz,
+                                   float* out, void* stream);
 
 /* Shape (w, h, d) of pyramid level `level` (0 = finest). */
 OCTMC_API int octmc_pair_level_shape(const octmc_pair* pair, int32_t level, int32_t* w, int32_t* h, int32_t* d);
@@ -337,7 +398,9 @@ OCTMC_API int octmc_server_create(octmc_ctx* ctx, uint64_t hbm_budget_bytes, int
                                   octmc_server** out);
 
 /* Queue a request; *id identifies its completion.  The call validates the
- * request and returns at once.  Errors: OCTMC_E_INVALID / SHAPE / DTYPE,
+ * request and returns at once.  OCTMC_PREALIGN is not accepted here: create
+ * the prealigned volumes with octmc_pair_create (or octmc_prealign and
+ * octmc_resample_axial) and submit those.  Errors: OCTMC_E_INVALID / SHAPE / DTYPE,
  * OCTMC_E_OOM if its footprint exceeds the whole budget (it could never be
  * admitted). */
 OCTMC_API int octmc_server_submit(octmc_server* srv, const octmc_request* req, uint64_t* id);

@@ -12,6 +12,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,6 +24,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 CHECK_NAN = 0x1
 DETECT_INVALID = 0x2
 ENFACE_PROJECT = 0x4
+PREALIGN = 0x8
 MAX_LEVELS = 8
 
 TERM_F, TERM_DATA, TERM_STR, TERM_ANG, TERM_REG, TERM_MEAN, TERM_STR05, TERM_ANG05, TERM_ETA, TERM_GP = range(10)
@@ -35,7 +37,8 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_DTYPE", -4: "E_OOM", -
 # exported symbols of include/octmc.h (checked by the CPU test suite)
 SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_create", "octmc_destroy",
            "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_validity_from_octa",
-           "octmc_enface_project", "octmc_enface_workspace_size", "octmc_eval",
+           "octmc_enface_project", "octmc_enface_workspace_size", "octmc_prealign_eval", "octmc_prealign",
+           "octmc_pair_prealignment", "octmc_resample_axial", "octmc_eval",
            "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge",
            "octmc_request_footprint", "octmc_server_create", "octmc_server_submit", "octmc_server_poll",
            "octmc_server_status", "octmc_server_destroy")
@@ -47,7 +50,8 @@ class Params(C.Structure):
                 ("eps_reg", C.c_double), ("flyback_frac", C.c_double), ("mean_weight", C.c_double),
                 ("levels", C.c_int32), ("iters_per_level", C.c_int32), ("lbfgs_m", C.c_int32),
                 ("ls_max_evals", C.c_int32), ("c1", C.c_double), ("c2", C.c_double),
-                ("merge_kappa", C.c_double), ("merge_tau", C.c_double), ("flags", C.c_uint32)]
+                ("merge_kappa", C.c_double), ("merge_tau", C.c_double), ("flags", C.c_uint32),
+                ("prealign_iters", C.c_int32), ("gamma_tilt", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -116,6 +120,11 @@ def lib():
         L.octmc_enface_project.argtypes = [vp, C.POINTER(Shape), vp, vp, C.c_int32, vp, C.POINTER(C.c_double), vp, vp,
                                            C.POINTER(C.c_double), vp, C.c_uint64, vp]
         L.octmc_enface_workspace_size.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_uint64)]
+        dpp = C.POINTER(C.c_double)
+        L.octmc_prealign_eval.argtypes = [vp, C.c_int32, dpp, C.c_double, dpp, dpp, dpp, vp]
+        L.octmc_prealign.argtypes = [vp, C.c_double, C.c_int32, dpp, C.POINTER(Report), vp]
+        L.octmc_pair_prealignment.argtypes = [vp, dpp, vp, vp]
+        L.octmc_resample_axial.argtypes = [vp, C.POINTER(Shape), vp, vp, vp, vp]
         L.octmc_eval.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.octmc_eval_profile.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), vp]
         L.octmc_eval_batched.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
@@ -211,7 +220,7 @@ class Pair:
 
     def __init__(self, sx, sy, *, ox=None, oy=None, ax=None, ay=None, vx=None, vy=None, params: Params | None = None,
                  dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,
-                 project_enface: bool = False, **param_overrides):
+                 project_enface: bool = False, prealign: bool = False, **param_overrides):
         self.ctx = ctx or context(0)
         dev = torch.device("cuda", self.ctx.device)
         self.params = params if params is not None else default_params()
@@ -221,6 +230,8 @@ class Pair:
             self.params.flags |= DETECT_INVALID
         if project_enface:  # en face images by the projection of Sec. 2.3 when ax, ay are not given
             self.params.flags |= ENFACE_PROJECT
+        if prealign:  # stage-1 rough axial prealignment before ingest
+            self.params.flags |= PREALIGN
         sx, sy = _f32(sx, dev), _f32(sy, dev)
         h, w, d = sx.shape
         if sy.shape != sx.shape:
@@ -270,6 +281,40 @@ class Pair:
                                         _stream(stream)))
         return list(ms)
 
+    def prealign_eval(self, level: int, theta, gamma_tilt: float = 1.0, stream=None):
+        """Stage-1 objective at level `level` and theta (2 (h + w) values):
+        (terms dict, T, gradient with respect to theta as numpy float64)."""
+        w, h, _ = self.level_shape(level)
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).ravel())
+        if th.size != 2 * (w + h):
+            raise ValueError(f"theta needs {2 * (w + h)} values at level {level}")
+        terms = np.zeros(NTERMS)
+        g = np.zeros_like(th)
+        T = C.c_double()
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+        _check(lib().octmc_prealign_eval(self._h, level, dp(th), float(gamma_tilt), dp(terms), C.byref(T), dp(g),
+                                         _stream(stream)))
+        return dict(zip(TERM_NAMES, terms.tolist())), T.value, g
+
+    def prealign(self, gamma_tilt: float = 1.0, iters_per_level: int = 100, stream=None):
+        """The stage-1 solve on this pair's pyramid: theta at the finest level
+        and the per-level report."""
+        th = np.zeros(2 * (self.shape.w + self.shape.h))
+        rep = Report()
+        _check(lib().octmc_prealign(self._h, float(gamma_tilt), int(iters_per_level),
+                                    th.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rep), _stream(stream)))
+        return th, rep.as_list()
+
+    def prealignment(self, stream=None):
+        """Stage-1 result of a pair created with prealign=True: theta (numpy)
+        and the axial field dz [2][h][w] (device)."""
+        th = np.zeros(2 * (self.shape.w + self.shape.h))
+        dz = torch.empty((2, self.shape.h, self.shape.w), dtype=torch.float32,
+                         device=torch.device("cuda", self.ctx.device))
+        _check(lib().octmc_pair_prealignment(self._h, th.ctypes.data_as(C.POINTER(C.c_double)), _ptr(dz),
+                                             _stream(stream)))
+        return th, dz
+
     def register(self, *, merged: bool = False, stream=None):
         """Full solve.  Returns (disp [2][h][w][3], merged_oct or None,
         merged_octa or None, per-level report list)."""
@@ -312,6 +357,21 @@ def validity_from_octa(vol: torch.Tensor, scan: int, *, ctx: Context | None = No
     out = torch.empty(h if scan == 0 else w, dtype=torch.float32, device=dev)
     shape = Shape(w, h, d, F32, MEM_DEVICE)
     _check(lib().octmc_validity_from_octa(ctx._h, C.byref(shape), _ptr(vol), int(scan), _ptr(out), _stream(stream)))
+    return out
+
+
+def resample_axial(vol: torch.Tensor, dz: torch.Tensor, *, ctx: Context | None = None, stream=None) -> torch.Tensor:
+    """vol [h][w][d] resampled along depth by the per-A-scan field dz [h][w]
+    (Catmull-Rom, clamped): out(i, j, k) = vol(i, j, k + dz(i, j))."""
+    ctx = ctx or context(0)
+    dev = torch.device("cuda", ctx.device)
+    v, z = _f32(vol, dev), _f32(dz, dev)
+    h, w, d = v.shape
+    if z.shape != (h, w):
+        raise ValueError("dz must be [h][w]")
+    out = torch.empty_like(v)
+    shape = Shape(w, h, d, F32, MEM_DEVICE)
+    _check(lib().octmc_resample_axial(ctx._h, C.byref(shape), _ptr(v), _ptr(z), _ptr(out), _stream(stream)))
     return out
 
 

@@ -1,0 +1,125 @@
+// Stage 1, rough axial prealignment (Fig. 1, Sec. 2.1 "optimization"):
+// kernels that expand the per-B-scan axial offsets and tilts into a
+// displacement field, reduce a field gradient back onto them, and resample
+// volumes axially (the prealigned volumes).
+//
+// theta holds, for the X-fast scan, h B-scans (rows j; fast axis x, w
+// A-scans each) and then, for the Y-fast scan, w B-scans (columns i; fast
+// axis y, h A-scans each), as (z_b, t_b) pairs; the field is
+//   dz(f, b) = z_b + t_b (f - (n_f - 1) / 2),  dx = dy = 0,
+// with f the index along the fast axis and n_f the B-scan length.
+#include "octmc_internal.h"
+
+namespace octmc {
+namespace {
+
+// [2][h][w][3] float32 field (dx = dy = 0) and, if dz != nullptr, the axial
+// component alone as [2][h][w].
+__global__ void k_tilt_expand(const double* __restrict__ th, int w, int h, float* __restrict__ disp,
+                              float* __restrict__ dz)
+{
+    const size_t na = (size_t)w * h;
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 2 * na) return;
+    const int V = q >= na ? 1 : 0;
+    const size_t a = q - (size_t)V * na;
+    const int i = (int)(a % w), j = (int)(a / w);
+    const int f = V == 0 ? i : j, b = V == 0 ? j : i;
+    const int nf = V == 0 ? w : h;
+    const double* t = th + (V == 0 ? 0 : 2 * (size_t)h) + 2 * (size_t)b;
+    const float v = (float)(t[0] + t[1] * ((double)f - 0.5 * (nf - 1)));
+    if (disp) {
+        disp[q * 3 + 0] = 0.0f;
+        disp[q * 3 + 1] = 0.0f;
+        disp[q * 3 + 2] = v;
+    }
+    if (dz) dz[q] = v;
+}
+
+// Adjoint of the expansion: one wave per B-scan sums the axial gradient and
+// its first moment about the B-scan centre in float64, in a fixed order.
+__global__ __launch_bounds__(256) void k_tilt_reduce(const float* __restrict__ grad, int w, int h,
+                                                     double* __restrict__ gth)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= h + w) return;  // uniform per wave
+    const int V = wid < h ? 0 : 1;
+    const int b = V == 0 ? wid : wid - h;
+    const int nf = V == 0 ? w : h;
+    const double c = 0.5 * (nf - 1);
+    const size_t base = (size_t)V * w * h;
+    double s0 = 0.0, s1 = 0.0;
+    for (int f = lane; f < nf; f += 64) {
+        const size_t a = V == 0 ? (size_t)b * w + f : (size_t)f * w + b;
+        const double g = grad[(base + a) * 3 + 2];
+        s0 += g;
+        s1 += g * ((double)f - c);
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        s0 += __shfl_xor(s0, m);
+        s1 += __shfl_xor(s1, m);
+    }
+    if (lane == 0) {
+        double* o = gth + (V == 0 ? 0 : 2 * (size_t)h) + 2 * (size_t)b;
+        o[0] = s0;
+        o[1] = s1;
+    }
+}
+
+// out(i, j, k) = I(vol, i, j, k + dz(i, j)): the cubic Hermite interpolator
+// with central-difference tangents (Catmull-Rom) along depth, tap indices
+// clamped to the A-scan.  One thread per output sample.
+__global__ void k_resample_z(const float* __restrict__ vol, const float* __restrict__ dz, size_t na, int d,
+                             float* __restrict__ out)
+{
+    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= na * d) return;
+    const size_t a = q / d;
+    const int k = (int)(q - a * d);
+    // integer and fractional parts of the shift taken apart so that the
+    // fraction is exact (k + dz rounded in float32 would not be); beyond
+    // +-(d + 2) every tap is clamped anyway
+    const float z = fminf(fmaxf(dz[a], -(float)(d + 2)), (float)(d + 2));
+    const float fz = floorf(z);
+    const float t = z - fz;
+    const int n = k + (int)fz;
+    const float t2 = t * t, t3 = t2 * t;
+    const float h00 = 2.0f * t3 - 3.0f * t2 + 1.0f, h10 = t3 - 2.0f * t2 + t;
+    const float h01 = -2.0f * t3 + 3.0f * t2, h11 = t3 - t2;
+    const float wt[4] = {-0.5f * h10, h00 - 0.5f * h11, h01 + 0.5f * h10, 0.5f * h11};
+    const float* __restrict__ col = vol + a * d;
+    float v = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        int idx = n - 1 + e;
+        idx = idx < 0 ? 0 : (idx >= d ? d - 1 : idx);
+        v += wt[e] * col[idx];
+    }
+    out[q] = v;
+}
+
+}  // namespace
+
+hipError_t launch_tilt_expand(const double* theta, int w, int h, float* disp, float* dz, hipStream_t s)
+{
+    const size_t n = 2 * (size_t)w * h;
+    hipLaunchKernelGGL(k_tilt_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, w, h, disp, dz);
+    return hipGetLastError();
+}
+
+hipError_t launch_tilt_reduce(const float* grad, int w, int h, double* gtheta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tilt_reduce, dim3((unsigned)((w + h + 3) / 4)), dim3(256), 0, s, grad, w, h, gtheta);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_z(const float* vol, const float* dz, size_t na, int d, float* out, hipStream_t s)
+{
+    const size_t n = na * d;
+    hipLaunchKernelGGL(k_resample_z, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vol, dz, na, d, out);
+    return hipGetLastError();
+}
+
+}  // namespace octmc

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/octmc.h"
 
@@ -165,8 +166,38 @@ hipError_t launch_enface_mean(const float* vol, int na, int d, float* out, hipSt
 hipError_t launch_count_nonfinite(const float* v, size_t n, unsigned* counter, hipStream_t s);
 hipError_t launch_copy_bscans(float* vol, int w, int h, int d, const int* src, int V, hipStream_t s);
 hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf, hipStream_t s);
-// input validity of one OCTA volume (Sec. 2.2): means[nb] float64 scratch,
-// valid[nb] float32 output, nb = h (V = 0) or w (V = 1)
+// Stage 1, rough axial prealignment (kernels_prealign.hip, prealign.hip).
+// theta: X-fast B-scans (h rows) then Y-fast B-scans (w columns), (offset,
+// tilt) each.  launch_tilt_expand writes the [2][h][w][3] field (disp) and/or
+// its axial component [2][h][w] (dz); launch_tilt_reduce the gradient with
+// respect to theta from a field gradient; launch_resample_z the volume
+// resampled along depth by a per-A-scan field.
+hipError_t launch_tilt_expand(const double* theta, int w, int h, float* disp, float* dz, hipStream_t s);
+hipError_t launch_tilt_reduce(const float* grad, int w, int h, double* gtheta, hipStream_t s);
+hipError_t launch_resample_z(const float* vol, const float* dz, size_t na, int d, float* out, hipStream_t s);
+// stage-1 solve over the pair's pyramid (theta at the finest level)
+int prealign_solve(octmc_pair* pair, double gamma, int iters, std::vector<double>& theta, octmc_report* rep,
+                   hipStream_t s);
+// octmc_pair_create with OCTMC_PREALIGN
+int prealign_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, const float* oct_x,
+                    const float* oct_y, const float* octa_x, const float* octa_y, const float* enface_x,
+                    const float* enface_y, const float* valid_x, const float* valid_y, hipStream_t s,
+                    octmc_pair** out);
+// pair accessors (runtime.hip)
+int pair_nlev(const octmc_pair* pair);
+const octmc_params& pair_params(const octmc_pair* pair);
+int pair_device(const octmc_pair* pair);
+const std::vector<double>& pair_theta(const octmc_pair* pair);
+
+// line search statistics of one pyramid level
+struct LevelStats {
+    int iters = 0, evals = 0, ls_fail = 0;
+    double f_start = 0, f_end = 0;
+};
+// cubic interpolation step of the zoom phase of the strong Wolfe line
+// search, kept 10 % inside the bracket (runtime.hip)
+double cubic_min(double a0, double f0, double g0, double a1, double f1, double g1);
+
 // Segmentation-free en face projection (Sec. 2.3) of one scan; `scratch`
 // holds enface_scratch_bytes(w, h, d) device bytes; `valid` is a device
 // vector of nb = (V == 0 ? h : w) floats or NULL (all valid); `fixed` a host
@@ -178,6 +209,8 @@ int enface_max_bscan();
 hipError_t launch_enface_project(const float* oct, const float* octa, int w, int h, int d, int V,
                                  const float* valid, const double* fixed, float* out, int* count, double* stats_host,
                                  void* scratch, hipStream_t s);
+// input validity of one OCTA volume (Sec. 2.2): means[nb] float64 scratch,
+// valid[nb] float32 output, nb = h (V = 0) or w (V = 1)
 hipError_t launch_validity(const float* vol, int w, int h, int d, int V, double* means, float* valid,
                            hipStream_t s);
 

@@ -80,6 +80,7 @@ struct octmc_pair {
     std::vector<void*> owned;
     Slab* slab = nullptr;  // when set, all device memory comes from it
     int busy = 0;
+    std::vector<double> theta;  // stage-1 offsets and tilts (created with OCTMC_PREALIGN)
 
     template <typename T>
     hipError_t alloc(T** p, size_t bytes)
@@ -224,13 +225,10 @@ struct Solver {
     float* xt32 = nullptr;
 };
 
-struct LevelStats {
-    int iters = 0, evals = 0, ls_fail = 0;
-    double f_start = 0, f_end = 0;
-};
+}  // namespace
 
 // cubic interpolation step of the zoom phase, kept 10 % inside the bracket
-double cubic_min(double a0, double f0, double g0, double a1, double f1, double g1)
+double octmc::cubic_min(double a0, double f0, double g0, double a1, double f1, double g1)
 {
     const double lo = std::min(a0, a1), hi = std::max(a0, a1), span = hi - lo;
     const double mid = 0.5 * (a0 + a1);
@@ -244,6 +242,8 @@ double cubic_min(double a0, double f0, double g0, double a1, double f1, double g
     if (!std::isfinite(a) || a < lo + 0.1 * span || a > hi - 0.1 * span) return mid;
     return a;
 }
+
+namespace {
 
 struct LevelRun {
     octmc_pair* P;
@@ -513,14 +513,18 @@ struct DirectEvaluator final : Evaluator {
 }  // namespace
 
 octmc_dtype octmc::pair_dtype(const octmc_pair* pair) { return pair->dtype; }
+int octmc::pair_nlev(const octmc_pair* pair) { return pair->nlev; }
+const octmc_params& octmc::pair_params(const octmc_pair* pair) { return pair->params; }
+int octmc::pair_device(const octmc_pair* pair) { return pair->ctx->device; }
+const std::vector<double>& octmc::pair_theta(const octmc_pair* pair) { return pair->theta; }
 
 int octmc::ctx_device(const octmc_ctx* ctx) { return ctx->device; }
 
 int octmc::validate_params(const octmc_params* p)
 {
     if (!p) return fail(OCTMC_E_INVALID, "params is NULL");
-    const double vals[] = {p->alpha, p->delta0, p->eps_huber, p->eps_reg, p->flyback_frac, p->mean_weight,
-                           p->c1, p->c2, p->merge_kappa, p->merge_tau};
+    const double vals[] = {p->alpha, p->delta0,  p->eps_huber,   p->eps_reg,  p->flyback_frac, p->mean_weight,
+                           p->c1,    p->c2,      p->merge_kappa, p->merge_tau, p->gamma_tilt};
     for (double v : vals)
         if (!finite_param(v)) return fail(OCTMC_E_INVALID, "parameters must be finite");
     if (p->alpha < 0) return fail(OCTMC_E_INVALID, "alpha must be >= 0");
@@ -532,7 +536,9 @@ int octmc::validate_params(const octmc_params* p)
     if (p->lbfgs_m < 1 || p->lbfgs_m > 8) return fail(OCTMC_E_INVALID, "lbfgs_m must lie in [1, 8]");
     if (p->ls_max_evals < 1) return fail(OCTMC_E_INVALID, "ls_max_evals must be >= 1");
     if (!(p->c1 > 0 && p->c1 < p->c2 && p->c2 < 1)) return fail(OCTMC_E_INVALID, "need 0 < c1 < c2 < 1");
-    if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT))
+    if (p->prealign_iters < 0) return fail(OCTMC_E_INVALID, "prealign_iters must be >= 0");
+    if (p->gamma_tilt < 0) return fail(OCTMC_E_INVALID, "gamma_tilt must be >= 0");
+    if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN))
         return fail(OCTMC_E_INVALID, "unknown flags");
     return OCTMC_OK;
 }
@@ -627,6 +633,8 @@ int octmc_params_default(octmc_params* out)
     p.merge_kappa = 1.0;
     p.merge_tau = 0.05;
     p.flags = 0;
+    p.prealign_iters = 100;
+    p.gamma_tilt = 1.0;
     *out = p;
     return OCTMC_OK;
 }
@@ -650,6 +658,87 @@ int octmc_destroy(octmc_ctx* ctx)
 
 }  // extern "C"
 
+// Stage 1 before ingest (Fig. 1): a structural-only pair (delta0 = 0, no en
+// face images) of float32 device copies of the inputs carries the stage-1
+// solve; both structural volumes and the OCTA volumes are then resampled
+// axially with its field, and the pair is created from the prealigned
+// volumes with the remaining flags.
+int octmc::prealign_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape,
+                           const float* oct_x, const float* oct_y, const float* octa_x, const float* octa_y,
+                           const float* enface_x, const float* enface_y, const float* valid_x,
+                           const float* valid_y, hipStream_t s, octmc_pair** out)
+{
+    const int w = shape->w, h = shape->h, d = shape->d;
+    const size_t na = (size_t)w * h, nv = na * d;
+    const bool host = shape->mem == OCTMC_MEM_HOST;
+    const hipMemcpyKind kind = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const bool have_octa = octa_x && octa_y;
+    DevBuf tmp;
+    auto dalloc = [&](size_t bytes) -> float* {
+        void* q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) return nullptr;
+        tmp.ptrs.push_back(q);
+        return static_cast<float*>(q);
+    };
+    const int nvol = have_octa ? 4 : 2;
+    const float* src[4] = {oct_x, oct_y, octa_x, octa_y};
+    float* in[4] = {nullptr, nullptr, nullptr, nullptr};
+    float* pre[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int q = 0; q < nvol; ++q) {
+        in[q] = dalloc(nv * 4);
+        pre[q] = dalloc(nv * 4);
+        if (!in[q] || !pre[q]) return fail(OCTMC_E_OOM, "out of device memory (prealignment)");
+        HIP_TRY(hipMemcpyAsync(in[q], src[q], nv * 4, kind, s));
+    }
+    float* zero = dalloc(na * 4);
+    float* dz = dalloc(2 * na * 4);
+    double* th_d = (double*)dalloc(2 * (size_t)(w + h) * 8);
+    if (!zero || !dz || !th_d) return fail(OCTMC_E_OOM, "out of device memory (prealignment)");
+    HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(zero), 0u, na, s));
+    octmc_params p1 = *params;
+    p1.flags &= OCTMC_CHECK_NAN;
+    p1.delta0 = 0.0;  // the en face OCTA data is not used in this stage (Sec. 2.4)
+    octmc_shape sh1 = *shape;
+    sh1.mem = OCTMC_MEM_DEVICE;
+    std::vector<double> th;
+    {
+        octmc_pair* P1 = nullptr;
+        OCTMC_TRY(pair_create_impl(ctx, &p1, &sh1, in[0], in[1], nullptr, nullptr, zero, zero, nullptr, nullptr, s,
+                                   nullptr, &P1));
+        std::unique_ptr<octmc_pair> g1(P1);
+        OCTMC_TRY(prealign_solve(P1, params->gamma_tilt, params->prealign_iters, th, nullptr, s));
+    }
+    HIP_TRY(hipMemcpyAsync(th_d, th.data(), th.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_tilt_expand(th_d, w, h, nullptr, dz, s));
+    for (int q = 0; q < nvol; ++q) HIP_TRY(launch_resample_z(in[q], dz + (q & 1) * na, na, d, pre[q], s));
+    // en face images (depth projections, unchanged by axial shifts) and
+    // validity vectors as given, on the device
+    float* enf[2] = {nullptr, nullptr};
+    float* val[2] = {nullptr, nullptr};
+    if (enface_x && enface_y) {
+        enf[0] = dalloc(na * 4);
+        enf[1] = dalloc(na * 4);
+        if (!enf[0] || !enf[1]) return fail(OCTMC_E_OOM, "out of device memory (prealignment)");
+        HIP_TRY(hipMemcpyAsync(enf[0], enface_x, na * 4, kind, s));
+        HIP_TRY(hipMemcpyAsync(enf[1], enface_y, na * 4, kind, s));
+    }
+    if (valid_x && valid_y) {
+        val[0] = dalloc((size_t)h * 4);
+        val[1] = dalloc((size_t)w * 4);
+        if (!val[0] || !val[1]) return fail(OCTMC_E_OOM, "out of device memory (prealignment)");
+        HIP_TRY(hipMemcpyAsync(val[0], valid_x, (size_t)h * 4, kind, s));
+        HIP_TRY(hipMemcpyAsync(val[1], valid_y, (size_t)w * 4, kind, s));
+    }
+    octmc_params p2 = *params;
+    p2.flags &= ~OCTMC_PREALIGN;
+    octmc_pair* P = nullptr;
+    OCTMC_TRY(pair_create_impl(ctx, &p2, &sh1, pre[0], pre[1], have_octa ? pre[2] : nullptr,
+                               have_octa ? pre[3] : nullptr, enf[0], enf[1], val[0], val[1], s, nullptr, &P));
+    P->theta = th;
+    *out = P;
+    return OCTMC_OK;
+}
+
 int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape,
                             const float* oct_x, const float* oct_y, const float* octa_x, const float* octa_y,
                             const float* enface_x, const float* enface_y, const float* valid_x, const float* valid_y,
@@ -671,6 +760,11 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
         return fail(OCTMC_E_INVALID, "OCTA inputs must be given for both scans");
     if ((valid_x != nullptr) != (valid_y != nullptr)) return fail(OCTMC_E_INVALID, "give both validity vectors or none");
     HIP_TRY(hipSetDevice(ctx->device));
+    if (params->flags & OCTMC_PREALIGN) {
+        if (slab) return fail(OCTMC_E_INVALID, "OCTMC_PREALIGN is not available for served requests");
+        return prealign_create(ctx, params, shape, oct_x, oct_y, octa_x, octa_y, enface_x, enface_y, valid_x, valid_y,
+                               s, out);
+    }
     auto* P = new octmc_pair();
     std::unique_ptr<octmc_pair> guard(P);
     P->slab = slab;

@@ -305,6 +305,9 @@ int check_request(const octmc_request* req)
         return fail(OCTMC_E_INVALID, "inputs must be given for both scans");
     if (req->merged_octa && !octa) return fail(OCTMC_E_INVALID, "merged_octa needs OCTA volumes");
     if (req->merged_octa && !req->merged_oct) return fail(OCTMC_E_INVALID, "merged_octa needs merged_oct");
+    if (req->params.flags & OCTMC_PREALIGN)
+        return fail(OCTMC_E_INVALID, "OCTMC_PREALIGN is not available for served requests (prealign with "
+                                     "octmc_pair_create, then submit the prealigned volumes)");
     return OCTMC_OK;
 }
 

@@ -423,3 +423,33 @@ def random_field(w: int, h: int, amp: float, seed: int) -> torch.Tensor:
     out-of-range sample positions)."""
     rng = np.random.default_rng(seed)
     return torch.from_numpy(rng.uniform(-amp, amp, size=(2, h, w, 3)))
+
+
+def layered_axial_pair(h: int, w: int, d: int, mX, mY):
+    """Analytic layered volumes [h][w][d] (four logistic layers over laterally
+    curved boundaries) acquired with per-A-scan axial offsets mX, mY ([h][w]):
+    scan V at (i, j, k) is the structure at depth k + m^V(i, j).  No lateral
+    motion; the aligning pull fields satisfy d^X - d^Y = m^Y - m^X."""
+    def vol(m):
+        z = np.arange(d)[None, None, :] + np.asarray(m, dtype=np.float64)[:, :, None]
+        x = np.arange(w)[None, :, None]
+        y = np.arange(h)[:, None, None]
+        out = np.zeros((h, w, d))
+        for cl, a in ((0.30, 0.9), (0.42, -0.5), (0.55, 0.6), (0.70, 0.7)):
+            b = d * cl + 1.5 * np.sin(x / 5.0) + 1.2 * np.cos(y / 6.0)
+            out += a / (1 + np.exp(-(z - b) / 1.2))
+        return out
+    return vol(mX), vol(mY)
+
+
+def planted_axial_motion(h: int, w: int, seed: int = 0, jump: float = 2.0, tilt_x: float = 0.04,
+                         tilt_y: float = -0.03):
+    """Per-B-scan axial offsets (random walks, a jump in the X-fast scan) and
+    one tilt per scan along its fast axis: (mX, mY) [h][w]."""
+    rng = np.random.default_rng(seed)
+    sX = np.cumsum(rng.normal(0, 0.3, h))
+    sX[h // 2:] += jump
+    rY = np.cumsum(rng.normal(0, 0.3, w))
+    mX = sX[:, None] + tilt_x * (np.arange(w)[None, :] - (w - 1) / 2)
+    mY = rY[None, :] + tilt_y * (np.arange(h)[:, None] - (h - 1) / 2)
+    return mX, mY

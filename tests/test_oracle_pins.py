@@ -771,20 +771,7 @@ def test_enface_projection_fixed_mapping_and_details(orc):
 # Stage 1, rough axial prealignment (Fig. 1, Sec. 2.1).
 
 def _layered_pair(h, w, d, mX, mY):
-    """Analytic layered volumes (smooth logistic layers over laterally curved
-    boundaries) acquired with per-A-scan axial offsets mX, mY: scan V at
-    (i, j, k) is the structure at depth k + m^V(i, j).  The aligning pull
-    fields satisfy d^X - d^Y = m^Y - m^X."""
-    def vol(m):
-        z = np.arange(d)[None, None, :] + m[:, :, None]
-        x = np.arange(w)[None, :, None]
-        y = np.arange(h)[:, None, None]
-        out = np.zeros((h, w, d))
-        for cl, a in ((0.30, 0.9), (0.42, -0.5), (0.55, 0.6), (0.70, 0.7)):
-            b = d * cl + 1.5 * np.sin(x / 5.0) + 1.2 * np.cos(y / 6.0)
-            out += a / (1 + np.exp(-(z - b) / 1.2))
-        return out
-    return vol(mX), vol(mY)
+    return synth.layered_axial_pair(h, w, d, mX, mY)
 
 
 def test_tilt_expand_closed_form_and_adjoint(orc):
@@ -891,13 +878,7 @@ def test_prealign_recovers_planted_axial_motion_and_tilt(orc):
     0.1 px RMS (the motion itself is 0.8 px RMS)."""
     h = w = 24
     d = 48
-    rng = np.random.default_rng(0)
-    c = (w - 1) / 2
-    sX = np.cumsum(rng.normal(0, 0.3, h))
-    sX[12:] += 2.0
-    rY = np.cumsum(rng.normal(0, 0.3, w))
-    mX = sX[:, None] + 0.04 * (np.arange(w)[None, :] - c)
-    mY = rY[None, :] - 0.03 * (np.arange(h)[:, None] - c)
+    mX, mY = synth.planted_axial_motion(h, w)
     X, Y = _layered_pair(h, w, d, mX, mY)
     th, rep = orc.prealign(X, Y, orc.Params(levels=2), 1.0, 80)
     D = orc.tilt_expand(th, w, h)
