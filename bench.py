@@ -305,6 +305,28 @@ def enface_bench(octmc, torch, log, reps=20):
     return res
 
 
+def prealign_bench(octmc, torch, pair, dtype, log, iters=100):
+    """Stage-1 rough axial prealignment (per-B-scan offset and tilt) of the
+    dense pair: a structural-only pair (delta0 = 0), 4 levels x `iters`
+    L-BFGS steps, timed on the host clock around the solve."""
+    h, w, _ = pair.sx.shape
+    z = torch.zeros((h, w), device="cuda")
+    Q = octmc.Pair(pair.sx, pair.sy, ax=z, ay=z, delta0=0.0, levels=4, dtype=dtype)
+    log(f"stage-1 prealignment, 4 levels x {iters} steps")
+    Q.prealign(1.0, 5)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th, rep = Q.prealign(1.0, iters)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    Q.close()
+    evals = int(sum(r["evals"] for r in rep))
+    return {"seconds": round(sec, 4), "evals": evals, "ms_per_eval": round(1000 * sec / max(evals, 1), 4),
+            "storage": dtype, "levels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                                         for r in rep],
+            "paper_context": "26.7 s for the prealignment of a 500^2 x 465 pair (i7-6700K + GTX 960, CPU-heavy)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +340,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-enface", action="store_true", help="skip the en face projection timing")
+    ap.add_argument("--no-prealign", action="store_true", help="skip the stage-1 prealignment timing")
     ap.add_argument("--enface-only", action="store_true", help="time only the en face projection")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=48.0)
@@ -478,6 +501,8 @@ def main():
 
     for v in out.get("storage_variants", {}).values():
         v.pop("solution", None)
+    if not args.no_prealign:
+        out["prealign"] = prealign_bench(octmc, torch, pair, args.dtype, log)
     if not args.no_serve:
         out["serving"] = serving(octmc, torch, args.serve_requests, args.serve_budget_gib, args.serve_max_active, log)
 

@@ -23,7 +23,9 @@
  *
  * Readings of points the paper leaves open are stated where they are used.
  * Parity pins for every function live in tests/ (closed forms, invariants,
- * library routines and finite differences).
+ * library routines and finite differences), except one: orc_tilt_term, the
+ * stage-1 tilt normalisation T, whose formula the paper leaves to earlier
+ * work that is not available -- parity unpinned.
  */
 #include <math.h>
 #include <stdint.h>
