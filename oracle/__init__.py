@@ -128,6 +128,19 @@ def lib():
         L.orc_prealign.restype = C.c_int
         L.orc_resample_z.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp, dp]
         L.orc_resample_z.restype = None
+        dpp = C.POINTER(dp)
+        ip = C.POINTER(C.c_int)
+        L.orc_eval_multi.argtypes = [C.c_int, dpp, dpp, dpp, ip, C.c_int, C.c_int, C.c_int, dp,
+                                     C.POINTER(_Params), dp, dp, dp, dp]
+        L.orc_eval_multi.restype = C.c_int
+        L.orc_upsample_multi.argtypes = [C.c_int, dp, C.c_int, C.c_int, dp, C.c_int, C.c_int]
+        L.orc_upsample_multi.restype = None
+        L.orc_register_multi.argtypes = [C.c_int, dpp, dpp, dpp, ip, C.c_int, C.c_int, C.c_int, C.POINTER(_Params),
+                                         dp, dp]
+        L.orc_register_multi.restype = C.c_int
+        L.orc_merge_multi.argtypes = [C.c_int, dpp, dpp, dpp, ip, C.c_int, C.c_int, C.c_int, dp, C.c_double,
+                                      C.c_double, dp, dp]
+        L.orc_merge_multi.restype = None
         L.orc_validity.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.orc_validity.restype = None
         L.orc_round_storage.argtypes = [dp, C.c_size_t, C.c_int]
@@ -507,3 +520,87 @@ def resample_z(vol, dz):
     out = np.zeros_like(vol)
     lib().orc_resample_z(_p(vol), w, h, d, _p(dz), _p(out))
     return out
+
+
+# ----------------------------------------------------------------------------
+# More than two volumes.  vols: list of n structural volumes [h][w][d];
+# orient: 0 (X-fast) or 1 (Y-fast) per volume; enface: n images [h][w];
+# valid: n vectors (h values for X-fast, w for Y-fast) or None (all valid).
+
+class Multi:
+    def __init__(self, vols, orient, enface, valid=None):
+        self.S = [_f64(v) for v in vols]
+        self.A = [_f64(a) for a in enface]
+        self.orient = [int(o) for o in orient]
+        h, w, d = self.S[0].shape
+        self.whd = (w, h, d)
+        self.V = [np.ones(h if o == 0 else w) for o in self.orient] if valid is None else \
+            [_f64(v) for v in valid]
+        self._keep = (self.S, self.A, self.V)
+
+    def ptrs(self, arrs):
+        return (C.POINTER(C.c_double) * len(arrs))(*[_p(a) for a in arrs])
+
+    def orient_c(self):
+        return (C.c_int * len(self.orient))(*self.orient)
+
+
+def pair_index(n: int):
+    """The pairs (P, Q), P < Q, in the order the multi-volume functions use."""
+    return [(P, Q) for P in range(n) for Q in range(P + 1, n)]
+
+
+def evaluate_multi(mv: Multi, D, params: Params | None = None, eta=None, grad: bool = True):
+    """n-volume objective: (terms dict, per-pair (S_str05, S_ang05), gradient [n][h][w][3])."""
+    params = params or Params()
+    D = _f64(D)
+    n = len(mv.S)
+    w, h, d = mv.whd
+    assert D.shape == (n, h, w, 3)
+    np_ = n * (n - 1) // 2
+    eta = np.ones(np_) if eta is None else _f64(eta)
+    terms = np.zeros(8)
+    p05 = np.zeros((np_, 2))
+    g = np.zeros_like(D) if grad else None
+    pc = params.c()
+    rc = lib().orc_eval_multi(n, mv.ptrs(mv.S), mv.ptrs(mv.A), mv.ptrs(mv.V), mv.orient_c(), w, h, d, _p(D),
+                              C.byref(pc), _p(eta), _p(terms), _p(p05), _p(g) if grad else None)
+    if rc:
+        raise RuntimeError(f"orc_eval_multi failed ({rc})")
+    return dict(zip(TERM_NAMES, terms.tolist())), p05, g
+
+
+def upsample_multi(Dc, wf: int, hf: int):
+    Dc = _f64(Dc)
+    n, hc, wc, _ = Dc.shape
+    out = np.zeros((n, hf, wf, 3))
+    lib().orc_upsample_multi(n, _p(Dc), wc, hc, _p(out), wf, hf)
+    return out
+
+
+def register_multi(mv: Multi, params: Params | None = None):
+    params = params or Params()
+    n = len(mv.S)
+    w, h, d = mv.whd
+    D = np.zeros((n, h, w, 3))
+    rep = np.zeros((params.levels, 4))
+    pc = params.c()
+    rc = lib().orc_register_multi(n, mv.ptrs(mv.S), mv.ptrs(mv.A), mv.ptrs(mv.V), mv.orient_c(), w, h, d,
+                                  C.byref(pc), _p(D), _p(rep))
+    if rc:
+        raise RuntimeError(f"orc_register_multi failed ({rc})")
+    return D, [dict(f_start=r[0], f_end=r[1], iters=int(r[2]), evals=int(r[3])) for r in rep]
+
+
+def merge_multi(mv: Multi, D, octa=None, kappa: float = 1.0, tau: float = 0.05):
+    """Merged OCT (and OCTA, from the given OCTA volumes with invalid B-scans
+    already replaced) of n registered volumes."""
+    D = _f64(D)
+    n = len(mv.S)
+    w, h, d = mv.whd
+    mo = np.zeros((h, w, d))
+    O = [_f64(o) for o in octa] if octa is not None else None
+    ma = np.zeros((h, w, d)) if O is not None else None
+    lib().orc_merge_multi(n, mv.ptrs(mv.S), mv.ptrs(O) if O is not None else None, mv.ptrs(mv.V), mv.orient_c(),
+                          w, h, d, _p(D), float(kappa), float(tau), _p(mo), _p(ma) if ma is not None else None)
+    return mo, ma

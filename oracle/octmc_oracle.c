@@ -1418,3 +1418,389 @@ EXPORT void orc_resample_z(const double* vol, int w, int h, int d, const double*
             out[(size_t)a * d + k] = v[0];
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* More than two volumes (Sec. 2.1 input: at least two raster scans, at least
+ * one orthogonal to the others; the generalisation to more volumes is left
+ * to earlier work).  Readings:
+ *   - every volume V has an orientation o_V (0: X-fast, B-scans are rows j;
+ *     1: Y-fast, columns i) and its own field d^V;
+ *   - the data term is the two-volume data term (Eqs. 2-9) summed over all
+ *     unordered pairs of volumes, each pair with its own eta (Eq. 10 at the
+ *     level's initial field); the validity of Eq. 5 is resampled along each
+ *     volume's own slow axis;
+ *   - R is summed over the volumes, each with its own acquisition order;
+ *   - M = gamma d / (n N_A) sum_c (sum_V sum_ij d^V_ij,c)^2 (n = 2: the
+ *     two-volume term);
+ *   - the merge weights of all volumes are normalised together; OCTA
+ *     weights are multiplied by each volume's resampled validity; the
+ *     lowest-density volume is used where every weight is 0 (OCT), a gap
+ *     where every OCTA weight is 0.
+ * With two volumes of orientations (0, 1) every function below equals its
+ * two-volume counterpart. */
+static void valid_sample(const double* v, int o, int w, int h, int i, int j, const double* dV, double* tv, double* dtv,
+                         int* comp)
+{
+    double r[2];
+    if (o == 0) {
+        orc_sample1(v, h, j + dV[1], r);
+        *comp = 1;
+    } else {
+        orc_sample1(v, w, i + dV[0], r);
+        *comp = 0;
+    }
+    *tv = r[0] <= 0 ? 0 : (r[0] >= 1 ? 1 : r[0]);
+    *dtv = (r[0] > 0 && r[0] < 1) ? r[1] : 0;
+}
+
+/* Data term of the pair (P, Q) at one output A-scan: part[5] as data_ascan,
+ * g[0..2] = d/d(d^P), g[3..5] = d/d(d^Q) of part[0]. */
+static void data_pair_ascan(const double* sp, const double* sq, const double* ap, const double* aq, const double* vp,
+                            const double* vq, int op, int oq, int w, int h, int d, const double* dP, const double* dQ,
+                            int i, int j, double delta0, double eps_h, double eta, double part[5], double g[6])
+{
+    double lam = 0, gp[3] = {0, 0, 0}, gq[3] = {0, 0, 0};
+    for (int k = 0; k < d; k++) {
+        double ip[4], iq[4], lh[2];
+        orc_sample3(sp, w, h, d, i + dP[0], j + dP[1], k + dP[2], ip);
+        orc_sample3(sq, w, h, d, i + dQ[0], j + dQ[1], k + dQ[2], iq);
+        orc_pseudo_huber(ip[0] - iq[0], eps_h, lh);
+        lam += lh[0];
+        for (int c = 0; c < 3; c++) {
+            gp[c] += lh[1] * ip[1 + c];
+            gq[c] += lh[1] * iq[1 + c];
+        }
+    }
+    double jp[3], jq[3], la[2];
+    orc_sample2(ap, w, h, i + dP[0], j + dP[1], jp);
+    orc_sample2(aq, w, h, i + dQ[0], j + dQ[1], jq);
+    orc_pseudo_huber(jp[0] - jq[0], eps_h, la);
+    double tvp, dtvp, tvq, dtvq;
+    int cp, cq;
+    valid_sample(vp, op, w, h, i, j, dP, &tvp, &dtvp, &cp);
+    valid_sample(vq, oq, w, h, i, j, dQ, &tvq, &dtvq, &cq);
+    const double delta = delta0 * tvp * tvq, dd = (double)d;
+    part[0] = eta * (1 - delta) * lam + (dd / eta) * delta * la[0];
+    part[1] = (1 - delta) * lam;
+    part[2] = delta * dd * la[0];
+    part[3] = (1 - 0.5 * tvp * tvq) * lam;
+    part[4] = 0.5 * tvp * tvq * dd * la[0];
+    const double dpd = -eta * lam + (dd / eta) * la[0];
+    for (int c = 0; c < 2; c++) {
+        g[c] = eta * (1 - delta) * gp[c] + (dd / eta) * delta * la[1] * jp[1 + c];
+        g[3 + c] = -(eta * (1 - delta) * gq[c] + (dd / eta) * delta * la[1] * jq[1 + c]);
+    }
+    g[2] = eta * (1 - delta) * gp[2];
+    g[5] = -(eta * (1 - delta) * gq[2]);
+    g[cp] += dpd * delta0 * tvq * dtvp;
+    g[3 + cq] += dpd * delta0 * tvp * dtvq;
+}
+
+/* R of one volume with orientation o (the acquisition order of reg_term),
+ * added to `total` in link order. */
+static double reg_volume(const double* DV, double* GV, int o, int w, int h, int d, double eps_r, double flyback_frac,
+                         double alpha, double total)
+{
+    const int blen = o == 0 ? w : h, nb = o == 0 ? h : w;
+    const double f = floor(flyback_frac * blen + 0.5), wfb = 1.0 / sqrt(1.0 + f);
+    const long n = (long)nb * blen;
+    for (long t = 0; t + 1 < n; t++) {
+        const long t1 = t + 1;
+        const int fa = (int)(t % blen), sa = (int)(t / blen), fb = (int)(t1 % blen), sb = (int)(t1 / blen);
+        const int ia = o == 0 ? fa : sa, ja = o == 0 ? sa : fa, ib = o == 0 ? fb : sb, jb = o == 0 ? sb : fb;
+        const double om = sa == sb ? 1.0 : wfb;
+        const double* da = DV + ((size_t)ja * w + ia) * 3;
+        const double* db = DV + ((size_t)jb * w + ib) * 3;
+        for (int c = 0; c < 3; c++) {
+            double lh[2];
+            orc_pseudo_huber(db[c] - da[c], eps_r, lh);
+            total += om * d * lh[0];
+            if (GV) {
+                GV[((size_t)jb * w + ib) * 3 + c] += alpha * om * d * lh[1];
+                GV[((size_t)ja * w + ia) * 3 + c] -= alpha * om * d * lh[1];
+            }
+        }
+    }
+    return total;
+}
+
+static int pair_count(int n) { return n * (n - 1) / 2; }
+
+/* The n-volume objective.  S, A, Vv: per volume the structural volume, the
+ * en face image and the validity vector (h values for orientation 0, w for
+ * 1); D: [n][h][w][3]; eta: [n (n - 1) / 2] per pair (P < Q, in the order
+ * (0,1), (0,2), ..., (1,2), ...).  terms[T_COUNT] as orc_eval (sums over the
+ * pairs; T_STR05 and T_ANG05 summed as well); pair05 (may be NULL):
+ * [npairs][2] = the pairs' S_str and S_ang at delta0 = 0.5 (for eta);
+ * grad: [n][h][w][3] or NULL. */
+EXPORT int orc_eval_multi(int n, const double* const* S, const double* const* A, const double* const* Vv,
+                          const int* orient, int w, int h, int d, const double* D, const orc_params* p,
+                          const double* eta, double* terms, double* pair05, double* grad)
+{
+    if (n < 2 || n > 8) return -1;
+    const size_t na = (size_t)w * h;
+    const int np = pair_count(n);
+    double* part = (double*)malloc(na * 5 * sizeof(double));
+    double* g = (double*)malloc(na * 6 * sizeof(double));
+    if (!part || !g) {
+        free(part);
+        free(g);
+        return -1;
+    }
+    if (grad) memset(grad, 0, (size_t)n * na * 3 * sizeof(double));
+    double s[5] = {0, 0, 0, 0, 0};
+    int q = 0;
+    for (int P = 0; P < n; P++)
+        for (int Q = P + 1; Q < n; Q++, q++) {
+#pragma omp parallel for schedule(dynamic, 4)
+            for (long a = 0; a < (long)na; a++) {
+                const int i = (int)(a % w), j = (int)(a / w);
+                data_pair_ascan(S[P], S[Q], A[P], A[Q], Vv[P], Vv[Q], orient[P], orient[Q], w, h, d,
+                                D + ((size_t)P * na + a) * 3, D + ((size_t)Q * na + a) * 3, i, j, p->delta0, p->eps_h,
+                                eta[q], part + a * 5, g + a * 6);
+            }
+            double sp[5] = {0, 0, 0, 0, 0};
+            for (size_t a = 0; a < na; a++)
+                for (int c = 0; c < 5; c++) sp[c] += part[a * 5 + c];
+            for (int c = 0; c < 5; c++) s[c] += sp[c];
+            if (pair05) {
+                pair05[2 * q] = sp[3];
+                pair05[2 * q + 1] = sp[4];
+            }
+            if (grad)
+                for (size_t a = 0; a < na; a++)
+                    for (int c = 0; c < 3; c++) {
+                        grad[((size_t)P * na + a) * 3 + c] += g[a * 6 + c];
+                        grad[((size_t)Q * na + a) * 3 + c] += g[a * 6 + 3 + c];
+                    }
+        }
+    double r = 0;
+    for (int V = 0; V < n; V++)
+        r = reg_volume(D + (size_t)V * na * 3, grad ? grad + (size_t)V * na * 3 : NULL, orient[V], w, h, d, p->eps_r,
+                       p->flyback_frac, p->alpha, r);
+    double sum[3] = {0, 0, 0};
+    for (size_t e = 0; e < (size_t)n * na; e++)
+        for (int c = 0; c < 3; c++) sum[c] += D[e * 3 + c];
+    double m = 0;
+    for (int c = 0; c < 3; c++) m += sum[c] * sum[c];
+    m *= p->mean_weight * d / ((double)n * (double)na);
+    if (grad)
+        for (size_t e = 0; e < (size_t)n * na; e++)
+            for (int c = 0; c < 3; c++) grad[e * 3 + c] += 2.0 * p->mean_weight * d * sum[c] / ((double)n * (double)na);
+    terms[T_DATA] = s[0];
+    terms[T_STR] = s[1];
+    terms[T_ANG] = s[2];
+    terms[T_STR05] = s[3];
+    terms[T_ANG05] = s[4];
+    terms[T_REG] = r;
+    terms[T_MEAN] = m;
+    terms[T_F] = s[0] + p->alpha * r + m;
+    free(part);
+    free(g);
+    (void)np;
+    return 0;
+}
+
+/* Level transition for n fields (orc_upsample per volume). */
+EXPORT void orc_upsample_multi(int n, const double* coarse, int wc, int hc, double* fine, int wf, int hf)
+{
+    for (int V = 0; V < n; V++) {
+        const double* C = coarse + (size_t)V * wc * hc * 3;
+        double* Fo = fine + (size_t)V * wf * hf * 3;
+        for (int j = 0; j < hf; j++)
+            for (int i = 0; i < wf; i++) {
+                double x = (i - 0.5) / 2.0, y = (j - 0.5) / 2.0;
+                if (x < 0) x = 0;
+                if (x > wc - 1) x = wc - 1;
+                if (y < 0) y = 0;
+                if (y > hc - 1) y = hc - 1;
+                int x0 = (int)floor(x), y0 = (int)floor(y);
+                int x1 = x0 + 1 < wc ? x0 + 1 : wc - 1, y1 = y0 + 1 < hc ? y0 + 1 : hc - 1;
+                double fx = x - x0, fy = y - y0;
+                for (int c = 0; c < 3; c++) {
+                    double v00 = C[((size_t)y0 * wc + x0) * 3 + c], v10 = C[((size_t)y0 * wc + x1) * 3 + c];
+                    double v01 = C[((size_t)y1 * wc + x0) * 3 + c], v11 = C[((size_t)y1 * wc + x1) * 3 + c];
+                    double v = (1 - fy) * ((1 - fx) * v00 + fx * v10) + fy * ((1 - fx) * v01 + fx * v11);
+                    Fo[((size_t)j * wf + i) * 3 + c] = 2.0 * v;
+                }
+            }
+    }
+}
+
+typedef struct {
+    int n;
+    const double* const* S;
+    const double* const* A;
+    const double* const* Vv;
+    const int* orient;
+    int w, h, d;
+    const orc_params* p;
+    const double* eta;
+    double terms[T_COUNT];
+} multi_ctx;
+
+static int multi_fg(void* vctx, const double* x, double* f, double* g)
+{
+    multi_ctx* c = (multi_ctx*)vctx;
+    if (orc_eval_multi(c->n, c->S, c->A, c->Vv, c->orient, c->w, c->h, c->d, x, c->p, c->eta, c->terms, NULL, g))
+        return -1;
+    *f = c->terms[T_F];
+    return 0;
+}
+
+/* The n-volume registration: per-volume pyramids (as orc_register, with the
+ * same storage rounding), zero fields at the coarsest level, each pair's eta
+ * at the level's initial field (Eq. 10), L-BFGS over all fields, upsampling
+ * between levels.  D_out: [n][h][w][3]; levels_rep (may be NULL): per level,
+ * coarsest first, f_start, f_end, iters, evals. */
+EXPORT int orc_register_multi(int n, const double* const* S, const double* const* A, const double* const* Vv,
+                              const int* orient, int w, int h, int d, const orc_params* p, double* D_out,
+                              double* levels_rep)
+{
+    int L = p->levels;
+    if (L < 1 || L > 8 || n < 2 || n > 8) return -1;
+    int W[8], H[8], Dd[8];
+    double* PS[8][8];
+    double* PA[8][8];
+    double* PV[8][8];
+    W[0] = w; H[0] = h; Dd[0] = d;
+    for (int V = 0; V < n; V++) {
+        const size_t nv0 = (size_t)w * h * d;
+        PS[0][V] = (double*)malloc(nv0 * sizeof(double));
+        memcpy(PS[0][V], S[V], nv0 * sizeof(double));
+        PA[0][V] = (double*)A[V];
+        PV[0][V] = (double*)Vv[V];
+    }
+    for (int l = 1; l < L; l++) {
+        W[l] = (W[l - 1] + 1) / 2; H[l] = (H[l - 1] + 1) / 2; Dd[l] = (Dd[l - 1] + 1) / 2;
+        for (int V = 0; V < n; V++) {
+            PS[l][V] = (double*)malloc((size_t)W[l] * H[l] * Dd[l] * sizeof(double));
+            PA[l][V] = (double*)malloc((size_t)W[l] * H[l] * sizeof(double));
+            const int nb = orient[V] == 0 ? H[l] : W[l];
+            PV[l][V] = (double*)malloc((size_t)nb * sizeof(double));
+            orc_pyr_down3(PS[l - 1][V], W[l - 1], H[l - 1], Dd[l - 1], PS[l][V]);
+            orc_pyr_down2(PA[l - 1][V], W[l - 1], H[l - 1], PA[l][V]);
+            orc_pyr_down1(PV[l - 1][V], orient[V] == 0 ? H[l - 1] : W[l - 1], PV[l][V]);
+        }
+    }
+    if (p->store)
+        for (int l = 0; l < L; l++)
+            for (int V = 0; V < n; V++) orc_round_storage(PS[l][V], (size_t)W[l] * H[l] * Dd[l], p->store);
+    const int np = pair_count(n);
+    double eta[28], p05[56];
+    int rc = 0;
+    double* Dc = NULL;
+    for (int l = L - 1; l >= 0; l--) {
+        const size_t nn = (size_t)n * W[l] * H[l] * 3;
+        double* Dl = (double*)calloc(nn, sizeof(double));
+        if (Dc) {
+            orc_upsample_multi(n, Dc, W[l + 1], H[l + 1], Dl, W[l], H[l]);
+            free(Dc);
+        }
+        for (int q = 0; q < np; q++) eta[q] = 1.0;
+        double terms[T_COUNT];
+        orc_eval_multi(n, (const double* const*)PS[l], (const double* const*)PA[l], (const double* const*)PV[l], orient,
+                       W[l], H[l], Dd[l], Dl, p, eta, terms, p05, NULL);
+        for (int q = 0; q < np; q++) eta[q] = orc_eta_from_terms(p05[2 * q], p05[2 * q + 1]);
+        multi_ctx ctx = {n, (const double* const*)PS[l], (const double* const*)PA[l], (const double* const*)PV[l],
+                         orient, W[l], H[l], Dd[l], p, eta, {0}};
+        orc_lbfgs_report rep;
+        rc = orc_lbfgs((int)nn, Dl, multi_fg, &ctx, p->lbfgs_m, p->iters, p->ls_max_evals, p->c1, p->c2, &rep);
+        if (levels_rep) {
+            double* r = levels_rep + (size_t)(L - 1 - l) * 4;
+            r[0] = rep.f_start; r[1] = rep.f_end; r[2] = rep.iters; r[3] = rep.evals;
+        }
+        Dc = Dl;
+        if (rc) break;
+    }
+    if (rc == 0) memcpy(D_out, Dc, (size_t)n * w * h * 3 * sizeof(double));
+    free(Dc);
+    for (int V = 0; V < n; V++) free(PS[0][V]);
+    for (int l = 1; l < L; l++)
+        for (int V = 0; V < n; V++) {
+            free(PS[l][V]);
+            free(PA[l][V]);
+            free(PV[l][V]);
+        }
+    return rc;
+}
+
+/* Density of one field ([h][w][3]) as orc_density. */
+static void density_one(const double* DV, int w, int h, double* rho)
+{
+    double* grid = (double*)calloc((size_t)w * h, sizeof(double));
+    for (int pass = 0; pass < 2; pass++)
+        for (int j = 0; j < h; j++)
+            for (int i = 0; i < w; i++) {
+                double x = i + DV[((size_t)j * w + i) * 3 + 0], y = j + DV[((size_t)j * w + i) * 3 + 1];
+                x = x < 0 ? 0 : (x > w - 1 ? w - 1 : x);
+                y = y < 0 ? 0 : (y > h - 1 ? h - 1 : y);
+                const int x0 = (int)floor(x), y0 = (int)floor(y);
+                const int x1 = x0 + 1 < w ? x0 + 1 : w - 1, y1 = y0 + 1 < h ? y0 + 1 : h - 1;
+                const double fx = x - x0, fy = y - y0;
+                if (pass == 0) {
+                    grid[(size_t)y0 * w + x0] += (1 - fx) * (1 - fy);
+                    grid[(size_t)y0 * w + x1] += fx * (1 - fy);
+                    grid[(size_t)y1 * w + x0] += (1 - fx) * fy;
+                    grid[(size_t)y1 * w + x1] += fx * fy;
+                } else {
+                    rho[(size_t)j * w + i] = (1 - fx) * (1 - fy) * grid[(size_t)y0 * w + x0] +
+                                             fx * (1 - fy) * grid[(size_t)y0 * w + x1] +
+                                             (1 - fx) * fy * grid[(size_t)y1 * w + x0] + fx * fy * grid[(size_t)y1 * w + x1];
+                }
+            }
+    free(grid);
+}
+
+/* n-volume merge (readings above).  O (may be NULL) are the OCTA volumes with
+ * invalid B-scans already replaced by their nearest valid neighbours. */
+EXPORT void orc_merge_multi(int n, const double* const* S, const double* const* O, const double* const* Vv,
+                            const int* orient, int w, int h, int d, const double* D, double kappa, double tau,
+                            double* merged_oct, double* merged_octa)
+{
+    const size_t na = (size_t)w * h;
+    double* rho = (double*)malloc((size_t)n * na * sizeof(double));
+    for (int V = 0; V < n; V++) density_one(D + (size_t)V * na * 3, w, h, rho + (size_t)V * na);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long a = 0; a < (long)na; a++) {
+        const int i = (int)(a % w), j = (int)(a / w);
+        double wt[8], ow[8], sw = 0, so = 0;
+        int lowest = 0;
+        for (int V = 0; V < n; V++) {
+            const double r = rho[(size_t)V * na + a];
+            wt[V] = exp(-kappa * fmax(0.0, r - 1.0));
+            if (wt[V] < tau) wt[V] = 0;
+            sw += wt[V];
+            if (r < rho[(size_t)lowest * na + a]) lowest = V;
+        }
+        for (int V = 0; V < n; V++) {
+            double tv, dtv;
+            int comp;
+            valid_sample(Vv[V], orient[V], w, h, i, j, D + ((size_t)V * na + a) * 3, &tv, &dtv, &comp);
+            ow[V] = wt[V] * tv;
+            so += ow[V];
+        }
+        for (int V = 0; V < n; V++) {
+            if (sw > 0) wt[V] /= sw;
+            else wt[V] = V == lowest ? 1.0 : 0.0;
+            if (so > 0) ow[V] /= so;
+        }
+        for (int k = 0; k < d; k++) {
+            double mo = 0, ma = 0;
+            for (int V = 0; V < n; V++) {
+                const double* dV = D + ((size_t)V * na + a) * 3;
+                double sv[4];
+                orc_sample3(S[V], w, h, d, i + dV[0], j + dV[1], k + dV[2], sv);
+                mo += wt[V] * sv[0];
+                if (merged_octa) {
+                    double ov[4];
+                    orc_sample3(O[V], w, h, d, i + dV[0], j + dV[1], k + dV[2], ov);
+                    ma += ow[V] * ov[0];
+                }
+            }
+            merged_oct[a * d + k] = mo;
+            if (merged_octa) merged_octa[a * d + k] = ma;
+        }
+    }
+    free(rho);
+}

@@ -224,6 +224,24 @@ def _quantile(x: torch.Tensor, q: float) -> float:
     return float(torch.quantile(flat[::step].float(), q))
 
 
+@dataclass
+class Scans:
+    """n raster scans of one phantom: volumes [h][w][d] float32 in the common
+    frame, en face images [h][w], validity per scan (h values for an X-fast
+    scan, whose B-scans are rows; w for a Y-fast scan, whose B-scans are
+    columns), orientation per scan (0: X-fast, 1: Y-fast) and the ground-truth
+    pull fields d_gt [n][h][w][3] float64."""
+
+    S: list
+    A: list
+    V: list
+    orient: list
+    d_gt: torch.Tensor
+    O: list | None = None
+    saccade_ij: list = field(default_factory=list)
+    meta: dict = field(default_factory=dict)
+
+
 def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = None, d: int | None = None,
               device: str | torch.device = "cpu", octa_volumes: bool = True, white_lines: bool = False,
               drift: float | None = None, saccades=None, amp: float | None = None,
@@ -240,6 +258,20 @@ def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = N
     0.5 exp(-s / 0.1) for the structural reflectivity s, attenuated below the
     deepest layer boundary (e-folding depth 0.05 d), so that the vitreous and
     the deep choroid are bright and the retina between vessels is dark."""
+    sc = make_scans(workload, pair, (0, 1), n=n, d=d, device=device, octa_volumes=octa_volumes,
+                    white_lines=white_lines, drift=drift, saccades=saccades, amp=amp, decorrelation=decorrelation)
+    return Pair(sx=sc.S[0], sy=sc.S[1], ax=sc.A[0], ay=sc.A[1], vx=sc.V[0], vy=sc.V[1], d_gt=sc.d_gt,
+                ox=sc.O[0] if sc.O else None, oy=sc.O[1] if sc.O else None, saccade_ij=sc.saccade_ij,
+                meta=sc.meta)
+
+
+def make_scans(workload: str | dict = "tiny", pair: int = 0, orients=(0, 1, 0, 1), *, n: int | None = None,
+               d: int | None = None, device: str | torch.device = "cpu", octa_volumes: bool = True,
+               white_lines: bool = False, drift: float | None = None, saccades=None, amp: float | None = None,
+               decorrelation: bool = False) -> Scans:
+    """n = len(orients) scans of one phantom, each with its own motion (see
+    make_pair for the options).  With orients (0, 1) this is make_pair's
+    pair; every further scan draws its motion from a stream of its own."""
     cfg = dict(WORKLOADS[workload]) if isinstance(workload, str) else dict(workload)
     if n is not None:
         cfg["n"] = n
@@ -255,21 +287,21 @@ def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = N
     device = torch.device(device)
     r_ph, r_ve, r_mx, r_my = _rng_streams(cfg["index"], pair)
     fly = int(round(0.25 * n))
+    ns = len(orients)
 
-    # motion of both scans
-    mX, tsX = _motion(r_mx, n, cfg["drift"], cfg["saccades"], cfg["amp"], fly)
-    mY, tsY = _motion(r_my, n, cfg["drift"], cfg["saccades"], cfg["amp"], fly)
-    tX, tY = acquisition_times(n, fly)
-    posX = mX[tX]  # [h][w][3] motion at each output A-scan
-    posY = mY[tY]
+    # motion of every scan
+    mrng = [r_mx, r_my] + [np.random.default_rng(np.random.SeedSequence([SEED_BASE + cfg["index"], pair, 100 + s]))
+                           for s in range(2, ns)]
+    tXY = acquisition_times(n, fly)
+    mot = [_motion(mrng[s], n, cfg["drift"], cfg["saccades"], cfg["amp"], fly) for s in range(ns)]
+    pos = [mot[s][0][tXY[orients[s]]] for s in range(ns)]  # [h][w][3] motion at each output A-scan
     # The truth's coordinate frame is arbitrary: place it so that the motion
-    # of both scans has zero mean, which is the gauge the mean-displacement
+    # of all scans has zero mean, which is the gauge the mean-displacement
     # term selects (the registered volumes stay centred on the output grid).
-    c = np.concatenate([posX.reshape(-1, 3), posY.reshape(-1, 3)]).mean(axis=0)
-    posX = posX - c
-    posY = posY - c
-    margin = int(math.ceil(max(np.abs(posX[..., :2]).max(), np.abs(posY[..., :2]).max()))) + 3
-    mz = int(math.ceil(max(np.abs(posX[..., 2]).max(), np.abs(posY[..., 2]).max()))) + 3
+    c = np.concatenate([q.reshape(-1, 3) for q in pos]).mean(axis=0)
+    pos = [q - c for q in pos]
+    margin = int(math.ceil(max(np.abs(q[..., :2]).max() for q in pos))) + 3
+    mz = int(math.ceil(max(np.abs(q[..., 2]).max() for q in pos))) + 3
     # The truth lives on a grid twice as fine as the scans (fine index
     # u = 2 (x + margin)), so that trilinear acquisition sampling blurs only
     # at the fine scale.
@@ -352,50 +384,45 @@ def make_pair(workload: str | dict = "tiny", pair: int = 0, *, n: int | None = N
                                        align_corners=True)[0, 0]
         return out
 
-    sx = sample(truth, posX)
-    sy = sample(truth, posY)
+    S = [sample(truth, q) for q in pos]
     del truth
-    ox = sample(octa_truth, posX)
-    oy = sample(octa_truth, posY)
+    O = [sample(octa_truth, q) for q in pos]
     del octa_truth
     # Rayleigh noise of scale 0.1 per scan: sigma sqrt(-2 ln U)
-    for o in (ox, oy):
+    for o in O:
         uq = torch.rand(o.shape, generator=gen, device=device).clamp_min_(1e-12)
         o += 0.1 * torch.sqrt(-2.0 * torch.log(uq))
         del uq
 
-    vx = torch.ones(n, dtype=torch.float32, device=device)
-    vy = torch.ones(n, dtype=torch.float32, device=device)
+    Vv = [torch.ones(n, dtype=torch.float32, device=device) for _ in range(ns)]
     sac = []
     if white_lines:
-        for ts, V in ((tsX, 0), (tsY, 1)):
-            for t in ts:
+        for s in range(ns):
+            o = orients[s]
+            for t in mot[s][1]:
                 b = int(t // (n + fly))
                 if b >= n:
                     continue
-                sac.append((V, b))
-                vec = vx if V == 0 else vy
-                vec[max(0, b - 2):b + 3] = 0.0
-                if V == 0:
-                    ox[b] = 1.0 + 0.05 * torch.rand(ox[b].shape, generator=gen, device=device)
+                sac.append((s, b))
+                Vv[s][max(0, b - 2):b + 3] = 0.0
+                if o == 0:
+                    O[s][b] = 1.0 + 0.05 * torch.rand(O[s][b].shape, generator=gen, device=device)
                 else:
-                    oy[:, b] = 1.0 + 0.05 * torch.rand(oy[:, b].shape, generator=gen, device=device)
-    ax = ox.mean(dim=2)
-    ay = oy.mean(dim=2)
-    scale = _quantile(torch.cat([ax.reshape(-1), ay.reshape(-1)]), 0.99)
-    ax /= scale
-    ay /= scale
-    ox /= scale
-    oy /= scale
+                    O[s][:, b] = 1.0 + 0.05 * torch.rand(O[s][:, b].shape, generator=gen, device=device)
+    A = [o.mean(dim=2) for o in O]
+    scale = _quantile(torch.cat([a.reshape(-1) for a in A]), 0.99)
+    for a in A:
+        a /= scale
+    for o in O:
+        o /= scale
 
-    dgt = np.stack([_inverse_field(posX), _inverse_field(posY)])
+    dgt = np.stack([_inverse_field(q) for q in pos])
     dgt -= dgt.reshape(-1, 3).mean(axis=0)
     meta = dict(workload=workload if isinstance(workload, str) else "custom", pair=pair, n=n, d=d,
-                flyback=fly, margin=margin, saccade_times=(tsX.tolist(), tsY.tolist()),
-                levels=cfg.get("levels", 3))
-    return Pair(sx=sx, sy=sy, ax=ax, ay=ay, vx=vx, vy=vy, d_gt=torch.from_numpy(dgt),
-                ox=ox if octa_volumes else None, oy=oy if octa_volumes else None,
-                saccade_ij=sac, meta=meta)
+                flyback=fly, margin=margin, saccade_times=tuple(m[1].tolist() for m in mot),
+                levels=cfg.get("levels", 3), orients=tuple(orients))
+    return Scans(S=S, A=A, V=Vv, orient=list(orients), d_gt=torch.from_numpy(dgt),
+                 O=O if octa_volumes else None, saccade_ij=sac, meta=meta)
 
 
 def perturbed_field(d_gt: torch.Tensor, sigma: float, seed: int) -> torch.Tensor:

@@ -885,3 +885,100 @@ def test_prealign_recovers_planted_axial_motion_and_tilt(orc):
     err = (D[0, :, :, 2] - D[1, :, :, 2]) - (mY - mX)
     assert np.sqrt((err ** 2).mean()) < 0.1
     assert rep[-1]["f_end"] < rep[-1]["f_start"]
+
+
+# ---------------------------------------------------------------------------
+# More than two volumes.
+
+def _multi_inputs(orients, n=20, d=24, seed=0):
+    sc = synth.make_scans("tiny", seed, tuple(orients), n=n, d=d, white_lines=True)
+    return sc
+
+
+def test_multi_two_volumes_equal_the_pair_functions(orc):
+    """Two volumes of orientations (0, 1): objective, gradient, solve and merge
+    are bit for bit the two-volume functions (which carry their own pins)."""
+    p = synth.make_pair("tiny", 0, n=20, d=24, white_lines=True)
+    vx, vy = p.vx.numpy().copy(), p.vy.numpy().copy()
+    vy[4] = 0.4
+    lv = orc.level_from(p.sx, p.sy, p.ax, p.ay, vx, vy)
+    mv = orc.Multi([p.sx, p.sy], [0, 1], [p.ax, p.ay], [vx, vy])
+    D = RNG.normal(0, 1.0, (2, 20, 20, 3))
+    pp = orc.Params(alpha=0.7, mean_weight=1.3, levels=2, iters=15)
+    t2, g2 = orc.evaluate(lv, D, pp, 1.3)
+    tm, p05, gm = orc.evaluate_multi(mv, D, pp, [1.3])
+    assert t2 == tm and np.array_equal(g2, gm)
+    assert p05[0, 0] == t2["str05"] and p05[0, 1] == t2["ang05"]
+    Dr, rep = orc.register(lv, pp)
+    Dm, repm = orc.register_multi(mv, pp)
+    assert np.array_equal(Dr, Dm)
+    mo, ma, _, _ = orc.merge(p.sx, p.sy, Dr, p.ox, p.oy, vx, vy)
+    mo2, ma2 = orc.merge_multi(mv, Dr, [p.ox, p.oy])
+    assert np.array_equal(mo, mo2) and np.array_equal(ma, ma2)
+
+
+def test_multi_objective_invariances(orc):
+    sc = _multi_inputs((0, 1, 0))
+    n, h, w = 3, 20, 20
+    mv = orc.Multi(sc.S, sc.orient, sc.A, sc.V)
+    D = RNG.normal(0, 0.8, (n, h, w, 3))
+    eta = np.array([1.1, 0.9, 1.3])  # pairs (0,1), (0,2), (1,2)
+    t, _, g = orc.evaluate_multi(mv, D, orc.Params(), eta)
+    # relabelling the volumes (and with them the fields and the pairs' eta)
+    perm = [2, 0, 1]
+    mv2 = orc.Multi([sc.S[q] for q in perm], [sc.orient[q] for q in perm], [sc.A[q] for q in perm],
+                    [sc.V[q] for q in perm])
+    pairs = orc.pair_index(3)
+    eta2 = [eta[pairs.index(tuple(sorted((perm[P], perm[Q]))))] for P, Q in pairs]
+    t2, _, g2 = orc.evaluate_multi(mv2, D[perm], orc.Params(), eta2)
+    for key in ("F", "data", "reg", "mean"):
+        assert math.isclose(t[key], t2[key], rel_tol=1e-12), key
+    assert np.allclose(g[perm], g2, rtol=1e-12, atol=1e-12)
+    # identical volumes at zero displacement: no data term
+    same = orc.Multi([sc.S[0]] * 3, [0, 1, 0], [sc.A[0]] * 3)
+    t0, _, _ = orc.evaluate_multi(same, np.zeros((n, h, w, 3)))
+    assert t0["data"] == 0.0
+
+
+def test_multi_gradient_matches_finite_differences(orc):
+    sc = _multi_inputs((0, 1, 1), n=12, d=16, seed=1)
+    mv = orc.Multi(sc.S, sc.orient, sc.A, sc.V)
+    D = RNG.normal(0, 0.7, (3, 12, 12, 3))
+    eta = [1.2, 0.8, 1.0]
+    _, _, g = orc.evaluate_multi(mv, D, orc.Params(), eta)
+    eps = 1e-6
+    for _ in range(12):
+        idx = tuple(int(RNG.integers(0, s)) for s in D.shape)
+        Dp, Dm = D.copy(), D.copy()
+        Dp[idx] += eps
+        Dm[idx] -= eps
+        fd = (orc.evaluate_multi(mv, Dp, orc.Params(), eta, grad=False)[0]["F"] -
+              orc.evaluate_multi(mv, Dm, orc.Params(), eta, grad=False)[0]["F"]) / (2 * eps)
+        assert abs(fd - g[idx]) <= 1e-5 * max(1.0, abs(g[idx])), (idx, fd, g[idx])
+
+
+def test_multi_merge_two_pairs_fill_white_line_gaps(orc):
+    """Fig. 4(d): with one pair, the crossing of an invalid X-fast B-scan and
+    an invalid Y-fast B-scan has no valid OCTA data (a gap, 0); a second,
+    valid pair fills it with the mean of its two scans."""
+    h = w = 16
+    d = 8
+    rng = np.random.default_rng(4)
+    S = [rng.random((h, w, d)) for _ in range(4)]
+    O = [rng.random((h, w, d)) + 0.5 for _ in range(4)]
+    A = [np.zeros((h, w))] * 4
+    j0, i0 = 7, 9
+    vX1 = np.ones(h)
+    vX1[j0] = 0.0
+    vY1 = np.ones(w)
+    vY1[i0] = 0.0
+    D0 = np.zeros((4, h, w, 3))
+    one = orc.Multi(S[:2], [0, 1], A[:2], [vX1, vY1])
+    _, ma1 = orc.merge_multi(one, D0[:2], O[:2])
+    assert np.all(ma1[j0, i0] == 0.0)
+    two = orc.Multi(S, [0, 1, 0, 1], A, [vX1, vY1, np.ones(h), np.ones(w)])
+    mo2, ma2 = orc.merge_multi(two, D0, O)
+    assert np.allclose(ma2[j0, i0], 0.5 * (O[2][j0, i0] + O[3][j0, i0]), rtol=0, atol=1e-14)
+    # away from the white lines all four scans count equally (identity fields: density 1)
+    assert np.allclose(ma2[2, 3], 0.25 * sum(o[2, 3] for o in O), rtol=0, atol=1e-14)
+    assert np.allclose(mo2[2, 3], 0.25 * sum(s[2, 3] for s in S), rtol=0, atol=1e-14)
