@@ -293,6 +293,49 @@ OCTMC_API int octmc_pair_prealignment(const octmc_pair* pair, double* theta_out,
 OCTMC_API int octmc_resample_axial(octmc_ctx* ctx, const octmc_shape* shape, const float* vol, const float* dz,
                                    float* out, void* stream);
 
+/* More than two volumes (Sec. 2.1 input: at least two raster scans, at least
+ * one orthogonal to the others; the paper leaves the generalisation to
+ * earlier work).  Every volume V has an orientation (0: X-fast, B-scans are
+ * rows j; 1: Y-fast, columns i) and its own field.  Objective: the
+ * two-volume data term (Eqs. 2-9) summed over all volume pairs P < Q, each
+ * pair with its own eta (Eq. 10) and the validity of Eq. 5 resampled along
+ * each volume's slow axis; plus alpha R summed over the volumes in their own
+ * acquisition orders; plus M = gamma d / (n N_A) sum_c (sum_V sum_ij d)^2.
+ * For n = 2 with orientations (0, 1) it is the pair objective.  The merge
+ * normalises the density weights over all volumes (a second orthogonal pair
+ * fills the first pair's white-line crossings, Fig. 4).
+ *
+ * octmc_multi_create: n (2..8) volumes of one shape; orient[n] (both
+ * orientations must occur); oct[n] structural volumes [h][w][d] float32;
+ * octa (NULL or n OCTA volumes), enface (NULL or n en face images [h][w]),
+ * valid (NULL or n vectors of h values for X-fast, w for Y-fast volumes), as
+ * octmc_pair_create (OCTMC_DETECT_INVALID and OCTMC_ENFACE_PROJECT apply per
+ * volume; OCTMC_PREALIGN is not available here).  Pointers live in
+ * shape->mem memory and are copied.  Errors: as octmc_pair_create. */
+typedef struct octmc_multi octmc_multi;
+OCTMC_API int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, int32_t n,
+                                 const int32_t* orient, const float* const* oct, const float* const* octa,
+                                 const float* const* enface, const float* const* valid, void* stream,
+                                 octmc_multi** out);
+OCTMC_API int octmc_multi_destroy(octmc_multi* multi);
+
+/* One evaluation of the n-volume objective at pyramid level `level`: disp
+ * device [n][h][w][3] float32 (level pixels), terms device
+ * float64[OCTMC_NTERMS] (OCTMC_TERM_ETA is the first pair's eta), grad
+ * device [n][h][w][3] float32 or NULL; eta_mode as octmc_eval (per pair).
+ * Asynchronous on `stream`.  Errors: OCTMC_E_INVALID, OCTMC_E_BUSY, OCTMC_E_DEVICE. */
+OCTMC_API int octmc_multi_eval(octmc_multi* multi, int32_t level, const float* disp, double* terms, float* grad,
+                               int32_t eta_mode, void* stream);
+
+/* The n-volume registration (the multi-resolution L-BFGS of octmc_register
+ * over all n fields) and, if merged_oct != NULL, the merge.  disp_out device
+ * [n][h][w][3]; merged_oct, merged_octa (needs OCTA volumes) device
+ * [h][w][d] float32 or NULL; rep as octmc_register (eta of the first pair).
+ * Synchronises `stream`.  Errors: OCTMC_E_INVALID, OCTMC_E_BUSY, OCTMC_E_OOM,
+ * OCTMC_E_DEVICE. */
+OCTMC_API int octmc_multi_register(octmc_multi* multi, float* disp_out, float* merged_oct, float* merged_octa,
+                                   octmc_report* rep, void* stream);
+
 /* Shape (w, h, d) of pyramid level `level` (0 = finest). */
 OCTMC_API int octmc_pair_level_shape(const octmc_pair* pair, int32_t level, int32_t* w, int32_t* h, int32_t* d);
 

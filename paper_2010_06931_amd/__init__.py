@@ -38,7 +38,8 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_DTYPE", -4: "E_OOM", -
 SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_create", "octmc_destroy",
            "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_validity_from_octa",
            "octmc_enface_project", "octmc_enface_workspace_size", "octmc_prealign_eval", "octmc_prealign",
-           "octmc_pair_prealignment", "octmc_resample_axial", "octmc_eval",
+           "octmc_pair_prealignment", "octmc_resample_axial", "octmc_multi_create", "octmc_multi_destroy",
+           "octmc_multi_eval", "octmc_multi_register", "octmc_eval",
            "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge",
            "octmc_request_footprint", "octmc_server_create", "octmc_server_submit", "octmc_server_poll",
            "octmc_server_status", "octmc_server_destroy")
@@ -125,6 +126,12 @@ def lib():
         L.octmc_prealign.argtypes = [vp, C.c_double, C.c_int32, dpp, C.POINTER(Report), vp]
         L.octmc_pair_prealignment.argtypes = [vp, dpp, vp, vp]
         L.octmc_resample_axial.argtypes = [vp, C.POINTER(Shape), vp, vp, vp, vp]
+        L.octmc_multi_create.argtypes = [vp, C.POINTER(Params), C.POINTER(Shape), C.c_int32, C.POINTER(C.c_int32),
+                                         C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
+                                         C.POINTER(vp)]
+        L.octmc_multi_destroy.argtypes = [vp]
+        L.octmc_multi_eval.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
+        L.octmc_multi_register.argtypes = [vp, vp, vp, vp, C.POINTER(Report), vp]
         L.octmc_eval.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.octmc_eval_profile.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), vp]
         L.octmc_eval_batched.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
@@ -358,6 +365,81 @@ def validity_from_octa(vol: torch.Tensor, scan: int, *, ctx: Context | None = No
     shape = Shape(w, h, d, F32, MEM_DEVICE)
     _check(lib().octmc_validity_from_octa(ctx._h, C.byref(shape), _ptr(vol), int(scan), _ptr(out), _stream(stream)))
     return out
+
+
+class Multi:
+    """n >= 2 raster scans registered jointly (two-volume terms over all
+    pairs).  vols: structural volumes [h][w][d]; orients: 0 (X-fast) or 1
+    (Y-fast) per volume; octa, enface, valid: lists of n or None."""
+
+    def __init__(self, vols, orients, *, octa=None, enface=None, valid=None, params: Params | None = None,
+                 dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,
+                 project_enface: bool = False, **param_overrides):
+        self.ctx = ctx or context(0)
+        dev = torch.device("cuda", self.ctx.device)
+        self.params = params if params is not None else default_params()
+        for k, v in param_overrides.items():
+            setattr(self.params, k, v)
+        if detect_invalid:
+            self.params.flags |= DETECT_INVALID
+        if project_enface:
+            self.params.flags |= ENFACE_PROJECT
+        n = len(vols)
+        self._has_octa = octa is not None
+        S = [_f32(v, dev) for v in vols]
+        h, w, d = S[0].shape
+        self.n = n
+        self.shape = Shape(w, h, d, _DTYPES[dtype], MEM_DEVICE)
+        lists = {}
+        for name, lst in (("octa", octa), ("enface", enface), ("valid", valid)):
+            lists[name] = None if lst is None else [_f32(x, dev) for x in lst]
+        self._keep = (S, lists)
+        arr = lambda ts: None if ts is None else (C.c_void_p * n)(*[t.data_ptr() for t in ts])
+        orient = (C.c_int32 * n)(*[int(o) for o in orients])
+        self._h = C.c_void_p()
+        _check(lib().octmc_multi_create(self.ctx._h, C.byref(self.params), C.byref(self.shape), n, orient, arr(S),
+                                        arr(lists["octa"]), arr(lists["enface"]), arr(lists["valid"]),
+                                        _stream(stream), C.byref(self._h)))
+        self._keep = None  # the library copied the inputs
+
+    def level_shape(self, level: int):
+        w, h, d = self.shape.w, self.shape.h, self.shape.d
+        for _ in range(level):
+            w, h, d = (w + 1) // 2, (h + 1) // 2, (d + 1) // 2
+        return w, h, d
+
+    def eval(self, level: int, disp: torch.Tensor, *, grad: bool = True, eta_mode: int = 1, stream=None):
+        """n-volume objective terms (float64[NTERMS], device) and gradient."""
+        w, h, _ = self.level_shape(level)
+        if disp.shape != (self.n, h, w, 3) or disp.dtype != torch.float32 or not disp.is_cuda:
+            raise ValueError(f"disp must be a float32 cuda tensor of shape ({self.n}, {h}, {w}, 3)")
+        disp = disp.contiguous()
+        terms = torch.empty(NTERMS, dtype=torch.float64, device=disp.device)
+        g = torch.empty_like(disp) if grad else None
+        _check(lib().octmc_multi_eval(self._h, level, _ptr(disp), _ptr(terms), _ptr(g), eta_mode, _stream(stream)))
+        return terms, g
+
+    def register(self, *, merged: bool = False, stream=None):
+        """Joint solve: (disp [n][h][w][3], merged_oct or None, merged_octa or None, report)."""
+        h, w, d = self.shape.h, self.shape.w, self.shape.d
+        dev = torch.device("cuda", self.ctx.device)
+        disp = torch.empty((self.n, h, w, 3), dtype=torch.float32, device=dev)
+        mo = torch.empty((h, w, d), dtype=torch.float32, device=dev) if merged else None
+        ma = torch.empty_like(mo) if merged and self._has_octa else None
+        rep = Report()
+        _check(lib().octmc_multi_register(self._h, _ptr(disp), _ptr(mo), _ptr(ma), C.byref(rep), _stream(stream)))
+        return disp, mo, ma, rep.as_list()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().octmc_multi_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def resample_axial(vol: torch.Tensor, dz: torch.Tensor, *, ctx: Context | None = None, stream=None) -> torch.Tensor:

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liboctmc.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["kernels_eval.hip", "kernels_prep.hip", "kernels_lbfgs.hip", "kernels_merge.hip", "kernels_enface.hip",
-           "kernels_prealign.hip", "runtime.hip", "prealign.hip", "server.hip"]
+           "kernels_prealign.hip", "runtime.hip", "prealign.hip", "multi.hip", "server.hip"]
 ARCH = os.environ.get("OCTMC_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-fvisibility=hidden", "-DOCTMC_BUILD",
          # no packed FP32 instructions in generated code

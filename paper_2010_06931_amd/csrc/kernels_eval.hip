@@ -727,9 +727,14 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
         sample2(J.ay, w, h, i, j, dY[0], dY[1], jy);
         double LA, GA;
         huber_d((double)jx[0] - (double)jy[0], J.eps_h, LA, GA);
+        // validity (Eq. 5) varies along each scan's slow axis: y for an X-fast
+        // scan (index j, component dy), x for a Y-fast scan
+        const int oX = J.orient & 1, oY = (J.orient >> 1) & 1;
         float rx[2], ry[2];
-        sample1(J.vx, h, j, dX[1], rx);  // X-fast validity varies along y (Eq. 5)
-        sample1(J.vy, w, i, dY[0], ry);  // Y-fast along x
+        if (oX == 0) sample1(J.vx, h, j, dX[1], rx);
+        else sample1(J.vx, w, i, dX[0], rx);
+        if (oY == 1) sample1(J.vy, w, i, dY[0], ry);
+        else sample1(J.vy, h, j, dY[1], ry);
         const double tvx = rx[0] <= 0.f ? 0.0 : (rx[0] >= 1.f ? 1.0 : (double)rx[0]);
         const double dtvx = (rx[0] > 0.f && rx[0] < 1.f) ? (double)rx[1] : 0.0;
         const double tvy = ry[0] <= 0.f ? 0.0 : (ry[0] >= 1.f ? 1.0 : (double)ry[0]);
@@ -747,19 +752,22 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
             const double dpd = -eta * lam + dd / eta * LA;  // d(data)/d(delta)
             double g[6];
             g[0] = ws * p0.y + wa * GA * jx[1];
-            g[1] = ws * p0.z + wa * GA * jx[2] + dpd * J.delta0 * tvy * dtvx;
+            g[1] = ws * p0.z + wa * GA * jx[2];
             g[2] = ws * p0.w;
-            g[3] = -(ws * p1.x + wa * GA * jy[1]) + dpd * J.delta0 * tvx * dtvy;
+            g[3] = -(ws * p1.x + wa * GA * jy[1]);
             g[4] = -(ws * p1.y + wa * GA * jy[2]);
             g[5] = -(ws * p1.z);
+            g[oX == 0 ? 1 : 0] += dpd * J.delta0 * tvy * dtvx;
+            g[oY == 1 ? 3 : 4] += dpd * J.delta0 * tvx * dtvy;
             // scan-order regulariser (gather form: this A-scan's two links)
             double reg = 0.0;
             for (int V = 0; V < 2; ++V) {
                 const float* DV = J.disp + (size_t)V * na * 3;
                 const float* da = DV + (size_t)a * 3;
+                const int oV = V == 0 ? oX : oY;  // acquisition order of the slot's scan
                 double omp, omn;
-                const int pa = prev_ascan(V, i, j, w, h, J.wfb, omp);
-                const int nb = next_ascan(V, i, j, w, h, J.wfb, omn);
+                const int pa = prev_ascan(oV, i, j, w, h, J.wfb, omp);
+                const int nb = next_ascan(oV, i, j, w, h, J.wfb, omn);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     double Lr, dLr;

@@ -35,10 +35,11 @@ __device__ __forceinline__ void bilin(float x, float y, int w, int h, int& x0, i
     fy = y - y0;
 }
 
-__global__ void k_density(const float* __restrict__ disp, int w, int h, unsigned long long* __restrict__ grid)
+__global__ void k_density(const float* __restrict__ disp, int w, int h, unsigned long long* __restrict__ grid,
+                          int nvol)
 {
     const int na = w * h;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < 2 * na; q += gridDim.x * blockDim.x) {
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nvol * na; q += gridDim.x * blockDim.x) {
         const int V = q / na, a = q % na;
         const int i = a % w, j = a / w;
         int x0, y0, x1, y1;
@@ -196,6 +197,88 @@ __global__ __launch_bounds__(256) void k_merge_volume(const void* __restrict__ s
     }
 }
 
+// n-volume merge weights: OCT weights wo[V][a] normalised over the volumes
+// (the lowest-density volume where all vanish; the first on a tie) and OCTA
+// weights wa[V][a] = OCT weight before normalisation times the resampled
+// validity along the volume's slow axis, normalised (0 where all vanish)
+__global__ void k_merge_weights_multi(const float* __restrict__ disp, int w, int h,
+                                      const unsigned long long* __restrict__ grid, const MultiVols mv, double kappa,
+                                      double tau, float* __restrict__ wo, float* __restrict__ wa)
+{
+    const int na = w * h;
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < na; a += gridDim.x * blockDim.x) {
+        const int i = a % w, j = a / w;
+        double rho[kMaxVol], wt[kMaxVol], ow[kMaxVol];
+        double sw = 0.0, so = 0.0;
+        int lowest = 0;
+        for (int V = 0; V < mv.n; ++V) {
+            const float* dv = disp + ((size_t)V * na + a) * 3;
+            int x0, y0, x1, y1;
+            float fx, fy;
+            bilin(i + dv[0], j + dv[1], w, h, x0, y0, x1, y1, fx, fy);
+            const unsigned long long* G = grid + (size_t)V * na;
+            rho[V] = ((1.0 - fx) * (1.0 - fy) * (double)G[(size_t)y0 * w + x0] +
+                      (double)fx * (1.0 - fy) * (double)G[(size_t)y0 * w + x1] +
+                      (1.0 - fx) * (double)fy * (double)G[(size_t)y1 * w + x0] +
+                      (double)fx * (double)fy * (double)G[(size_t)y1 * w + x1]) / kFix;
+            wt[V] = exp(-kappa * fmax(0.0, rho[V] - 1.0));
+            if (wt[V] < tau) wt[V] = 0.0;
+            sw += wt[V];
+            if (rho[V] < rho[lowest]) lowest = V;
+            ow[V] = 0.0;
+            if (mv.valid[V])
+                ow[V] = wt[V] * (mv.orient[V] == 0 ? valid_at(mv.valid[V], h, j, dv[1])
+                                                    : valid_at(mv.valid[V], w, i, dv[0]));
+            so += ow[V];
+        }
+        for (int V = 0; V < mv.n; ++V) {
+            const double o = sw > 0 ? wt[V] / sw : (V == lowest ? 1.0 : 0.0);
+            wo[(size_t)V * na + a] = (float)o;
+            wa[(size_t)V * na + a] = (float)(so > 0 ? ow[V] / so : 0.0);
+        }
+    }
+}
+
+// one thread per output sample: the weighted sum over the volumes of the
+// Eq. 2 interpolator's value at each volume's sample position
+template <typename T>
+__global__ __launch_bounds__(256) void k_merge_volume_multi(const MultiVols mv, const float* __restrict__ disp,
+                                                            const float* __restrict__ wts, int w, int h, int d,
+                                                            float* __restrict__ out)
+{
+    const int na = w * h;
+    const size_t total = (size_t)na * d;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int a = (int)(q / d), k = (int)(q - (size_t)a * d);
+        const int i = a % w, j = a / w;
+        float res = 0.f;
+        for (int V = 0; V < mv.n; ++V) {
+            const float wgt = wts[(size_t)V * na + a];
+            if (wgt == 0.f) continue;
+            const float* dv = disp + ((size_t)V * na + a) * 3;
+            const float fxf = floorf(dv[0]), fyf = floorf(dv[1]), fzf = floorf(dv[2]);
+            const int nx = i + (int)fxf, ny = j + (int)fyf, nz = k + (int)fzf;
+            float wx[4], wy[4], wz[4];
+            cr_w(dv[0] - fxf, wx);
+            cr_w(dv[1] - fyf, wy);
+            cr_w(dv[2] - fzf, wz);
+            float v = 0.f;
+            for (int b = 0; b < 4; ++b) {
+                const size_t row = (size_t)clampi(ny - 1 + b, 0, h - 1) * w;
+                for (int c = 0; c < 4; ++c) {
+                    const size_t col = (row + clampi(nx - 1 + c, 0, w - 1)) * d;
+                    float z = 0.f;
+                    for (int e = 0; e < 4; ++e) z = fmaf(wz[e], ld<T>(mv.vol[V], col + clampi(nz - 1 + e, 0, d - 1)), z);
+                    v = fmaf(wx[c] * wy[b], z, v);
+                }
+            }
+            res = fmaf(wgt, v, res);
+        }
+        out[q] = res;
+    }
+}
+
 inline int grid_for(size_t n, int cap = 65536)
 {
     size_t g = (n + 255) / 256;
@@ -205,9 +288,39 @@ inline int grid_for(size_t n, int cap = 65536)
 
 }  // namespace
 
-hipError_t launch_density(const float* disp, int w, int h, unsigned long long* grid, hipStream_t s)
+hipError_t launch_density(const float* disp, int w, int h, unsigned long long* grid, hipStream_t s, int nvol)
 {
-    hipLaunchKernelGGL(k_density, dim3(grid_for((size_t)2 * w * h)), dim3(256), 0, s, disp, w, h, grid);
+    hipLaunchKernelGGL(k_density, dim3(grid_for((size_t)nvol * w * h)), dim3(256), 0, s, disp, w, h, grid, nvol);
+    return hipGetLastError();
+}
+hipError_t launch_merge_weights_multi(const float* disp, int w, int h, const unsigned long long* grid,
+                                      const MultiVols& mv, double kappa, double tau, float* wo, float* wa,
+                                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_merge_weights_multi, dim3(grid_for((size_t)w * h)), dim3(256), 0, s, disp, w, h, grid, mv,
+                       kappa, tau, wo, wa);
+    return hipGetLastError();
+}
+hipError_t launch_merge_volume_multi(const MultiVols& mv, octmc_dtype dt, const float* disp, const float* wts, int w,
+                                     int h, int d, float* out, hipStream_t s)
+{
+    const size_t n = (size_t)w * h * d;
+    switch (dt) {
+    case OCTMC_F32:
+        hipLaunchKernelGGL(k_merge_volume_multi<float>, dim3(grid_for(n)), dim3(256), 0, s, mv, disp, wts, w, h, d,
+                           out);
+        break;
+    case OCTMC_BF16:
+        hipLaunchKernelGGL(k_merge_volume_multi<bf16_t>, dim3(grid_for(n)), dim3(256), 0, s, mv, disp, wts, w, h, d,
+                           out);
+        break;
+    case OCTMC_F16:
+        hipLaunchKernelGGL(k_merge_volume_multi<f16_t>, dim3(grid_for(n)), dim3(256), 0, s, mv, disp, wts, w, h, d,
+                           out);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 hipError_t launch_merge_weights(const float* disp, int w, int h, const unsigned long long* grid, const float* vx,

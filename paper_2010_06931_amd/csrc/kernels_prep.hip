@@ -116,9 +116,10 @@ __global__ void k_copy_bscans(float* __restrict__ vol, int w, int h, int d, cons
     }
 }
 
-__global__ void k_upsample(const double* __restrict__ C, int wc, int hc, double* __restrict__ Fo, int wf, int hf)
+__global__ void k_upsample(const double* __restrict__ C, int wc, int hc, double* __restrict__ Fo, int wf, int hf,
+                           int nvol)
 {
-    const int total = 2 * wf * hf;
+    const int total = nvol * wf * hf;
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
         const int V = q / (wf * hf);
         const int r = q % (wf * hf);
@@ -252,10 +253,11 @@ hipError_t launch_copy_bscans(float* vol, int w, int h, int d, const int* src, i
     hipLaunchKernelGGL(k_copy_bscans, dim3(grid_for((size_t)w * h * d)), dim3(256), 0, s, vol, w, h, d, src, V);
     return hipGetLastError();
 }
-hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf, hipStream_t s)
+hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf, hipStream_t s,
+                           int nvol)
 {
-    hipLaunchKernelGGL(k_upsample, dim3(grid_for((size_t)2 * wf * hf)), dim3(256), 0, s, coarse, wc, hc, fine, wf,
-                       hf);
+    hipLaunchKernelGGL(k_upsample, dim3(grid_for((size_t)nvol * wf * hf)), dim3(256), 0, s, coarse, wc, hc, fine, wf,
+                       hf, nvol);
     return hipGetLastError();
 }
 

@@ -142,6 +142,7 @@ struct CombineJob {
     double* terms;       // [OCTMC_NTERMS] (mode 1)
     int w, h, d, na, blk_begin, nblk, nsum;
     int mode;            // 0: only set eta (Eq. 10); 1: full evaluation
+    int orient;          // scan orientation of the two slots (bit 0: first, bit 1: second; 0 X-fast, 1 Y-fast)
     double delta0, eps_h, eps_r, alpha, gamma, wfb;
 };
 struct CombineJobs {
@@ -165,7 +166,8 @@ hipError_t launch_pyr1(const float* in, int n, float* out, hipStream_t s);
 hipError_t launch_enface_mean(const float* vol, int na, int d, float* out, hipStream_t s);
 hipError_t launch_count_nonfinite(const float* v, size_t n, unsigned* counter, hipStream_t s);
 hipError_t launch_copy_bscans(float* vol, int w, int h, int d, const int* src, int V, hipStream_t s);
-hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf, hipStream_t s);
+hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, int wf, int hf, hipStream_t s,
+                           int nvol = 2);
 // Stage 1, rough axial prealignment (kernels_prealign.hip, prealign.hip).
 // theta: X-fast B-scans (h rows) then Y-fast B-scans (w columns), (offset,
 // tilt) each.  launch_tilt_expand writes the [2][h][w][3] field (disp) and/or
@@ -183,6 +185,8 @@ int prealign_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shap
                     const float* oct_y, const float* octa_x, const float* octa_y, const float* enface_x,
                     const float* enface_y, const float* valid_x, const float* valid_y, hipStream_t s,
                     octmc_pair** out);
+// evaluation scratch of a pair whose finest level has na A-scans (runtime.hip)
+int pair_alloc_scratch(octmc_pair* pair, size_t na, hipStream_t s);
 // pair accessors (runtime.hip)
 int pair_nlev(const octmc_pair* pair);
 const octmc_params& pair_params(const octmc_pair* pair);
@@ -242,7 +246,21 @@ hipError_t launch_to_f32(const double* in, float* out, size_t n, hipStream_t s);
 hipError_t launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s);
 
 // merge (kernels_merge.hip)
-hipError_t launch_density(const float* disp, int w, int h, unsigned long long* grid, hipStream_t s);
+hipError_t launch_density(const float* disp, int w, int h, unsigned long long* grid, hipStream_t s, int nvol = 2);
+// merge of n volumes (2..kMaxVol): OCT and OCTA weights [n][na] from the
+// densities and validities, then the weighted sum of the resampled volumes
+constexpr int kMaxVol = 8;
+struct MultiVols {
+    const void* vol[kMaxVol];   // storage-type (or float32) volumes [h][w][d]
+    const float* valid[kMaxVol];  // validity vectors (nullptr: no OCTA weights)
+    int orient[kMaxVol];
+    int n;
+};
+hipError_t launch_merge_weights_multi(const float* disp, int w, int h, const unsigned long long* grid,
+                                      const MultiVols& mv, double kappa, double tau, float* wo, float* wa,
+                                      hipStream_t s);
+hipError_t launch_merge_volume_multi(const MultiVols& mv, octmc_dtype dt, const float* disp, const float* wts, int w,
+                                     int h, int d, float* out, hipStream_t s);
 hipError_t launch_merge_weights(const float* disp, int w, int h, const unsigned long long* grid,
                                 const float* vx, const float* vy, double kappa, double tau, float4* wts,
                                 hipStream_t s);

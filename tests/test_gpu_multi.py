@@ -1,0 +1,136 @@
+"""More than two volumes on the GPU, through the C ABI, against the FP64
+oracle: the n-volume objective and gradient (10^-4 relative), the joint
+solve (0.05 px RMS), the merge (10^-4) including the filling of one pair's
+white-line crossings by a second pair, and n = 2 against the pair path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import grad_rel, log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def octmc():
+    import paper_2010_06931_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def scans():
+    return synth.make_scans("tiny", 2, (0, 1, 0, 1), n=40, d=64, white_lines=True)
+
+
+def _oracle_multi(sc, idx=None):
+    idx = list(range(len(sc.S))) if idx is None else idx
+    return oracle.Multi([sc.S[q] for q in idx], [sc.orient[q] for q in idx], [sc.A[q] for q in idx],
+                        [sc.V[q] for q in idx])
+
+
+def _gpu_multi(octmc, sc, idx=None, **kw):
+    idx = list(range(len(sc.S))) if idx is None else idx
+    return octmc.Multi([sc.S[q] for q in idx], [sc.orient[q] for q in idx], enface=[sc.A[q] for q in idx],
+                       valid=[sc.V[q] for q in idx], **kw)
+
+
+def test_multi_two_volumes_match_the_pair_path(octmc):
+    p = synth.make_pair("tiny", 0, n=40, d=64, white_lines=True)
+    D = synth.perturbed_field(p.d_gt, 0.3, 2).float().cuda()
+    log("n = 2 multi vs pair, level 0")
+    P = octmc.Pair(p.sx, p.sy, ax=p.ax, ay=p.ay, vx=p.vx, vy=p.vy, levels=2)
+    M = octmc.Multi([p.sx, p.sy], [0, 1], enface=[p.ax, p.ay], valid=[p.vx, p.vy], levels=2)
+    t1, g1 = P.eval(0, D, eta_mode=0)
+    t2, g2 = M.eval(0, D, eta_mode=0)
+    torch.cuda.synchronize()
+    a, b = octmc.terms_dict(t1), octmc.terms_dict(t2)
+    for key in ("F", "data", "str", "ang", "reg", "mean"):
+        assert rel(b[key], a[key]) < 1e-12 or abs(b[key] - a[key]) < 1e-9, key
+    assert grad_rel(g2.double().cpu().numpy(), g1.double().cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_multi_objective_parity(octmc, scans, level):
+    sc = scans
+    n = len(sc.S)
+    M = _gpu_multi(octmc, sc, levels=2)
+    w, h, d = M.level_shape(level)
+    rng = np.random.default_rng(level)
+    D = rng.normal(0, 0.8, (n, h, w, 3))
+    # oracle inputs at this level: the pyramid of every volume
+    S = [s.double().numpy() for s in sc.S]
+    A = [a.double().numpy() for a in sc.A]
+    V = [v.double().numpy() for v in sc.V]
+    for _ in range(level):
+        S = [oracle.pyr_down3(s) for s in S]
+        A = [oracle.pyr_down2(a) for a in A]
+        V = [oracle.pyr_down1(v) for v in V]
+    om = oracle.Multi(S, sc.orient, A, V)
+    t0, p05, _ = oracle.evaluate_multi(om, D, oracle.Params(), None, grad=False)
+    eta = np.array([oracle.eta_from_terms(a, b) for a, b in p05])
+    ref, _, gref = oracle.evaluate_multi(om, D, oracle.Params(), eta)
+    log(f"n = 4 objective at level {level} ({w}x{h}x{d})")
+    t, g = M.eval(level, torch.from_numpy(D).float().cuda(), eta_mode=0)
+    torch.cuda.synchronize()
+    td = octmc.terms_dict(t)
+    for key in ("F", "data", "str", "ang", "reg", "mean"):
+        assert rel(td[key], ref[key]) < 1e-4, (key, td[key], ref[key])
+    assert grad_rel(g.double().cpu().numpy(), gref) < 1e-4
+
+
+def test_multi_register_parity(octmc, scans):
+    sc = scans
+    log("n = 4 joint solve, 2 levels x 40 steps, GPU")
+    M = _gpu_multi(octmc, sc, levels=2, iters_per_level=40)
+    Dg, _, _, rep = M.register()
+    torch.cuda.synchronize()
+    log("n = 4 joint solve in the oracle")
+    Do, repo = oracle.register_multi(_oracle_multi(sc), oracle.Params(levels=2, iters=40))
+    err = np.sqrt(((Dg.double().cpu().numpy() - Do) ** 2).mean())
+    assert err < 0.05, err
+    for r, ro in zip(rep, repo):
+        assert abs(r["f_end"] - ro["f_end"]) <= 0.05 * abs(ro["f_end"]), (r, ro)
+    assert rep[-1]["f_end"] < rep[-1]["f_start"]
+
+
+def test_multi_merge_parity_and_gap_filling(octmc):
+    """Identity fields (no solve steps), white lines in the first pair only:
+    the merge equals the oracle's, and at the first pair's white-line
+    crossings the second pair supplies the OCTA data."""
+    sc = synth.make_scans("tiny", 3, (0, 1, 0, 1), n=36, d=48, white_lines=True)
+    # white lines only in the first pair
+    V = [sc.V[0], sc.V[1], torch.ones_like(sc.V[2]), torch.ones_like(sc.V[3])]
+    O = [sc.O[0], sc.O[1], sc.O[2], sc.O[3]]
+    log("n = 4 merge at identity fields")
+    M = octmc.Multi(sc.S, sc.orient, octa=O, valid=V, levels=1, iters_per_level=0)
+    D, mo, ma, _ = M.register(merged=True)
+    torch.cuda.synchronize()
+    assert not D.any()
+    Osub = [oracle.substitute_invalid(O[q], V[q], sc.orient[q]) for q in range(4)]
+    om = oracle.Multi(sc.S, sc.orient, [oracle.enface_mean(o) for o in Osub], V)
+    rmo, rma = oracle.merge_multi(om, np.zeros((4, 36, 36, 3)), Osub)
+    assert np.abs(mo.double().cpu().numpy() - rmo).max() <= 1e-4 * np.abs(rmo).max()
+    assert np.abs(ma.double().cpu().numpy() - rma).max() <= 1e-4 * np.abs(rma).max()
+    bx = np.flatnonzero(V[0].numpy() == 0)  # invalid rows of the X-fast scan of pair 1
+    by = np.flatnonzero(V[1].numpy() == 0)  # invalid columns of its Y-fast scan
+    assert bx.size and by.size
+    cross = ma.cpu().numpy()[np.ix_(bx, by)]
+    assert np.all(cross > 0.0)  # filled by the second pair
+    log("the first pair alone leaves a gap there")
+    M2 = octmc.Multi(sc.S[:2], sc.orient[:2], octa=O[:2], valid=V[:2], levels=1, iters_per_level=0)
+    _, _, ma2, _ = M2.register(merged=True)
+    torch.cuda.synchronize()
+    assert np.all(ma2.cpu().numpy()[np.ix_(bx, by)] == 0.0)
+
+
+def test_multi_rejects_bad_input(octmc, scans):
+    sc = scans
+    with pytest.raises(octmc.OctmcError):
+        octmc.Multi(sc.S[:1], [0], enface=sc.A[:1])
+    with pytest.raises(octmc.OctmcError):
+        octmc.Multi([sc.S[0], sc.S[2]], [0, 0], enface=[sc.A[0], sc.A[2]])  # no orthogonal scan
+    with pytest.raises(octmc.OctmcError):
+        _gpu_multi(octmc, sc, prealign_iters=5, flags=octmc.PREALIGN)
