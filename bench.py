@@ -155,7 +155,7 @@ def _interior_rms(D, gt, border=8):
     import numpy as np
     e = D.double().cpu().numpy() - gt.double().cpu().numpy()
     h, w = e.shape[1:3]
-    m = np.zeros((2, h, w), bool)
+    m = np.zeros(e.shape[:3], bool)
     m[:, border:h - border, border:w - border] = True
     e -= e[m].mean(axis=0)
     return np.sqrt((e[m] ** 2).mean(axis=0))
@@ -327,6 +327,43 @@ def prealign_bench(octmc, torch, pair, dtype, log, iters=100):
             "paper_context": "26.7 s for the prealignment of a 500^2 x 465 pair (i7-6700K + GTX 960, CPU-heavy)"}
 
 
+def multi_bench(octmc, torch, log, reps=50):
+    """Four volumes (two orthogonal pairs of one phantom, white lines) at the
+    clinical 300^2 x 640 size: evaluations of the four-volume objective (six
+    pair terms) per second at the finest level and one joint solve (4 levels
+    x 100 steps), BF16 storage."""
+    import synth
+    log("four volumes 300x300x640: generating")
+    sc = synth.make_scans("clinical", 0, (0, 1, 0, 1), device="cuda", white_lines=True)
+    M = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=4, dtype="bf16")
+    n, h, w = 4, sc.S[0].shape[0], sc.S[0].shape[1]
+    D = (sc.d_gt + 0.2 * torch.randn(sc.d_gt.shape, generator=torch.Generator().manual_seed(1),
+                                     dtype=torch.float64)).float().cuda()
+    M.eval(0, D, eta_mode=0)
+    for _ in range(5):
+        M.eval(0, D)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        M.eval(0, D)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    log("four volumes: joint solve")
+    t0 = time.perf_counter()
+    Dsol, _, _, rep = M.register()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    err = [round(float(x), 4) for x in _interior_rms(Dsol, sc.d_gt)]
+    M.close()
+    return {"workload": "four volumes (X, Y, X, Y) 300x300 A-scans x 640 samples, BF16 storage",
+            "ms_per_eval": round(ms, 4), "evals_per_s": round(1000.0 / ms, 1), "pair_terms_per_eval": 6,
+            "solve_seconds": round(sec, 3), "solve_evals": int(sum(r["evals"] for r in rep)),
+            "solve_rms_vs_ground_truth_px": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,6 +378,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-enface", action="store_true", help="skip the en face projection timing")
     ap.add_argument("--no-prealign", action="store_true", help="skip the stage-1 prealignment timing")
+    ap.add_argument("--no-multi", action="store_true", help="skip the four-volume timing")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="time only the stage-1 prealignment, the four-volume path and the projection")
     ap.add_argument("--enface-only", action="store_true", help="time only the en face projection")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=48.0)
@@ -373,6 +413,16 @@ def main():
         f"({free / 2**30:.1f} GiB free)")
     if args.enface_only:
         print(json.dumps({"enface_projection": enface_bench(octmc, torch, log)}), flush=True)
+        return
+    if args.extras_only:
+        log(f"generating the dense pair {args.n}x{args.n}x{args.d} on cuda (structural)")
+        pair = synth.make_pair("dense", n=args.n, d=args.d, device="cuda", octa_volumes=False)
+        extra = {"prealign": prealign_bench(octmc, torch, pair, args.dtype, log)}
+        del pair
+        torch.cuda.empty_cache()
+        extra["multi_volume"] = multi_bench(octmc, torch, log)
+        extra["enface_projection"] = enface_bench(octmc, torch, log)
+        print(json.dumps(extra), flush=True)
         return
     log(f"generating the dense pair {args.n}x{args.n}x{args.d} on cuda")
     pair = synth.make_pair("dense", n=args.n, d=args.d, device="cuda", octa_volumes=False)
@@ -505,6 +555,9 @@ def main():
         out["prealign"] = prealign_bench(octmc, torch, pair, args.dtype, log)
     if not args.no_serve:
         out["serving"] = serving(octmc, torch, args.serve_requests, args.serve_budget_gib, args.serve_max_active, log)
+
+    if not args.no_multi:
+        out["multi_volume"] = multi_bench(octmc, torch, log)
 
     if not args.no_enface:
         del P

@@ -16,6 +16,18 @@ namespace {
 constexpr int kB = 256;
 constexpr int kMaxBlocks = 512;
 
+// sum (or max for the last row when `maxrow`) of a double over the 64 lanes
+// of a wave, in a fixed butterfly order
+__device__ __forceinline__ double wave_reduce(double v, bool maxrow)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off);
+        v = maxrow ? fmax(v, o) : v + o;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(kB) void k_multidot(const DotSpec spec, size_t n, double* __restrict__ blk)
 {
     const int nd = spec.ndots;
@@ -29,38 +41,48 @@ __global__ __launch_bounds__(kB) void k_multidot(const DotSpec spec, size_t n, d
             if (q < nd) acc[q] += spec.v[spec.a[q]][t] * spec.v[spec.b[q]][t];
         if (spec.gmax_vec >= 0) gmax = fmax(gmax, fabs(spec.v[spec.gmax_vec][t]));
     }
-    __shared__ double sh[kB];
-    const int nrow = nd + 1;
-    for (int q = 0; q < nrow; ++q) {
-        double v = 0.0;
+    // rows reduced within each wave (butterfly), then the waves in order
+    __shared__ double sh[kB / 64][kMaxDots + 1];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-        for (int r = 0; r < kMaxDots; ++r)
-            if (r == q) v = acc[r];
-        if (q == nd) v = gmax;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int s = kB / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s)
-                sh[threadIdx.x] = (q == nd) ? fmax(sh[threadIdx.x], sh[threadIdx.x + s])
-                                            : sh[threadIdx.x] + sh[threadIdx.x + s];
-            __syncthreads();
+    for (int q = 0; q < kMaxDots; ++q) {
+        if (q < nd) {  // uniform
+            const double v = wave_reduce(acc[q], false);
+            if (lane == 0) sh[wv][q] = v;
         }
-        if (threadIdx.x == 0) blk[(size_t)blockIdx.x * (kMaxDots + 1) + q] = sh[0];
-        __syncthreads();
+    }
+    {
+        const double v = wave_reduce(gmax, true);
+        if (lane == 0) sh[wv][nd] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q <= nd; q += kB) {
+        double s = sh[0][q];
+        for (int w = 1; w < kB / 64; ++w) s = (q == nd) ? fmax(s, sh[w][q]) : s + sh[w][q];
+        blk[(size_t)blockIdx.x * (kMaxDots + 1) + q] = s;
     }
 }
 
-// fixed-order final sum: thread q sums column q over the blocks in order
+// fixed-order final sum: the rows are dealt round robin to the waves; a
+// lane sums a contiguous run of blocks in order, the wave then reduces its
+// lanes in a fixed butterfly order
 __global__ __launch_bounds__(kB) void k_multidot_final(int nrow, int gmax_row, int nblk,
                                                        const double* __restrict__ blk, double* __restrict__ out)
 {
-    for (int q = threadIdx.x; q < nrow; q += kB) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int per = (nblk + 63) / 64;
+    for (int q = wv; q < nrow; q += kB / 64) {
+        const bool mx = q == gmax_row;
         double s = 0.0;
-        for (int b = 0; b < nblk; ++b) {
-            const double v = blk[(size_t)b * (kMaxDots + 1) + q];
-            s = (q == gmax_row) ? fmax(s, v) : s + v;
+        for (int e = 0; e < per; ++e) {
+            const int b = lane * per + e;
+            if (b < nblk) {
+                const double v = blk[(size_t)b * (kMaxDots + 1) + q];
+                s = mx ? fmax(s, v) : s + v;
+            }
         }
-        out[q] = s;
+        s = wave_reduce(s, mx);
+        if (lane == 0) out[q] = s;
     }
 }
 

@@ -71,6 +71,31 @@ __global__ __launch_bounds__(kMB) void k_field_sum(const float* __restrict__ dis
         for (int c = 0; c < 3; ++c) blk[(size_t)blockIdx.x * 3 + c] = red[c][0];
 }
 
+// lanes sum contiguous runs of partials in order, then a fixed butterfly
+__device__ __forceinline__ double wave_sum_rows(const double* __restrict__ blk, int stride, int row, int nblk)
+{
+    const int lane = threadIdx.x & 63;
+    const int per = (nblk + 63) / 64;
+    double s = 0.0;
+    for (int e = 0; e < per; ++e) {
+        const int b = lane * per + e;
+        if (b < nblk) s += blk[(size_t)b * stride + row];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
+// the three field sums from the block partials of k_field_sum (one wave each)
+__global__ __launch_bounds__(kMB) void k_field_sum_final(const double* __restrict__ blk, int nblk,
+                                                         double* __restrict__ S)
+{
+    const int wv = threadIdx.x >> 6;
+    if (wv >= 3) return;  // uniform per wave
+    const double s = wave_sum_rows(blk, 3, wv, nblk);
+    if ((threadIdx.x & 63) == 0) S[wv] = s;
+}
+
 struct GatherSpec {
     const double* pg[kMaxVol * (kMaxVol - 1) / 2];  // per pair gradient [2][na][3]
     signed char pq[kMaxVol][kMaxVol - 1];  // for each volume: its pairs in order
@@ -79,32 +104,27 @@ struct GatherSpec {
 };
 
 // gradient per volume = sum over its pairs (pair order) + dM/dd; g . p partials
-__global__ __launch_bounds__(kMB) void k_gather(const GatherSpec spec, size_t na, const double* __restrict__ sum_blk,
-                                                int nsum, double mscale, const double* __restrict__ p,
+__global__ __launch_bounds__(kMB) void k_gather(const GatherSpec spec, size_t na, const double* __restrict__ Sdev,
+                                                double mscale, const double* __restrict__ p,
                                                 double* __restrict__ g64, float* __restrict__ g32,
                                                 double* __restrict__ blk)
 {
     __shared__ double red[kMB];
-    __shared__ double S[3];
-    if (threadIdx.x < 3) {
-        double t = 0.0;
-        for (int b = 0; b < nsum; ++b) t += sum_blk[(size_t)b * 3 + threadIdx.x];
-        S[threadIdx.x] = t;
-    }
-    __syncthreads();
+    const double S[3] = {Sdev[0], Sdev[1], Sdev[2]};
     double gp = 0.0;
-    const size_t total = (size_t)spec.n * na * 3;
-    for (size_t e = (size_t)blockIdx.x * kMB + threadIdx.x; e < total; e += (size_t)gridDim.x * kMB) {
-        const int V = (int)(e / (na * 3));
-        const size_t r = e - (size_t)V * na * 3;
+    const size_t nr = na * 3;
+    for (size_t r = (size_t)blockIdx.x * kMB + threadIdx.x; r < nr; r += (size_t)gridDim.x * kMB) {
         const int c = (int)(r % 3);
-        double g = 0.0;
-        for (int t = 0; t < spec.n - 1; ++t)
-            g += spec.pg[spec.pq[V][t]][(size_t)spec.slot[V][t] * na * 3 + r];
-        g += mscale * S[c];
-        if (g64) g64[e] = g;
-        if (g32) g32[e] = (float)g;
-        if (p) gp += g * p[e];
+        for (int V = 0; V < spec.n; ++V) {
+            double g = 0.0;
+            for (int t = 0; t < spec.n - 1; ++t)
+                g += spec.pg[spec.pq[V][t]][(size_t)spec.slot[V][t] * nr + r];
+            g += mscale * S[c];
+            const size_t e = (size_t)V * nr + r;
+            if (g64) g64[e] = g;
+            if (g32) g32[e] = (float)g;
+            if (p) gp += g * p[e];
+        }
     }
     red[threadIdx.x] = gp;
     __syncthreads();
@@ -121,14 +141,14 @@ struct FinalSpec {
     double gamma, alpha, na;
 };
 
-// multi-volume terms from the pairs' terms (pair order), M and g . p
-__global__ void k_multi_final(const FinalSpec spec, const double* __restrict__ sum_blk, int nsum,
-                              const double* __restrict__ gp_blk, int ngp, double* __restrict__ terms)
+// multi-volume terms from the pairs' terms (pair order), M and g . p; one wave
+__global__ __launch_bounds__(64) void k_multi_final(const FinalSpec spec, const double* __restrict__ Sdev,
+                                                    const double* __restrict__ gp_blk, int ngp,
+                                                    double* __restrict__ terms)
 {
+    const double gp = wave_sum_rows(gp_blk, 1, 0, ngp);
     if (threadIdx.x != 0) return;
-    double S[3] = {0.0, 0.0, 0.0};
-    for (int b = 0; b < nsum; ++b)
-        for (int c = 0; c < 3; ++c) S[c] += sum_blk[(size_t)b * 3 + c];
+    const double S[3] = {Sdev[0], Sdev[1], Sdev[2]};
     double m = 0.0;
     for (int c = 0; c < 3; ++c) m += S[c] * S[c];
     m *= spec.gamma * spec.d / ((double)spec.n * spec.na);
@@ -143,8 +163,6 @@ __global__ void k_multi_final(const FinalSpec spec, const double* __restrict__ s
         s05 += t[OCTMC_TERM_STR05];
         a05 += t[OCTMC_TERM_ANG05];
     }
-    double gp = 0.0;
-    for (int b = 0; b < ngp; ++b) gp += gp_blk[b];
     terms[OCTMC_TERM_F] = f + m;
     terms[OCTMC_TERM_DATA] = data;
     terms[OCTMC_TERM_STR] = str;
@@ -182,6 +200,7 @@ struct octmc_multi {
     double* pgrad = nullptr;  // [npairs][2][na0][3]
     double* pterms = nullptr; // [npairs][NTERMS]
     double* sum_blk = nullptr;
+    double* fsum = nullptr;  // [3] sum of all fields
     double* gp_blk = nullptr;
     std::vector<void*> owned;
     int busy = 0;
@@ -229,6 +248,7 @@ struct MultiEvaluator final : Evaluator {
         const size_t nq = (size_t)M->n * na;
         const int nsum = grid_n(nq);
         hipLaunchKernelGGL(k_field_sum, dim3(nsum), dim3(kMB), 0, s, ea.disp, nq, M->sum_blk);
+        hipLaunchKernelGGL(k_field_sum_final, dim3(1), dim3(kMB), 0, s, M->sum_blk, nsum, M->fsum);
         GatherSpec gs{};
         gs.n = M->n;
         int cnt[kMaxVol] = {};
@@ -242,9 +262,9 @@ struct MultiEvaluator final : Evaluator {
         }
         const octmc_params& pr = M->params;
         const double mscale = 2.0 * pr.mean_weight * M->d[level] / ((double)M->n * (double)na);
-        const int ng = grid_n(nq * 3);
-        hipLaunchKernelGGL(k_gather, dim3(ng), dim3(kMB), 0, s, gs, na, M->sum_blk, nsum, mscale, ea.p, ea.grad64,
-                           ea.grad, M->gp_blk);
+        const int ng = grid_n(na * 3);
+        hipLaunchKernelGGL(k_gather, dim3(ng), dim3(kMB), 0, s, gs, na, M->fsum, mscale, ea.p, ea.grad64, ea.grad,
+                           M->gp_blk);
         FinalSpec fs{};
         for (int q = 0; q < np; ++q) fs.pt[q] = M->pterms + (size_t)q * OCTMC_NTERMS;
         fs.npairs = np;
@@ -253,7 +273,7 @@ struct MultiEvaluator final : Evaluator {
         fs.gamma = pr.mean_weight;
         fs.alpha = pr.alpha;
         fs.na = (double)na;
-        hipLaunchKernelGGL(k_multi_final, dim3(1), dim3(64), 0, s, fs, M->sum_blk, nsum, M->gp_blk, ng, ea.terms);
+        hipLaunchKernelGGL(k_multi_final, dim3(1), dim3(64), 0, s, fs, M->fsum, M->gp_blk, ng, ea.terms);
         HIP_TRY(hipGetLastError());
         return OCTMC_OK;
     }
@@ -484,6 +504,7 @@ int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params, const octmc_s
     HIP_TRY(M->alloc(&M->pterms, np * OCTMC_NTERMS * 8));
     HIP_TRY(M->alloc(&M->sum_blk, (size_t)kMBlocks * 3 * 8));
     HIP_TRY(M->alloc(&M->gp_blk, (size_t)kMBlocks * 8));
+    HIP_TRY(M->alloc(&M->fsum, 3 * 8));
     HIP_TRY(hipStreamSynchronize(s));  // staging is freed on return
     *out = M.release();
     return OCTMC_OK;
