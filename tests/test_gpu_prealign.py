@@ -147,3 +147,33 @@ def test_prealign_objective_parity_clinical_size(octmc):
                                      1.0)
     assert rel(t["F"] + T, ref["F1"]) < 1e-4
     assert grad_rel(g, gref) < 1e-4
+
+
+def test_full_pipeline_flags_equal_the_chained_entry_points(octmc):
+    """Fig. 1 in one call (prealignment, saccade detection, projection,
+    registration, merge) equals the same steps chained through the separate
+    entry points, bit for bit."""
+    pair = synth.make_pair("tiny", 1, n=48, d=64, white_lines=True, decorrelation=True)
+    kw = dict(levels=2, iters_per_level=20, prealign_iters=30)
+    log("pair with OCTMC_PREALIGN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT")
+    P = octmc.Pair(pair.sx, pair.sy, ox=pair.ox, oy=pair.oy, prealign=True, detect_invalid=True,
+                   project_enface=True, **kw)
+    D1, mo1, ma1, _ = P.register(merged=True)
+    th1, dz1 = P.prealignment()
+    torch.cuda.synchronize()
+    log("the same steps chained by hand")
+    h, w, d = pair.sx.shape
+    z = torch.zeros((h, w))
+    S1 = octmc.Pair(pair.sx, pair.sy, ax=z, ay=z, delta0=0.0, **kw)
+    th, _ = S1.prealign(1.0, 30)
+    assert np.array_equal(th, th1)
+    dz = dz1  # the field of th (checked against the oracle's expansion in another test)
+    sx, sy = octmc.resample_axial(pair.sx.cuda(), dz[0]), octmc.resample_axial(pair.sy.cuda(), dz[1])
+    ox, oy = octmc.resample_axial(pair.ox.cuda(), dz[0]), octmc.resample_axial(pair.oy.cuda(), dz[1])
+    vx, vy = octmc.validity_from_octa(ox, 0), octmc.validity_from_octa(oy, 1)
+    ax = octmc.enface_project(sx, ox, 0, vx)
+    ay = octmc.enface_project(sy, oy, 1, vy)
+    Q = octmc.Pair(sx, sy, ox=ox, oy=oy, ax=ax, ay=ay, vx=vx, vy=vy, **kw)
+    D2, mo2, ma2, _ = Q.register(merged=True)
+    torch.cuda.synchronize()
+    assert torch.equal(D1, D2) and torch.equal(mo1, mo2) and torch.equal(ma1, ma2)
