@@ -129,3 +129,44 @@ def test_serve_rejects_invalid_requests(octmc, mix):
         srv.submit(q.sx, q.sy, torch.empty((2, n, n, 3), device="cuda"), ax=q.ax, ay=q.ay, alpha=-1.0)
     assert srv.status() == dict(queued=0, active=0, done=0)
     srv.close()
+
+
+def test_serve_with_detection_and_projection(octmc):
+    """Requests that detect validity and project their en face images
+    (scratch taken from the request's reserved memory) give the same result
+    as the same pair created directly, and stay within their footprint;
+    stage 1 is refused at submission."""
+    pairs = [synth.make_pair("serving", 10 + k, n=n, d=d, white_lines=True, decorrelation=True)
+             for k, (n, d) in enumerate([(40, 64), (48, 56)])]
+    flags = octmc.DETECT_INVALID | octmc.ENFACE_PROJECT
+    ref = []
+    for q in pairs:
+        P = octmc.Pair(q.sx, q.sy, ox=q.ox, oy=q.oy, levels=2, iters_per_level=20, detect_invalid=True,
+                       project_enface=True)
+        D, _, _, _ = P.register()
+        torch.cuda.synchronize()
+        ref.append(D)
+        P.close()
+    srv = octmc.Server(2 << 30, max_active=2)
+    outs = {}
+    log("serve: two requests with detection and projection")
+    for k, q in enumerate(pairs):
+        n = q.sx.shape[0]
+        disp = torch.empty((2, n, n, 3), device="cuda")
+        rid = srv.submit(q.sx, q.sy, disp, ox=q.ox, oy=q.oy, levels=2, iters_per_level=20, flags=flags, tag=k)
+        outs[rid] = (k, disp)
+    done = []
+    while len(done) < len(pairs):
+        got = srv.poll(8, wait_ms=60000)
+        assert got, "no completion within 60 s"
+        done += got
+    for c in done:
+        assert c["status"] == 0, c["error"]
+        assert c["bytes_used"] <= c["bytes_reserved"]
+        k, disp = outs[c["id"]]
+        assert torch.equal(disp, ref[k])
+    q = pairs[0]
+    with pytest.raises(octmc.OctmcError):
+        srv.submit(q.sx, q.sy, torch.empty((2, 40, 40, 3), device="cuda"), ox=q.ox, oy=q.oy,
+                   flags=octmc.PREALIGN)
+    srv.close()
