@@ -118,3 +118,32 @@ def test_request_footprint_and_validation(m):
     assert L.octmc_server_submit(None, C.byref(r), None) == -1
     n = C.c_int32()
     assert L.octmc_server_poll(None, None, 0, 0, C.byref(n)) == -1
+
+
+def test_shape_limits(m):
+    """The accepted shapes: square scans of at least 4 x 4 x 4 whose float32
+    volume stays below 2^31 bytes and whose coarsest pyramid level keeps at
+    least 4 samples per axis; everything else is OCTMC_E_SHAPE (-2), and an
+    unknown storage type OCTMC_E_DTYPE (-3)."""
+    L = m.lib()
+    b = C.c_uint64()
+
+    def rc(w, d, h=None, levels=3, dtype=0):
+        r = _request(m, w=w, d=d, levels=levels, dtype=dtype)
+        if h is not None:
+            r.shape.h = h
+        return L.octmc_request_footprint(C.byref(r), C.byref(b))
+
+    assert rc(800, 838, levels=4) == 0  # largest square volume at this depth: 2 145 280 000 bytes
+    big = b.value
+    assert big > 2 * 800 * 800 * 838 * 4
+    assert rc(800, 839, levels=4) == -2  # 2 147 840 000 bytes
+    assert rc(800, 838, levels=4, dtype=1) == 0  # the limit is on the float32 size in every storage type
+    assert rc(800, 839, levels=4, dtype=2) == -2
+    assert rc(4, 4, levels=1) == 0  # smallest
+    assert rc(3, 4, levels=1) == -2 and rc(4, 3, levels=1) == -2
+    assert rc(0, 16, levels=1) == -2 and rc(16, 0, levels=1) == -2
+    assert rc(64, 64, h=63) == -2  # not square
+    assert rc(32, 32, levels=4) == 0 and rc(32, 32, levels=5) == -2  # 4 samples at the coarsest level
+    assert rc(31, 64, levels=4) == 0  # 31 -> 16 -> 8 -> 4
+    assert rc(64, 64, dtype=7) == -3

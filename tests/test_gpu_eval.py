@@ -175,3 +175,33 @@ def test_eval_parity_full_size_sampled(octmc):
     gg = g.double().cpu().numpy().reshape(2, -1, 3)
     got = np.concatenate([gg[0][sample], gg[1][sample]], axis=1)
     assert grad_rel(got, gref) < TOL
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_eval_parity_max_size_sampled(octmc, dtype):
+    """The largest accepted volume (800 x 800 A-scans x 838 samples: w h d
+    float32 samples stay below 2^31 bytes): the data gradient of sampled
+    A-scans, corners and edges included, against the oracle, in the storage
+    types that use the one-sample and the two-sample structural kernel."""
+    n, d = 800, 838
+    log(f"generate {n}x{n}x{d} on cuda, storage {dtype}")
+    pair = synth.make_pair("dense", 1, n=n, d=d, device="cuda", octa_volumes=False)
+    P = _gpu_pair(octmc, pair, dtype=dtype, levels=4, alpha=0.0, mean_weight=0.0)
+    D = make_field(pair, "gt_noise", seed=3)
+    Dg = D.float().cuda()
+    log(f"eval {n}x{n}x{d} level 0")
+    terms, g = P.eval(0, Dg, eta_mode=1)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g).all()
+    rng = np.random.default_rng(1)
+    sample = np.concatenate([[0, n - 1, n * (n - 1), n * n - 1, n * (n // 2) + n // 2, n * 7, n * 7 + n - 1],
+                             rng.integers(0, n * n, 121)])
+    sx, sy = round_storage(pair.sx, dtype), round_storage(pair.sy, dtype)
+    log("oracle on the sampled A-scans")
+    lv = oracle.Level(*(oracle._f64(t) for t in (sx, sy, pair.ax, pair.ay, pair.vx, pair.vy)))
+    del sx, sy
+    _, gref = oracle.data_ascans(lv, Dg.double().cpu().numpy(), sample, _orc_params(P), 1.0)
+    gg = g.double().cpu().numpy().reshape(2, -1, 3)
+    got = np.concatenate([gg[0][sample], gg[1][sample]], axis=1)
+    assert grad_rel(got, gref) < TOL
