@@ -44,8 +44,15 @@ def log(msg):
 
 
 def source_sha():
+    """Hash of the structural kernels' source (the part of kernels_eval.hip
+    before the reduction helpers: stencils, k_struct, k_struct2), so that
+    counter figures go stale only when those kernels change."""
     p = os.path.join(ROOT, "paper_2010_06931_amd", "csrc", "kernels_eval.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    text = open(p, "rb").read()
+    cut = text.find(b"// deterministic block reduction helpers")
+    if cut < 0:
+        raise RuntimeError("kernels_eval.hip: reduction helpers marker not found")
+    return hashlib.sha256(text[:cut]).hexdigest()[:16]
 
 
 def load_traffic(dtype):
