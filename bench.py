@@ -338,7 +338,8 @@ def multi_bench(octmc, torch, log, reps=50):
     """Four volumes (two orthogonal pairs of one phantom, white lines) at the
     clinical 300^2 x 640 size: evaluations of the four-volume objective (six
     pair terms) per second at the finest level and one joint solve (4 levels
-    x 100 steps), BF16 storage."""
+    x 100 steps), BF16 storage; the evaluation also pair by pair (each volume
+    resampled once per pair) beside the fused pass."""
     import synth
     log("four volumes 300x300x640: generating")
     sc = synth.make_scans("clinical", 0, (0, 1, 0, 1), device="cuda", white_lines=True)
@@ -346,18 +347,25 @@ def multi_bench(octmc, torch, log, reps=50):
     n, h, w = 4, sc.S[0].shape[0], sc.S[0].shape[1]
     D = (sc.d_gt + 0.2 * torch.randn(sc.d_gt.shape, generator=torch.Generator().manual_seed(1),
                                      dtype=torch.float64)).float().cuda()
-    M.eval(0, D, eta_mode=0)
-    for _ in range(5):
-        M.eval(0, D)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        M.eval(0, D)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def time_evals(m):
+        m.eval(0, D, eta_mode=0)
+        for _ in range(5):
+            m.eval(0, D)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            m.eval(0, D)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = time_evals(M)
+    Mp = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=4, dtype="bf16", pairwise=True)
+    ms_pairwise = time_evals(Mp)
+    Mp.close()
     log("four volumes: joint solve")
     t0 = time.perf_counter()
     Dsol, _, _, rep = M.register()
@@ -367,6 +375,7 @@ def multi_bench(octmc, torch, log, reps=50):
     M.close()
     return {"workload": "four volumes (X, Y, X, Y) 300x300 A-scans x 640 samples, BF16 storage",
             "ms_per_eval": round(ms, 4), "evals_per_s": round(1000.0 / ms, 1), "pair_terms_per_eval": 6,
+            "ms_per_eval_pairwise": round(ms_pairwise, 4),
             "solve_seconds": round(sec, 3), "solve_evals": int(sum(r["evals"] for r in rep)),
             "solve_rms_vs_ground_truth_px": err}
 

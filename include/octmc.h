@@ -73,6 +73,10 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
                                      octmc_pair_create gets OCTA volumes and no en face images */
 #define OCTMC_PREALIGN 0x8u       /* octmc_pair_create first runs the stage-1 rough axial prealignment
                                      (octmc_prealign) and ingests the prealigned volumes */
+#define OCTMC_MULTI_PAIRWISE 0x10u /* octmc_multi_*: evaluate the structural term pair by pair (each
+                                     volume resampled once per pair it belongs to) instead of the
+                                     fused form (each volume resampled once), which serves n = 3 or 4
+                                     volumes in 16-bit storage with an even depth at that level */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
  * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
@@ -91,7 +95,8 @@ typedef struct {
     double c1, c2;       /* strong Wolfe constants                                [R: 1e-4, 0.9] */
     double merge_kappa;  /* density weight decay exp(-kappa (rho - 1))            [R: 1.0]  */
     double merge_tau;    /* weights below tau are clipped to 0                    [R: 0.05] */
-    uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN */
+    uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN |
+                            OCTMC_MULTI_PAIRWISE */
     int32_t prealign_iters; /* stage-1 L-BFGS steps per level                     [100]     */
     double gamma_tilt;   /* weight of the tilt normalisation T (Eq. 1, stage 1)   [R: 1.0]  */
 } octmc_params;
@@ -311,7 +316,11 @@ OCTMC_API int octmc_resample_axial(octmc_ctx* ctx, const octmc_shape* shape, con
  * valid (NULL or n vectors of h values for X-fast, w for Y-fast volumes), as
  * octmc_pair_create (OCTMC_DETECT_INVALID and OCTMC_ENFACE_PROJECT apply per
  * volume; OCTMC_PREALIGN is not available here).  Pointers live in
- * shape->mem memory and are copied.  Errors: as octmc_pair_create. */
+ * shape->mem memory and are copied.  With n = 3 or 4 volumes in BF16 or FP16
+ * storage, a level of even depth evaluates the structural term of all pairs
+ * in one fused pass that resamples each volume once (OCTMC_MULTI_PAIRWISE
+ * selects the pair-by-pair form; the two agree to float32 rounding).
+ * Errors: as octmc_pair_create. */
 typedef struct octmc_multi octmc_multi;
 OCTMC_API int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, int32_t n,
                                  const int32_t* orient, const float* const* oct, const float* const* octa,

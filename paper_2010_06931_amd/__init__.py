@@ -25,6 +25,7 @@ CHECK_NAN = 0x1
 DETECT_INVALID = 0x2
 ENFACE_PROJECT = 0x4
 PREALIGN = 0x8
+MULTI_PAIRWISE = 0x10
 MAX_LEVELS = 8
 
 TERM_F, TERM_DATA, TERM_STR, TERM_ANG, TERM_REG, TERM_MEAN, TERM_STR05, TERM_ANG05, TERM_ETA, TERM_GP = range(10)
@@ -370,11 +371,13 @@ def validity_from_octa(vol: torch.Tensor, scan: int, *, ctx: Context | None = No
 class Multi:
     """n >= 2 raster scans registered jointly (two-volume terms over all
     pairs).  vols: structural volumes [h][w][d]; orients: 0 (X-fast) or 1
-    (Y-fast) per volume; octa, enface, valid: lists of n or None."""
+    (Y-fast) per volume; octa, enface, valid: lists of n or None.
+    pairwise=True evaluates the structural term pair by pair instead of the
+    fused pass that resamples each volume once (n = 3 or 4, 16-bit storage)."""
 
     def __init__(self, vols, orients, *, octa=None, enface=None, valid=None, params: Params | None = None,
                  dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,
-                 project_enface: bool = False, **param_overrides):
+                 project_enface: bool = False, pairwise: bool = False, **param_overrides):
         self.ctx = ctx or context(0)
         dev = torch.device("cuda", self.ctx.device)
         self.params = params if params is not None else default_params()
@@ -384,6 +387,8 @@ class Multi:
             self.params.flags |= DETECT_INVALID
         if project_enface:
             self.params.flags |= ENFACE_PROJECT
+        if pairwise:
+            self.params.flags |= MULTI_PAIRWISE
         n = len(vols)
         self._has_octa = octa is not None
         S = [_f32(v, dev) for v in vols]

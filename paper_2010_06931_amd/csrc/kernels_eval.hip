@@ -854,6 +854,228 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize(const CombineJobs jobs)
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_struct_multi: the structural data term of n = 3 or 4 volumes at one
+// level (16-bit storage, even depth).  Each output A-scan resamples every
+// volume once: the lateral blend of its value and of its x and y derivatives
+// (separable: 4 taps along x per source row, then 4 along y), the depth
+// interpolation (Eq. 2) of all three, and the depth derivative of the value.
+// Every volume pair P < Q then forms the residual I_P - I_Q, the
+// pseudo-Huber loss (Eq. 4) and the loss derivative times both volumes'
+// derivatives, and writes the eight partial sums per A-scan that k_struct2
+// writes for one pair (loss; x, y, z of P; x, y, z of Q; 0).  The pair
+// kernels instead resample every volume once per pair it belongs to.
+// Lanes hold two samples each, on the output grid of the first volume, as
+// in k_struct2.
+
+struct StencilS {
+    uint32_t roff[4], coff[4];  // byte offsets of the 4 source rows and the 4 source columns
+    float wx[4], dwx[4], wy[4], dwy[4];
+    float wz[4], dwz[4];
+    int base;  // source sample of the first depth tap of output sample 0
+};
+
+template <typename T>
+__device__ __forceinline__ void make_stencil_s(StencilS& s, int i, int j, float dx, float dy, float dz, int w, int h,
+                                               int d)
+{
+    int nx, ny, nz;
+    float tx, ty, tz;
+    split(i, uni(dx), nx, tx);
+    split(j, uni(dy), ny, ty);
+    split(0, uni(dz), nz, tz);
+    nx = uni(nx);
+    ny = uni(ny);
+    nz = uni(nz);
+    cr_taps(uni(tx), s.wx, s.dwx);
+    cr_taps(uni(ty), s.wy, s.dwy);
+    cr_taps(uni(tz), s.wz, s.dwz);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        s.wz[c] = uni(s.wz[c]);
+        s.dwz[c] = uni(s.dwz[c]);
+        s.roff[c] = (uint32_t)uni((int)((uint32_t)clampi(ny - 1 + c, 0, h - 1) * (uint32_t)w * (uint32_t)d *
+                                        esize<T>::v));
+        s.coff[c] = (uint32_t)uni((int)((uint32_t)clampi(nx - 1 + c, 0, w - 1) * (uint32_t)d * esize<T>::v));
+    }
+    s.base = uni(nz - 1);
+}
+
+// value, x derivative and y derivative blends of the 16 columns at one depth
+__device__ __forceinline__ void blend3(const float (&c)[16], const StencilS& S, float& v, float& vx, float& vy)
+{
+    float r[4], dr[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        r[b] = S.wx[0] * c[b * 4];
+        dr[b] = S.dwx[0] * c[b * 4];
+#pragma unroll
+        for (int a = 1; a < 4; ++a) {
+            r[b] = fmaf(S.wx[a], c[b * 4 + a], r[b]);
+            dr[b] = fmaf(S.dwx[a], c[b * 4 + a], dr[b]);
+        }
+    }
+    v = S.wy[0] * r[0];
+    vx = S.wy[0] * dr[0];
+    vy = S.dwy[0] * r[0];
+#pragma unroll
+    for (int b = 1; b < 4; ++b) {
+        v = fmaf(S.wy[b], r[b], v);
+        vx = fmaf(S.wy[b], dr[b], vx);
+        vy = fmaf(S.dwy[b], r[b], vy);
+    }
+}
+
+// Blended values t0, t1 of the loaded pair (samples m, m + 1) to positions 2l
+// and 2l + 1 of the output grid: clamp (a pair below the A-scan holds sample
+// 0 twice, one above it sample d - 1 twice), then the shift by one sample
+// when the volume's positions start one sample after a pair boundary (r = 1).
+__device__ __forceinline__ void grid2(float t0, float t1, bool lo, bool hi, int r, float& c0, float& c1)
+{
+    const float u0 = hi ? t1 : t0, u1 = lo ? t0 : t1;
+    const float u0n = shl1(u0);
+    c0 = r ? u1 : u0;
+    c1 = r ? u0n : u1;
+}
+
+// the resampled value and its x, y, z derivatives at positions 2l, 2l + 1
+struct Resampled {
+    float i[2], x[2], y[2], z[2];
+};
+
+template <typename T>
+__device__ __forceinline__ void resample_step(Resampled& o, __amdgpu_buffer_rsrc_t rs, const StencilS& S, int E, int r,
+                                              int n, int lane, int d)
+{
+    const int m = E + kOutPerStep2 * n + 2 * lane;
+    const uint32_t voff = (uint32_t)clampi(m, 0, d - 2) * esize<T>::v;
+    float q0[16], q1[16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ld2<T>(rs, voff, S.roff[b] + S.coff[a], q0[b * 4 + a], q1[b * 4 + a]);
+    const bool lo = m < 0, hi = m > d - 2;
+    float v0, vx0, vy0, v1, vx1, vy1;
+    blend3(q0, S, v0, vx0, vy0);
+    blend3(q1, S, v1, vx1, vy1);
+    float c0, c1;
+    grid2(v0, v1, lo, hi, r, c0, c1);
+    {
+        const float c0n = shl1(c0), c1n = shl1(c1), c0nn = shl1(c0n);
+        o.i[0] = S.wz[0] * c0 + S.wz[1] * c1 + S.wz[2] * c0n + S.wz[3] * c1n;
+        o.i[1] = S.wz[0] * c1 + S.wz[1] * c0n + S.wz[2] * c1n + S.wz[3] * c0nn;
+        o.z[0] = S.dwz[0] * c0 + S.dwz[1] * c1 + S.dwz[2] * c0n + S.dwz[3] * c1n;
+        o.z[1] = S.dwz[0] * c1 + S.dwz[1] * c0n + S.dwz[2] * c1n + S.dwz[3] * c0nn;
+    }
+    grid2(vx0, vx1, lo, hi, r, c0, c1);
+    {
+        const float c0n = shl1(c0), c1n = shl1(c1), c0nn = shl1(c0n);
+        o.x[0] = S.wz[0] * c0 + S.wz[1] * c1 + S.wz[2] * c0n + S.wz[3] * c1n;
+        o.x[1] = S.wz[0] * c1 + S.wz[1] * c0n + S.wz[2] * c1n + S.wz[3] * c0nn;
+    }
+    grid2(vy0, vy1, lo, hi, r, c0, c1);
+    {
+        const float c0n = shl1(c0), c1n = shl1(c1), c0nn = shl1(c0n);
+        o.y[0] = S.wz[0] * c0 + S.wz[1] * c1 + S.wz[2] * c0n + S.wz[3] * c1n;
+        o.y[1] = S.wz[0] * c1 + S.wz[1] * c0n + S.wz[2] * c1n + S.wz[3] * c0nn;
+    }
+}
+
+template <int N>
+struct StructMultiJob {
+    const void* vol[N];            // storage-type volumes of this level, [h][w][d]
+    const float* disp;             // [N][h][w][3]
+    float* part[N * (N - 1) / 2];  // per pair (P, Q), P < Q in lexicographic order: [na][8]
+    int w, h, d, na;
+    uint32_t vol_bytes;
+    float eps_h;
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_struct_multi(const StructMultiJob<N> J)
+{
+    constexpr int NP = N * (N - 1) / 2;
+    const int wv = uni((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int w = J.w, h = J.h, d = J.d;
+    // 2 x 2 tiles in 8 bands of tile rows, swept column by column (as k_struct2)
+    const int tpr = (w + 1) >> 1;
+    const int trows = (h + 1) >> 1;
+    const int rpb = (trows + 7) >> 3;
+    const int band = lb / (rpb * tpr), tb = lb - band * (rpb * tpr);
+    const int trow = band * rpb + tb % rpb;
+    if (lb >= 8 * rpb * tpr || trow >= trows) return;  // whole block
+    const int i = 2 * (tb / rpb) + (wv & 1);
+    const int j = 2 * trow + (wv >> 1);
+    if (i >= w || j >= h) return;  // whole wave
+    const int a = uni(j * w + i);
+    StencilS S[N];
+    __amdgpu_buffer_rsrc_t rs[N];
+#pragma unroll
+    for (int V = 0; V < N; ++V) {
+        const float* dv = J.disp + ((size_t)V * J.na + a) * 3;
+        make_stencil_s<T>(S[V], i, j, dv[0], dv[1], dv[2], w, h, d);
+        rs[V] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.vol[V]), (short)0, (int)J.vol_bytes, kRsrcWord3);
+    }
+    // output grid: position 0 of step 0 holds sample base_0 - s0 of volume 0
+    const int s0 = S[0].base & 1;
+    int r[N], E[N];
+#pragma unroll
+    for (int V = 0; V < N; ++V) {
+        r[V] = uni((S[V].base - s0) & 1);
+        E[V] = S[V].base - s0 - r[V];  // even
+    }
+    const float eps = J.eps_h;
+    const float inv_eps = 1.0f / J.eps_h;
+    float acc[NP][7];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) acc[q][c] = 0.f;
+    const int nsteps = (d + kOutPerStep2 - 1) / kOutPerStep2;
+    for (int n = 0; n < nsteps; ++n) {
+        Resampled R[N];
+#pragma unroll
+        for (int V = 0; V < N; ++V) resample_step<T>(R[V], rs[V], S[V], E[V], r[V], n, lane, d);
+        const int p0 = 2 * lane;
+        const int o0 = kOutPerStep2 * n + p0 - s0;
+        const bool ok[2] = {p0 >= s0 && p0 <= 121 + s0 && o0 < d, p0 + 1 <= 121 + s0 && o0 + 1 < d};
+        int q = 0;
+#pragma unroll
+        for (int P = 0; P < N; ++P)
+#pragma unroll
+            for (int Q = P + 1; Q < N; ++Q, ++q) {
+                float L[2], G[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const float u = (R[P].i[e] - R[Q].i[e]) * inv_eps, uu = u * u;
+                    const float rsq = __builtin_amdgcn_rsqf(1.f + uu), sq = (1.f + uu) * rsq;
+                    L[e] = ok[e] ? eps * uu * __builtin_amdgcn_rcpf(sq + 1.f) : 0.f;
+                    G[e] = ok[e] ? u * rsq : 0.f;
+                }
+                acc[q][0] += L[0] + L[1];
+                acc[q][1] += G[0] * R[P].x[0] + G[1] * R[P].x[1];
+                acc[q][2] += G[0] * R[P].y[0] + G[1] * R[P].y[1];
+                acc[q][3] += G[0] * R[P].z[0] + G[1] * R[P].z[1];
+                acc[q][4] += G[0] * R[Q].x[0] + G[1] * R[Q].x[1];
+                acc[q][5] += G[0] * R[Q].y[0] + G[1] * R[Q].y[1];
+                acc[q][6] += G[0] * R[Q].z[0] + G[1] * R[Q].z[1];
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        float v[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = wave_sum(acc[q][c]);
+        if (lane == 0) {
+            float4* o = reinterpret_cast<float4*>(J.part[q] + (size_t)a * 8);
+            o[0] = make_float4(v[0], v[1], v[2], v[3]);
+            o[1] = make_float4(v[4], v[5], v[6], 0.f);
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s)
@@ -901,6 +1123,41 @@ hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t
     hipLaunchKernelGGL(k_combine, dim3(total_blocks), dim3(kRedBlock), 0, s, jobs);
     hipLaunchKernelGGL(k_finalize, dim3(jobs.n), dim3(kRedBlock), 0, s, jobs);
     return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_struct_multi_n(const void* const* vol, const float* disp, float* const* part, int w, int h,
+                                        int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s)
+{
+    StructMultiJob<N> J{};
+    for (int V = 0; V < N; ++V) J.vol[V] = vol[V];
+    for (int q = 0; q < N * (N - 1) / 2; ++q) J.part[q] = part[q];
+    J.disp = disp;
+    J.w = w;
+    J.h = h;
+    J.d = d;
+    J.na = w * h;
+    J.vol_bytes = vol_bytes;
+    J.eps_h = eps_h;
+    const int blocks = (8 * (((h + 1) / 2 + 7) / 8) * ((w + 1) / 2) + 7) / 8 * 8;  // a multiple of the 8 XCDs
+    if (dt == OCTMC_BF16)
+        hipLaunchKernelGGL((k_struct_multi<bf16_t, N>), dim3(blocks), dim3(256), 0, s, J);
+    else
+        hipLaunchKernelGGL((k_struct_multi<f16_t, N>), dim3(blocks), dim3(256), 0, s, J);
+    return hipGetLastError();
+}
+
+bool struct_multi_supported(int n, int d, octmc_dtype dt)
+{
+    return (n == 3 || n == 4) && d % 2 == 0 && (dt == OCTMC_BF16 || dt == OCTMC_F16);
+}
+
+hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp, float* const* part, int w, int h,
+                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s)
+{
+    if (!struct_multi_supported(n, d, dt)) return hipErrorInvalidValue;
+    if (n == 3) return launch_struct_multi_n<3>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s);
+    return launch_struct_multi_n<4>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s);
 }
 
 }  // namespace octmc

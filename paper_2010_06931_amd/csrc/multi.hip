@@ -244,7 +244,21 @@ struct MultiEvaluator final : Evaluator {
             args[q] = EvalArgs{M->views[q].get(), pd, M->pterms + (size_t)q * OCTMC_NTERMS, nullptr, nullptr,
                                M->pgrad + (size_t)q * 2 * na0 * 3, level, ea.eta_mode};
         }
-        for (int q0 = 0; q0 < np; q0 += kMaxJobs) OCTMC_TRY(eval_group(args.data() + q0, std::min(kMaxJobs, np - q0), s));
+        // the structural partials of all pairs in one pass that resamples every
+        // volume once, where the fused kernel serves this n, storage and depth
+        const bool fused = !(M->params.flags & OCTMC_MULTI_PAIRWISE) &&
+                           struct_multi_supported(M->n, M->d[level], M->dtype);
+        if (fused) {
+            const void* vols[kMaxVol];
+            float* parts[kMaxVol * (kMaxVol - 1) / 2];
+            for (int V = 0; V < M->n; ++V) vols[V] = M->vol[V].s[level];
+            for (int q = 0; q < np; ++q) parts[q] = M->views[q]->part;
+            const Level& L = M->views[0]->lev[level];
+            HIP_TRY(launch_struct_multi(vols, M->n, ea.disp, parts, L.w, L.h, L.d, L.vol_bytes,
+                                        (float)M->params.eps_huber, M->dtype, s));
+        }
+        for (int q0 = 0; q0 < np; q0 += kMaxJobs)
+            OCTMC_TRY(eval_group(args.data() + q0, std::min(kMaxJobs, np - q0), s, nullptr, !fused));
         const size_t nq = (size_t)M->n * na;
         const int nsum = grid_n(nq);
         hipLaunchKernelGGL(k_field_sum, dim3(nsum), dim3(kMB), 0, s, ea.disp, nq, M->sum_blk);

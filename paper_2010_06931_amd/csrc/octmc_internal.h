@@ -60,7 +60,7 @@ struct EvalArgs {
 // The hot path over up to kMaxJobs jobs (distinct pairs, one storage type,
 // any levels and sizes) in one launch per kernel, on stream s.  ev (4 events
 // or null) brackets the three stages for timing.
-int eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev = nullptr);
+int eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev = nullptr, bool with_struct = true);
 
 // How the solver gets its evaluations: directly on its stream, or through a
 // scheduler that groups the evaluations of several solvers.  eval() returns
@@ -157,6 +157,13 @@ hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype d
 // per-A-scan combination (total_blocks) followed by the fixed-order final
 // sums, one block per job
 hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s);
+// the structural partials of every volume pair of n volumes at one level,
+// each volume resampled once (n = 3 or 4, 16-bit storage, even depth: see
+// struct_multi_supported); part[q] is pair q's [na][8] partial buffer, the
+// pairs (P, Q), P < Q, in lexicographic order
+bool struct_multi_supported(int n, int d, octmc_dtype dt);
+hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp, float* const* part, int w, int h,
+                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s);
 
 // preparation (kernels_prep.hip)
 hipError_t launch_to_storage(const float* in, void* out, size_t n, octmc_dtype dt, hipStream_t s);

@@ -55,7 +55,7 @@ int nblk_combine(int na) { return (na + kRedBlock - 1) / kRedBlock; }
 
 }  // namespace
 
-int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev)
+int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, bool with_struct)
 {
     SumJobs sj{};
     StructJobs tj{};
@@ -116,7 +116,7 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev)
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_sum(sj, sb, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(launch_struct(tj, (tb + 7) / 8 * 8, dt, s));  // multiple of the 8 XCDs
+    if (with_struct) HIP_TRY(launch_struct(tj, (tb + 7) / 8 * 8, dt, s));  // multiple of the 8 XCDs
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (any_eta) {  // eta of the jobs that ask for it, before their evaluation
         CombineJobs c0{};
@@ -215,7 +215,8 @@ int octmc::validate_params(const octmc_params* p)
     if (!(p->c1 > 0 && p->c1 < p->c2 && p->c2 < 1)) return fail(OCTMC_E_INVALID, "need 0 < c1 < c2 < 1");
     if (p->prealign_iters < 0) return fail(OCTMC_E_INVALID, "prealign_iters must be >= 0");
     if (p->gamma_tilt < 0) return fail(OCTMC_E_INVALID, "gamma_tilt must be >= 0");
-    if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN))
+    if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN |
+                     OCTMC_MULTI_PAIRWISE))
         return fail(OCTMC_E_INVALID, "unknown flags");
     return OCTMC_OK;
 }

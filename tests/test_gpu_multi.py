@@ -134,3 +134,90 @@ def test_multi_rejects_bad_input(octmc, scans):
         octmc.Multi([sc.S[0], sc.S[2]], [0, 0], enface=[sc.A[0], sc.A[2]])  # no orthogonal scan
     with pytest.raises(octmc.OctmcError):
         _gpu_multi(octmc, sc, prealign_iters=5, flags=octmc.PREALIGN)
+
+
+_STORE = {"bf16": 1, "f16": 2}
+
+
+def _oracle_level_inputs(sc, level, idx, store=0):
+    """The oracle's volumes, en face images and validity at `level`: the exact
+    pyramid, each structural level rounded to the storage type as stored."""
+    S = [sc.S[q].double().numpy() for q in idx]
+    A = [sc.A[q].double().numpy() for q in idx]
+    V = [sc.V[q].double().numpy() for q in idx]
+    for _ in range(level):
+        S = [oracle.pyr_down3(s) for s in S]
+        A = [oracle.pyr_down2(a) for a in A]
+        V = [oracle.pyr_down1(v) for v in V]
+    if store:
+        S = [oracle.round_storage(s, store) for s in S]
+    return S, A, V
+
+
+@pytest.mark.parametrize("dtype,level,nvol", [("bf16", 0, 4), ("bf16", 1, 4), ("f16", 0, 4), ("bf16", 0, 3),
+                                              ("f16", 1, 3)])
+def test_multi_fused_objective_parity(octmc, scans, dtype, level, nvol):
+    """n = 3 and 4 volumes in 16-bit storage: the fused structural pass (each
+    volume resampled once per output A-scan) against the oracle on the
+    volumes rounded as stored (10^-4 relative), and against the pair-by-pair
+    evaluation of the same library (float32 rounding apart)."""
+    sc = scans
+    idx = list(range(nvol))
+    M = _gpu_multi(octmc, sc, idx, levels=2, dtype=dtype)
+    Mp = _gpu_multi(octmc, sc, idx, levels=2, dtype=dtype, pairwise=True)
+    w, h, d = M.level_shape(level)
+    assert d % 2 == 0  # the fused pass serves even depths
+    rng = np.random.default_rng(10 + level + nvol)
+    D = rng.normal(0, 0.8, (nvol, h, w, 3))
+    S, A, V = _oracle_level_inputs(sc, level, idx, _STORE[dtype])
+    om = oracle.Multi(S, [sc.orient[q] for q in idx], A, V)
+    t0, p05, _ = oracle.evaluate_multi(om, D, oracle.Params(), None, grad=False)
+    eta = np.array([oracle.eta_from_terms(a, b) for a, b in p05])
+    ref, _, gref = oracle.evaluate_multi(om, D, oracle.Params(), eta)
+    log(f"n = {nvol} fused objective, {dtype}, level {level} ({w}x{h}x{d})")
+    Dg = torch.from_numpy(D).float().cuda()
+    t, g = M.eval(level, Dg, eta_mode=0)
+    tp, gp = Mp.eval(level, Dg, eta_mode=0)
+    torch.cuda.synchronize()
+    td, tpd = octmc.terms_dict(t), octmc.terms_dict(tp)
+    for key in ("F", "data", "str", "ang", "reg", "mean"):
+        assert rel(td[key], ref[key]) < 1e-4, (key, td[key], ref[key])
+        assert rel(td[key], tpd[key]) < 1e-5 or abs(td[key] - tpd[key]) < 1e-9, (key, td[key], tpd[key])
+    assert grad_rel(g.double().cpu().numpy(), gref) < 1e-4
+    assert grad_rel(g.double().cpu().numpy(), gp.double().cpu().numpy()) < 1e-5
+
+
+def test_multi_fused_odd_depth_level_uses_the_pair_path(octmc):
+    """A level of odd depth (66 -> 33) is evaluated pair by pair; the result
+    still meets the oracle's bar."""
+    sc = synth.make_scans("tiny", 4, (0, 1, 0, 1), n=36, d=66)
+    M = _gpu_multi(octmc, sc, levels=2, dtype="bf16")
+    w, h, d = M.level_shape(1)
+    assert d % 2 == 1
+    D = np.random.default_rng(2).normal(0, 0.5, (4, h, w, 3))
+    S, A, V = _oracle_level_inputs(sc, 1, range(4), 1)
+    om = oracle.Multi(S, sc.orient, A, V)
+    ref, _, gref = oracle.evaluate_multi(om, D, oracle.Params(), np.ones(6))
+    log("n = 4 bf16, odd depth at level 1")
+    t, g = M.eval(1, torch.from_numpy(D).float().cuda(), eta_mode=1)  # stored eta = 1
+    torch.cuda.synchronize()
+    td = octmc.terms_dict(t)
+    for key in ("F", "data", "str", "reg"):
+        assert rel(td[key], ref[key]) < 1e-4, (key, td[key], ref[key])
+    assert grad_rel(g.double().cpu().numpy(), gref) < 1e-4
+
+
+def test_multi_fused_register_parity(octmc, scans):
+    """The joint BF16 solve (fused structural pass at every level) against the
+    oracle's solve on pyramid levels rounded as stored: 0.05 px RMS."""
+    sc = scans
+    log("n = 4 bf16 joint solve, 2 levels x 40 steps, GPU")
+    M = _gpu_multi(octmc, sc, levels=2, iters_per_level=40, dtype="bf16")
+    Dg, _, _, rep = M.register()
+    torch.cuda.synchronize()
+    log("the same solve in the oracle, levels rounded to bfloat16")
+    Do, repo = oracle.register_multi(_oracle_multi(sc), oracle.Params(levels=2, iters=40, store=1))
+    err = np.sqrt(((Dg.double().cpu().numpy() - Do) ** 2).mean())
+    assert err < 0.05, err
+    for r, ro in zip(rep, repo):
+        assert abs(r["f_end"] - ro["f_end"]) <= 0.05 * abs(ro["f_end"]), (r, ro)
