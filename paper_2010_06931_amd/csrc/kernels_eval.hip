@@ -606,9 +606,10 @@ __global__ __launch_bounds__(kRedBlock) void k_sum(const SumJobs jobs)
     double v[4] = {0, 0, 0, 0};
     const int total = 2 * J.na;
     for (int q = b * kRedBlock + threadIdx.x; q < total; q += J.nblk * kRedBlock) {
-        v[0] += (double)J.disp[(size_t)q * 3 + 0];
-        v[1] += (double)J.disp[(size_t)q * 3 + 1];
-        v[2] += (double)J.disp[(size_t)q * 3 + 2];
+        const float* dq = q < J.na ? J.disp[0] + (size_t)q * 3 : J.disp[1] + (size_t)(q - J.na) * 3;
+        v[0] += (double)dq[0];
+        v[1] += (double)dq[1];
+        v[2] += (double)dq[2];
     }
     block_reduce_store<4>(v, J.blk + (size_t)b * 4);
 }
@@ -720,8 +721,8 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
         const float4 p0 = reinterpret_cast<const float4*>(J.part)[(size_t)a * 2];
         const float4 p1 = reinterpret_cast<const float4*>(J.part)[(size_t)a * 2 + 1];
         const double lam = p0.x;
-        const float* dX = J.disp + (size_t)a * 3;
-        const float* dY = J.disp + ((size_t)na + a) * 3;
+        const float* dX = J.disp[0] + (size_t)a * 3;
+        const float* dY = J.disp[1] + (size_t)a * 3;
         float jx[3], jy[3];
         sample2(J.ax, w, h, i, j, dX[0], dX[1], jx);
         sample2(J.ay, w, h, i, j, dY[0], dY[1], jy);
@@ -762,7 +763,7 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
             // scan-order regulariser (gather form: this A-scan's two links)
             double reg = 0.0;
             for (int V = 0; V < 2; ++V) {
-                const float* DV = J.disp + (size_t)V * na * 3;
+                const float* DV = J.disp[V];
                 const float* da = DV + (size_t)a * 3;
                 const int oV = V == 0 ? oX : oY;  // acquisition order of the slot's scan
                 double omp, omn;

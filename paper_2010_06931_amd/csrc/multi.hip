@@ -235,19 +235,26 @@ struct MultiEvaluator final : Evaluator {
         const int level = ea.level, np = (int)M->pairs.size();
         const size_t na = (size_t)M->w[level] * M->h[level], na0 = (size_t)M->w[0] * M->h[0];
         const size_t fb = na * 3 * sizeof(float);
-        std::vector<EvalArgs> args(np);
-        for (int q = 0; q < np; ++q) {
-            float* pd = M->pdisp + (size_t)q * 2 * na0 * 3;
-            HIP_TRY(hipMemcpyAsync(pd, ea.disp + (size_t)M->pairs[q].first * na * 3, fb, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(pd + na * 3, ea.disp + (size_t)M->pairs[q].second * na * 3, fb,
-                                   hipMemcpyDeviceToDevice, s));
-            args[q] = EvalArgs{M->views[q].get(), pd, M->pterms + (size_t)q * OCTMC_NTERMS, nullptr, nullptr,
-                               M->pgrad + (size_t)q * 2 * na0 * 3, level, ea.eta_mode};
-        }
         // the structural partials of all pairs in one pass that resamples every
         // volume once, where the fused kernel serves this n, storage and depth
         const bool fused = !(M->params.flags & OCTMC_MULTI_PAIRWISE) &&
                            struct_multi_supported(M->n, M->d[level], M->dtype);
+        std::vector<EvalArgs> args(np);
+        for (int q = 0; q < np; ++q) {
+            const float* fP = ea.disp + (size_t)M->pairs[q].first * na * 3;
+            const float* fQ = ea.disp + (size_t)M->pairs[q].second * na * 3;
+            args[q] = EvalArgs{M->views[q].get(), fP, M->pterms + (size_t)q * OCTMC_NTERMS, nullptr, nullptr,
+                               M->pgrad + (size_t)q * 2 * na0 * 3, level, ea.eta_mode};
+            if (fused) {
+                args[q].disp_y = fQ;  // the remaining pair kernels read the two fields where they are
+                continue;
+            }
+            // the pair structural kernels read the two fields as one [2][na][3] array
+            float* pd = M->pdisp + (size_t)q * 2 * na0 * 3;
+            HIP_TRY(hipMemcpyAsync(pd, fP, fb, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(pd + na * 3, fQ, fb, hipMemcpyDeviceToDevice, s));
+            args[q].disp = pd;
+        }
         if (fused) {
             const void* vols[kMaxVol];
             float* parts[kMaxVol * (kMaxVol - 1) / 2];

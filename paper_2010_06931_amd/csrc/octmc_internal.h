@@ -48,13 +48,15 @@ inline size_t slab_bytes(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 // One evaluation job: a pair at one of its pyramid levels.
 struct EvalArgs {
     octmc_pair* pair;
-    const float* disp;
+    const float* disp;               // [2][na][3], or the first slot's [na][3] when disp_y is set
     double* terms;
     float* grad;
     const double* p = nullptr;       // search direction for the directional derivative (or null)
     double* grad64 = nullptr;        // float64 gradient for the solver (or null)
     int level = 0;
     int eta_mode = 1;                // 0: set the level's eta first (Eq. 10)
+    const float* disp_y = nullptr;   // the second slot's [na][3] (null: disp + na * 3); needs with_struct =
+                                     // false in eval_group, whose structural kernels read [2][na][3]
 };
 
 // The hot path over up to kMaxJobs jobs (distinct pairs, one storage type,
@@ -115,7 +117,7 @@ struct StructJobs {
 // Hot path, step 0: sum of the displacements (for the mean term M), as one
 // row of block partials per block (summed in a fixed order by its readers).
 struct SumJob {
-    const float* disp;  // [2][na][3]
+    const float* disp[2];  // [na][3] per slot
     double* blk;        // [nblk][4] block partials
     int na, blk_begin, nblk;
 };
@@ -128,7 +130,7 @@ struct SumJobs {
 // regulariser, mean term, gradient and the deterministic global sums.
 struct CombineJob {
     const float* part;   // [na][8] from the structural kernel
-    const float* disp;   // [2][na][3]
+    const float* disp[2];  // [na][3] per slot
     float* grad;         // [2][na][3] or nullptr
     double* grad64;      // [2][na][3] float64 gradient (solver) or nullptr
     const float* ax;     // en face images [h][w]

@@ -72,7 +72,10 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
         const octmc_params& pr = P->params;
         if (P->dtype != dt) return fail(OCTMC_E_DTYPE, "batched pairs must share the storage type");
         const int nsum = std::min(kSumBlocks, (2 * L.na + kRedBlock - 1) / kRedBlock);
-        sj.j[q] = SumJob{ea[q].disp, P->sum_blk, L.na, sb, nsum};
+        const float* dy = ea[q].disp_y ? ea[q].disp_y : ea[q].disp + (size_t)L.na * 3;
+        if (with_struct && dy != ea[q].disp + (size_t)L.na * 3)
+            return fail(OCTMC_E_INVALID, "the structural kernels read both slots' fields as one [2][na][3] array");
+        sj.j[q] = SumJob{{ea[q].disp, dy}, P->sum_blk, L.na, sb, nsum};
         sb += nsum;
         tj.j[q] = StructJob{L.sx, L.sy, ea[q].disp, P->part, L.w, L.h, L.d, L.na, tb, L.vol_bytes,
                             (float)pr.eps_huber};
@@ -83,7 +86,8 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
         const double f = std::floor(pr.flyback_frac * blen + 0.5);
         CombineJob c{};
         c.part = P->part;
-        c.disp = ea[q].disp;
+        c.disp[0] = ea[q].disp;
+        c.disp[1] = dy;
         c.grad = ea[q].grad;
         c.grad64 = ea[q].grad64;
         c.ax = L.ax;
