@@ -380,6 +380,48 @@ def multi_bench(octmc, torch, log, reps=50):
             "solve_rms_vs_ground_truth_px": err}
 
 
+def autograd_bench(octmc, torch, log, reps=50):
+    """The differentiation variant: 8 independent pairs of 200^2 x 512 FP32
+    as one batched objective (one grouped launch per kernel) behind
+    torch.autograd (OctmcObjective): forward + backward per second, beside
+    the grouped evaluation alone and 8 single-pair evaluations."""
+    import synth
+    B = 8
+    log("autograd: generating 8 pairs 200x200x512")
+    pairs = [synth.make_pair("batch", b, device="cuda", octa_volumes=False) for b in range(B)]
+    Ps = [octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, levels=3) for q in pairs]
+    D = torch.stack([(q.d_gt + 0.2 * torch.randn(q.d_gt.shape, generator=torch.Generator().manual_seed(b),
+                                                 dtype=torch.float64)).float() for b, q in enumerate(pairs)]).cuda()
+    octmc.eval_batched(Ps, 0, D, eta_mode=0)  # each pair's eta at this level (Eq. 10)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def fwd_bwd():
+        Dv = D.detach().requires_grad_(True)
+        octmc.objective(Dv, Ps, 0).sum().backward()
+
+    ms_ad = timed(fwd_bwd)
+    ms_grouped = timed(lambda: octmc.eval_batched(Ps, 0, D))
+    ms_single = timed(lambda: [P.eval(0, D[b]) for b, P in enumerate(Ps)])
+    for P in Ps:
+        P.close()
+    return {"workload": "8 pairs 200x200 A-scans x 512 samples, FP32 storage, finest level",
+            "ms_per_forward_backward": round(ms_ad, 4), "pair_evals_per_s": round(B * 1000.0 / ms_ad, 1),
+            "ms_per_grouped_eval": round(ms_grouped, 4), "ms_per_8_single_evals": round(ms_single, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -395,8 +437,10 @@ def main():
     ap.add_argument("--no-enface", action="store_true", help="skip the en face projection timing")
     ap.add_argument("--no-prealign", action="store_true", help="skip the stage-1 prealignment timing")
     ap.add_argument("--no-multi", action="store_true", help="skip the four-volume timing")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the batched autograd timing")
     ap.add_argument("--extras-only", action="store_true",
-                    help="time only the stage-1 prealignment, the four-volume path and the projection")
+                    help="time only the stage-1 prealignment, the four-volume path, the batched autograd "
+                         "objective and the projection")
     ap.add_argument("--enface-only", action="store_true", help="time only the en face projection")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=48.0)
@@ -437,6 +481,7 @@ def main():
         del pair
         torch.cuda.empty_cache()
         extra["multi_volume"] = multi_bench(octmc, torch, log)
+        extra["autograd_batch"] = autograd_bench(octmc, torch, log)
         extra["enface_projection"] = enface_bench(octmc, torch, log)
         print(json.dumps(extra), flush=True)
         return
@@ -574,6 +619,8 @@ def main():
 
     if not args.no_multi:
         out["multi_volume"] = multi_bench(octmc, torch, log)
+    if not args.no_autograd:
+        out["autograd_batch"] = autograd_bench(octmc, torch, log)
 
     if not args.no_enface:
         del P
