@@ -76,7 +76,8 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
 #define OCTMC_MULTI_PAIRWISE 0x10u /* octmc_multi_*: evaluate the structural term pair by pair (each
                                      volume resampled once per pair it belongs to) instead of the
                                      fused form (each volume resampled once), which serves n = 3 or 4
-                                     volumes in 16-bit storage with an even depth at that level */
+                                     volumes in float32 storage, or in 16-bit storage at a level of
+                                     even depth */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
  * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
@@ -316,10 +317,11 @@ OCTMC_API int octmc_resample_axial(octmc_ctx* ctx, const octmc_shape* shape, con
  * valid (NULL or n vectors of h values for X-fast, w for Y-fast volumes), as
  * octmc_pair_create (OCTMC_DETECT_INVALID and OCTMC_ENFACE_PROJECT apply per
  * volume; OCTMC_PREALIGN is not available here).  Pointers live in
- * shape->mem memory and are copied.  With n = 3 or 4 volumes in BF16 or FP16
- * storage, a level of even depth evaluates the structural term of all pairs
- * in one fused pass that resamples each volume once (OCTMC_MULTI_PAIRWISE
- * selects the pair-by-pair form; the two agree to float32 rounding).
+ * shape->mem memory and are copied.  With n = 3 or 4 volumes (float32
+ * storage, or BF16/FP16 at a level of even depth) the structural term of
+ * all pairs is evaluated in one fused pass that resamples each volume once
+ * (OCTMC_MULTI_PAIRWISE selects the pair-by-pair form; the two agree to
+ * float32 rounding).
  * Errors: as octmc_pair_create. */
 typedef struct octmc_multi octmc_multi;
 OCTMC_API int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, int32_t n,

@@ -373,7 +373,7 @@ class Multi:
     pairs).  vols: structural volumes [h][w][d]; orients: 0 (X-fast) or 1
     (Y-fast) per volume; octa, enface, valid: lists of n or None.
     pairwise=True evaluates the structural term pair by pair instead of the
-    fused pass that resamples each volume once (n = 3 or 4, 16-bit storage)."""
+    fused pass that resamples each volume once (n = 3 or 4)."""
 
     def __init__(self, vols, orients, *, octa=None, enface=None, valid=None, params: Params | None = None,
                  dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,

@@ -160,9 +160,9 @@ hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype d
 // sums, one block per job
 hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s);
 // the structural partials of every volume pair of n volumes at one level,
-// each volume resampled once (n = 3 or 4, 16-bit storage, even depth: see
-// struct_multi_supported); part[q] is pair q's [na][8] partial buffer, the
-// pairs (P, Q), P < Q, in lexicographic order
+// each volume resampled once (n = 3 or 4; float32 storage, or 16-bit storage
+// at an even depth: see struct_multi_supported); part[q] is pair q's [na][8]
+// partial buffer, the pairs (P, Q), P < Q, in lexicographic order
 bool struct_multi_supported(int n, int d, octmc_dtype dt);
 hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp, float* const* part, int w, int h,
                                int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s);
