@@ -366,6 +366,11 @@ def multi_bench(octmc, torch, log, reps=50):
     Mp = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=4, dtype="bf16", pairwise=True)
     ms_pairwise = time_evals(Mp)
     Mp.close()
+    f32 = {}
+    for pw in (False, True):
+        Mf = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=4, dtype="f32", pairwise=pw)
+        f32["ms_per_eval_pairwise" if pw else "ms_per_eval"] = round(time_evals(Mf), 4)
+        Mf.close()
     log("four volumes: joint solve")
     t0 = time.perf_counter()
     Dsol, _, _, rep = M.register()
@@ -375,7 +380,7 @@ def multi_bench(octmc, torch, log, reps=50):
     M.close()
     return {"workload": "four volumes (X, Y, X, Y) 300x300 A-scans x 640 samples, BF16 storage",
             "ms_per_eval": round(ms, 4), "evals_per_s": round(1000.0 / ms, 1), "pair_terms_per_eval": 6,
-            "ms_per_eval_pairwise": round(ms_pairwise, 4),
+            "ms_per_eval_pairwise": round(ms_pairwise, 4), "float32_storage": f32,
             "solve_seconds": round(sec, 3), "solve_evals": int(sum(r["evals"] for r in rep)),
             "solve_rms_vs_ground_truth_px": err}
 

@@ -190,18 +190,20 @@ def test_multi_fused_objective_parity(octmc, scans, dtype, level, nvol, sigma):
     assert grad_rel(g.double().cpu().numpy(), gp.double().cpu().numpy()) < 1e-5
 
 
-def test_multi_fused_odd_depth_level_uses_the_pair_path(octmc):
-    """A level of odd depth (66 -> 33) is evaluated pair by pair; the result
-    still meets the oracle's bar."""
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_multi_odd_depth_level(octmc, dtype):
+    """A level of odd depth (66 -> 33): pair by pair in BF16 storage (two
+    samples per lane need an even depth), fused in float32 storage; both meet
+    the oracle's bar."""
     sc = synth.make_scans("tiny", 4, (0, 1, 0, 1), n=36, d=66)
-    M = _gpu_multi(octmc, sc, levels=2, dtype="bf16")
+    M = _gpu_multi(octmc, sc, levels=2, dtype=dtype)
     w, h, d = M.level_shape(1)
     assert d % 2 == 1
     D = np.random.default_rng(2).normal(0, 0.5, (4, h, w, 3))
-    S, A, V = _oracle_level_inputs(sc, 1, range(4), 1)
+    S, A, V = _oracle_level_inputs(sc, 1, range(4), _STORE[dtype])
     om = oracle.Multi(S, sc.orient, A, V)
     ref, _, gref = oracle.evaluate_multi(om, D, oracle.Params(), np.ones(6))
-    log("n = 4 bf16, odd depth at level 1")
+    log(f"n = 4 {dtype}, odd depth at level 1")
     t, g = M.eval(1, torch.from_numpy(D).float().cuda(), eta_mode=1)  # stored eta = 1
     torch.cuda.synchronize()
     td = octmc.terms_dict(t)
