@@ -205,3 +205,47 @@ def test_eval_parity_max_size_sampled(octmc, dtype):
     gg = g.double().cpu().numpy().reshape(2, -1, 3)
     got = np.concatenate([gg[0][sample], gg[1][sample]], axis=1)
     assert grad_rel(got, gref) < TOL
+
+
+def test_check_nan_rejects_non_finite_volumes(octmc):
+    """OCTMC_CHECK_NAN: a NaN or an Inf in a structural volume makes pair
+    creation fail with OCTMC_E_NAN (-6); the same volumes pass without the
+    flag, and finite volumes pass with it."""
+    pair = synth.make_pair("tiny", n=24, d=32)
+    for bad in (float("nan"), float("inf")):
+        sy = pair.sy.clone()
+        sy[5, 7, 11] = bad
+        log(f"pair creation with {bad} and OCTMC_CHECK_NAN")
+        with pytest.raises(octmc.OctmcError) as e:
+            octmc.Pair(pair.sx, sy, ax=pair.ax, ay=pair.ay, levels=2, flags=octmc.CHECK_NAN)
+        assert e.value.code == -6
+        octmc.Pair(pair.sx, sy, ax=pair.ax, ay=pair.ay, levels=2).close()
+    octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, levels=2, flags=octmc.CHECK_NAN).close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_degenerate_identical_and_constant_scans(octmc, dtype):
+    """Degenerate inputs.  Identical scans at zero displacement: every
+    resampled sample is the stored sample itself (the interpolation weights
+    are 0, 1, 0, 0), so the structural term and its gradient are exactly
+    zero.  Constant volumes at any displacement: the structural term matches
+    the oracle (it is zero up to rounding) and so does the gradient.  Eq. 10
+    leaves eta undefined when the structural term at delta0 vanishes, as it
+    does here, so eta is given (stored eta = 1) rather than computed."""
+    pair = synth.make_pair("tiny", n=32, d=48)
+    h, w, _ = pair.sx.shape
+    log(f"identical scans, zero displacement, {dtype}")
+    P = octmc.Pair(pair.sx, pair.sx, ax=pair.ax, ay=pair.ax, levels=2, dtype=dtype, alpha=0.0, mean_weight=0.0)
+    t, g = P.eval(0, torch.zeros((2, h, w, 3), device="cuda"), eta_mode=1)
+    torch.cuda.synchronize()
+    td = octmc.terms_dict(t)
+    assert td["str"] == 0.0 and td["ang"] == 0.0 and td["F"] == 0.0
+    assert not g.any()
+    P.close()
+    log(f"constant volumes, random displacement, {dtype}")
+    c = torch.full_like(pair.sx, 0.375)  # exact in every storage type
+    P = octmc.Pair(c, c, ax=pair.ax, ay=pair.ay, levels=2, dtype=dtype)
+    lv = oracle.level_from(c, c, pair.ax, pair.ay)
+    t, _ = _compare(octmc, P, lv, 0, make_field(pair, "uniform", seed=5), f"constant/{dtype}", eta_mode=1)
+    assert abs(t["str"]) <= 1e-6 * abs(t["F"])
+    P.close()
