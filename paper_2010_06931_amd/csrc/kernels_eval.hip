@@ -855,6 +855,21 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize(const CombineJobs jobs)
     }
 }
 
+// Sum over the wave in float32, left in lane 63: the row sums as in
+// wave_sum, then two row broadcasts (rows 1 and 3 add the last lane of the
+// row before them, then rows 2 and 3 add lane 31).  Six DPP additions,
+// no lane reads: for kernels that reduce many values per wave.
+__device__ __forceinline__ float wave_sum_last(float x)
+{
+    float v = row_shr_add<1>(x);
+    v = row_shr_add<2>(v);
+    v = row_shr_add<4>(v);
+    v = row_shr_add<8>(v);
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // k_struct_multi: the structural data term of n = 3 or 4 volumes at one
 // level (16-bit storage, even depth).  Each output A-scan resamples every
@@ -1068,8 +1083,8 @@ __global__ __launch_bounds__(256) void k_struct_multi(const StructMultiJob<N> J)
     for (int q = 0; q < NP; ++q) {
         float v[7];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) v[c] = wave_sum(acc[q][c]);
-        if (lane == 0) {
+        for (int c = 0; c < 7; ++c) v[c] = wave_sum_last(acc[q][c]);
+        if (lane == 63) {
             float4* o = reinterpret_cast<float4*>(J.part[q] + (size_t)a * 8);
             o[0] = make_float4(v[0], v[1], v[2], v[3]);
             o[1] = make_float4(v[4], v[5], v[6], 0.f);
@@ -1173,8 +1188,8 @@ __global__ __launch_bounds__(256, 3) void k_struct_multi1(const StructMultiJob<N
     for (int q = 0; q < NP; ++q) {
         float v[7];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) v[c] = wave_sum(acc[q][c]);
-        if (lane == 0) {
+        for (int c = 0; c < 7; ++c) v[c] = wave_sum_last(acc[q][c]);
+        if (lane == 63) {
             float4* o = reinterpret_cast<float4*>(J.part[q] + (size_t)a * 8);
             o[0] = make_float4(v[0], v[1], v[2], v[3]);
             o[1] = make_float4(v[4], v[5], v[6], 0.f);
