@@ -145,6 +145,12 @@ __device__ __forceinline__ void load_cols(float (&v)[16], __amdgpu_buffer_rsrc_t
     for (int q = 0; q < 16; ++q) v[q] = ldv<T>(r, voff, s.off[q]);
 }
 
+// Stage 1 (rough axial prealignment) evaluates at dx = dy = 0, where the
+// lateral weights are (0, 1, 0, 0) in x and y: the blend of the 16 columns
+// is exactly the centre column (index 5; every other product is an exact 0),
+// so the axial kernels load that column alone and skip the lateral adjoint.
+constexpr int kCentre = 5;
+
 __device__ __forceinline__ float blend(const float (&v)[16], const Stencil& s)
 {
     float c = 0.f;
@@ -196,7 +202,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-template <typename T>
+template <typename T, bool AXIAL>
 __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
 {
     const int wv = uni((int)(threadIdx.x >> 6));
@@ -247,12 +253,21 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     const int nsteps = (d + kOutPerStep - 1) / kOutPerStep;
     for (int n = 0; n < nsteps; ++n) {
         if (active) {
-            load_cols<T>(sx, rx, SX, n, lane, d);
-            load_cols<T>(sy, ry, SY, n, lane, d);
+            float vx, vy;
+            if constexpr (AXIAL) {
+                const int m = clampi(SX.base + n * kOutPerStep + lane, 0, d - 1);
+                const int my = clampi(SY.base + n * kOutPerStep + lane, 0, d - 1);
+                vx = ldv<T>(rx, (uint32_t)m * esize<T>::v, SX.off[kCentre]);
+                vy = ldv<T>(ry, (uint32_t)my * esize<T>::v, SY.off[kCentre]);
+            } else {
+                load_cols<T>(sx, rx, SX, n, lane, d);
+                load_cols<T>(sy, ry, SY, n, lane, d);
+                vx = blend(sx, SX);
+                vy = blend(sy, SY);
+            }
             // blended columns, then the depth interpolation of Eq. 2 and its
             // depth derivative: output lane l reads source lanes l .. l + 3
             float ix = 0.f, izx = 0.f, iy = 0.f, izy = 0.f;
-            float vx = blend(sx, SX), vy = blend(sy, SY);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 ix = fmaf(SX.wz[c], vx, ix);
@@ -277,52 +292,57 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
             lam += L;
             gzx += valid ? G * izx : 0.f;
             gzy += valid ? G * izy : 0.f;
-            // adjoint of the depth interpolation: source lane l collects the
-            // derivatives of output lanes l - 3 .. l (invalid lanes carry 0)
-            float hx = 0.f, hy = 0.f, g = G;
+            if constexpr (!AXIAL) {
+                // adjoint of the depth interpolation: source lane l collects the
+                // derivatives of output lanes l - 3 .. l (invalid lanes carry 0)
+                float hx = 0.f, hy = 0.f, g = G;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                hx = fmaf(SX.wz[c], g, hx);
-                hy = fmaf(SY.wz[c], g, hy);
-                if (c < 3) g = shr1(g);
-            }
+                for (int c = 0; c < 4; ++c) {
+                    hx = fmaf(SX.wz[c], g, hx);
+                    hy = fmaf(SY.wz[c], g, hy);
+                    if (c < 3) g = shr1(g);
+                }
 #pragma unroll
-            for (int q2 = 0; q2 < 16; ++q2) {
-                PX[q2] = fmaf(sx[q2], hx, PX[q2]);
-                PY[q2] = fmaf(sy[q2], hy, PY[q2]);
+                for (int q2 = 0; q2 < 16; ++q2) {
+                    PX[q2] = fmaf(sx[q2], hx, PX[q2]);
+                    PY[q2] = fmaf(sy[q2], hy, PY[q2]);
+                }
             }
         }
         if constexpr (esize<T>::v == 4) __builtin_amdgcn_s_barrier();
     }
     if (!active) return;
     // Gamma_x = sum_b wy_b sum_a dwx_a P_ab, Gamma_y = sum_b dwy_b sum_a wx_a P_ab
+    // (left at 0 by the axial kernel: stage 1 uses only the z components)
     float wx[4], dwx[4], wy[4], dwy[4];
     float gxx = 0.f, gyx = 0.f, gxy = 0.f, gyy = 0.f;
-    cr_taps(SX.tx, wx, dwx);
-    cr_taps(SX.ty, wy, dwy);
+    if constexpr (!AXIAL) {
+        cr_taps(SX.tx, wx, dwx);
+        cr_taps(SX.ty, wy, dwy);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        float rv = 0.f, rd = 0.f;
+        for (int b = 0; b < 4; ++b) {
+            float rv = 0.f, rd = 0.f;
 #pragma unroll
-        for (int a2 = 0; a2 < 4; ++a2) {
-            rv = fmaf(wx[a2], PX[b * 4 + a2], rv);
-            rd = fmaf(dwx[a2], PX[b * 4 + a2], rd);
+            for (int a2 = 0; a2 < 4; ++a2) {
+                rv = fmaf(wx[a2], PX[b * 4 + a2], rv);
+                rd = fmaf(dwx[a2], PX[b * 4 + a2], rd);
+            }
+            gxx = fmaf(wy[b], rd, gxx);
+            gyx = fmaf(dwy[b], rv, gyx);
         }
-        gxx = fmaf(wy[b], rd, gxx);
-        gyx = fmaf(dwy[b], rv, gyx);
-    }
-    cr_taps(SY.tx, wx, dwx);
-    cr_taps(SY.ty, wy, dwy);
+        cr_taps(SY.tx, wx, dwx);
+        cr_taps(SY.ty, wy, dwy);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        float rv = 0.f, rd = 0.f;
+        for (int b = 0; b < 4; ++b) {
+            float rv = 0.f, rd = 0.f;
 #pragma unroll
-        for (int a2 = 0; a2 < 4; ++a2) {
-            rv = fmaf(wx[a2], PY[b * 4 + a2], rv);
-            rd = fmaf(dwx[a2], PY[b * 4 + a2], rd);
+            for (int a2 = 0; a2 < 4; ++a2) {
+                rv = fmaf(wx[a2], PY[b * 4 + a2], rv);
+                rd = fmaf(dwx[a2], PY[b * 4 + a2], rd);
+            }
+            gxy = fmaf(wy[b], rd, gxy);
+            gyy = fmaf(dwy[b], rv, gyy);
         }
-        gxy = fmaf(wy[b], rd, gxy);
-        gyy = fmaf(dwy[b], rv, gyy);
     }
     lam = wave_sum(lam);
     gxx = wave_sum(gxx);
@@ -382,7 +402,7 @@ __device__ __forceinline__ void load_pairs(float (&q0)[16], float (&q1)[16], __a
     for (int q = 0; q < 16; ++q) ld2<T>(rs, voff, S.off[q], q0[q], q1[q]);
 }
 
-template <typename T>
+template <typename T, bool AXIAL>
 __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
 {
     const int wv = uni((int)(threadIdx.x >> 6));
@@ -432,11 +452,20 @@ __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
         if (active) {
             const int mX = EX + kOutPerStep2 * n + 2 * lane;
             const int mY = EY + kOutPerStep2 * n + 2 * lane;
-            load_pairs<T>(x0, x1, rx, SX, mX, d);
-            load_pairs<T>(y0, y1, ry, SY, mY, d);
+            float bx0, bx1, by0, by1;
+            if constexpr (AXIAL) {
+                ld2<T>(rx, (uint32_t)clampi(mX, 0, d - 2) * esize<T>::v, SX.off[kCentre], bx0, bx1);
+                ld2<T>(ry, (uint32_t)clampi(mY, 0, d - 2) * esize<T>::v, SY.off[kCentre], by0, by1);
+            } else {
+                load_pairs<T>(x0, x1, rx, SX, mX, d);
+                load_pairs<T>(y0, y1, ry, SY, mY, d);
+                bx0 = blend(x0, SX);
+                bx1 = blend(x1, SX);
+                by0 = blend(y0, SY);
+                by1 = blend(y1, SY);
+            }
             // clamp: a pair below the A-scan holds sample 0 twice, one above it sample d - 1 twice
             const bool loX = mX < 0, hiX = mX > d - 2, loY = mY < 0, hiY = mY > d - 2;
-            float bx0 = blend(x0, SX), bx1 = blend(x1, SX), by0 = blend(y0, SY), by1 = blend(y1, SY);
             const float cx0 = hiX ? bx1 : bx0, cx1 = loX ? bx0 : bx1;
             const float ty0 = hiY ? by1 : by0, ty1 = loY ? by0 : by1;
             // Y positions start one sample after the pair boundary when rY = 1
@@ -474,55 +503,59 @@ __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
             lam += L0 + L1;
             gzx += G0 * zx0 + G1 * zx1;
             gzy += G0 * zy0 + G1 * zy1;
-            // adjoint of the depth interpolation: position q collects the
-            // derivatives of the outputs at q, q - 1, q - 2, q - 3
-            const float G0p = shr1(G0), G1p = shr1(G1), G1pp = shr1(G1p);
-            const float hx0 = SX.wz[0] * G0 + SX.wz[1] * G1p + SX.wz[2] * G0p + SX.wz[3] * G1pp;
-            const float hx1 = SX.wz[0] * G1 + SX.wz[1] * G0 + SX.wz[2] * G1p + SX.wz[3] * G0p;
-            const float hy0 = SY.wz[0] * G0 + SY.wz[1] * G1p + SY.wz[2] * G0p + SY.wz[3] * G1pp;
-            const float hy1 = SY.wz[0] * G1 + SY.wz[1] * G0 + SY.wz[2] * G1p + SY.wz[3] * G0p;
-            // back to the loaded samples q0, q1: alignment shift, then clamp
-            const float hy1p = shr1(hy1);
-            const float uy0 = rY ? hy1p : hy0, uy1 = rY ? hy0 : hy1;
-            const float wx0 = loX ? hx0 + hx1 : (hiX ? 0.f : hx0);
-            const float wx1 = hiX ? hx0 + hx1 : (loX ? 0.f : hx1);
-            const float wy0 = loY ? uy0 + uy1 : (hiY ? 0.f : uy0);
-            const float wy1 = hiY ? uy0 + uy1 : (loY ? 0.f : uy1);
+            if constexpr (!AXIAL) {
+                // adjoint of the depth interpolation: position q collects the
+                // derivatives of the outputs at q, q - 1, q - 2, q - 3
+                const float G0p = shr1(G0), G1p = shr1(G1), G1pp = shr1(G1p);
+                const float hx0 = SX.wz[0] * G0 + SX.wz[1] * G1p + SX.wz[2] * G0p + SX.wz[3] * G1pp;
+                const float hx1 = SX.wz[0] * G1 + SX.wz[1] * G0 + SX.wz[2] * G1p + SX.wz[3] * G0p;
+                const float hy0 = SY.wz[0] * G0 + SY.wz[1] * G1p + SY.wz[2] * G0p + SY.wz[3] * G1pp;
+                const float hy1 = SY.wz[0] * G1 + SY.wz[1] * G0 + SY.wz[2] * G1p + SY.wz[3] * G0p;
+                // back to the loaded samples q0, q1: alignment shift, then clamp
+                const float hy1p = shr1(hy1);
+                const float uy0 = rY ? hy1p : hy0, uy1 = rY ? hy0 : hy1;
+                const float wx0 = loX ? hx0 + hx1 : (hiX ? 0.f : hx0);
+                const float wx1 = hiX ? hx0 + hx1 : (loX ? 0.f : hx1);
+                const float wy0 = loY ? uy0 + uy1 : (hiY ? 0.f : uy0);
+                const float wy1 = hiY ? uy0 + uy1 : (loY ? 0.f : uy1);
 #pragma unroll
-            for (int q2 = 0; q2 < 16; ++q2) {
-                PX[q2] = fmaf(x0[q2], wx0, fmaf(x1[q2], wx1, PX[q2]));
-                PY[q2] = fmaf(y0[q2], wy0, fmaf(y1[q2], wy1, PY[q2]));
+                for (int q2 = 0; q2 < 16; ++q2) {
+                    PX[q2] = fmaf(x0[q2], wx0, fmaf(x1[q2], wx1, PX[q2]));
+                    PY[q2] = fmaf(y0[q2], wy0, fmaf(y1[q2], wy1, PY[q2]));
+                }
             }
         }
     }
     if (!active) return;
     float wx[4], dwx[4], wy[4], dwy[4];
     float gxx = 0.f, gyx = 0.f, gxy = 0.f, gyy = 0.f;
-    cr_taps(SX.tx, wx, dwx);
-    cr_taps(SX.ty, wy, dwy);
+    if constexpr (!AXIAL) {
+        cr_taps(SX.tx, wx, dwx);
+        cr_taps(SX.ty, wy, dwy);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        float rv = 0.f, rd = 0.f;
+        for (int b = 0; b < 4; ++b) {
+            float rv = 0.f, rd = 0.f;
 #pragma unroll
-        for (int a2 = 0; a2 < 4; ++a2) {
-            rv = fmaf(wx[a2], PX[b * 4 + a2], rv);
-            rd = fmaf(dwx[a2], PX[b * 4 + a2], rd);
+            for (int a2 = 0; a2 < 4; ++a2) {
+                rv = fmaf(wx[a2], PX[b * 4 + a2], rv);
+                rd = fmaf(dwx[a2], PX[b * 4 + a2], rd);
+            }
+            gxx = fmaf(wy[b], rd, gxx);
+            gyx = fmaf(dwy[b], rv, gyx);
         }
-        gxx = fmaf(wy[b], rd, gxx);
-        gyx = fmaf(dwy[b], rv, gyx);
-    }
-    cr_taps(SY.tx, wx, dwx);
-    cr_taps(SY.ty, wy, dwy);
+        cr_taps(SY.tx, wx, dwx);
+        cr_taps(SY.ty, wy, dwy);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        float rv = 0.f, rd = 0.f;
+        for (int b = 0; b < 4; ++b) {
+            float rv = 0.f, rd = 0.f;
 #pragma unroll
-        for (int a2 = 0; a2 < 4; ++a2) {
-            rv = fmaf(wx[a2], PY[b * 4 + a2], rv);
-            rd = fmaf(dwx[a2], PY[b * 4 + a2], rd);
+            for (int a2 = 0; a2 < 4; ++a2) {
+                rv = fmaf(wx[a2], PY[b * 4 + a2], rv);
+                rd = fmaf(dwx[a2], PY[b * 4 + a2], rd);
+            }
+            gxy = fmaf(wy[b], rd, gxy);
+            gyy = fmaf(dwy[b], rv, gyy);
         }
-        gxy = fmaf(wy[b], rd, gxy);
-        gyy = fmaf(dwy[b], rv, gyy);
     }
     lam = wave_sum(lam);
     gxx = wave_sum(gxx);
@@ -1205,7 +1238,8 @@ hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s)
+template <bool AXIAL>
+static hipError_t launch_struct_t(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s)
 {
     // 16-bit storage: two samples per lane, unless a depth is odd (the last
     // pair of an A-scan would then start at an odd sample, not 32-bit aligned)
@@ -1214,10 +1248,10 @@ hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype d
     if (pairs) {
         switch (dt) {
         case OCTMC_BF16:
-            hipLaunchKernelGGL(k_struct2<bf16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+            hipLaunchKernelGGL((k_struct2<bf16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
             return hipGetLastError();
         case OCTMC_F16:
-            hipLaunchKernelGGL(k_struct2<f16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+            hipLaunchKernelGGL((k_struct2<f16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
             return hipGetLastError();
         default:
             return hipErrorInvalidValue;
@@ -1225,18 +1259,23 @@ hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype d
     }
     switch (dt) {
     case OCTMC_F32:
-        hipLaunchKernelGGL(k_struct<float>, dim3(total_blocks), dim3(256), 0, s, jobs);
+        hipLaunchKernelGGL((k_struct<float, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
         break;
     case OCTMC_BF16:
-        hipLaunchKernelGGL(k_struct<bf16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+        hipLaunchKernelGGL((k_struct<bf16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
         break;
     case OCTMC_F16:
-        hipLaunchKernelGGL(k_struct<f16_t>, dim3(total_blocks), dim3(256), 0, s, jobs);
+        hipLaunchKernelGGL((k_struct<f16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
         break;
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s, bool axial)
+{
+    return axial ? launch_struct_t<true>(jobs, total_blocks, dt, s) : launch_struct_t<false>(jobs, total_blocks, dt, s);
 }
 
 hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s)

@@ -57,6 +57,7 @@ struct EvalArgs {
     int eta_mode = 1;                // 0: set the level's eta first (Eq. 10)
     const float* disp_y = nullptr;   // the second slot's [na][3] (null: disp + na * 3); needs with_struct =
                                      // false in eval_group, whose structural kernels read [2][na][3]
+    bool axial = false;              // dx = dy = 0 everywhere (stage 1): the x, y partials are left at 0
 };
 
 // The hot path over up to kMaxJobs jobs (distinct pairs, one storage type,
@@ -155,7 +156,10 @@ struct CombineJobs {
 // ---------------------------------------------------------------------------
 // launchers (kernels_eval.hip)
 hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s);
-hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s);
+// axial: every displacement has dx = dy = 0 (stage 1); the kernels then read
+// the centre column alone and leave the x and y partials at 0
+hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s,
+                         bool axial = false);
 // per-A-scan combination (total_blocks) followed by the fixed-order final
 // sums, one block per job
 hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s);

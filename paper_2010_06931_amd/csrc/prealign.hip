@@ -103,6 +103,7 @@ struct StageEval {
         HIP_TRY(hipMemcpyAsync(th_d, th.data(), n * 8, hipMemcpyHostToDevice, s));
         HIP_TRY(launch_tilt_expand(th_d, w, h, disp, nullptr, s));
         EvalArgs ea{P, disp, terms_d, grad, nullptr, nullptr, level, 1};
+        ea.axial = true;  // the field has dx = dy = 0; only its z gradient is used
         OCTMC_TRY(eval_group(&ea, 1, s));
         HIP_TRY(launch_tilt_reduce(grad, w, h, gth_d, s));
         g.resize(n);

@@ -120,7 +120,9 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_sum(sj, sb, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    if (with_struct) HIP_TRY(launch_struct(tj, (tb + 7) / 8 * 8, dt, s));  // multiple of the 8 XCDs
+    bool axial = true;
+    for (int q = 0; q < n; ++q) axial &= ea[q].axial;
+    if (with_struct) HIP_TRY(launch_struct(tj, (tb + 7) / 8 * 8, dt, s, axial));  // multiple of the 8 XCDs
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (any_eta) {  // eta of the jobs that ask for it, before their evaluation
         CombineJobs c0{};
