@@ -27,7 +27,10 @@
  *     outputs are valid once that stream has completed the call's work; calls
  *     that return host values synchronise the stream themselves.
  *   - Asynchronous device faults surface at a later call as OCTMC_E_DEVICE.
- *   - Threading: one host thread per pair object at a time.
+ *   - Threading: one host thread per object (pair, multi) at a time.  An
+ *     object holds one set of evaluation scratch buffers, so its asynchronous
+ *     calls must also be ordered on the device: issue them on one stream, or
+ *     synchronise between streams.
  */
 #ifndef OCTMC_H
 #define OCTMC_H
