@@ -147,3 +147,29 @@ def test_shape_limits(m):
     assert rc(32, 32, levels=4) == 0 and rc(32, 32, levels=5) == -2  # 4 samples at the coarsest level
     assert rc(31, 64, levels=4) == 0  # 31 -> 16 -> 8 -> 4
     assert rc(64, 64, dtype=7) == -3
+
+
+def test_readme_c_example_compiles_and_fails_cleanly(m, tmp_path):
+    """The C example in README.md compiles against include/octmc.h, links
+    against liboctmc.so and, given inputs it cannot use (no GPU here; a
+    volume too small for its pyramid on a GPU), returns an error code with a
+    message instead of crashing."""
+    text = open(os.path.join(ROOT, "README.md")).read()
+    code = text.split("```c\n", 1)[1].split("```", 1)[0]
+    main = """
+int main(void)
+{
+    static float sx[8 * 8 * 16], sy[8 * 8 * 16], ax[64], ay[64];
+    return register_pair(8, 16, sx, sy, ax, ay, (float*)0) == 0 ? 0 : 3;
+}
+"""
+    src = tmp_path / "example.c"
+    src.write_text(code + main)
+    exe = tmp_path / "example"
+    lib = os.path.dirname(m.LIB_PATH)
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe), "-L", lib, "-loctmc",
+                    f"-Wl,-rpath,{lib}"], check=True)
+    # with a GPU the 8 x 8 x 16 volume is refused for its 4 levels (OCTMC_E_SHAPE): an error either way
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 3, (r.returncode, r.stdout, r.stderr)
+    assert "octmc:" in r.stderr
