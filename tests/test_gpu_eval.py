@@ -230,8 +230,9 @@ def test_degenerate_identical_and_constant_scans(octmc, dtype):
     are 0, 1, 0, 0), so the structural term and its gradient are exactly
     zero.  Constant volumes at any displacement: the structural term matches
     the oracle (it is zero up to rounding) and so does the gradient.  Eq. 10
-    leaves eta undefined when the structural term at delta0 vanishes, as it
-    does here, so eta is given (stored eta = 1) rather than computed."""
+    leaves eta undefined when the structural term at delta0 vanishes; here it
+    is zero only up to rounding (outside the exact-zero guard that sets
+    eta = 1), so eta is given (stored eta = 1) rather than computed."""
     pair = synth.make_pair("tiny", n=32, d=48)
     h, w, _ = pair.sx.shape
     log(f"identical scans, zero displacement, {dtype}")
