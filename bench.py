@@ -151,6 +151,30 @@ def cpu_baseline(pair, D, target_s=15.0):
                       f"{na}/{nsample}"}
 
 
+def cpu_baseline_small(torch):
+    """The FP64 oracle's full objective and gradient (every term) on the tiny
+    64^2 x 128 pair, on one host thread and on all of them: evaluations per
+    second (a reported baseline beside the sampled one above)."""
+    import oracle
+    import synth
+    pair = synth.make_pair("tiny", 0)
+    lv = oracle.level_from_pair(pair)
+    D = pair.d_gt.double().numpy()
+    prm = oracle.Params()
+    nall = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    res = {"workload": "tiny pair 64x64 A-scans x 128 samples, full objective and gradient, FP64 oracle"}
+    for tag, nt in (("one_thread", 1), ("all_threads", nall)):
+        used = oracle.set_threads(nt)
+        oracle.evaluate(lv, D, prm, 1.0)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 2.0:
+            oracle.evaluate(lv, D, prm, 1.0)
+            reps += 1
+        res[tag] = {"evals_per_s": round(reps / (time.perf_counter() - t0), 3), "threads": used}
+    oracle.set_threads(nall)
+    return res
+
+
 SERVE_SIZES = (300, 400, 500, 600)
 SERVE_DEPTHS = (512, 640, 800)
 UM_PER_PX = (12.0, 12.0, 3.0)  # transverse x, y and axial spacing of the dense / serving scans
@@ -558,6 +582,16 @@ def main():
         print(json.dumps({"ms_per_eval": ms}))
         return
 
+    # spread of single evaluations: one event between consecutive evaluations
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record()
+    for k in range(args.steps):
+        P.eval(0, D, grad=grad, terms=terms)
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    per_eval = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    pct = {f"p{q}": round(float(np.percentile(per_eval, q)), 5) for q in (10, 50, 90)}
+
     # dominant kernel timed live with HIP events on its stream
     stages = np.array([P.eval_profile(0, D, grad=grad, terms=terms) for _ in range(max(20, args.steps // 4))])
     st_ms = stages.mean(axis=0)
@@ -580,7 +614,7 @@ def main():
            "config": {"workload": f"dense orthogonal pair {w}x{h} A-scans x {d} samples, finest level, "
                                   f"storage {args.dtype}", "w": w, "h": h, "d": d, "level": 0,
                       "storage": args.dtype, "parallelism": "single GPU"},
-           "roofline": roof, "roofline_other": other,
+           "roofline": roof, "roofline_other": other, "ms_per_eval_percentiles": pct,
            "kernel_ms": {"sum": round(st_ms[0], 5), "struct": round(st_ms[1], 5), "combine": round(st_ms[2], 5)},
            "hbm_GBps_algorithmic": round(hbm, 1)}
 
@@ -675,6 +709,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(pair, D)
+        out["cpu_baseline_small"] = cpu_baseline_small(torch)
     print(json.dumps(out), flush=True)
 
 

@@ -155,6 +155,12 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def set_threads(n: int) -> int:
+    """Host threads of the oracle's parallel loops (timing only; results do not
+    depend on it).  Returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
+
+
 def _p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 

@@ -34,6 +34,24 @@
 
 #define EXPORT __attribute__((visibility("default")))
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Host threads the oracle's parallel loops use from now on (timing only:
+ * every sum is formed per A-scan and combined in a fixed order, so results do
+ * not depend on it).  Returns the count in effect. */
+EXPORT int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* Parameters of the objective and the solver.  Field meaning:
  *   alpha        weight of the scan-order regulariser R (Eq. 1)
  *   delta0       default angiography weight (Eq. 8)
