@@ -226,3 +226,31 @@ def test_multi_fused_register_parity(octmc, scans):
     assert err < 0.05, err
     for r, ro in zip(rep, repo):
         assert abs(r["f_end"] - ro["f_end"]) <= 0.05 * abs(ro["f_end"]), (r, ro)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_multi_fused_full_size_matches_pairwise(octmc, dtype):
+    """Four volumes of 300 x 300 A-scans x 640 samples, in the launch
+    configuration the benchmark times: the fused structural pass against the
+    pair-by-pair evaluation (each pair's structural kernel is pinned to the
+    oracle by the pair tests, at full size included), float32 rounding
+    apart, at levels 0 and 1."""
+    log(f"four volumes 300x300x640 on cuda, {dtype}")
+    sc = synth.make_scans("clinical", 0, (0, 1, 0, 1), device="cuda", white_lines=True)
+    M = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=4, dtype=dtype)
+    Mp = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=4, dtype=dtype, pairwise=True)
+    gen = torch.Generator().manual_seed(4)
+    for level in (0, 1):
+        w, h, d = M.level_shape(level)
+        D = (1.5 * torch.randn((4, h, w, 3), generator=gen)).float().cuda()
+        log(f"fused vs pairwise, level {level} ({w}x{h}x{d})")
+        t, g = M.eval(level, D, eta_mode=0)
+        tp, gp = Mp.eval(level, D, eta_mode=0)
+        torch.cuda.synchronize()
+        td, tpd = octmc.terms_dict(t), octmc.terms_dict(tp)
+        for key in ("F", "data", "str", "ang", "reg", "mean"):
+            assert rel(td[key], tpd[key]) < 1e-5 or abs(td[key] - tpd[key]) < 1e-9, (level, key, td[key], tpd[key])
+        assert grad_rel(g.double().cpu().numpy(), gp.double().cpu().numpy()) < 1e-5
+    M.close()
+    Mp.close()
