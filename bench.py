@@ -582,6 +582,21 @@ def main():
         print(json.dumps({"ms_per_eval": ms}))
         return
 
+    # achievable HBM rate on this device: a 1 GiB device-to-device copy (read + write)
+    ca = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        cb.copy_(ca)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * COPY_BYTES * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del ca, cb
+
     # spread of single evaluations: one event between consecutive evaluations
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     evs[0].record()
@@ -616,7 +631,7 @@ def main():
                       "storage": args.dtype, "parallelism": "single GPU"},
            "roofline": roof, "roofline_other": other, "ms_per_eval_percentiles": pct,
            "kernel_ms": {"sum": round(st_ms[0], 5), "struct": round(st_ms[1], 5), "combine": round(st_ms[2], 5)},
-           "hbm_GBps_algorithmic": round(hbm, 1)}
+           "hbm_GBps_algorithmic": round(hbm, 1), "hbm_copy_GBps": round(copy_gbs, 1)}
 
     if not args.no_variants:
         var = {}
