@@ -192,6 +192,20 @@ def _interior_rms(D, gt, border=8):
     return np.sqrt((e[m] ** 2).mean(axis=0))
 
 
+def _relative_rms(D, gt, border=8):
+    """Per-component RMS of the error of the relative displacement
+    d^X - d^Y (what the data term sees) over A-scans away from the border,
+    after removing its mean.  A smooth warp common to both scans changes
+    neither scan's agreement with the other, so it is left out of this
+    figure but not out of _interior_rms."""
+    import numpy as np
+    e = (D[0] - D[1]).double().cpu().numpy() - (gt[0] - gt[1]).double().cpu().numpy()
+    h, w = e.shape[:2]
+    e = e[border:h - border, border:w - border].reshape(-1, 3)
+    e -= e.mean(axis=0)
+    return np.sqrt((e ** 2).mean(axis=0))
+
+
 def serving(octmc, torch, nreq, budget_gib, max_active, log):
     """Mixed-size requests through the server (BF16 storage) against
     sequential FP32 solves of the same trace on the same GPU."""
@@ -690,6 +704,10 @@ def main():
                         "levels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()} for r in rep],
                         "evals_total": int(sum(r["evals"] for r in rep)),
                         "rms_vs_ground_truth_px": [round(float(x), 4) for x in rms_main],
+                        "relative_rms_vs_ground_truth_px": [round(float(x), 4) for x in
+                                                            _relative_rms(Dsol, pair.d_gt)],
+                        "relative_motion_rms_px": [round(float(x), 4) for x in
+                                                   _relative_rms(torch.zeros_like(pair.d_gt), pair.d_gt)],
                         "rms_vs_ground_truth_um": [round(float(x * s), 2) for x, s in zip(rms_main, UM_PER_PX)],
                         "rms_vs_fp32_storage_solve_px": vs32(Dsol)}
         for dt, v in out.get("storage_variants", {}).items():
