@@ -145,7 +145,7 @@ def cpu_baseline(pair, D, target_s=15.0):
     t0 = time.perf_counter()
     oracle.data_ascans(lv, Dn, sample, prm, 1.0)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.set_threads(0)  # the threads its parallel loops used
     return {"value": (nsample / na) / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"data term of {nsample} random A-scans of the {w}x{h}x{d} pair ({dt:.1f} s), scaled by "
                       f"{na}/{nsample}"}
