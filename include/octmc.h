@@ -92,7 +92,8 @@ typedef struct {
     double eps_reg;      /* pseudo-Huber parameter of R, in pixels                [R: 0.1]  */
     double flyback_frac; /* flyback per B-scan, fraction of the B-scan length     [R: 0.25] */
     double mean_weight;  /* gamma_M of the mean-displacement term M               [R: 1.0]  */
-    int32_t levels;      /* pyramid levels (factor 2, Sec. 2.1)                   [3]       */
+    int32_t levels;      /* pyramid levels (factor 2, Sec. 2.1), 1..8; 0: automatic, the fewest
+                            levels whose coarsest level is at most 32 A-scans wide [3]       */
     int32_t iters_per_level; /* accepted L-BFGS steps per level                   [100]     */
     int32_t lbfgs_m;     /* L-BFGS memory (1..8)                                  [R: 5]    */
     int32_t ls_max_evals;/* evaluations per line search                           [R: 20]   */
@@ -108,7 +109,8 @@ typedef struct {
  * when it is at most about one pixel at the coarsest level.  On synthetic
  * scans with 10-13 px of motion between them, a coarsest level of 19-32
  * A-scans (5 levels at 300-500 A-scans) removed most of it, where 38-63
- * A-scans (4 levels) left it in a local minimum. */
+ * A-scans (4 levels) left it in a local minimum.  levels = 0 chooses such a
+ * depth from the shape. */
 
 typedef struct {
     int32_t w, h, d;   /* A-scans per row, rows, samples per A-scan; w == h */
@@ -354,6 +356,10 @@ OCTMC_API int octmc_multi_eval(octmc_multi* multi, int32_t level, const float* d
  * OCTMC_E_DEVICE. */
 OCTMC_API int octmc_multi_register(octmc_multi* multi, float* disp_out, float* merged_oct, float* merged_octa,
                                    octmc_report* rep, void* stream);
+
+/* The number of pyramid levels the pair holds (the resolved count when it was
+ * created with levels = 0).  Errors: OCTMC_E_INVALID (NULL). */
+OCTMC_API int octmc_pair_levels(const octmc_pair* pair, int32_t* levels);
 
 /* Shape (w, h, d) of pyramid level `level` (0 = finest). */
 OCTMC_API int octmc_pair_level_shape(const octmc_pair* pair, int32_t level, int32_t* w, int32_t* h, int32_t* d);

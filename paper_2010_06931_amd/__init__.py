@@ -37,8 +37,9 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_SHAPE", -3: "E_DTYPE", -4: "E_OOM", -
 
 # exported symbols of include/octmc.h (checked by the CPU test suite)
 SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_create", "octmc_destroy",
-           "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_level_shape", "octmc_validity_from_octa",
-           "octmc_enface_project", "octmc_enface_workspace_size", "octmc_prealign_eval", "octmc_prealign",
+           "octmc_pair_create", "octmc_pair_destroy", "octmc_pair_levels", "octmc_pair_level_shape",
+           "octmc_validity_from_octa", "octmc_enface_project", "octmc_enface_workspace_size", "octmc_prealign_eval",
+           "octmc_prealign",
            "octmc_pair_prealignment", "octmc_resample_axial", "octmc_multi_create", "octmc_multi_destroy",
            "octmc_multi_eval", "octmc_multi_register", "octmc_eval",
            "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge",
@@ -118,6 +119,7 @@ def lib():
         L.octmc_pair_create.argtypes = [vp, C.POINTER(Params), C.POINTER(Shape)] + [vp] * 8 + [vp, C.POINTER(vp)]
         L.octmc_pair_destroy.argtypes = [vp]
         L.octmc_pair_level_shape.argtypes = [vp, C.c_int32] + [C.POINTER(C.c_int32)] * 3
+        L.octmc_pair_levels.argtypes = [vp, C.POINTER(C.c_int32)]
         L.octmc_validity_from_octa.argtypes = [vp, C.POINTER(Shape), vp, C.c_int32, vp, vp]
         L.octmc_enface_project.argtypes = [vp, C.POINTER(Shape), vp, vp, C.c_int32, vp, C.POINTER(C.c_double), vp, vp,
                                            C.POINTER(C.c_double), vp, C.c_uint64, vp]
@@ -254,7 +256,10 @@ class Pair:
 
     @property
     def levels(self) -> int:
-        return self.params.levels
+        """Pyramid levels the pair holds (resolved when created with levels=0)."""
+        n = C.c_int32()
+        _check(lib().octmc_pair_levels(self._h, C.byref(n)))
+        return n.value
 
     def level_shape(self, level: int):
         w, h, d = C.c_int32(), C.c_int32(), C.c_int32()

@@ -443,12 +443,15 @@ int merge_multi_impl(octmc_multi* M, const float* disp, float* merged_oct, float
 
 extern "C" {
 
-int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, int32_t n,
+int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params_in, const octmc_shape* shape, int32_t n,
                        const int32_t* orient, const float* const* oct, const float* const* octa,
                        const float* const* enface, const float* const* valid, void* stream, octmc_multi** out)
 {
     if (!ctx || !shape || !orient || !oct || !out) return fail(OCTMC_E_INVALID, "NULL argument");
     if (n < 2 || n > kMaxVol) return fail(OCTMC_E_INVALID, "n must lie in [2, 8]");
+    if (!params_in) return fail(OCTMC_E_INVALID, "params is NULL");
+    const octmc_params resolved = resolve_levels(*params_in, *shape);
+    const octmc_params* params = &resolved;
     OCTMC_TRY(validate_params(params));
     OCTMC_TRY(validate_shape(params, shape));
     if (params->flags & OCTMC_PREALIGN) return fail(OCTMC_E_INVALID, "OCTMC_PREALIGN is not available for n volumes");

@@ -203,6 +203,22 @@ const std::vector<double>& octmc::pair_theta(const octmc_pair* pair) { return pa
 
 int octmc::ctx_device(const octmc_ctx* ctx) { return ctx->device; }
 
+octmc_params octmc::resolve_levels(const octmc_params& p, const octmc_shape& shape)
+{
+    octmc_params r = p;
+    if (p.levels != 0) return r;
+    int wl = shape.w, dl = shape.d, L = 1;
+    while (L < OCTMC_MAX_LEVELS && wl > kAutoCoarsest) {
+        const int nw = (wl + 1) / 2, nd = (dl + 1) / 2;
+        if (nw < 4 || nd < 4) break;
+        wl = nw;
+        dl = nd;
+        ++L;
+    }
+    r.levels = L;
+    return r;
+}
+
 int octmc::validate_params(const octmc_params* p)
 {
     if (!p) return fail(OCTMC_E_INVALID, "params is NULL");
@@ -622,8 +638,10 @@ int octmc_pair_create(octmc_ctx* ctx, const octmc_params* params, const octmc_sh
                       const float* enface_y, const float* valid_x, const float* valid_y, void* stream,
                       octmc_pair** out)
 {
-    return pair_create_impl(ctx, params, shape, oct_x, oct_y, octa_x, octa_y, enface_x, enface_y, valid_x, valid_y,
-                            static_cast<hipStream_t>(stream), nullptr, out);
+    octmc_params pr{};
+    if (params && shape) pr = resolve_levels(*params, *shape);
+    return pair_create_impl(ctx, params && shape ? &pr : params, shape, oct_x, oct_y, octa_x, octa_y, enface_x,
+                            enface_y, valid_x, valid_y, static_cast<hipStream_t>(stream), nullptr, out);
 }
 
 int octmc_validity_from_octa(octmc_ctx* ctx, const octmc_shape* shape, const float* octa, int32_t scan,
@@ -717,6 +735,13 @@ int octmc_pair_destroy(octmc_pair* pair)
         (void)hipDeviceSynchronize();
     }
     delete pair;
+    return OCTMC_OK;
+}
+
+int octmc_pair_levels(const octmc_pair* pair, int32_t* levels)
+{
+    if (!pair || !levels) return fail(OCTMC_E_INVALID, "NULL argument");
+    *levels = pair->nlev;
     return OCTMC_OK;
 }
 

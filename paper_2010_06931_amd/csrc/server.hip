@@ -294,8 +294,9 @@ void worker_main(octmc_server* S, Worker* W)
 int check_request(const octmc_request* req)
 {
     if (!req) return fail(OCTMC_E_INVALID, "request is NULL");
-    OCTMC_TRY(validate_params(&req->params));
-    OCTMC_TRY(validate_shape(&req->params, &req->shape));
+    const octmc_params pr = resolve_levels(req->params, req->shape);
+    OCTMC_TRY(validate_params(&pr));
+    OCTMC_TRY(validate_shape(&pr, &req->shape));
     if (!req->oct_x || !req->oct_y || !req->disp_out) return fail(OCTMC_E_INVALID, "oct_x, oct_y, disp_out required");
     const bool octa = req->octa_x && req->octa_y, enf = req->enface_x && req->enface_y;
     if (!octa && !enf) return fail(OCTMC_E_INVALID, "need both OCTA volumes or both en face images");
@@ -313,8 +314,8 @@ int check_request(const octmc_request* req)
 
 size_t request_footprint(const octmc_request* req)
 {
-    return pair_footprint(req->params, req->shape, req->octa_x != nullptr, req->valid_x != nullptr,
-                          req->merged_oct != nullptr);
+    return pair_footprint(resolve_levels(req->params, req->shape), req->shape, req->octa_x != nullptr,
+                          req->valid_x != nullptr, req->merged_oct != nullptr);
 }
 
 void destroy_server(octmc_server* S)
@@ -405,6 +406,7 @@ int octmc_server_submit(octmc_server* srv, const octmc_request* req, uint64_t* i
         Job j;
         j.id = srv->next_id++;
         j.req = *req;
+        j.req.params = resolve_levels(req->params, req->shape);
         j.footprint = fp;
         j.t_submit = srv->now();
         if (id) *id = j.id;

@@ -173,3 +173,23 @@ int main(void)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 3, (r.returncode, r.stdout, r.stderr)
     assert "octmc:" in r.stderr
+
+
+def test_automatic_levels(m):
+    """levels = 0 resolves to the fewest levels whose coarsest level is at
+    most 32 A-scans wide (never below 4 samples along an axis); the request
+    footprint, which sizes every level, shows the resolved count."""
+    L = m.lib()
+    b0, b1 = C.c_uint64(), C.c_uint64()
+
+    def same(w, d, levels):
+        assert L.octmc_request_footprint(C.byref(_request(m, w=w, d=d, levels=0)), C.byref(b0)) == 0
+        assert L.octmc_request_footprint(C.byref(_request(m, w=w, d=d, levels=levels)), C.byref(b1)) == 0
+        return b0.value == b1.value
+
+    assert same(500, 800, 5)   # 500 250 125 63 32
+    assert same(300, 640, 5)   # 300 150 75 38 19
+    assert same(64, 128, 2)    # 64 32
+    assert same(32, 64, 1)
+    assert same(600, 8, 2)     # depth 8 -> 4 stops the halving
+    assert not same(500, 800, 4)

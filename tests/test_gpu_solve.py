@@ -111,3 +111,27 @@ def test_register_with_merge_and_enface_from_octa(octmc):
     assert mo.shape == (32, 32, 40) and ma.shape == (32, 32, 40)
     assert torch.isfinite(mo).all() and torch.isfinite(ma).all()
     assert all(r["iters"] <= 10 for r in rep)
+
+
+def test_automatic_levels_equal_the_explicit_count(octmc):
+    """levels = 0 resolves to the fewest levels whose coarsest level is at
+    most 32 A-scans wide (96 -> 48 -> 24: 3 levels); the solve is then bit
+    for bit the one with levels = 3, for a pair and for four volumes."""
+    pair = synth.make_pair("tiny", 2, n=96, d=64)
+    kw = dict(ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, iters_per_level=20)
+    log("pair with levels = 0")
+    P0 = octmc.Pair(pair.sx, pair.sy, levels=0, **kw)
+    P3 = octmc.Pair(pair.sx, pair.sy, levels=3, **kw)
+    assert P0.levels == 3 and P3.levels == 3
+    D0, _, _, r0 = P0.register()
+    D3, _, _, r3 = P3.register()
+    torch.cuda.synchronize()
+    assert len(r0) == 3 and torch.equal(D0, D3)
+    log("four volumes with levels = 0")
+    sc = synth.make_scans("tiny", 5, (0, 1, 0, 1), n=96, d=64)
+    M0 = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=0, iters_per_level=10)
+    M3 = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=3, iters_per_level=10)
+    E0, _, _, q0 = M0.register()
+    E3, _, _, q3 = M3.register()
+    torch.cuda.synchronize()
+    assert len(q0) == 3 and torch.equal(E0, E3)
