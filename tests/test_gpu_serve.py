@@ -170,3 +170,27 @@ def test_serve_with_detection_and_projection(octmc):
         srv.submit(q.sx, q.sy, torch.empty((2, 40, 40, 3), device="cuda"), ox=q.ox, oy=q.oy,
                    flags=octmc.PREALIGN)
     srv.close()
+
+
+def test_serve_automatic_levels(octmc):
+    """A request with levels = 0 is served with the resolved depth (80 -> 40
+    -> 20: 3 levels): the same field as a pair created with levels = 3, within
+    its footprint."""
+    q = synth.make_pair("serving", 20, n=80, d=48)
+    P = octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, levels=3, iters_per_level=15)
+    ref, _, _, _ = P.register()
+    torch.cuda.synchronize()
+    P.close()
+    srv = octmc.Server(1 << 30, max_active=1)
+    disp = torch.empty((2, 80, 80, 3), device="cuda")
+    log("serve: one request with levels = 0")
+    rid = srv.submit(q.sx, q.sy, disp, ax=q.ax, ay=q.ay, levels=0, iters_per_level=15, tag=0)
+    got = []
+    while not got:
+        got = srv.poll(1, wait_ms=60000)
+        assert got, "no completion within 60 s"
+    c = got[0]
+    assert c["id"] == rid and c["status"] == 0, c["error"]
+    assert c["bytes_used"] <= c["bytes_reserved"]
+    assert torch.equal(disp, ref)
+    srv.close()
