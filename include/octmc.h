@@ -93,7 +93,7 @@ typedef struct {
     double flyback_frac; /* flyback per B-scan, fraction of the B-scan length     [R: 0.25] */
     double mean_weight;  /* gamma_M of the mean-displacement term M               [R: 1.0]  */
     int32_t levels;      /* pyramid levels (factor 2, Sec. 2.1), 1..8; 0: automatic, the fewest
-                            levels whose coarsest level is at most 32 A-scans wide [3]       */
+                            levels whose coarsest level is at most 16 A-scans wide [3]       */
     int32_t iters_per_level; /* accepted L-BFGS steps per level                   [100]     */
     int32_t lbfgs_m;     /* L-BFGS memory (1..8)                                  [R: 5]    */
     int32_t ls_max_evals;/* evaluations per line search                           [R: 20]   */
@@ -107,10 +107,10 @@ typedef struct {
 } octmc_params;
 /* Choosing `levels`: the solve removes lateral motion between the scans well
  * when it is at most about one pixel at the coarsest level.  On synthetic
- * scans with 10-13 px of motion between them, a coarsest level of 19-32
- * A-scans (5 levels at 300-500 A-scans) removed most of it, where 38-63
- * A-scans (4 levels) left it in a local minimum.  levels = 0 chooses such a
- * depth from the shape. */
+ * scans with 10-13 px of motion between them and 100 steps per level, a
+ * coarsest level of 10-16 A-scans (6 levels at 300-500 A-scans) removed most
+ * of it, where 38-63 A-scans (4 levels) left it in a local minimum.
+ * levels = 0 chooses such a depth from the shape. */
 
 typedef struct {
     int32_t w, h, d;   /* A-scans per row, rows, samples per A-scan; w == h */

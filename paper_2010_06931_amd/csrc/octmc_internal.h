@@ -78,7 +78,7 @@ int validate_params(const octmc_params* p);
 // params with levels = 0 (automatic) replaced by the level count for `shape`:
 // the fewest levels whose coarsest level is at most kAutoCoarsest A-scans
 // wide, stopping before an axis would fall below 4 samples
-constexpr int kAutoCoarsest = 32;
+constexpr int kAutoCoarsest = 16;
 octmc_params resolve_levels(const octmc_params& p, const octmc_shape& shape);
 int validate_shape(const octmc_params* params, const octmc_shape* shape);
 

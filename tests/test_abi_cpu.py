@@ -177,7 +177,7 @@ int main(void)
 
 def test_automatic_levels(m):
     """levels = 0 resolves to the fewest levels whose coarsest level is at
-    most 32 A-scans wide (never below 4 samples along an axis); the request
+    most 16 A-scans wide (never below 4 samples along an axis); the request
     footprint, which sizes every level, shows the resolved count."""
     L = m.lib()
     b0, b1 = C.c_uint64(), C.c_uint64()
@@ -187,9 +187,9 @@ def test_automatic_levels(m):
         assert L.octmc_request_footprint(C.byref(_request(m, w=w, d=d, levels=levels)), C.byref(b1)) == 0
         return b0.value == b1.value
 
-    assert same(500, 800, 5)   # 500 250 125 63 32
-    assert same(300, 640, 5)   # 300 150 75 38 19
-    assert same(64, 128, 2)    # 64 32
-    assert same(32, 64, 1)
+    assert same(500, 800, 6)   # 500 250 125 63 32 16
+    assert same(300, 640, 6)   # 300 150 75 38 19 10
+    assert same(64, 128, 3)    # 64 32 16
+    assert same(16, 64, 1)
     assert same(600, 8, 2)     # depth 8 -> 4 stops the halving
-    assert not same(500, 800, 4)
+    assert not same(500, 800, 5)

@@ -174,10 +174,10 @@ def test_serve_with_detection_and_projection(octmc):
 
 def test_serve_automatic_levels(octmc):
     """A request with levels = 0 is served with the resolved depth (80 -> 40
-    -> 20: 3 levels): the same field as a pair created with levels = 3, within
-    its footprint."""
+    -> 20 -> 10: 4 levels): the same field as a pair created with levels = 4,
+    within its footprint."""
     q = synth.make_pair("serving", 20, n=80, d=48)
-    P = octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, levels=3, iters_per_level=15)
+    P = octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, levels=4, iters_per_level=15)
     ref, _, _, _ = P.register()
     torch.cuda.synchronize()
     P.close()

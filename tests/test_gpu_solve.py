@@ -115,23 +115,23 @@ def test_register_with_merge_and_enface_from_octa(octmc):
 
 def test_automatic_levels_equal_the_explicit_count(octmc):
     """levels = 0 resolves to the fewest levels whose coarsest level is at
-    most 32 A-scans wide (96 -> 48 -> 24: 3 levels); the solve is then bit
-    for bit the one with levels = 3, for a pair and for four volumes."""
+    most 16 A-scans wide (96 -> 48 -> 24 -> 12: 4 levels); the solve is then
+    bit for bit the one with levels = 4, for a pair and for four volumes."""
     pair = synth.make_pair("tiny", 2, n=96, d=64)
     kw = dict(ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, iters_per_level=20)
     log("pair with levels = 0")
     P0 = octmc.Pair(pair.sx, pair.sy, levels=0, **kw)
-    P3 = octmc.Pair(pair.sx, pair.sy, levels=3, **kw)
-    assert P0.levels == 3 and P3.levels == 3
+    P4 = octmc.Pair(pair.sx, pair.sy, levels=4, **kw)
+    assert P0.levels == 4 and P4.levels == 4
     D0, _, _, r0 = P0.register()
-    D3, _, _, r3 = P3.register()
+    D4, _, _, r4 = P4.register()
     torch.cuda.synchronize()
-    assert len(r0) == 3 and torch.equal(D0, D3)
+    assert len(r0) == 4 and torch.equal(D0, D4)
     log("four volumes with levels = 0")
     sc = synth.make_scans("tiny", 5, (0, 1, 0, 1), n=96, d=64)
     M0 = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=0, iters_per_level=10)
-    M3 = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=3, iters_per_level=10)
+    M4 = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=4, iters_per_level=10)
     E0, _, _, q0 = M0.register()
-    E3, _, _, q3 = M3.register()
+    E4, _, _, q4 = M4.register()
     torch.cuda.synchronize()
-    assert len(q0) == 3 and torch.equal(E0, E3)
+    assert len(q0) == 4 and torch.equal(E0, E4)
