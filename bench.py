@@ -710,6 +710,18 @@ def main():
                                                    _relative_rms(torch.zeros_like(pair.d_gt), pair.d_gt)],
                         "rms_vs_ground_truth_um": [round(float(x * s), 2) for x, s in zip(rms_main, UM_PER_PX)],
                         "rms_vs_fp32_storage_solve_px": vs32(Dsol)}
+        # the same pair with the automatic pyramid depth (levels = 0)
+        Pa = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=args.dtype, levels=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Da, _, _, _ = Pa.register()
+        torch.cuda.synchronize()
+        out["solve"]["automatic_levels"] = {
+            "levels": Pa.levels, "seconds": round(time.perf_counter() - t0, 4),
+            "rms_vs_ground_truth_px": [round(float(x), 4) for x in _interior_rms(Da, pair.d_gt)],
+            "relative_rms_vs_ground_truth_px": [round(float(x), 4) for x in _relative_rms(Da, pair.d_gt)]}
+        Pa.close()
+        del Da
         for dt, v in out.get("storage_variants", {}).items():
             Dq = v.pop("solution", None)
             if Dq is None:
