@@ -208,7 +208,9 @@ def _relative_rms(D, gt, border=8):
 
 def serving(octmc, torch, nreq, budget_gib, max_active, log):
     """Mixed-size requests through the server (BF16 storage) against
-    sequential FP32 solves of the same trace on the same GPU."""
+    sequential FP32 solves of the same trace on the same GPU: with the
+    workload's 4 levels (Poisson trace and two burst modes), then with the
+    automatic pyramid depth (levels = 0, Poisson trace only)."""
     import numpy as np
     import synth
     classes = [(n, d) for n in SERVE_SIZES for d in SERVE_DEPTHS]
@@ -225,36 +227,32 @@ def serving(octmc, torch, nreq, budget_gib, max_active, log):
         n = classes[c][0]
         return torch.empty((2, n, n, 3), dtype=torch.float32, device="cuda")
 
-    # sequential plain FP32 solves, first-come first-served on the trace
-    log(f"serving: {nreq} sequential FP32 solves")
-    seq_t, seq_D = [], {}
-    for r in range(nreq):
-        q = pairs[cls[r]]
-        t0 = time.perf_counter()
-        P = octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, dtype="f32", levels=4)
-        D, _, _, _ = P.register()
-        torch.cuda.synchronize()
-        P.close()
-        seq_t.append(time.perf_counter() - t0)
-        if cls[r] not in seq_D:
-            seq_D[cls[r]] = D
-    done = 0.0
-    seq_lat = []
-    for r in range(nreq):
-        done = max(done, arrival[r]) + seq_t[r]
-        seq_lat.append(done - arrival[r])
-    seq = {"pairs_per_s_burst": round(nreq / sum(seq_t), 3),
-           "pairs_per_s_trace": round(nreq / done, 3),
-           "latency_p50_s": round(float(np.percentile(seq_lat, 50)), 3),
-           "latency_p99_s": round(float(np.percentile(seq_lat, 99)), 3),
-           "solve_s_mean": round(float(np.mean(seq_t)), 4)}
+    def sequential(levels):
+        """Plain FP32 solves, first-come first-served on the trace."""
+        log(f"serving: {nreq} sequential FP32 solves, levels = {levels}")
+        seq_t, seq_D = [], {}
+        for r in range(nreq):
+            q = pairs[cls[r]]
+            t0 = time.perf_counter()
+            P = octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, dtype="f32", levels=levels)
+            D, _, _, _ = P.register()
+            torch.cuda.synchronize()
+            P.close()
+            seq_t.append(time.perf_counter() - t0)
+            if cls[r] not in seq_D:
+                seq_D[cls[r]] = D
+        done = 0.0
+        seq_lat = []
+        for r in range(nreq):
+            done = max(done, arrival[r]) + seq_t[r]
+            seq_lat.append(done - arrival[r])
+        return {"pairs_per_s_burst": round(nreq / sum(seq_t), 3),
+                "pairs_per_s_trace": round(nreq / done, 3),
+                "latency_p50_s": round(float(np.percentile(seq_lat, 50)), 3),
+                "latency_p99_s": round(float(np.percentile(seq_lat, 99)), 3),
+                "solve_s_mean": round(float(np.mean(seq_t)), 4)}, seq_D
 
-    torch.cuda.empty_cache()  # return the generator's cached blocks to the device
-    del_free, _ = torch.cuda.mem_get_info()
-    budget = int(min(budget_gib * (1 << 30), 0.6 * del_free))
-    log(f"serving: memory budget {budget / 2**30:.1f} GiB")
-
-    def served(mode, times):
+    def served(mode, times, levels, budget):
         srv = octmc.Server(budget, max_active=max_active, mode=mode)
         outs = {}
         t0 = time.perf_counter()
@@ -264,7 +262,8 @@ def serving(octmc, torch, nreq, budget_gib, max_active, log):
                 time.sleep(wait)
             q = pairs[cls[r]]
             disp = out_of(cls[r])
-            rid = srv.submit(q.sx, q.sy, disp, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, dtype="bf16", levels=4, tag=r)
+            rid = srv.submit(q.sx, q.sy, disp, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, dtype="bf16", levels=levels,
+                             tag=r)
             outs[rid] = (r, disp)
         comp = []
         while len(comp) < nreq:
@@ -281,30 +280,47 @@ def serving(octmc, torch, nreq, budget_gib, max_active, log):
                "max_reserved_GiB": round(max(c["bytes_reserved"] for c in comp) / (1 << 30), 3)}
         return res, {outs[c["id"]][0]: outs[c["id"]][1] for c in comp}
 
+    def accuracy(got, seq_D):
+        """Served BF16 against ground truth and against the FP32 solve of the same input."""
+        acc_gt_bf16, acc_gt_f32, acc_vs_f32 = [], [], []
+        for r, D in got.items():
+            c = cls[r]
+            gt = pairs[c].d_gt
+            acc_gt_bf16.append(_interior_rms(D, gt))
+            acc_gt_f32.append(_interior_rms(seq_D[c], gt))
+            acc_vs_f32.append(np.sqrt(((D - seq_D[c]).double().cpu().numpy() ** 2).reshape(-1, 3).mean(axis=0)))
+        med = lambda a: [round(float(x), 3) for x in np.median(np.array(a), axis=0)]
+        return {"served_bf16_vs_ground_truth": med(acc_gt_bf16),
+                "sequential_fp32_vs_ground_truth": med(acc_gt_f32),
+                "served_bf16_vs_sequential_fp32": med(acc_vs_f32)}
+
+    seq, seq_D = sequential(4)
+    torch.cuda.empty_cache()  # return the generator's cached blocks to the device
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(budget_gib * (1 << 30), 0.6 * free))
+    log(f"serving: memory budget {budget / 2**30:.1f} GiB")
     log("serving: Poisson trace, grouped launches")
-    poisson, got = served(octmc.SERVE_GROUPED, arrival)
+    poisson, got = served(octmc.SERVE_GROUPED, arrival, 4, budget)
     log("serving: burst, grouped launches")
-    burst, _ = served(octmc.SERVE_GROUPED, np.zeros(nreq))
+    burst, _ = served(octmc.SERVE_GROUPED, np.zeros(nreq), 4, budget)
     log("serving: burst, one stream per request")
-    burst_streams, _ = served(octmc.SERVE_STREAMS, np.zeros(nreq))
-    # accuracy: served BF16 against ground truth and against the FP32 solve of the same input
-    acc_gt_bf16, acc_gt_f32, acc_vs_f32 = [], [], []
-    for r, D in got.items():
-        c = cls[r]
-        gt = pairs[c].d_gt
-        acc_gt_bf16.append(_interior_rms(D, gt))
-        acc_gt_f32.append(_interior_rms(seq_D[c], gt))
-        acc_vs_f32.append(np.sqrt(((D - seq_D[c]).double().cpu().numpy() ** 2).reshape(-1, 3).mean(axis=0)))
-    med = lambda a: [round(float(x), 3) for x in np.median(np.array(a), axis=0)]
+    burst_streams, _ = served(octmc.SERVE_STREAMS, np.zeros(nreq), 4, budget)
+    acc = accuracy(got, seq_D)
+    del got, seq_D
+    seq0, seq_D0 = sequential(0)
+    log("serving: Poisson trace, grouped launches, levels = 0")
+    poisson0, got0 = served(octmc.SERVE_GROUPED, arrival, 0, budget)
+    auto = {"levels": "0 (automatic: 6 levels at 300-500 A-scans, 7 at 600)",
+            "served_poisson_grouped": poisson0, "sequential_fp32": seq0,
+            "accuracy_median_rms_px": accuracy(got0, seq_D0)}
     return {"requests": nreq, "size_classes": [f"{n}x{n}x{d}" for n, d in classes],
             "arrivals": "Poisson, mean inter-arrival 0.25 s", "max_active": max_active, "storage": "bf16",
             "budget_GiB": round(budget / 2**30, 2),
             "levels": 4, "iters_per_level": 100,
             "served_poisson_grouped": poisson, "served_burst_grouped": burst,
             "served_burst_streams": burst_streams, "sequential_fp32": seq,
-            "accuracy_median_rms_px": {"served_bf16_vs_ground_truth": med(acc_gt_bf16),
-                                       "sequential_fp32_vs_ground_truth": med(acc_gt_f32),
-                                       "served_bf16_vs_sequential_fp32": med(acc_vs_f32)}}
+            "accuracy_median_rms_px": acc,
+            "automatic_levels": auto}
 
 
 def enface_bench(octmc, torch, log, reps=20):
