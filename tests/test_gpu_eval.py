@@ -154,27 +154,64 @@ def test_eval_batched_matches_single(octmc):
 
 
 @pytest.mark.slow
-def test_eval_parity_full_size_sampled(octmc):
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_eval_parity_full_size_sampled(octmc, dtype):
     """500 x 500 A-scans x 800 samples, generated on the GPU, in the launch
-    configuration the benchmark times: the data gradient of 192 sampled
-    A-scans (incl. corners and edges) against the oracle."""
-    log("generate dense 500x500x800 on cuda")
+    configuration the benchmark times (BF16 storage: the two-sample kernel;
+    float32: the one-sample kernel): the data gradient of 192 sampled A-scans
+    (incl. corners and edges) against the oracle."""
+    log(f"generate dense 500x500x800 on cuda, storage {dtype}")
     pair = synth.make_pair("dense", device="cuda", octa_volumes=False)
-    P = _gpu_pair(octmc, pair, levels=4, alpha=0.0, mean_weight=0.0)
+    P = _gpu_pair(octmc, pair, dtype=dtype, levels=4, alpha=0.0, mean_weight=0.0)
     D = make_field(pair, "gt_noise", seed=7)
     Dg = D.float().cuda()
-    log("eval dense level 0")
+    log(f"eval dense level 0, storage {dtype}")
     terms, g = P.eval(0, Dg, eta_mode=1)  # stored eta = 1
     torch.cuda.synchronize()
     assert octmc.terms_dict(terms)["eta"] == 1.0
     n = 500
     rng = np.random.default_rng(0)
     sample = np.concatenate([[0, n - 1, n * (n - 1), n * n - 1, n * 250 + 250], rng.integers(0, n * n, 187)])
-    lv = oracle.Level(*(oracle._f64(t) for t in (pair.sx, pair.sy, pair.ax, pair.ay, pair.vx, pair.vy)))
+    sx, sy = round_storage(pair.sx, dtype), round_storage(pair.sy, dtype)
+    lv = oracle.Level(*(oracle._f64(t) for t in (sx, sy, pair.ax, pair.ay, pair.vx, pair.vy)))
+    del sx, sy
     _, gref = oracle.data_ascans(lv, Dg.double().cpu().numpy(), sample, _orc_params(P), 1.0)
     gg = g.double().cpu().numpy().reshape(2, -1, 3)
     got = np.concatenate([gg[0][sample], gg[1][sample]], axis=1)
     assert grad_rel(got, gref) < TOL
+
+
+@pytest.mark.slow
+def test_eval_transposed_problem_full_size(octmc):
+    """Transposing both scans (i <-> j), swapping the X-fast and Y-fast roles
+    and the x and y components maps the objective onto itself, the symmetry
+    the oracle is pinned to.  At the benchmark's size and storage (500 x 500
+    x 800, BF16) the whole objective (eta at the field, both data terms,
+    regulariser, mean term) and its gradient agree between the two problems;
+    the two runs read the volumes in different orders, so this checks the
+    X-fast and Y-fast paths of the kernels against each other at full size."""
+    log("generate dense 500x500x800 on cuda (with its transpose)")
+    pair = synth.make_pair("dense", device="cuda", octa_volumes=False)
+
+    def T(v):
+        return v.transpose(0, 1).contiguous()
+
+    def swap(D):  # fields of the transposed problem <-> fields of the original
+        return torch.stack([T(D[1])[..., [1, 0, 2]], T(D[0])[..., [1, 0, 2]]]).contiguous()
+
+    P = _gpu_pair(octmc, pair, dtype="bf16", levels=4)
+    Q = octmc.Pair(T(pair.sy), T(pair.sx), ax=T(pair.ay), ay=T(pair.ax), vx=pair.vy, vy=pair.vx, dtype="bf16",
+                   levels=4)
+    D = make_field(pair, "gt_noise", seed=11).float().cuda()
+    log("eval original and transposed problems, level 0, eta at the field")
+    t, g = P.eval(0, D, eta_mode=0)
+    tq, gq = Q.eval(0, swap(D), eta_mode=0)
+    torch.cuda.synchronize()
+    a, b = octmc.terms_dict(t), octmc.terms_dict(tq)
+    for k in ("eta", "F", "data", "str", "ang", "reg", "str05", "ang05"):
+        assert rel(b[k], a[k]) < 1e-5, (k, a[k], b[k])
+    assert abs(b["mean"] - a["mean"]) <= 1e-5 * max(abs(a["mean"]), 1e-6 * abs(a["F"])), (a["mean"], b["mean"])
+    assert grad_rel(swap(gq).double().cpu().numpy(), g.double().cpu().numpy()) < 1e-5
 
 
 @pytest.mark.slow
