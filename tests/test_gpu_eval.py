@@ -154,12 +154,12 @@ def test_eval_batched_matches_single(octmc):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_eval_parity_full_size_sampled(octmc, dtype):
     """500 x 500 A-scans x 800 samples, generated on the GPU, in the launch
-    configuration the benchmark times (BF16 storage: the two-sample kernel;
-    float32: the one-sample kernel): the data gradient of 192 sampled A-scans
-    (incl. corners and edges) against the oracle."""
+    configuration the benchmark times (BF16 and FP16 storage: the two-sample
+    kernel; float32: the one-sample kernel): the data gradient of 192 sampled
+    A-scans (incl. corners and edges) against the oracle."""
     log(f"generate dense 500x500x800 on cuda, storage {dtype}")
     pair = synth.make_pair("dense", device="cuda", octa_volumes=False)
     P = _gpu_pair(octmc, pair, dtype=dtype, levels=4, alpha=0.0, mean_weight=0.0)
