@@ -146,9 +146,10 @@ def cpu_baseline(pair, D, target_s=15.0):
     oracle.data_ascans(lv, Dn, sample, prm, 1.0)
     dt = time.perf_counter() - t0
     cores = oracle.set_threads(0)  # the threads its parallel loops used
+    what = (f"data term of all {na} A-scans" if nsample == na else
+            f"data term of {nsample} random A-scans, scaled by {na}/{nsample},")
     return {"value": (nsample / na) / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"data term of {nsample} random A-scans of the {w}x{h}x{d} pair ({dt:.1f} s), scaled by "
-                      f"{na}/{nsample}"}
+            "sample": f"{what} of the {w}x{h}x{d} pair ({dt:.1f} s)"}
 
 
 def cpu_baseline_small(torch):
