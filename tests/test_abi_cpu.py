@@ -151,9 +151,9 @@ def test_shape_limits(m):
 
 def test_readme_c_example_compiles_and_fails_cleanly(m, tmp_path):
     """The C example in README.md compiles against include/octmc.h, links
-    against liboctmc.so and, given inputs it cannot use (no GPU here; a
-    volume too small for its pyramid on a GPU), returns an error code with a
-    message instead of crashing."""
+    against liboctmc.so and, given inputs it cannot use (no GPU here; on a
+    GPU, the NULL output field), returns an error code with a message
+    instead of crashing."""
     text = open(os.path.join(ROOT, "README.md")).read()
     code = text.split("```c\n", 1)[1].split("```", 1)[0]
     main = """
@@ -169,7 +169,7 @@ int main(void)
     lib = os.path.dirname(m.LIB_PATH)
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe), "-L", lib, "-loctmc",
                     f"-Wl,-rpath,{lib}"], check=True)
-    # with a GPU the 8 x 8 x 16 volume is refused for its 4 levels (OCTMC_E_SHAPE): an error either way
+    # with a GPU, octmc_register refuses the NULL output field (OCTMC_E_INVALID): an error either way
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 3, (r.returncode, r.stdout, r.stderr)
     assert "octmc:" in r.stderr
