@@ -260,6 +260,7 @@ void worker_main(octmc_server* S, Worker* W)
     for (;;) {
         Job job;
         size_t off = 0;
+        double t_admit = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
@@ -270,13 +271,14 @@ void worker_main(octmc_server* S, Worker* W)
             job = S->queue.front();
             S->queue.pop_front();
             ++S->active;
+            t_admit = S->now();  // under the lock: admission times follow admission order
         }
         S->cv_admit.notify_all();  // the next request may fit as well
         octmc_completion c{};
         c.id = job.id;
         c.tag = job.req.tag;
         c.t_submit = job.t_submit;
-        c.t_admit = S->now();
+        c.t_admit = t_admit;
         c.bytes_reserved = job.footprint;
         run_job(S, W, job, off, c);
         c.t_done = S->now();
