@@ -446,6 +446,9 @@ typedef struct {
     uint64_t tag;
     int32_t status; /* octmc_status of the request's solve */
     int32_t reserved;
+    /* t_submit: queued; t_admit: taken from the queue with its memory
+     * reserved (admission times follow arrival order); t_done: solve and
+     * outputs complete, before the memory is released */
     double t_submit, t_admit, t_done;
     uint64_t bytes_reserved; /* footprint taken from the server's memory */
     uint64_t bytes_used;     /* of which the request actually used */
