@@ -23,9 +23,10 @@
  *
  * Readings of points the paper leaves open are stated where they are used.
  * Parity pins for every function live in tests/ (closed forms, invariants,
- * library routines and finite differences), except one: orc_tilt_term, the
- * stage-1 tilt normalisation T, whose formula the paper leaves to earlier
- * work that is not available -- parity unpinned.
+ * library routines and finite differences).  The stage-1 tilt normalisation
+ * T (orc_tilt_term) has no formula in the paper, which leaves it to earlier
+ * work; it is pinned to the properties its reading states (the energy of each
+ * scan's common slope, zero for zero-sum tilts, independent per scan).
  */
 #include <math.h>
 #include <stdint.h>
@@ -1226,12 +1227,14 @@ EXPORT void orc_enface_project(const double* oct, const double* octa, int w, int
  * f the index along the fast axis, n_f the B-scan length.
  *
  * T, the tilt normalisation (Eq. 1), is defined only in earlier work that is
- * not available; reading (parity unpinned): a quadratic penalty on the sum of
- * each scan's tilts, which fixes the two degrees of freedom the data term
+ * not available; reading: a quadratic penalty on the sum of each scan's
+ * tilts, which fixes the two degrees of freedom the data term
  * cannot see (a common plane a x + b y added to both scans' fields), as M
  * fixes the translations:
  *   T = sum_V gamma_t d n_f (n_f^2 - 1) / (24 n_b) (sum_b t_b)^2,
- * scaled so that a uniform tilt tau costs gamma_t d N_A var_f tau^2 / 2. */
+ * i.e. gamma_t d / 2 times the squared norm of the common slope of each
+ * scan's field along its fast axis, so that a uniform tilt tau costs
+ * gamma_t d N_A var_f tau^2 / 2. */
 static void tilt_dims(int V, int w, int h, int* nb, int* nf, int* off)
 {
     *nb = V == 0 ? h : w;

@@ -818,6 +818,91 @@ def test_prealign_gradient_matches_finite_differences(orc):
         assert abs(fd - g[q]) <= 1e-5 * max(1.0, abs(g[q])), (q, fd, g[q])
 
 
+def _slope_projection_energy(D, V):
+    """Squared norm of the part of scan V's axial field that is one common
+    slope along the scan's fast axis (x for X-fast, y for Y-fast): the least
+    squares fit of dz = tau (f - c) + (one offset per B-scan), by numpy's
+    lstsq on the explicit design matrix."""
+    dz = D[V, :, :, 2]
+    h, w = dz.shape
+    lines = dz if V == 0 else dz.T  # one B-scan per row, fast axis along it
+    nb, nf = lines.shape
+    rows, cols = np.meshgrid(np.arange(nb), np.arange(nf), indexing="ij")
+    A = np.zeros((nb * nf, nb + 1))
+    A[np.arange(nb * nf), rows.ravel()] = 1.0                # per-B-scan offsets
+    A[:, nb] = cols.ravel() - cols.mean()                    # the common slope
+    coef, *_ = np.linalg.lstsq(A, lines.ravel(), rcond=None)
+    tau = coef[nb]
+    return float(((tau * A[:, nb]) ** 2).sum())
+
+
+def test_tilt_term_is_the_common_slope_energy(orc):
+    """T is the tilt normalisation of Eq. 1 (its formula is in earlier work
+    that is not available).  Its reading states three properties, each
+    checked here without the oracle's own expression: T is gamma_t d / 2
+    times the squared norm of each scan's common slope along its fast axis
+    (least squares over the expanded field, so a wrong constant, a missing
+    n_f or a sum of squared tilts instead of the squared sum fails);
+    tilt patterns whose sum is zero cost nothing; the two scans add
+    independently; and the quadratic form satisfies theta . grad T = 2 T."""
+    for (h, w, d, g) in ((7, 9, 13, 1.0), (12, 5, 40, 0.35), (6, 6, 1, 2.0)):
+        th = RNG.standard_normal(2 * (w + h))
+        D = orc.tilt_expand(th, w, h)
+        T, gT = orc.tilt_term(th, w, h, d, g)
+        E = _slope_projection_energy(D, 0) + _slope_projection_energy(D, 1)
+        assert math.isclose(T, 0.5 * g * d * E, rel_tol=1e-10), (h, w, T, 0.5 * g * d * E)
+        # Euler's identity for a homogeneous quadratic
+        assert math.isclose(float(th @ gT), 2.0 * T, rel_tol=1e-12)
+        # the offsets z_b do not enter
+        assert not gT[0::2].any()
+        # the scans add independently
+        thX, thY = th.copy(), th.copy()
+        thX[2 * h:] = 0.0
+        thY[:2 * h] = 0.0
+        TX, _ = orc.tilt_term(thX, w, h, d, g)
+        TY, _ = orc.tilt_term(thY, w, h, d, g)
+        assert math.isclose(T, TX + TY, rel_tol=1e-13)
+        # zero-sum tilt patterns (per scan) cost nothing, whatever the offsets
+        tz = th.copy()
+        tz[1:2 * h:2] -= tz[1:2 * h:2].mean()
+        tz[2 * h + 1::2] -= tz[2 * h + 1::2].mean()
+        T0, g0 = orc.tilt_term(tz, w, h, d, g)
+        assert abs(T0) < 1e-24 * max(1.0, T) + 1e-28 and np.abs(g0).max() < 1e-12
+        # a uniform tilt tau on one scan costs gamma_t d N_A var_f tau^2 / 2,
+        # var_f the population variance of the fast-axis index
+        tau = 0.37
+        tu = np.zeros_like(th)
+        tu[1:2 * h:2] = tau
+        Tu, _ = orc.tilt_term(tu, w, h, d, g)
+        assert math.isclose(Tu, 0.5 * g * d * (w * h) * np.var(np.arange(w)) * tau ** 2, rel_tol=1e-13)
+
+
+def test_tilt_term_fixes_the_common_plane(orc):
+    """The data term cannot see a plane a x + b y added to both scans'
+    axial fields (pinned below); T is what fixes those two degrees of
+    freedom: such a plane, written in each scan's B-scan parameters, costs
+    gamma_t d / 2 times the plane's squared norm over both fields, and
+    nothing only for a = b = 0."""
+    h, w, d = 8, 11, 20
+    a, b = 0.04, -0.025
+    th = np.zeros(2 * (w + h))
+    # X-fast B-scan j (fast axis x): z = a (w - 1) / 2 + b j, t = a
+    th[0:2 * h:2] = a * (w - 1) / 2 + b * np.arange(h)
+    th[1:2 * h:2] = a
+    # Y-fast B-scan i (fast axis y): z = b (h - 1) / 2 + a i, t = b
+    th[2 * h::2] = b * (h - 1) / 2 + a * np.arange(w)
+    th[2 * h + 1::2] = b
+    D = orc.tilt_expand(th, w, h)
+    plane = a * np.arange(w)[None, :] + b * np.arange(h)[:, None]
+    assert np.allclose(D[0, :, :, 2], plane, atol=1e-14) and np.allclose(D[1, :, :, 2], plane, atol=1e-14)
+    T, _ = orc.tilt_term(th, w, h, d, 1.0)
+    # the plane's part along x in the X-fast field and along y in the Y-fast one
+    ex = ((a * (np.arange(w) - (w - 1) / 2)) ** 2).sum() * h
+    ey = ((b * (np.arange(h) - (h - 1) / 2)) ** 2).sum() * w
+    assert math.isclose(T, 0.5 * d * (ex + ey), rel_tol=1e-12)
+    assert orc.tilt_term(np.zeros_like(th), w, h, d, 1.0)[0] == 0.0
+
+
 def test_data_term_blind_to_a_common_plane(orc):
     """The two degrees of freedom T fixes: a plane a x + b y added to both
     scans' axial fields leaves the data term unchanged (interior voxels; the
