@@ -92,6 +92,8 @@ def lib():
         L.orc_eta_from_terms.argtypes = [C.c_double, C.c_double]
         L.orc_eta_from_terms.restype = C.c_double
         L.orc_pyr_down3.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
+        L.orc_pyr_down3_f32.argtypes = [dp, C.c_int, C.c_int, C.c_int, dp]
+        L.orc_pyr_down3_f32.restype = None
         L.orc_pyr_down2.argtypes = [dp, C.c_int, C.c_int, dp]
         L.orc_pyr_down1.argtypes = [dp, C.c_int, dp]
         L.orc_upsample.argtypes = [dp, C.c_int, C.c_int, dp, C.c_int, C.c_int]
@@ -143,6 +145,8 @@ def lib():
         L.orc_merge_multi.restype = None
         L.orc_validity.argtypes = [dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.orc_validity.restype = None
+        L.orc_set_progress.argtypes = [C.c_int]
+        L.orc_set_progress.restype = None
         L.orc_round_storage.argtypes = [dp, C.c_size_t, C.c_int]
         L.orc_round_storage.restype = None
         _lib = L
@@ -153,6 +157,12 @@ def _f64(a) -> np.ndarray:
     if hasattr(a, "detach"):
         a = a.detach().cpu().numpy()
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def set_progress(every: int) -> None:
+    """Print the L-BFGS step count and objective to stderr every `every`
+    accepted steps of any oracle solve (0: off).  Printing only."""
+    lib().orc_set_progress(int(every))
 
 
 def set_threads(n: int) -> int:
@@ -287,6 +297,16 @@ def pyr_down3(vol):
     return out
 
 
+def pyr_down3_f32(vol):
+    """The 2 x 2 x 2 box of pyr_down3 in single precision (depth, then x,
+    then y), for pyramids rounded to a 16-bit storage type."""
+    vol = _f64(vol)
+    h, w, d = vol.shape
+    out = np.zeros(((h + 1) // 2, (w + 1) // 2, (d + 1) // 2))
+    lib().orc_pyr_down3_f32(_p(vol), w, h, d, _p(out))
+    return out
+
+
 def pyr_down2(img):
     img = _f64(img)
     h, w = img.shape
@@ -302,12 +322,19 @@ def pyr_down1(v):
     return out
 
 
-def pyramid(lv: Level, levels: int):
+def pyramid(lv: Level, levels: int, store: int = 0):
+    """Pyramid levels of a pair.  store = 1 (bfloat16) or 2 (binary16): the
+    structural levels are built in single precision from the unrounded level
+    above and each is then rounded to the storage type, as a solve with that
+    storage sees them (level 0 included)."""
+    down = pyr_down3_f32 if store else pyr_down3
     out = [lv]
     for _ in range(1, levels):
         p = out[-1]
-        out.append(Level(pyr_down3(p.sx), pyr_down3(p.sy), pyr_down2(p.ax), pyr_down2(p.ay),
+        out.append(Level(down(p.sx), down(p.sy), pyr_down2(p.ax), pyr_down2(p.ay),
                          pyr_down1(p.vx), pyr_down1(p.vy)))
+    if store:
+        out = [Level(round_storage(q.sx, store), round_storage(q.sy, store), q.ax, q.ay, q.vx, q.vy) for q in out]
     return out
 
 

@@ -30,6 +30,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -68,7 +69,10 @@ EXPORT int orc_set_threads(int n)
  *   store        storage type of the structural volumes in the solve: 0 =
  *                exact, 1 = bfloat16, 2 = IEEE binary16; every pyramid level
  *                is built from the unrounded level above it and then rounded
- *                to nearest, ties to even (see orc_round_storage) */
+ *                to nearest, ties to even (see orc_round_storage); the
+ *                levels that are rounded are built in single precision
+ *                (orc_pyr_down3_f32), the precision of the device pyramid,
+ *                so that both sides take the same rounding decisions */
 typedef struct {
     double alpha, delta0, eps_h, eps_r, flyback_frac, mean_weight;
     int levels, iters, lbfgs_m, ls_max_evals;
@@ -445,6 +449,35 @@ EXPORT void orc_pyr_down3(const double* in, int w, int h, int d, double* out)
             }
 }
 
+/* The same 2 x 2 x 2 box in single precision, for pyramids whose levels are
+ * then rounded to a 16-bit storage type.  Rounding to the storage type
+ * decides a quantised value, so it is taken from a level computed in the
+ * precision the pyramid is built in on the device (single), from the
+ * single-precision level above; the box is separable, summed along depth,
+ * then x, then y, and scaled by 1/8 (exact).  `in` holds single-precision
+ * values (the input volume, or a level this function wrote). */
+EXPORT void orc_pyr_down3_f32(const double* in, int w, int h, int d, double* out)
+{
+    int w2 = (w + 1) / 2, h2 = (h + 1) / 2, d2 = (d + 1) / 2;
+    for (int J = 0; J < h2; J++)
+        for (int I = 0; I < w2; I++)
+            for (int K = 0; K < d2; K++) {
+                float sy[2];
+                for (int b = 0; b < 2; b++) {
+                    float sxz[2];
+                    for (int a = 0; a < 2; a++) {
+                        int y = clampi(2 * J + b, 0, h - 1);
+                        int x = clampi(2 * I + a, 0, w - 1);
+                        const double* col = in + ((size_t)y * w + x) * d;
+                        sxz[a] = (float)col[clampi(2 * K, 0, d - 1)] + (float)col[clampi(2 * K + 1, 0, d - 1)];
+                    }
+                    sy[b] = sxz[0] + sxz[1];
+                }
+                const float s = sy[0] + sy[1];
+                out[((size_t)J * w2 + I) * d2 + K] = (double)(0.125f * s);
+            }
+}
+
 EXPORT void orc_pyr_down2(const double* in, int w, int h, double* out)
 {
     int w2 = (w + 1) / 2, h2 = (h + 1) / 2;
@@ -611,6 +644,12 @@ static int line_search(ls_state* st, double f0, double g0, double c1, double c2,
     }
 }
 
+/* Progress of long solves: every `every` accepted steps (0: never) orc_lbfgs
+ * prints the step count, the evaluations and the objective to stderr.
+ * Printing only; the arithmetic does not depend on it. */
+static int g_progress_every = 0;
+EXPORT void orc_set_progress(int every) { g_progress_every = every > 0 ? every : 0; }
+
 EXPORT int orc_lbfgs(int n, double* x, orc_fg_fn fg, void* ctx, int m, int max_iter,
                      int ls_max_evals, double c1, double c2, orc_lbfgs_report* rep)
 {
@@ -703,6 +742,10 @@ EXPORT int orc_lbfgs(int n, double* x, orc_fg_fn fg, void* ctx, int m, int max_i
         memcpy(g, gt, n * sizeof(double));
         f = fn;
         it++;
+        if (g_progress_every && it % g_progress_every == 0) {
+            fprintf(stderr, "[oracle] lbfgs n=%d step %d evals %d f=%.10g\n", n, it, rep->evals, f);
+            fflush(stderr);
+        }
     }
     rep->iters = it;
     rep->f_end = f;
@@ -741,6 +784,16 @@ EXPORT void orc_round_storage(double* v, size_t n, int store)
     } else if (store == 2) {
         for (size_t i = 0; i < n; i++) v[i] = round_format(v[i], 11, -14, 65504.0);
     }
+}
+
+/* The pyramid filter of a solve: exact for float storage, single precision
+ * (orc_pyr_down3_f32) when the levels are rounded to a 16-bit type. */
+static void pyr_down3_for(int store, const double* in, int w, int h, int d, double* out)
+{
+    if (store)
+        orc_pyr_down3_f32(in, w, h, d, out);
+    else
+        orc_pyr_down3(in, w, h, d, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -788,8 +841,8 @@ EXPORT int orc_register(const double* sx, const double* sy, const double* ax, co
         AY[l] = (double*)malloc(ni * sizeof(double));
         VX[l] = (double*)malloc(H[l] * sizeof(double));
         VY[l] = (double*)malloc(W[l] * sizeof(double));
-        orc_pyr_down3(SX[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SX[l]);
-        orc_pyr_down3(SY[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SY[l]);
+        pyr_down3_for(p->store, SX[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SX[l]);
+        pyr_down3_for(p->store, SY[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SY[l]);
         orc_pyr_down2(AX[l - 1], W[l - 1], H[l - 1], AX[l]);
         orc_pyr_down2(AY[l - 1], W[l - 1], H[l - 1], AY[l]);
         orc_pyr_down1(VX[l - 1], H[l - 1], VX[l]);
@@ -1377,8 +1430,8 @@ EXPORT int orc_prealign(const double* sx, const double* sy, int w, int h, int d,
         const size_t nv = (size_t)W[l] * H[l] * Dd[l];
         SX[l] = (double*)malloc(nv * sizeof(double));
         SY[l] = (double*)malloc(nv * sizeof(double));
-        orc_pyr_down3(SX[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SX[l]);
-        orc_pyr_down3(SY[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SY[l]);
+        pyr_down3_for(p->store, SX[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SX[l]);
+        pyr_down3_for(p->store, SY[l - 1], W[l - 1], H[l - 1], Dd[l - 1], SY[l]);
     }
     double *sx0 = NULL, *sy0 = NULL;
     if (p->store) {
@@ -1699,7 +1752,7 @@ EXPORT int orc_register_multi(int n, const double* const* S, const double* const
             PA[l][V] = (double*)malloc((size_t)W[l] * H[l] * sizeof(double));
             const int nb = orient[V] == 0 ? H[l] : W[l];
             PV[l][V] = (double*)malloc((size_t)nb * sizeof(double));
-            orc_pyr_down3(PS[l - 1][V], W[l - 1], H[l - 1], Dd[l - 1], PS[l][V]);
+            pyr_down3_for(p->store, PS[l - 1][V], W[l - 1], H[l - 1], Dd[l - 1], PS[l][V]);
             orc_pyr_down2(PA[l - 1][V], W[l - 1], H[l - 1], PA[l][V]);
             orc_pyr_down1(PV[l - 1][V], orient[V] == 0 ? H[l - 1] : W[l - 1], PV[l][V]);
         }

@@ -407,6 +407,32 @@ def test_pyramid_closed_forms(orc):
     assert orc.pyr_down3(b).mean() == pytest.approx(b.mean(), abs=1e-14)
 
 
+def test_pyramid_single_precision_for_rounded_storage(orc):
+    """The single-precision box of 16-bit storage pyramids: exact where every
+    partial sum is representable (dyadic inputs), within the error bound of
+    three levels of float32 additions (3 u times the mean of |x|, u = 2^-24)
+    of the pinned float64 box elsewhere, ragged sizes included; and a rounded
+    pyramid's levels are the storage rounding of those single-precision
+    levels (level 0 the rounded input)."""
+    rng = np.random.default_rng(5)
+    dy = rng.integers(-64, 64, size=(5, 7, 9)) / 8.0
+    np.testing.assert_array_equal(orc.pyr_down3_f32(dy), orc.pyr_down3(dy))
+    for shape in ((6, 8, 10), (5, 7, 9), (1, 3, 2)):
+        v = rng.random(shape).astype(np.float32).astype(np.float64) * 3.0
+        v = v.astype(np.float32).astype(np.float64)
+        a, b = orc.pyr_down3_f32(v), orc.pyr_down3(v)
+        assert np.all(a.astype(np.float32).astype(np.float64) == a)  # single-precision values
+        # the mean of |x| over each block bounds the block's |values|
+        bound = 3 * 2.0 ** -24 * orc.pyr_down3(np.abs(v)) * (1 + 1e-12)
+        assert np.all(np.abs(a - b) <= bound + 2.0 ** -24 * np.abs(b))
+    lv = orc.level_from(rng.random((6, 6, 8)).astype(np.float32), rng.random((6, 6, 8)).astype(np.float32),
+                        np.zeros((6, 6)), np.zeros((6, 6)))
+    pr = orc.pyramid(lv, 3, store=1)
+    assert np.array_equal(pr[0].sx, orc.round_storage(lv.sx, 1))
+    np.testing.assert_array_equal(pr[1].sy, orc.round_storage(orc.pyr_down3_f32(lv.sy), 1))
+    np.testing.assert_array_equal(pr[2].sx, orc.round_storage(orc.pyr_down3_f32(orc.pyr_down3_f32(lv.sx)), 1))
+
+
 def test_upsample_closed_forms(orc):
     c = np.broadcast_to(np.array([0.5, -0.25, 1.5]), (2, 4, 5, 3)).copy()
     np.testing.assert_allclose(orc.upsample(c, 10, 8), np.broadcast_to(2 * c[0, 0, 0], (2, 8, 10, 3)))
