@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import grad_rel, log, make_field, rel
+from gpu_util import grad_err, grad_rel, log, make_field, rel
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -41,7 +41,7 @@ def _check_against_oracle(octmc, pairs, Ps, level, D, F, grad, tag):
         eta = octmc.terms_dict(P.eval(level, D[b].detach().contiguous(), grad=False)[0])["eta"]
         ref, gref = oracle.evaluate(lv, D[b].detach().double().cpu().numpy(), _orc_params(P), eta)
         assert rel(F[b].item(), ref["F"]) < TOL, (tag, b, F[b].item(), ref["F"])
-        e = grad_rel(grad[b].double().cpu().numpy(), gref)
+        e = grad_err(grad[b].double().cpu().numpy(), gref)
         assert e < TOL, (tag, b, e)
 
 

@@ -1,8 +1,11 @@
 """GPU parity of the hot path (one objective + gradient evaluation) against
 the FP64 oracle, through the C ABI.
 
-Tolerance: 1e-4 relative on the objective terms and 1e-4 relative (norm-wise)
-on the gradient, FP32 kernels against the FP64 oracle.
+Tolerance: 1e-4 relative on the objective terms, and on the gradient 1e-4
+both norm-wise and element-wise (|g - g_ref| <= 1e-4 (|g_ref| + 0.1
+max |g_ref|), the floor set by the float32 rounding of the residual that the
+pseudo-Huber kink magnifies; see gpu_util.ELEM_FLOOR), float32 kernels
+against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -10,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import grad_rel, log, make_field, rel, round_storage
+from gpu_util import grad_err, grad_rel, log, make_field, rel, round_storage
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -49,7 +52,7 @@ def _compare(octmc, P, lv, level, D, tag, tol=TOL, eta_mode=0):
     for k in ("F", "data", "str", "ang", "reg", "str05", "ang05"):
         assert rel(t[k], ref[k]) < tol or abs(t[k] - ref[k]) < 1e-9 * max(1.0, abs(ref["F"])), (tag, k, t[k], ref[k])
     assert abs(t["mean"] - ref["mean"]) <= tol * max(abs(ref["mean"]), 1e-6 * abs(ref["F"])), (tag, t["mean"], ref["mean"])
-    e = grad_rel(g.double().cpu().numpy(), gref)
+    e = grad_err(g.double().cpu().numpy(), gref)
     assert e < tol, (tag, e)
     return t, g
 
@@ -82,17 +85,16 @@ def test_eval_parity_odd_depth(octmc, dtype):
     kernel (16-bit storage); random fields give both parities of the first
     depth tap in both scans."""
     pair = synth.make_pair("tiny", n=36, d=151)
-    # the library builds every level from the exact level above and stores it rounded
-    pyr = oracle.pyramid(oracle.level_from_pair(pair), 2)
-    if dtype != "f32":
-        pyr = [oracle.Level(oracle.round_storage(lv.sx, 1), oracle.round_storage(lv.sy, 1), lv.ax, lv.ay, lv.vx,
-                            lv.vy) for lv in pyr]
+    # the library builds every level in float32 from the unrounded level above
+    # and stores it rounded; the oracle's rounded pyramid takes the same
+    # rounding decisions (oracle.pyramid with store = 1)
+    pyr = oracle.pyramid(oracle.level_from_pair(pair), 2, store=0 if dtype == "f32" else 1)
     P = _gpu_pair(octmc, pair, dtype=dtype, levels=2)
     for level in range(2):
         w, h, d = P.level_shape(level)
         for case, seed in (("uniform", 1), ("smooth", 2)):
             D = synth.random_field(w, h, 3.0, seed) if case == "uniform" else synth.smooth_random_field(w, h, 2.5, seed)
-            _compare(octmc, P, pyr[level], level, D, f"odd/{dtype}/{level}/{case}", tol=TOL if dtype == "f32" else 2e-4)
+            _compare(octmc, P, pyr[level], level, D, f"odd/{dtype}/{level}/{case}")
 
 
 def test_eval_parity_validity_and_white_lines(octmc):
@@ -154,31 +156,23 @@ def test_eval_batched_matches_single(octmc):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
-def test_eval_parity_full_size_sampled(octmc, dtype):
-    """500 x 500 A-scans x 800 samples, generated on the GPU, in the launch
-    configuration the benchmark times (BF16 and FP16 storage: the two-sample
-    kernel; float32: the one-sample kernel): the data gradient of 192 sampled
-    A-scans (incl. corners and edges) against the oracle."""
-    log(f"generate dense 500x500x800 on cuda, storage {dtype}")
-    pair = synth.make_pair("dense", device="cuda", octa_volumes=False)
-    P = _gpu_pair(octmc, pair, dtype=dtype, levels=4, alpha=0.0, mean_weight=0.0)
-    D = make_field(pair, "gt_noise", seed=7)
-    Dg = D.float().cuda()
-    log(f"eval dense level 0, storage {dtype}")
-    terms, g = P.eval(0, Dg, eta_mode=1)  # stored eta = 1
-    torch.cuda.synchronize()
-    assert octmc.terms_dict(terms)["eta"] == 1.0
-    n = 500
-    rng = np.random.default_rng(0)
-    sample = np.concatenate([[0, n - 1, n * (n - 1), n * n - 1, n * 250 + 250], rng.integers(0, n * n, 187)])
+@pytest.mark.parametrize("workload,dtype", [("clinical", "f32"), ("dense", "bf16"), ("dense", "f16"),
+                                            ("dense", "f32")])
+def test_eval_parity_full_size_whole_objective(octmc, workload, dtype):
+    """The clinical (300 x 300 x 640, float32) and the dense (500 x 500 x 800,
+    BF16, FP16 and float32 storage) pairs, generated on the GPU, in the launch
+    configuration the benchmark times, with the default alpha and mean term and
+    eta computed at the field (Eq. 10): F, every term (both data terms, the
+    regulariser, the mean term, eta) and every gradient entry of all A-scans
+    against the oracle (Eqs. 1-10)."""
+    log(f"generate {workload} on cuda, storage {dtype}")
+    pair = synth.make_pair(workload, device="cuda", octa_volumes=False)
+    P = _gpu_pair(octmc, pair, dtype=dtype, levels=4)
     sx, sy = round_storage(pair.sx, dtype), round_storage(pair.sy, dtype)
     lv = oracle.Level(*(oracle._f64(t) for t in (sx, sy, pair.ax, pair.ay, pair.vx, pair.vy)))
     del sx, sy
-    _, gref = oracle.data_ascans(lv, Dg.double().cpu().numpy(), sample, _orc_params(P), 1.0)
-    gg = g.double().cpu().numpy().reshape(2, -1, 3)
-    got = np.concatenate([gg[0][sample], gg[1][sample]], axis=1)
-    assert grad_rel(got, gref) < TOL
+    _compare(octmc, P, lv, 0, make_field(pair, "gt_noise", seed=7), f"{workload}/{dtype}/whole objective")
+    P.close()
 
 
 @pytest.mark.slow
@@ -241,7 +235,7 @@ def test_eval_parity_max_size_sampled(octmc, dtype):
     _, gref = oracle.data_ascans(lv, Dg.double().cpu().numpy(), sample, _orc_params(P), 1.0)
     gg = g.double().cpu().numpy().reshape(2, -1, 3)
     got = np.concatenate([gg[0][sample], gg[1][sample]], axis=1)
-    assert grad_rel(got, gref) < TOL
+    assert grad_err(got, gref) < TOL
 
 
 def test_check_nan_rejects_non_finite_volumes(octmc):

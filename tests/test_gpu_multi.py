@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import grad_rel, log, rel
+from gpu_util import grad_err, grad_rel, log, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -78,7 +78,7 @@ def test_multi_objective_parity(octmc, scans, level):
     td = octmc.terms_dict(t)
     for key in ("F", "data", "str", "ang", "reg", "mean"):
         assert rel(td[key], ref[key]) < 1e-4, (key, td[key], ref[key])
-    assert grad_rel(g.double().cpu().numpy(), gref) < 1e-4
+    assert grad_err(g.double().cpu().numpy(), gref) < 1e-4
 
 
 def test_multi_register_parity(octmc, scans):
@@ -141,12 +141,15 @@ _STORE = {"f32": 0, "bf16": 1, "f16": 2}
 
 def _oracle_level_inputs(sc, level, idx, store=0):
     """The oracle's volumes, en face images and validity at `level`: the exact
-    pyramid, each structural level rounded to the storage type as stored."""
+    pyramid, each structural level rounded to the storage type as stored
+    (16-bit storage: levels built in single precision, as the device builds
+    them, so both sides take the same rounding decisions)."""
     S = [sc.S[q].double().numpy() for q in idx]
     A = [sc.A[q].double().numpy() for q in idx]
     V = [sc.V[q].double().numpy() for q in idx]
+    down = oracle.pyr_down3_f32 if store else oracle.pyr_down3
     for _ in range(level):
-        S = [oracle.pyr_down3(s) for s in S]
+        S = [down(s) for s in S]
         A = [oracle.pyr_down2(a) for a in A]
         V = [oracle.pyr_down1(v) for v in V]
     if store:
@@ -186,7 +189,7 @@ def test_multi_fused_objective_parity(octmc, scans, dtype, level, nvol, sigma):
     for key in ("F", "data", "str", "ang", "reg", "mean"):
         assert rel(td[key], ref[key]) < 1e-4, (key, td[key], ref[key])
         assert rel(td[key], tpd[key]) < 1e-5 or abs(td[key] - tpd[key]) < 1e-9, (key, td[key], tpd[key])
-    assert grad_rel(g.double().cpu().numpy(), gref) < 1e-4
+    assert grad_err(g.double().cpu().numpy(), gref) < 1e-4
     assert grad_rel(g.double().cpu().numpy(), gp.double().cpu().numpy()) < 1e-5
 
 
@@ -209,7 +212,7 @@ def test_multi_odd_depth_level(octmc, dtype):
     td = octmc.terms_dict(t)
     for key in ("F", "data", "str", "reg"):
         assert rel(td[key], ref[key]) < 1e-4, (key, td[key], ref[key])
-    assert grad_rel(g.double().cpu().numpy(), gref) < 1e-4
+    assert grad_err(g.double().cpu().numpy(), gref) < 1e-4
 
 
 def test_multi_fused_register_parity(octmc, scans):

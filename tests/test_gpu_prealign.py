@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import grad_rel, log, rel
+from gpu_util import grad_err, grad_rel, log, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def test_prealign_objective_and_gradient_parity(octmc, planted, level):
         assert rel(t["F"] + T, ref["F1"]) < 1e-4, (t, T, ref)
         assert rel(T, ref["T"]) < 1e-12 or abs(T - ref["T"]) < 1e-12
         assert rel(t["reg"], ref["reg"]) < 1e-4 and t["ang"] == 0.0
-        assert grad_rel(g, gref) < 1e-4
+        assert grad_err(g, gref) < 1e-4
 
 
 def test_prealign_solve_parity_and_recovery(octmc, planted):
@@ -124,6 +124,11 @@ def test_pair_created_with_prealignment(octmc, planted):
     torch.cuda.synchronize()
     td = octmc.terms_dict(t)
     ref, gref = oracle.evaluate(lv, np.zeros((2, h, w, 3)), oracle.Params(), td["eta"])
+    # norm-wise: the two sides evaluate different volumes here (the pair's are
+    # resampled in float32, up to 2e-6 from the oracle's float64 resampling),
+    # and at D = 0 after prealignment many residuals sit at the pseudo-Huber
+    # kink, which magnifies such input differences entry by entry; the
+    # evaluation itself is checked entry by entry on identical inputs above
     assert rel(td["F"], ref["F"]) < 1e-4 and grad_rel(g.double().cpu().numpy(), gref) < 1e-4
     # after prealignment the residual axial misalignment is small
     res = (D[0, ..., 2] - D[1, ..., 2]) - (mY - mX)
@@ -146,7 +151,7 @@ def test_prealign_objective_parity_clinical_size(octmc):
     ref, gref = oracle.prealign_eval(pair.sx.cpu().numpy(), pair.sy.cpu().numpy(), th, oracle.Params(delta0=0.0),
                                      1.0)
     assert rel(t["F"] + T, ref["F1"]) < 1e-4
-    assert grad_rel(g, gref) < 1e-4
+    assert grad_err(g, gref) < 1e-4
 
 
 def test_full_pipeline_flags_equal_the_chained_entry_points(octmc):
