@@ -93,7 +93,7 @@ typedef struct {
     double flyback_frac; /* flyback per B-scan, fraction of the B-scan length     [R: 0.25] */
     double mean_weight;  /* gamma_M of the mean-displacement term M               [R: 1.0]  */
     int32_t levels;      /* pyramid levels (factor 2, Sec. 2.1), 1..8; 0: automatic, the fewest
-                            levels whose coarsest level is at most 16 A-scans wide [3]       */
+                            levels whose coarsest level is at most 16 A-scans wide [0]       */
     int32_t iters_per_level; /* accepted L-BFGS steps per level                   [100]     */
     int32_t lbfgs_m;     /* L-BFGS memory (1..8)                                  [R: 5]    */
     int32_t ls_max_evals;/* evaluations per line search                           [R: 20]   */

@@ -1238,39 +1238,48 @@ hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, bool AXIAL>
+static hipError_t launch_struct_subsets(const StructJobs& jobs, hipStream_t s)
+{
+    // 16-bit storage: two samples per lane for the jobs whose depth is even;
+    // an odd depth keeps one sample per lane (the last pair of an A-scan
+    // would start at an odd sample, not 32-bit aligned).  The kernel is chosen
+    // per job, so a job's result does not depend on the other jobs of its
+    // launch; each subset has its own grid (a multiple of the 8 XCDs).
+    StructJobs even{}, odd{};
+    int be = 0, bo = 0;
+    for (int q = 0; q < jobs.n; ++q) {
+        StructJob J = jobs.j[q];
+        const int nb = struct_blocks(J.w, J.h);
+        if (J.d % 2 == 0) {
+            J.blk_begin = be;
+            be += nb;
+            even.j[even.n++] = J;
+        } else {
+            J.blk_begin = bo;
+            bo += nb;
+            odd.j[odd.n++] = J;
+        }
+    }
+    if (even.n) hipLaunchKernelGGL((k_struct2<T, AXIAL>), dim3((be + 7) / 8 * 8), dim3(256), 0, s, even);
+    if (odd.n) hipLaunchKernelGGL((k_struct<T, AXIAL>), dim3((bo + 7) / 8 * 8), dim3(256), 0, s, odd);
+    return hipGetLastError();
+}
+
 template <bool AXIAL>
 static hipError_t launch_struct_t(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s)
 {
-    // 16-bit storage: two samples per lane, unless a depth is odd (the last
-    // pair of an A-scan would then start at an odd sample, not 32-bit aligned)
-    bool pairs = dt != OCTMC_F32;
-    for (int q = 0; q < jobs.n; ++q) pairs &= (jobs.j[q].d % 2) == 0;
-    if (pairs) {
-        switch (dt) {
-        case OCTMC_BF16:
-            hipLaunchKernelGGL((k_struct2<bf16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
-            return hipGetLastError();
-        case OCTMC_F16:
-            hipLaunchKernelGGL((k_struct2<f16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
-            return hipGetLastError();
-        default:
-            return hipErrorInvalidValue;
-        }
-    }
     switch (dt) {
     case OCTMC_F32:
         hipLaunchKernelGGL((k_struct<float, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
-        break;
+        return hipGetLastError();
     case OCTMC_BF16:
-        hipLaunchKernelGGL((k_struct<bf16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
-        break;
+        return launch_struct_subsets<bf16_t, AXIAL>(jobs, s);
     case OCTMC_F16:
-        hipLaunchKernelGGL((k_struct<f16_t, AXIAL>), dim3(total_blocks), dim3(256), 0, s, jobs);
-        break;
+        return launch_struct_subsets<f16_t, AXIAL>(jobs, s);
     default:
         return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype dt, hipStream_t s, bool axial)
@@ -1299,7 +1308,7 @@ static hipError_t launch_struct_multi_n(const void* const* vol, const float* dis
     J.na = w * h;
     J.vol_bytes = vol_bytes;
     J.eps_h = eps_h;
-    const int blocks = (8 * (((h + 1) / 2 + 7) / 8) * ((w + 1) / 2) + 7) / 8 * 8;  // a multiple of the 8 XCDs
+    const int blocks = (struct_blocks(w, h) + 7) / 8 * 8;  // a multiple of the 8 XCDs
     if (dt == OCTMC_F32)
         hipLaunchKernelGGL((k_struct_multi1<N>), dim3(blocks), dim3(256), 0, s, J);
     else if (dt == OCTMC_BF16)

@@ -15,6 +15,7 @@
 // pairs' float64 gradients are summed per volume in a fixed order, M is
 // added from the fixed-order sum of all fields, and the device L-BFGS of the
 // pair solve runs over all n fields.
+#include <atomic>
 #include <memory>
 #include <utility>
 #include <vector>
@@ -203,7 +204,7 @@ struct octmc_multi {
     double* fsum = nullptr;  // [3] sum of all fields
     double* gp_blk = nullptr;
     std::vector<void*> owned;
-    int busy = 0;
+    std::atomic<int> busy{0};  // a solve holds the object (taken by compare-and-swap)
 
     template <typename T>
     hipError_t alloc(T** p, size_t bytes)
@@ -550,7 +551,7 @@ int octmc_multi_eval(octmc_multi* m, int32_t level, const float* disp, double* t
     if (!m || !disp || !terms) return fail(OCTMC_E_INVALID, "multi, disp and terms are required");
     if (level < 0 || level >= m->nlev) return fail(OCTMC_E_INVALID, "level out of range");
     if (eta_mode != 0 && eta_mode != 1) return fail(OCTMC_E_INVALID, "eta_mode must be 0 or 1");
-    if (m->busy) return fail(OCTMC_E_BUSY, "object is in use");
+    if (m->busy.load()) return fail(OCTMC_E_BUSY, "object is in use");
     HIP_TRY(hipSetDevice(ctx_device(m->ctx)));
     MultiEvaluator ev;
     ev.M = m;
@@ -564,14 +565,14 @@ int octmc_multi_register(octmc_multi* m, float* disp_out, float* merged_oct, flo
     if (!m || !disp_out) return fail(OCTMC_E_INVALID, "NULL argument");
     if (merged_octa && !m->vol[0].octa) return fail(OCTMC_E_INVALID, "no OCTA volumes were given at creation");
     if (merged_octa && !merged_oct) return fail(OCTMC_E_INVALID, "merged_octa needs merged_oct");
-    if (m->busy) return fail(OCTMC_E_BUSY, "object is in use");
-    HIP_TRY(hipSetDevice(ctx_device(m->ctx)));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    m->busy = 1;
+    int idle = 0;
+    if (!m->busy.compare_exchange_strong(idle, 1)) return fail(OCTMC_E_BUSY, "object is in use");
     struct Unbusy {
         octmc_multi* p;
-        ~Unbusy() { p->busy = 0; }
+        ~Unbusy() { p->busy.store(0); }
     } ub{m};
+    HIP_TRY(hipSetDevice(ctx_device(m->ctx)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
     const octmc_params& pr = m->params;
     const size_t n0 = (size_t)3 * m->n * m->w[0] * m->h[0];
     Solver sv;

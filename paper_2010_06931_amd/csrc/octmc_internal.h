@@ -45,6 +45,8 @@ struct Slab {
 };
 inline size_t slab_bytes(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
 
+struct EvalView;
+
 // One evaluation job: a pair at one of its pyramid levels.
 struct EvalArgs {
     octmc_pair* pair;
@@ -58,6 +60,7 @@ struct EvalArgs {
     const float* disp_y = nullptr;   // the second slot's [na][3] (null: disp + na * 3); needs with_struct =
                                      // false in eval_group, whose structural kernels read [2][na][3]
     bool axial = false;              // dx = dy = 0 everywhere (stage 1): the x, y partials are left at 0
+    const EvalView* view = nullptr;  // the level's data, parameters and scratch; null: those of pair at level
 };
 
 // The hot path over up to kMaxJobs jobs (distinct pairs, one storage type,
@@ -119,6 +122,9 @@ struct StructJobs {
     StructJob j[kMaxJobs];
     int n;
 };
+// Blocks of one structural job: one 2 x 2 tile of A-scans per block, in 8
+// bands of whole tile rows (one per XCD).
+inline int struct_blocks(int w, int h) { return 8 * (((h + 1) / 2 + 7) / 8) * ((w + 1) / 2); }
 
 // Hot path, step 0: sum of the displacements (for the mean term M), as one
 // row of block partials per block (summed in a fixed order by its readers).

@@ -62,30 +62,45 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
     CombineJobs cj{};
     sj.n = tj.n = cj.n = n;
     int sb = 0, tb = 0, cb = 0;
-    octmc_dtype dt = ea[0].pair->dtype;
+    EvalView views[kMaxJobs];
+    for (int q = 0; q < n; ++q) {
+        if (ea[q].view) {
+            views[q] = *ea[q].view;
+        } else {
+            octmc_pair* P = ea[q].pair;
+            EvalView& v = views[q];
+            v.L = P->lev[ea[q].level];
+            v.dtype = P->dtype;
+            v.params = &P->params;
+            v.part = P->part;
+            v.sum_blk = P->sum_blk;
+            v.comb_blk = P->comb_blk;
+            v.eta = P->eta + ea[q].level;
+            v.orient = P->orient;
+        }
+    }
+    const octmc_dtype dt = views[0].dtype;
     bool any_eta = false;
     for (int q = 0; q < n; ++q) {
-        octmc_pair* P = ea[q].pair;
-        const int level = ea[q].level;
-        const Level& L = P->lev[level];
+        const EvalView& V = views[q];
+        const Level& L = V.L;
         any_eta |= ea[q].eta_mode == 0;
-        const octmc_params& pr = P->params;
-        if (P->dtype != dt) return fail(OCTMC_E_DTYPE, "batched pairs must share the storage type");
+        const octmc_params& pr = *V.params;
+        if (V.dtype != dt) return fail(OCTMC_E_DTYPE, "batched pairs must share the storage type");
         const int nsum = std::min(kSumBlocks, (2 * L.na + kRedBlock - 1) / kRedBlock);
         const float* dy = ea[q].disp_y ? ea[q].disp_y : ea[q].disp + (size_t)L.na * 3;
         if (with_struct && dy != ea[q].disp + (size_t)L.na * 3)
             return fail(OCTMC_E_INVALID, "the structural kernels read both slots' fields as one [2][na][3] array");
-        sj.j[q] = SumJob{{ea[q].disp, dy}, P->sum_blk, L.na, sb, nsum};
+        sj.j[q] = SumJob{{ea[q].disp, dy}, V.sum_blk, L.na, sb, nsum};
         sb += nsum;
-        tj.j[q] = StructJob{L.sx, L.sy, ea[q].disp, P->part, L.w, L.h, L.d, L.na, tb, L.vol_bytes,
+        tj.j[q] = StructJob{L.sx, L.sy, ea[q].disp, V.part, L.w, L.h, L.d, L.na, tb, L.vol_bytes,
                             (float)pr.eps_huber};
-        // one 2 x 2 tile of A-scans per block; 8 bands of whole tile rows
-        tb += 8 * (((L.h + 1) / 2 + 7) / 8) * ((L.w + 1) / 2);
+        tb += struct_blocks(L.w, L.h);
         const int nc = nblk_combine(L.na);
         const int blen = L.w;  // square scans: every B-scan has w A-scans
         const double f = std::floor(pr.flyback_frac * blen + 0.5);
         CombineJob c{};
-        c.part = P->part;
+        c.part = V.part;
         c.disp[0] = ea[q].disp;
         c.disp[1] = dy;
         c.grad = ea[q].grad;
@@ -94,11 +109,11 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
         c.ay = L.ay;
         c.vx = L.vx;
         c.vy = L.vy;
-        c.sum_blk = P->sum_blk;
+        c.sum_blk = V.sum_blk;
         c.nsum = nsum;
-        c.eta = P->eta + level;
+        c.eta = V.eta;
         c.p = ea[q].p;
-        c.blk = P->comb_blk;
+        c.blk = V.comb_blk;
         c.terms = ea[q].terms;
         c.w = L.w;
         c.h = L.h;
@@ -107,7 +122,7 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
         c.blk_begin = cb;
         c.nblk = nc;
         c.mode = 1;
-        c.orient = P->orient;
+        c.orient = V.orient;
         c.delta0 = pr.delta0;
         c.eps_h = pr.eps_huber;
         c.eps_r = pr.eps_reg;
@@ -324,7 +339,7 @@ int octmc_params_default(octmc_params* out)
     p.eps_reg = 0.1;
     p.flyback_frac = 0.25;
     p.mean_weight = 1.0;
-    p.levels = 3;
+    p.levels = 0;  // automatic: the coarsest level at most kAutoCoarsest A-scans wide
     p.iters_per_level = 100;
     p.lbfgs_m = 5;
     p.ls_max_evals = 20;
@@ -856,7 +871,12 @@ int octmc::register_impl(octmc_pair* pair, float* disp_out, float* merged_oct, f
 {
     if (!pair || !disp_out) return fail(OCTMC_E_INVALID, "NULL argument");
     if (merged_octa && !pair->octa[0]) return fail(OCTMC_E_INVALID, "no OCTA volumes were given at creation");
-    if (pair->busy) return fail(OCTMC_E_BUSY, "pair is in use");
+    int idle = 0;
+    if (!pair->busy.compare_exchange_strong(idle, 1)) return fail(OCTMC_E_BUSY, "pair is in use");
+    struct Unbusy {
+        octmc_pair* p;
+        ~Unbusy() { p->busy.store(0); }
+    } ub{pair};
     HIP_TRY(hipSetDevice(pair->ctx->device));
     DirectEvaluator direct;
     if (!ev) ev = &direct;
@@ -911,11 +931,6 @@ int octmc::register_impl(octmc_pair* pair, float* disp_out, float* merged_oct, f
         HIP_TRY(hipHostMalloc(&h_dots, (kMaxDots + 1) * 8, hipHostMallocDefault));
         hf.b = h_dots;
     }
-    pair->busy = 1;
-    struct Unbusy {
-        octmc_pair* p;
-        ~Unbusy() { p->busy = 0; }
-    } ub{pair};
     if (rep) {
         std::memset(rep, 0, sizeof(*rep));
         rep->nlevels = pair->nlev;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -29,6 +30,22 @@ struct Level {
     uint32_t vol_bytes = 0;
 };
 
+// Everything one evaluation job reads besides its displacement: the level's
+// volumes, en face images and validity, the objective's parameters, and the
+// scratch its kernels write (per-A-scan partials [na][8] float32, the
+// displacement-sum block rows [<= 256][4] and the combination block rows
+// [nblk][8] float64) with the level's eta (one float64).
+struct EvalView {
+    Level L;
+    octmc_dtype dtype = OCTMC_F32;
+    const octmc_params* params = nullptr;
+    float* part = nullptr;
+    double* sum_blk = nullptr;
+    double* comb_blk = nullptr;
+    double* eta = nullptr;
+    int orient = 2;
+};
+
 }  // namespace octmc
 
 struct octmc_pair {
@@ -49,7 +66,7 @@ struct octmc_pair {
     double* dot_out = nullptr;  // [kMaxDots + 1]
     std::vector<void*> owned;
     octmc::Slab* slab = nullptr;  // when set, all device memory comes from it
-    int busy = 0;
+    std::atomic<int> busy{0};  // a solve holds the pair (taken by compare-and-swap)
     std::vector<double> theta;  // stage-1 offsets and tilts (created with OCTMC_PREALIGN)
     // scan orientation of the two slots (bit 0: first, bit 1: second; 0 =
     // X-fast, 1 = Y-fast): the validity direction and acquisition order

@@ -166,8 +166,11 @@ struct GroupEval final : Evaluator {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_ticket.wait(lk, [&] { return t.launched; });
         }
+        // the worker's stream waits for the set in every case, so that a
+        // synchronisation of that stream covers the batcher's work too
+        const hipError_t we = hipStreamWaitEvent(s, W->done, 0);
         if (t.rc != OCTMC_OK) return fail(t.rc, t.err);
-        HIP_TRY(hipStreamWaitEvent(s, W->done, 0));
+        HIP_TRY(we);
         return OCTMC_OK;
     }
 };
@@ -208,8 +211,14 @@ void batcher_main(octmc_server* S)
             while (q1 < take.size() && q1 - q0 < (size_t)kMaxJobs && pair_dtype(take[q1]->ea.pair) == dt) ++q1;
             const int rc = launch_set(bs, take.data() + q0, (int)(q1 - q0));
             if (rc != OCTMC_OK) {
+                // Part of the set may already be queued on bs and still write
+                // into the requests' slabs: let it finish before the workers
+                // see the failure (and free their slabs), and record every
+                // done event so that their streams' waits are complete.
                 const std::string msg = octmc_last_error();
+                (void)hipStreamSynchronize(bs);
                 for (size_t q = q0; q < q1; ++q) {
+                    (void)hipEventRecord(take[q]->done, bs);
                     take[q]->rc = rc;
                     take[q]->err = msg;
                 }

@@ -38,7 +38,7 @@ def test_version_and_defaults(m):
     assert "gfx950" in m.version()
     p = m.default_params()
     assert p.delta0 == 0.5 and p.eps_huber == 1e-3  # fixed by the paper
-    assert p.levels == 3 and p.lbfgs_m == 5 and p.iters_per_level == 100
+    assert p.levels == 0 and p.lbfgs_m == 5 and p.iters_per_level == 100  # 0: automatic pyramid depth
 
 
 def test_invalid_arguments_are_reported(m):
