@@ -1,18 +1,27 @@
 """The serving API (octmc_server_*) through the C ABI: requests of mixed
 sizes, pyramid depths and storage types solved concurrently give the same
 displacements (bitwise) and merged volumes as each request solved alone with
-octmc_register; admission follows arrival order and the memory budget."""
+octmc_register; a served request of the tiny workload (64 x 64 x 128, 3
+levels x 100 steps) lies within 0.05 px RMS of the FP64 oracle's solve;
+admission follows arrival order and the memory budget."""
+import numpy as np
 import pytest
 import torch
 
+import oracle
 import synth
 from gpu_util import log
 
 pytestmark = pytest.mark.gpu
 
-# (n, d, levels, dtype, iterations per level)
+# (n, d, levels, dtype, iterations per level).  The BF16 request of depth 50
+# reaches an odd depth (25) at its second level, where it takes the
+# one-sample structural kernel while the other BF16 requests of a grouped
+# launch take the two-sample one.  The last request is the tiny workload's
+# pair, solved as its workload is defined.
 MIX = [(40, 64, 2, "f32", 30), (48, 80, 3, "bf16", 30), (32, 48, 2, "f32", 40), (56, 64, 3, "f16", 25),
-       (36, 40, 2, "bf16", 30)]
+       (36, 40, 2, "bf16", 30), (36, 50, 2, "bf16", 30), (64, 128, 3, "f32", 100)]
+TINY = len(MIX) - 1
 
 
 @pytest.fixture(scope="module")
@@ -24,7 +33,17 @@ def octmc():
 
 @pytest.fixture(scope="module")
 def mix():
-    return [synth.make_pair("serving", k, n=n, d=d, octa_volumes=(k == 0)) for k, (n, d, *_) in enumerate(MIX)]
+    return [synth.make_pair("tiny") if k == TINY else synth.make_pair("serving", k, n=n, d=d, octa_volumes=(k == 0))
+            for k, (n, d, *_) in enumerate(MIX)]
+
+
+@pytest.fixture(scope="module")
+def tiny_oracle(mix):
+    """The oracle's solve of the tiny request (every other parameter at the
+    library's default, which the oracle shares)."""
+    n, d, lv, dt, it = MIX[TINY]
+    D, _ = oracle.register(oracle.level_from_pair(mix[TINY]), oracle.Params(levels=lv, iters=it))
+    return D
 
 
 def _alone(octmc, pairs):
@@ -57,7 +76,7 @@ def _serve(octmc, srv, pairs):
 
 
 @pytest.mark.parametrize("mode", ["grouped", "streams"])
-def test_serve_results_equal_alone_and_in_mix(octmc, mix, mode):
+def test_serve_results_equal_alone_and_in_mix(octmc, mix, tiny_oracle, mode):
     log(f"serve: {len(MIX)} requests alone")
     ref = _alone(octmc, mix)
     m = octmc.SERVE_GROUPED if mode == "grouped" else octmc.SERVE_STREAMS
@@ -77,6 +96,10 @@ def test_serve_results_equal_alone_and_in_mix(octmc, mix, mode):
         assert [r["evals"] for r in c["report"]] == [r["evals"] for r in rep]
         if k == 0:
             assert torch.equal(mo, rmo) and torch.equal(ma, rma)
+        if k == TINY:
+            rms = float(np.sqrt(((disp.double().cpu().numpy() - tiny_oracle) ** 2).mean()))
+            log(f"served tiny request vs the oracle's solve: {rms:.4f} px RMS")
+            assert rms <= 0.05, rms
         overlap += sum(1 for o in done if o["id"] != c["id"] and o["t_admit"] < c["t_done"] and
                        c["t_admit"] < o["t_done"])
     assert overlap > 0  # the requests really ran concurrently
