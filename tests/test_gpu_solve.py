@@ -135,3 +135,62 @@ def test_automatic_levels_equal_the_explicit_count(octmc):
     E4, _, _, q4 = M4.register()
     torch.cuda.synchronize()
     assert len(q0) == 4 and torch.equal(E0, E4)
+
+
+# Stored FP64 oracle solves of the larger workloads (tests/golden, written by
+# tests/golden/make_solve_golden.py from the oracle alone).  The solve is
+# chaotic at these sizes: the oracle's own solution moves by 0.08-0.15 px RMS
+# when its input volumes are perturbed by a relative 1e-7 or 1e-6 (measured at
+# 300 x 300 x 640 with 4 and 6 levels; the distance does not shrink with the
+# perturbation), so no float32 implementation can match it to 0.05 px there.
+# Each golden of float32 inputs stores that distance, and the bar is
+# GOLDEN_FACTOR times it (never below the 0.05 px of the tiny workload); the
+# per-level objectives must agree to 5 % (as for the tiny workload; measured:
+# within 1.1 %), and the GPU solve must be as far
+# from the ground truth as the oracle's, to 0.05 px per component.
+GOLDEN_FACTOR = 4.0
+GOLDEN_CASES = [("clinical", 4, 0, "f32"), ("clinical", 4, 1, "bf16"), ("clinical", 6, 0, "f32"),
+                ("dense", 4, 0, "bf16")]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("workload,levels,store,dtype", GOLDEN_CASES)
+def test_register_matches_stored_oracle_solve(octmc, workload, levels, store, dtype):
+    """Full solves of the clinical (300 x 300 x 640) and dense (500 x 500 x
+    800) pairs, generated on the GPU exactly as for the stored oracle solve
+    (same input hash), at the workload's 4 levels and at the automatic depth,
+    against the oracle's FP64 solve of the same inputs (rounded to the
+    storage type for store = 1)."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_solve_golden as G
+    g = G.load(workload, levels, store)
+    if g is None:
+        pytest.skip(f"no stored oracle solve of {workload} with {levels} levels, storage {store}")
+    Do, meta = g
+    sens = meta.get("perturbation", {}).get("rms_px")
+    if sens is None:  # the sensitivity is a property of the inputs: take the float32-input golden's
+        g0 = G.load(workload, levels, 0)
+        sens = None if g0 is None else g0[1].get("perturbation", {}).get("rms_px")
+    log(f"generate {workload} on cuda")
+    pair = synth.make_pair(workload, meta["pair"], device="cuda", octa_volumes=False)
+    assert G.input_hash(pair) == meta["input_sha256"], "the generator gave other inputs than the stored solve saw"
+    P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=dtype,
+                   levels=meta["params"]["levels"], iters_per_level=meta["params"]["iters"])
+    log(f"register {workload} {dtype} levels {levels}")
+    D, _, _, rep = P.register()
+    torch.cuda.synchronize()
+    Dg = D.double().cpu().numpy()
+    rms = float(np.sqrt(((Dg - Do) ** 2).mean()))
+    bar = max(0.05, GOLDEN_FACTOR * sens) if sens is not None else 0.05
+    gt = pair.d_gt.numpy()
+    e_gpu = np.sqrt(((Dg - gt) ** 2).reshape(-1, 3).mean(axis=0))
+    e_orc = np.sqrt(((Do - gt) ** 2).reshape(-1, 3).mean(axis=0))
+    print(f"{workload} {dtype} levels {levels}: {rms:.4f} px RMS from the oracle's solve "
+          f"(its own sensitivity {sens} px, bar {bar:.3f} px); error against ground truth "
+          f"{np.round(e_gpu, 3)} px, oracle's {np.round(e_orc, 3)} px")
+    for r, o in zip(rep, meta["levels"]):
+        assert abs(r["f_end"] - o["f_end"]) < 0.05 * o["f_end"], (r, o)
+    assert np.all(np.abs(e_gpu - e_orc) <= 0.05), (e_gpu, e_orc)
+    assert rms <= bar, (rms, bar)
