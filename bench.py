@@ -324,6 +324,103 @@ def serving(octmc, torch, nreq, budget_gib, max_active, log):
             "automatic_levels": auto}
 
 
+def _golden(workload, levels, store, pair):
+    """The oracle's stored solve of a workload pair (tests/golden, written by
+    its script from the oracle alone), if it was made from the same inputs."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_solve_golden as G
+    g = G.load(workload, levels, store)
+    if g is None or g[1].get("input_sha256") != G.input_hash(pair):
+        return None
+    return g
+
+
+def _rms_px(a, b):
+    """Per-component RMS distance of two fields (numpy or torch)."""
+    import numpy as np
+    a = a.double().cpu().numpy() if hasattr(a, "cpu") else np.asarray(a, dtype=np.float64)
+    b = b.double().cpu().numpy() if hasattr(b, "cpu") else np.asarray(b, dtype=np.float64)
+    return [round(float(x), 4) for x in np.sqrt(((a - b) ** 2).reshape(-1, 3).mean(axis=0))]
+
+
+def clinical_bench(octmc, torch, log, steps=200, warmup=20):
+    """The clinical workload (300 x 300 A-scans x 640 samples, float32
+    storage): evaluations per second of the full objective and gradient at
+    the finest level, the structural kernel (k_struct<float>) against its
+    roofs, and full solves at the workload's 4 levels and at the automatic
+    depth: time, gauge-free error against ground truth, and distance to the
+    FP64 oracle's solve of the same inputs (stored)."""
+    import numpy as np
+    import synth
+    log("clinical 300x300x640: generating on cuda")
+    pair = synth.make_pair("clinical", device="cuda", octa_volumes=False)
+    h, w, d = pair.sx.shape
+    P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype="f32", levels=4)
+    rng = np.random.default_rng(1)
+    D = (pair.d_gt + torch.from_numpy(rng.normal(0, 0.2, tuple(pair.d_gt.shape)))).float().cuda()
+    terms = torch.empty(octmc.NTERMS, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(D)
+    P.eval(0, D, grad=grad, terms=terms, eta_mode=0)
+    for _ in range(warmup):
+        P.eval(0, D, grad=grad, terms=terms)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        P.eval(0, D, grad=grad, terms=terms)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = np.array([P.eval_profile(0, D, grad=grad, terms=terms) for _ in range(40)]).mean(axis=0)
+    alg = 2 * w * h * d * 4 + w * h * EXTRA_BYTES_PER_ASCAN
+    t_struct = st[1] * 1e-3
+    hbm = alg / t_struct / 1e9
+    tfl = FLOP_PER_VOXEL_PAIR * w * h * d / t_struct / 1e12
+    out = {"workload": f"clinical orthogonal pair {w}x{h} A-scans x {d} samples, finest level, storage f32",
+           "evals_per_s": round(1000.0 / ms, 2), "ms_per_eval": round(ms, 5),
+           "hbm_GBps_algorithmic_eval": round(alg / (ms * 1e-3) / 1e9, 1),
+           "kernel_ms": {"sum": round(st[0], 5), "struct": round(st[1], 5), "combine": round(st[2], 5)},
+           "roofline_struct": {"kernel": "k_struct<float>", "algorithmic_bytes": alg,
+                               "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(hbm / HBM_PEAK_GBS, 4)},
+                               "alu": {"achieved": round(tfl, 2), "peak": round(VALU_PEAK_TFLOPS, 1),
+                                       "unit": "TFLOP/s", "frac": round(tfl / VALU_PEAK_TFLOPS, 4)}}}
+    P.close()
+    motion = _relative_rms(torch.zeros_like(pair.d_gt), pair.d_gt)
+    out["relative_motion_rms_px"] = [round(float(x), 4) for x in motion]
+    sol = {}
+    for levels in (4, 0):
+        for dt, store in (("f32", 0), ("bf16", 1)):
+            Q = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=dt,
+                           levels=levels)
+            Q.register()  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Ds, _, _, rep = Q.register()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            L = Q.levels
+            Q.close()
+            r = {"levels": L, "seconds": round(el, 4), "evals_total": int(sum(x["evals"] for x in rep)),
+                 "relative_rms_vs_ground_truth_px": [round(float(x), 4) for x in _relative_rms(Ds, pair.d_gt)]}
+            for st_, tag in ((0, "fp32_inputs"), (store, "rounded_inputs")):
+                if tag == "rounded_inputs" and store == 0:
+                    continue
+                g = _golden("clinical", L, st_, pair)
+                if g is not None:
+                    Do, meta = g
+                    r[f"rms_vs_oracle_{tag}_px"] = _rms_px(Ds, Do)
+                    pert = meta.get("perturbation")
+                    if pert:
+                        r[f"oracle_self_sensitivity_{tag}"] = pert
+            sol[f"{dt}_levels{levels}"] = r
+            log(f"clinical solve {dt} levels {L}: {el:.3f} s, {r}")
+    out["solve"] = sol
+    del pair
+    torch.cuda.empty_cache()
+    return out
+
+
 def enface_bench(octmc, torch, log, reps=20):
     """The segmentation-free en face projection (Sec. 2.3) of one OCTA volume,
     with its percentile normalisation and with a fixed mapping, at the
@@ -535,6 +632,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the four-volume timing")
     ap.add_argument("--no-autograd", action="store_true", help="skip the batched autograd timing")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the whole-pipeline timing at 500^2 x 465")
+    ap.add_argument("--no-clinical", action="store_true", help="skip the 300^2 x 640 float32 evaluation and solves")
     ap.add_argument("--extras-only", action="store_true",
                     help="time only the stage-1 prealignment, the four-volume path, the batched autograd "
                          "objective and the projection")
@@ -727,6 +825,18 @@ def main():
                                                    _relative_rms(torch.zeros_like(pair.d_gt), pair.d_gt)],
                         "rms_vs_ground_truth_um": [round(float(x * s), 2) for x, s in zip(rms_main, UM_PER_PX)],
                         "rms_vs_fp32_storage_solve_px": vs32(Dsol)}
+        # against the FP64 oracle's solve of the same inputs (stored; float32
+        # inputs, so for 16-bit storage this is storage plus compute error)
+        g = _golden("dense", 4, 0, pair)
+        if g is not None:
+            Do, meta = g
+            for dt, Dq in sols.items():
+                px = _rms_px(Dq, Do)
+                rec = out["solve"] if dt == args.dtype else out["storage_variants"][dt]
+                rec["rms_vs_oracle_px"] = px
+                rec["rms_vs_oracle_um"] = [round(x * u, 3) for x, u in zip(px, UM_PER_PX)]
+            if meta.get("perturbation"):
+                out["solve"]["oracle_self_sensitivity"] = meta["perturbation"]
         # the same pair with the automatic pyramid depth (levels = 0)
         Pa = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=args.dtype, levels=0)
         torch.cuda.synchronize()
@@ -751,6 +861,8 @@ def main():
 
     for v in out.get("storage_variants", {}).values():
         v.pop("solution", None)
+    if not args.no_clinical:
+        out["clinical"] = clinical_bench(octmc, torch, log)
     if not args.no_prealign:
         out["prealign"] = prealign_bench(octmc, torch, pair, args.dtype, log)
     if not args.no_serve:
