@@ -383,6 +383,39 @@ OCTMC_API int octmc_eval(octmc_pair* pair, int32_t level, const float* disp, dou
 OCTMC_API int octmc_eval_batched(octmc_pair* const* pairs, int32_t npairs, int32_t level, const float* disp,
                        double* terms, float* grad, int32_t eta_mode, void* stream);
 
+/* octmc_eval for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It makes no allocation of any kind (no hipMalloc, hipFree or allocating
+ * library routine); the caller passes every input and output, and the
+ * kernels' scratch is a static device array of the library, one per GPU,
+ * held until the process ends: OCTMC_NOALLOC_SCRATCH_BYTES bytes, enough
+ * for w * h <= OCTMC_NOALLOC_MAX_ASCANS A-scans.
+ *   ctx      context of the device (its creation resolved the array's address);
+ *   params   objective parameters (alpha, delta0, eps_huber, eps_reg,
+ *            flyback_frac, mean_weight; the solver fields are not used);
+ *   shape    w == h, d, dtype of sx/sy, mem = OCTMC_MEM_DEVICE;
+ *   sx, sy   device [h][w][d] structural volumes in the storage type `dtype`
+ *            (float32, or bfloat16 / binary16 as 16-bit words);
+ *   ax, ay   device [h][w] float32 en face images;
+ *   vx, vy   device float32 validity, vx [h] (X-fast B-scans) and vy [w]
+ *            (Y-fast); all ones for fully valid scans;
+ *   disp, terms, grad as octmc_eval (grad may be NULL);
+ *   eta      device float64[1]: eta_mode 0 writes this displacement's eta
+ *            (Eq. 10) there before the evaluation, eta_mode 1 reads it.
+ * The result equals octmc_eval's on a pair holding the same level 0 data
+ * with the same eta.  Errors: OCTMC_E_INVALID (NULL inputs, host memory,
+ * bad parameters), OCTMC_E_SHAPE (w != h, too small, or w * h above
+ * OCTMC_NOALLOC_MAX_ASCANS), OCTMC_E_DTYPE.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads,
+ * other contexts) race and must be ordered by the caller. */
+#define OCTMC_NOALLOC_MAX_ASCANS (512 * 512)
+#define OCTMC_NOALLOC_SCRATCH_BYTES (OCTMC_NOALLOC_MAX_ASCANS * 32 + 8192 + (OCTMC_NOALLOC_MAX_ASCANS + 255) / 256 * 64)
+OCTMC_API int octmc_eval_noalloc(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, const void* sx,
+                                 const void* sy, const float* ax, const float* ay, const float* vx, const float* vy,
+                                 const float* disp, double* eta, double* terms, float* grad, int32_t eta_mode,
+                                 void* stream);
+
 /* octmc_eval with HIP events recorded on `stream` between its kernels:
  * stage_ms[0] = displacement sum (mean term), [1] = structural resample /
  * residual / depth reduction (the dominant kernel), [2] = en face, validity,

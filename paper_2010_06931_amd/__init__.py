@@ -42,7 +42,7 @@ SYMBOLS = ("octmc_version", "octmc_last_error", "octmc_params_default", "octmc_c
            "octmc_prealign",
            "octmc_pair_prealignment", "octmc_resample_axial", "octmc_multi_create", "octmc_multi_destroy",
            "octmc_multi_eval", "octmc_multi_register", "octmc_eval",
-           "octmc_eval_profile", "octmc_eval_batched", "octmc_register", "octmc_merge",
+           "octmc_eval_profile", "octmc_eval_batched", "octmc_eval_noalloc", "octmc_register", "octmc_merge",
            "octmc_request_footprint", "octmc_server_create", "octmc_server_submit", "octmc_server_poll",
            "octmc_server_status", "octmc_server_destroy")
 SERVE_GROUPED, SERVE_STREAMS = 0, 1
@@ -138,6 +138,7 @@ def lib():
         L.octmc_eval.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.octmc_eval_profile.argtypes = [vp, C.c_int32, vp, vp, vp, C.c_int32, C.POINTER(C.c_float), vp]
         L.octmc_eval_batched.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, vp, vp, C.c_int32, vp]
+        L.octmc_eval_noalloc.argtypes = [vp, C.POINTER(Params), C.POINTER(Shape)] + [vp] * 10 + [C.c_int32, vp]
         L.octmc_register.argtypes = [vp, vp, vp, vp, C.POINTER(Report), vp]
         L.octmc_merge.argtypes = [vp, vp, vp, vp, vp]
         L.octmc_request_footprint.argtypes = [C.POINTER(Request), C.POINTER(C.c_uint64)]
@@ -218,6 +219,28 @@ def context(device: int = 0) -> Context:
     if device not in _default_ctx:
         _default_ctx[device] = Context(device)
     return _default_ctx[device]
+
+
+def eval_noalloc(sx, sy, ax, ay, vx, vy, disp, eta, terms, grad=None, *, dtype: str = "f32",
+                 params: Params | None = None, eta_mode: int = 1, ctx: Context | None = None, stream=None):
+    """octmc_eval_noalloc: one evaluation on caller-owned device tensors with
+    the library's static scratch; neither this wrapper nor the library
+    allocates device memory.  sx, sy [h][w][d] in the storage type (float32,
+    bfloat16 or float16 tensors), ax, ay [h][w], vx [h], vy [w], disp and
+    grad [2][h][w][3] float32, eta float64[1] (written for eta_mode 0, read
+    for 1), terms float64[NTERMS]."""
+    ctx = ctx or context(0)
+    h, w, d = sx.shape
+    want = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    for t in (sx, sy):
+        if t.dtype != want or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (h, w, d):
+            raise ValueError(f"volumes must be contiguous {want} cuda tensors of one shape")
+    prm = params if params is not None else default_params()
+    shape = Shape(w, h, d, _DTYPES[dtype], MEM_DEVICE)
+    _check(lib().octmc_eval_noalloc(ctx._h, C.byref(prm), C.byref(shape), _ptr(sx), _ptr(sy), _ptr(ax), _ptr(ay),
+                                    _ptr(vx), _ptr(vy), _ptr(disp), _ptr(eta), _ptr(terms), _ptr(grad), eta_mode,
+                                    _stream(stream)))
+    return terms, grad
 
 
 class Pair:

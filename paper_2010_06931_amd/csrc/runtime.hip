@@ -11,6 +11,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,6 +32,46 @@ int octmc::fail(int code, const std::string& msg)
 namespace {
 
 size_t esize(octmc_dtype dt) { return dt == OCTMC_F32 ? 4 : 2; }
+
+// ---------------------------------------------------------------------------
+// Scratch of octmc_eval_noalloc: one file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends), laid out as the
+// per-A-scan partials [na][8] float32, the displacement-sum block rows
+// [256][4] float64 and the combination block rows [nblk][8] float64, for at
+// most kNoAllocMaxAscans A-scans.  Host code never uses the array's name as
+// an address: octmc_create resolves the device address once per device
+// (hipGetSymbolAddress, with that device current) and every launch takes it.
+// Every kernel writes the whole part of the array it later reads, so nothing
+// has to start at zero.
+constexpr size_t kNoAllocPart = (size_t)OCTMC_NOALLOC_MAX_ASCANS * 8 * 4;
+constexpr size_t kNoAllocSum = 256 * 4 * 8;
+constexpr size_t kNoAllocComb = ((size_t)OCTMC_NOALLOC_MAX_ASCANS + 255) / 256 * 8 * 8;
+constexpr size_t kNoAllocBytes = kNoAllocPart + kNoAllocSum + kNoAllocComb;
+static_assert(kNoAllocPart % 256 == 0 && kNoAllocSum % 256 == 0, "sub-buffers stay 256-byte aligned");
+static_assert(kNoAllocBytes == OCTMC_NOALLOC_SCRATCH_BYTES, "the size the header states");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `device`, resolved
+// on the first call for that device.
+int scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(OCTMC_E_INVALID, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(OCTMC_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return OCTMC_OK;
+}
 
 struct DevBuf {
     std::vector<void*> ptrs;
@@ -361,7 +402,9 @@ int octmc_create(int device_ordinal, octmc_ctx** out)
     HIP_TRY(hipGetDeviceCount(&n));
     if (device_ordinal < 0 || device_ordinal >= n) return fail(OCTMC_E_INVALID, "no such device");
     HIP_TRY(hipSetDevice(device_ordinal));
-    *out = new octmc_ctx{device_ordinal};
+    void* scr = nullptr;
+    OCTMC_TRY(scratch_address(device_ordinal, &scr));
+    *out = new octmc_ctx{device_ordinal, scr};
     return OCTMC_OK;
 }
 
@@ -777,6 +820,50 @@ int octmc_eval(octmc_pair* pair, int32_t level, const float* disp, double* terms
     if (eta_mode != 0 && eta_mode != 1) return fail(OCTMC_E_INVALID, "eta_mode must be 0 or 1");
     HIP_TRY(hipSetDevice(pair->ctx->device));
     EvalArgs ea{pair, disp, terms, grad, nullptr, nullptr, level, eta_mode};
+    return eval_group(&ea, 1, static_cast<hipStream_t>(stream));
+}
+
+int octmc_eval_noalloc(octmc_ctx* ctx, const octmc_params* params, const octmc_shape* shape, const void* sx,
+                       const void* sy, const float* ax, const float* ay, const float* vx, const float* vy,
+                       const float* disp, double* eta, double* terms, float* grad, int32_t eta_mode, void* stream)
+{
+    if (!ctx || !params || !shape) return fail(OCTMC_E_INVALID, "ctx, params and shape are required");
+    if (!sx || !sy || !ax || !ay || !vx || !vy || !disp || !eta || !terms)
+        return fail(OCTMC_E_INVALID, "volumes, en face images, validity, disp, eta and terms are required");
+    if (eta_mode != 0 && eta_mode != 1) return fail(OCTMC_E_INVALID, "eta_mode must be 0 or 1");
+    octmc_params pr = *params;
+    pr.levels = 1;  // one level: the pyramid depth plays no part here
+    OCTMC_TRY(validate_params(&pr));
+    if (shape->mem != OCTMC_MEM_DEVICE) return fail(OCTMC_E_INVALID, "octmc_eval_noalloc takes device inputs");
+    OCTMC_TRY(validate_shape(&pr, shape));
+    const int w = shape->w, h = shape->h, d = shape->d;
+    const size_t na = (size_t)w * h;
+    if (na > (size_t)OCTMC_NOALLOC_MAX_ASCANS)
+        return fail(OCTMC_E_SHAPE, "w * h exceeds OCTMC_NOALLOC_MAX_ASCANS (the static scratch of octmc_eval_noalloc)");
+    if (!ctx->noalloc_scratch) return fail(OCTMC_E_DEVICE, "the context holds no scratch address");
+    HIP_TRY(hipSetDevice(ctx->device));
+    EvalView v;
+    v.L.w = w;
+    v.L.h = h;
+    v.L.d = d;
+    v.L.na = (int)na;
+    v.L.sx = const_cast<void*>(sx);  // read only
+    v.L.sy = const_cast<void*>(sy);
+    v.L.ax = const_cast<float*>(ax);
+    v.L.ay = const_cast<float*>(ay);
+    v.L.vx = const_cast<float*>(vx);
+    v.L.vy = const_cast<float*>(vy);
+    v.L.vol_bytes = (uint32_t)(na * d * esize(shape->dtype));
+    v.dtype = shape->dtype;
+    v.params = &pr;
+    char* base = static_cast<char*>(ctx->noalloc_scratch);
+    v.part = reinterpret_cast<float*>(base);
+    v.sum_blk = reinterpret_cast<double*>(base + kNoAllocPart);
+    v.comb_blk = reinterpret_cast<double*>(base + kNoAllocPart + kNoAllocSum);
+    v.eta = eta;
+    v.orient = 2;
+    EvalArgs ea{nullptr, disp, terms, grad, nullptr, nullptr, 0, eta_mode};
+    ea.view = &v;
     return eval_group(&ea, 1, static_cast<hipStream_t>(stream));
 }
 

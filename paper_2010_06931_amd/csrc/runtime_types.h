@@ -15,6 +15,9 @@
 
 struct octmc_ctx {
     int device;
+    // device address of the evaluation scratch of octmc_eval_noalloc (the
+    // file-scope array of runtime.hip on this device), resolved at creation
+    void* noalloc_scratch = nullptr;
 };
 
 namespace octmc {
