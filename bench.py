@@ -324,12 +324,20 @@ def serving(octmc, torch, nreq, budget_gib, max_active, log):
     seq0, seq_D0 = sequential(0)
     log("serving: Poisson trace, grouped launches, levels = 0")
     poisson0, got0 = served(octmc.SERVE_GROUPED, arrival, 0, budget)
+    log("serving: Poisson trace, one stream per request, levels = 0")
+    poisson0s, _ = served(octmc.SERVE_STREAMS, arrival, 0, budget)
+    log("serving: burst, grouped launches, levels = 0")
+    burst0, _ = served(octmc.SERVE_GROUPED, np.zeros(nreq), 0, budget)
+    log("serving: burst, one stream per request, levels = 0")
+    burst0s, _ = served(octmc.SERVE_STREAMS, np.zeros(nreq), 0, budget)
     auto = {"levels": "0 (automatic: 6 levels at 300-500 A-scans, 7 at 600)",
-            "served_poisson_grouped": poisson0, "sequential_fp32": seq0,
+            "served_poisson_grouped": poisson0, "served_poisson_streams": poisson0s,
+            "served_burst_grouped": burst0, "served_burst_streams": burst0s, "sequential_fp32": seq0,
             "accuracy_median_rms_px": accuracy(got0, seq_D0)}
     return {"requests": nreq, "size_classes": [f"{n}x{n}x{d}" for n, d in classes],
             "arrivals": "Poisson, mean inter-arrival 0.25 s", "max_active": max_active, "storage": "bf16",
             "budget_GiB": round(budget / 2**30, 2),
+            "grouped_mode": "evaluations of fewer than 128^2 A-scans grouped, larger ones on the request's stream",
             "levels": 4, "iters_per_level": 100,
             "served_poisson_grouped": poisson, "served_burst_grouped": burst,
             "served_burst_streams": burst_streams, "sequential_fp32": seq,

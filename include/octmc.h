@@ -447,8 +447,10 @@ OCTMC_API int octmc_merge(octmc_pair* pair, const float* disp, float* merged_oct
  * its pyramid, float64 solver state and scratch in its part of that range
  * until it completes.  The evaluations of the active requests, each at its
  * own pyramid level and size, run either as grouped launches (one launch per
- * kernel covers every request waiting for an evaluation; OCTMC_SERVE_GROUPED)
- * or each on its request's own stream (OCTMC_SERVE_STREAMS).  A request's
+ * kernel covers every request waiting for an evaluation of fewer than 128^2
+ * A-scans, while larger ones, which fill the device alone, run on their
+ * request's stream; OCTMC_SERVE_GROUPED) or each on its request's own stream
+ * (OCTMC_SERVE_STREAMS).  A request's
  * result is the same in both modes and equals octmc_register's for the same
  * inputs: every reduction runs in a fixed order per request.
  */

@@ -608,7 +608,7 @@ class Server:
     octmc_server_create).  Tensors passed to submit() are kept alive until
     their completion has been polled."""
 
-    def __init__(self, hbm_budget_bytes: int, max_active: int = 8, mode: int = SERVE_GROUPED,
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 8, mode: int = SERVE_STREAMS,
                  ctx: Context | None = None):
         self.ctx = ctx or context(0)
         self._h = C.c_void_p()

@@ -77,6 +77,8 @@ struct Evaluator {
 };
 
 octmc_dtype pair_dtype(const octmc_pair* pair);
+// A-scans (w h) of a pair's pyramid level.
+int pair_level_ascans(const octmc_pair* pair, int level);
 int validate_params(const octmc_params* p);
 // params with levels = 0 (automatic) replaced by the level count for `shape`:
 // the fewest levels whose coarsest level is at most kAutoCoarsest A-scans

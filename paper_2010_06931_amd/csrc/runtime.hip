@@ -252,6 +252,7 @@ int octmc::pair_alloc_scratch(octmc_pair* P, size_t na, hipStream_t s)
 }
 
 octmc_dtype octmc::pair_dtype(const octmc_pair* pair) { return pair->dtype; }
+int octmc::pair_level_ascans(const octmc_pair* pair, int level) { return pair->lev[level].na; }
 int octmc::pair_nlev(const octmc_pair* pair) { return pair->nlev; }
 const octmc_params& octmc::pair_params(const octmc_pair* pair) { return pair->params; }
 int octmc::pair_device(const octmc_pair* pair) { return pair->ctx->device; }

@@ -13,7 +13,8 @@
 //              waiting for and runs each set of up to kMaxJobs as one launch
 //              per kernel, every job at its own level and size; sets
 //              alternate between two streams, and the next set forms while
-//              up to two run on the device
+//              up to two run on the device.  Evaluations large enough to fill
+//              the device alone run on their request's stream instead.
 //
 // The solver of a request is the same code as octmc_register's and every
 // reduction runs in a fixed order per job, so a request's result does not
@@ -143,12 +144,21 @@ struct octmc_server {
 
 namespace {
 
+// Evaluations of at least this many A-scans fill the device with one launch
+// per kernel (one wave per output A-scan, about 3 000 resident waves), so
+// grouping them with others saves nothing and only makes the request wait for
+// the batcher: they run directly on the request's stream.  Smaller ones (the
+// coarse pyramid levels) are grouped, where one launch replaces several
+// nearly empty ones.
+constexpr int kGroupMaxAscans = 128 * 128;
+
 struct GroupEval final : Evaluator {
     octmc_server* S;
     Worker* W;
     GroupEval(octmc_server* s, Worker* w) : S(s), W(w) {}
     int eval(const EvalArgs& ea, hipStream_t s) override
     {
+        if (ea.pair && pair_level_ascans(ea.pair, ea.level) >= kGroupMaxAscans) return eval_group(&ea, 1, s);
         HIP_TRY(hipEventRecord(W->ready, s));
         Ticket& t = W->ticket;
         t.ea = ea;

@@ -17,10 +17,12 @@ pytestmark = pytest.mark.gpu
 # (n, d, levels, dtype, iterations per level).  The BF16 request of depth 50
 # reaches an odd depth (25) at its second level, where it takes the
 # one-sample structural kernel while the other BF16 requests of a grouped
-# launch take the two-sample one.  The last request is the tiny workload's
+# launch take the two-sample one.  The 130 x 130 request's finest level is
+# large enough (at least 128^2 A-scans) to run on its own stream in grouped
+# mode, its coarser one is grouped.  The last request is the tiny workload's
 # pair, solved as its workload is defined.
 MIX = [(40, 64, 2, "f32", 30), (48, 80, 3, "bf16", 30), (32, 48, 2, "f32", 40), (56, 64, 3, "f16", 25),
-       (36, 40, 2, "bf16", 30), (36, 50, 2, "bf16", 30), (64, 128, 3, "f32", 100)]
+       (36, 40, 2, "bf16", 30), (36, 50, 2, "bf16", 30), (130, 40, 2, "bf16", 20), (64, 128, 3, "f32", 100)]
 TINY = len(MIX) - 1
 
 
