@@ -663,6 +663,8 @@ def main():
     ap.add_argument("--serve-max-active", type=int, default=8)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed evaluations and the calibration copies (for rocprofv3)")
+    ap.add_argument("--profile-workload", default="dense", choices=["dense", "clinical"],
+                    help="with --profile-only: the dense pair (--dtype storage) or the clinical pair (float32)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic of the structural kernel from two rocprofv3 counter passes")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_struct_dense_counters.json"))
@@ -701,6 +703,21 @@ def main():
         extra["pipeline"] = pipeline_bench(octmc, torch, log)
         extra["enface_projection"] = enface_bench(octmc, torch, log)
         print(json.dumps(extra), flush=True)
+        return
+    if args.profile_only and args.profile_workload == "clinical":
+        # the clinical workload's finest-level evaluations alone (float32 storage), for rocprofv3
+        log("generating the clinical pair 300x300x640 on cuda")
+        pair = synth.make_pair("clinical", device="cuda", octa_volumes=False)
+        P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype="f32", levels=4)
+        D = (pair.d_gt + torch.from_numpy(np.random.default_rng(1).normal(0, 0.2, tuple(pair.d_gt.shape)))).float().cuda()
+        terms = torch.empty(octmc.NTERMS, dtype=torch.float64, device="cuda")
+        grad = torch.empty_like(D)
+        P.eval(0, D, grad=grad, terms=terms, eta_mode=0)
+        for _ in range(args.warmup + args.steps):
+            P.eval(0, D, grad=grad, terms=terms)
+        torch.cuda.synchronize()
+        st = np.array([P.eval_profile(0, D, grad=grad, terms=terms) for _ in range(args.steps)]).mean(axis=0)
+        print(json.dumps({"workload": "clinical 300x300x640 f32", "struct_ms_events": round(float(st[1]), 5)}))
         return
     log(f"generating the dense pair {args.n}x{args.n}x{args.d} on cuda")
     pair = synth.make_pair("dense", n=args.n, d=args.d, device="cuda", octa_volumes=False)
