@@ -81,6 +81,14 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
                                      fused form (each volume resampled once), which serves n = 3 or 4
                                      volumes in float32 storage, or in 16-bit storage at a level of
                                      even depth */
+#define OCTMC_HOST_LINE_SEARCH 0x20u /* octmc_register: take the L-BFGS decisions (history update,
+                                       search direction, line-search steps) on the host, with a
+                                       round trip after every dot-product pass and every trial
+                                       evaluation.  Without it they are taken on the device by
+                                       single-thread kernels in the same float64 operations, with
+                                       the same result bit for bit, and the host enqueues several
+                                       iterations ahead (lbfgs_m <= 6; the host form otherwise, and
+                                       always for octmc_multi_register and grouped serving) */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
  * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
@@ -101,7 +109,7 @@ typedef struct {
     double merge_kappa;  /* density weight decay exp(-kappa (rho - 1))            [R: 1.0]  */
     double merge_tau;    /* weights below tau are clipped to 0                    [R: 0.05] */
     uint32_t flags;      /* OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN |
-                            OCTMC_MULTI_PAIRWISE */
+                            OCTMC_MULTI_PAIRWISE | OCTMC_HOST_LINE_SEARCH */
     int32_t prealign_iters; /* stage-1 L-BFGS steps per level                     [100]     */
     double gamma_tilt;   /* weight of the tilt normalisation T (Eq. 1, stage 1)   [R: 1.0]  */
 } octmc_params;

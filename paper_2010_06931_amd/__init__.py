@@ -26,6 +26,7 @@ DETECT_INVALID = 0x2
 ENFACE_PROJECT = 0x4
 PREALIGN = 0x8
 MULTI_PAIRWISE = 0x10
+HOST_LINE_SEARCH = 0x20
 MAX_LEVELS = 8
 
 TERM_F, TERM_DATA, TERM_STR, TERM_ANG, TERM_REG, TERM_MEAN, TERM_STR05, TERM_ANG05, TERM_ETA, TERM_GP = range(10)
@@ -253,7 +254,8 @@ class Pair:
 
     def __init__(self, sx, sy, *, ox=None, oy=None, ax=None, ay=None, vx=None, vy=None, params: Params | None = None,
                  dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,
-                 project_enface: bool = False, prealign: bool = False, **param_overrides):
+                 project_enface: bool = False, prealign: bool = False, host_line_search: bool = False,
+                 **param_overrides):
         self.ctx = ctx or context(0)
         dev = torch.device("cuda", self.ctx.device)
         self.params = params if params is not None else default_params()
@@ -265,6 +267,8 @@ class Pair:
             self.params.flags |= ENFACE_PROJECT
         if prealign:  # stage-1 rough axial prealignment before ingest
             self.params.flags |= PREALIGN
+        if host_line_search:  # L-BFGS decisions on the host (the device form gives the same bits)
+            self.params.flags |= HOST_LINE_SEARCH
         sx, sy = _f32(sx, dev), _f32(sy, dev)
         h, w, d = sx.shape
         if sy.shape != sx.shape:

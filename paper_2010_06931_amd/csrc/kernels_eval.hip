@@ -205,6 +205,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
 template <typename T, bool AXIAL>
 __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
 {
+    if (jobs.skip && *jobs.skip) return;
     const int wv = uni((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -405,6 +406,7 @@ __device__ __forceinline__ void load_pairs(float (&q0)[16], float (&q1)[16], __a
 template <typename T, bool AXIAL>
 __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
 {
+    if (jobs.skip && *jobs.skip) return;
     const int wv = uni((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -631,6 +633,7 @@ __device__ __forceinline__ int find_job(const int* begins, int n)
 
 __global__ __launch_bounds__(kRedBlock) void k_sum(const SumJobs jobs)
 {
+    if (jobs.skip && *jobs.skip) return;
     int jid = 0;
     for (int q = 1; q < jobs.n; ++q)
         if ((int)blockIdx.x >= jobs.j[q].blk_begin) jid = q;
@@ -736,6 +739,7 @@ __device__ __forceinline__ int next_ascan(int V, int i, int j, int w, int h, dou
 
 __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
 {
+    if (jobs.skip && *jobs.skip) return;
     int jid = 0;
     for (int q = 1; q < jobs.n; ++q)
         if ((int)blockIdx.x >= jobs.j[q].blk_begin) jid = q;
@@ -859,6 +863,7 @@ __global__ __launch_bounds__(kRedBlock) void k_combine(const CombineJobs jobs)
 // the objective terms (mode 1) or the level's eta (mode 0, Eq. 10).
 __global__ __launch_bounds__(kRedBlock) void k_finalize(const CombineJobs jobs)
 {
+    if (jobs.skip && *jobs.skip) return;
     const CombineJob& J = jobs.j[blockIdx.x];
     double s[8];
     sum_rows<8>(J.blk, J.nblk, s);
@@ -1247,6 +1252,7 @@ static hipError_t launch_struct_subsets(const StructJobs& jobs, hipStream_t s)
     // per job, so a job's result does not depend on the other jobs of its
     // launch; each subset has its own grid (a multiple of the 8 XCDs).
     StructJobs even{}, odd{};
+    even.skip = odd.skip = jobs.skip;
     int be = 0, bo = 0;
     for (int q = 0; q < jobs.n; ++q) {
         StructJob J = jobs.j[q];

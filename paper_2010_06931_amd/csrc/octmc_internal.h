@@ -61,6 +61,7 @@ struct EvalArgs {
                                      // false in eval_group, whose structural kernels read [2][na][3]
     bool axial = false;              // dx = dy = 0 everywhere (stage 1): the x, y partials are left at 0
     const EvalView* view = nullptr;  // the level's data, parameters and scratch; null: those of pair at level
+    const int* skip = nullptr;       // device flag: when nonzero every kernel of the evaluation does nothing
 };
 
 // The hot path over up to kMaxJobs jobs (distinct pairs, one storage type,
@@ -74,6 +75,10 @@ int eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev = nullpt
 struct Evaluator {
     virtual ~Evaluator() = default;
     virtual int eval(const EvalArgs& ea, hipStream_t s) = 0;
+    // true when eval() only enqueues the evaluation on s (no host work), so
+    // that a solver may enqueue its iterations ahead with decisions taken on
+    // the device
+    virtual bool enqueue_only() const { return false; }
 };
 
 octmc_dtype pair_dtype(const octmc_pair* pair);
@@ -123,6 +128,7 @@ struct StructJob {
 struct StructJobs {
     StructJob j[kMaxJobs];
     int n;
+    const int* skip = nullptr;  // device flag: when nonzero the whole launch does nothing
 };
 // Blocks of one structural job: one 2 x 2 tile of A-scans per block, in 8
 // bands of whole tile rows (one per XCD).
@@ -138,6 +144,7 @@ struct SumJob {
 struct SumJobs {
     SumJob j[kMaxJobs];
     int n;
+    const int* skip = nullptr;  // device flag: when nonzero the whole launch does nothing
 };
 
 // Hot path, steps 2-4: en face term, validity weight, combination with eta,
@@ -164,6 +171,7 @@ struct CombineJob {
 struct CombineJobs {
     CombineJob j[kMaxJobs];
     int n;
+    const int* skip = nullptr;  // device flag: when nonzero the whole launch does nothing
 };
 
 // ---------------------------------------------------------------------------
@@ -224,9 +232,26 @@ struct LevelStats {
     int iters = 0, evals = 0, ls_fail = 0;
     double f_start = 0, f_end = 0;
 };
-// cubic interpolation step of the zoom phase of the strong Wolfe line
-// search, kept 10 % inside the bracket (runtime.hip)
-double cubic_min(double a0, double f0, double g0, double a1, double f1, double g1);
+// Safeguarded cubic step of the zoom phase of the strong Wolfe line search:
+// the minimiser of the cubic through (a0, f0, g0) and (a1, f1, g1), kept 10 %
+// inside the bracket (its midpoint when the cubic gives nothing usable).  The
+// host line search and the device one share this code; FMA contraction is off
+// so that both round every operation alike.
+__host__ __device__ inline double cubic_min(double a0, double f0, double g0, double a1, double f1, double g1)
+{
+#pragma clang fp contract(off)
+    const double lo = a1 < a0 ? a1 : a0, hi = a0 < a1 ? a1 : a0, span = hi - lo;
+    const double mid = 0.5 * (a0 + a1);
+    const double d1 = g0 + g1 - 3.0 * (f0 - f1) / (a0 - a1);
+    const double disc = d1 * d1 - g0 * g1;
+    if (!(disc >= 0)) return mid;
+    const double d2 = (a1 > a0 ? 1.0 : -1.0) * sqrt(disc);
+    const double den = g1 - g0 + 2.0 * d2;
+    if (den == 0) return mid;
+    const double a = a1 - (a1 - a0) * (g1 + d2 - d1) / den;
+    if (!__builtin_isfinite(a) || a < lo + 0.1 * span || a > hi - 0.1 * span) return mid;
+    return a;
+}
 
 // Segmentation-free en face projection (Sec. 2.3) of one scan; `scratch`
 // holds enface_scratch_bytes(w, h, d) device bytes; `valid` is a device
@@ -263,6 +288,62 @@ struct CombSpec {
     int nv;
 };
 hipError_t launch_lincomb(const CombSpec& spec, size_t n, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// The L-BFGS iteration with its decisions on the device (LevelRun::run_device).
+// Single-thread controller kernels take, in float64 and in the same order of
+// operations, the decisions LevelRun::run takes on the host, and every vector
+// kernel and evaluation of an iteration is predicated on flags they set, so
+// that the host can enqueue iterations ahead without waiting for them.  The
+// history is kept oldest first; where the host swaps buffer pointers, the
+// controllers rotate the device table vec[], so no vector is copied.
+constexpr int kLbMaxM = 6;  // the 3 + 2 m vectors of an iteration's dot products fit one keyed pass
+static_assert(3 + 2 * kLbMaxM <= kMaxDotVecs, "one keyed dot-product pass per iteration");
+struct LbStatus {  // the leading part of LbState that the host reads back
+    int status;    // 0 running; 1 gradient small; 2 line search failed; 3 step limit reached
+    int stall;     // the line search needs more trials than its iteration holds (the host resumes it)
+    int it, evals;
+    int ls_done, ls_ok;
+    double f, f_start;
+};
+static_assert(sizeof(LbStatus) == 40, "status block");
+struct LbState {
+    LbStatus h;
+    int skip_iter;   // status || stall: the iteration's kernels do nothing
+    int skip_trial;  // skip_iter || the line search ended: the trial and its evaluation do nothing
+    int do_accept;   // the accept kernel commits the trial point (set on success, cleared by the next iteration)
+    int resume;      // the host enqueues the trials of a stalled line search one at a time
+    int m, count, has_cand, iters_max, ls_max_evals;
+    int ls_phase, ls_i, ls_start;  // bracketing (0) or zoom (1); trial number; evaluations at its start
+    int ncomb;
+    double c1, c2;
+    // [g, s_c, y_c, S_0 .. S_{m-1}, Y_0 .. Y_{m-1}]: gradient, candidate pair, history oldest first
+    double* vec[3 + 2 * kLbMaxM];
+    double SY[kLbMaxM][kLbMaxM];  // s_k . y_l (k <= l read)
+    double YY[kLbMaxM][kLbMaxM];  // y_k . y_l
+    // search direction p = c_g g + sum_k (c_s[k] S_k + c_y[k] Y_k), k oldest first; gp = g . p
+    double c_g, c_s[kLbMaxM], c_y[kLbMaxM], gp;
+    // strong Wolfe line search
+    double a_try, a_prev, f_prev, g_prev, lo, flo, glo, hi, fhi, ghi, f0, g0;
+};
+struct LbInit {
+    double* vec[3 + 2 * kLbMaxM];
+    int m, iters_max, ls_max_evals;
+    double c1, c2;
+};
+hipError_t launch_lb_init(LbState* st, const LbInit& in, const double* terms, hipStream_t s);
+// the iteration's dot products (and max |g|) over st->vec, skipped with skip_iter
+hipError_t launch_lb_dots(LbState* st, int m, size_t n, double* blk, double* out, hipStream_t s);
+hipError_t launch_lb_c1(LbState* st, const double* dots, hipStream_t s);
+hipError_t launch_lb_lincomb(const LbState* st, size_t n, double* p, hipStream_t s);
+hipError_t launch_lb_trial(const LbState* st, const double* x, const double* p, size_t n, double* xt, float* xt32,
+                           hipStream_t s);
+// last = 1: the iteration's only trial slot (an unfinished search stalls)
+hipError_t launch_lb_c2(LbState* st, const double* terms, int last, hipStream_t s);
+hipError_t launch_lb_accept(const LbState* st, double* x, double* g, const double* xt, const double* gt, size_t n,
+                            hipStream_t s);
+// resume = 1: a stalled line search continues, one trial per host round trip; resume = 0: it ended
+hipError_t launch_lb_resume(LbState* st, int resume, hipStream_t s);
 hipError_t launch_trial(const double* x, const double* p, double alpha, size_t n, double* xt, float* xt32,
                         hipStream_t s);
 hipError_t launch_accept(double* x, double* g, const double* xt, const double* gt, double* s_out,

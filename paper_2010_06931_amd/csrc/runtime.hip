@@ -102,6 +102,10 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
     StructJobs tj{};
     CombineJobs cj{};
     sj.n = tj.n = cj.n = n;
+    // one skip flag for the grouped launch (a solver enqueued ahead of its decisions)
+    sj.skip = tj.skip = cj.skip = ea[0].skip;
+    for (int q = 1; q < n; ++q)
+        if (ea[q].skip != ea[0].skip) return fail(OCTMC_E_INVALID, "grouped evaluations must share their skip flag");
     int sb = 0, tb = 0, cb = 0;
     EvalView views[kMaxJobs];
     for (int q = 0; q < n; ++q) {
@@ -182,6 +186,7 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     if (any_eta) {  // eta of the jobs that ask for it, before their evaluation
         CombineJobs c0{};
+        c0.skip = cj.skip;
         int b0 = 0;
         for (int q = 0; q < n; ++q) {
             if (ea[q].eta_mode != 0) continue;
@@ -212,22 +217,6 @@ int check_level(const octmc_pair* P, int level)
 
 }  // namespace
 
-// cubic interpolation step of the zoom phase, kept 10 % inside the bracket
-double octmc::cubic_min(double a0, double f0, double g0, double a1, double f1, double g1)
-{
-    const double lo = std::min(a0, a1), hi = std::max(a0, a1), span = hi - lo;
-    const double mid = 0.5 * (a0 + a1);
-    const double d1 = g0 + g1 - 3.0 * (f0 - f1) / (a0 - a1);
-    const double disc = d1 * d1 - g0 * g1;
-    if (!(disc >= 0)) return mid;
-    const double d2 = (a1 > a0 ? 1.0 : -1.0) * std::sqrt(disc);
-    const double den = g1 - g0 + 2.0 * d2;
-    if (den == 0) return mid;
-    const double a = a1 - (a1 - a0) * (g1 + d2 - d1) / den;
-    if (!std::isfinite(a) || a < lo + 0.1 * span || a > hi - 0.1 * span) return mid;
-    return a;
-}
-
 namespace {
 
 bool finite_param(double v) { return std::isfinite(v); }
@@ -246,6 +235,7 @@ int octmc::pair_alloc_scratch(octmc_pair* P, size_t na, hipStream_t s)
     HIP_TRY(P->alloc(&P->terms, OCTMC_NTERMS * 8));
     HIP_TRY(P->alloc(&P->dot_blk, (size_t)512 * (kMaxDots + 1) * 8));
     HIP_TRY(P->alloc(&P->dot_out, (kMaxDots + 1) * 8));
+    HIP_TRY(P->alloc(&P->lb, sizeof(LbState)));
     static const std::vector<double> ones(OCTMC_MAX_LEVELS, 1.0);
     HIP_TRY(hipMemcpyAsync(P->eta, ones.data(), OCTMC_MAX_LEVELS * 8, hipMemcpyHostToDevice, s));
     return OCTMC_OK;
@@ -295,7 +285,7 @@ int octmc::validate_params(const octmc_params* p)
     if (p->prealign_iters < 0) return fail(OCTMC_E_INVALID, "prealign_iters must be >= 0");
     if (p->gamma_tilt < 0) return fail(OCTMC_E_INVALID, "gamma_tilt must be >= 0");
     if (p->flags & ~(OCTMC_CHECK_NAN | OCTMC_DETECT_INVALID | OCTMC_ENFACE_PROJECT | OCTMC_PREALIGN |
-                     OCTMC_MULTI_PAIRWISE))
+                     OCTMC_MULTI_PAIRWISE | OCTMC_HOST_LINE_SEARCH))
         return fail(OCTMC_E_INVALID, "unknown flags");
     return OCTMC_OK;
 }
@@ -355,7 +345,7 @@ size_t octmc::pair_footprint(const octmc_params& pr, const octmc_shape& sh, bool
     t += slab_bytes(na * 8 * 4) + slab_bytes(kSumBlocks * 4 * 8) +
          slab_bytes((size_t)nblk_combine((int)na) * 8 * 8) + slab_bytes(OCTMC_MAX_LEVELS * 8) +
          slab_bytes(OCTMC_NTERMS * 8) + slab_bytes((size_t)512 * (kMaxDots + 1) * 8) +
-         slab_bytes((kMaxDots + 1) * 8);
+         slab_bytes((kMaxDots + 1) * 8) + slab_bytes(sizeof(LbState));
     const size_t n0 = 6 * na;
     t += (size_t)(8 + 2 * pr.lbfgs_m) * slab_bytes(n0 * 8) + slab_bytes(n0 * 4);  // solver
     if (merged) t += slab_bytes(2 * na * 8) + slab_bytes(na * 16);                 // merge
@@ -1023,6 +1013,9 @@ int octmc::register_impl(octmc_pair* pair, float* disp_out, float* merged_oct, f
         std::memset(rep, 0, sizeof(*rep));
         rep->nlevels = pair->nlev;
     }
+    // the iteration's decisions on the device when the evaluator only
+    // enqueues work and the history fits one keyed dot-product pass
+    const bool device_ls = ev->enqueue_only() && !(pr.flags & OCTMC_HOST_LINE_SEARCH) && sv.m <= kLbMaxM;
     for (int l = pair->nlev - 1; l >= 0; --l) {
         const Level& L = pair->lev[l];
         const size_t n = (size_t)6 * L.na;
@@ -1036,7 +1029,10 @@ int octmc::register_impl(octmc_pair* pair, float* disp_out, float* merged_oct, f
         sv.n = n;
         LevelRun run{pair, l, &sv, s, n, h_terms, h_dots, ev};
         LevelStats st;
-        OCTMC_TRY(run.run(pr, st));
+        if (device_ls)
+            OCTMC_TRY(run.run_device(pr, st));
+        else
+            OCTMC_TRY(run.run(pr, st));
         if (rep) {
             const int r = pair->nlev - 1 - l;
             rep->iters[r] = st.iters;

@@ -67,6 +67,7 @@ struct octmc_pair {
     double* terms = nullptr;    // [OCTMC_NTERMS] solver scratch
     double* dot_blk = nullptr;  // [512][kMaxDots + 1]
     double* dot_out = nullptr;  // [kMaxDots + 1]
+    octmc::LbState* lb = nullptr;  // the device solver's state (LevelRun::run_device)
     std::vector<void*> owned;
     octmc::Slab* slab = nullptr;  // when set, all device memory comes from it
     std::atomic<int> busy{0};  // a solve holds the pair (taken by compare-and-swap)
@@ -190,6 +191,137 @@ struct LevelRun {
                 lo = aj; flo = fj; glo = gj;
             }
         }
+    }
+
+    // The same iteration as run(), with every decision taken on the device by
+    // the k_lb_* controllers and every kernel of an iteration predicated on
+    // their flags: the host enqueues kLbBatch iterations at a time, keeps two
+    // batches in flight and reads a 40-byte status per batch.  Each iteration
+    // holds one trial of its line search; a search that needs more stalls the
+    // later iterations, which then do nothing, and the host drives its
+    // remaining trials one round trip at a time, as run() does (so too for the
+    // first iteration of a level, whose unit step along the scaled steepest
+    // descent direction is the one least often accepted at once).
+    static constexpr int kLbBatch = 4;
+    int run_device(const octmc_params& pr, LevelStats& st)
+    {
+        LbState* S = P->lb;
+        const int m = sv->m;
+        HIP_TRY(launch_to_f32(sv->x, sv->xt32, n, s));
+        {
+            EvalArgs ea{P, sv->xt32, P->terms, nullptr, nullptr, sv->g, level, 0};
+            OCTMC_TRY(ev->eval(ea, s));
+        }
+        LbInit in{};
+        in.vec[0] = sv->g;
+        in.vec[1] = sv->sc;
+        in.vec[2] = sv->yc;
+        for (int k = 0; k < m; ++k) {
+            in.vec[3 + k] = sv->S[k];
+            in.vec[3 + m + k] = sv->Y[k];
+        }
+        in.m = m;
+        in.iters_max = pr.iters_per_level;
+        in.ls_max_evals = pr.ls_max_evals;
+        in.c1 = pr.c1;
+        in.c2 = pr.c2;
+        HIP_TRY(launch_lb_init(S, in, P->terms, s));
+        LbStatus* hs = reinterpret_cast<LbStatus*>(h_dots);  // three 40-byte slots of the pinned buffer
+        static_assert(3 * sizeof(LbStatus) <= (kMaxDots + 1) * sizeof(double), "status slots");
+        struct Events {
+            hipEvent_t e[2] = {nullptr, nullptr};
+            ~Events()
+            {
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } evs;
+        for (hipEvent_t& e : evs.e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        auto trial_slot = [&](int last) -> int {
+            HIP_TRY(launch_lb_trial(S, sv->x, sv->p, n, sv->xt, sv->xt32, s));
+            EvalArgs ea{P, sv->xt32, P->terms, nullptr, sv->p, sv->gt, level, 1};
+            ea.skip = &S->skip_trial;
+            OCTMC_TRY(ev->eval(ea, s));
+            HIP_TRY(launch_lb_c2(S, P->terms, last, s));
+            return OCTMC_OK;
+        };
+        auto head = [&]() -> int {  // dot products, history update, direction
+            HIP_TRY(launch_lb_dots(S, m, n, P->dot_blk, P->dot_out, s));
+            HIP_TRY(launch_lb_c1(S, P->dot_out, s));
+            HIP_TRY(launch_lb_lincomb(S, n, sv->p, s));
+            return OCTMC_OK;
+        };
+        auto read_now = [&](LbStatus& out) -> int {
+            HIP_TRY(hipMemcpyAsync(&hs[2], S, sizeof(LbStatus), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            out = hs[2];
+            return OCTMC_OK;
+        };
+        // the trials of a stalled line search, then its accept
+        auto finish_search = [&](LbStatus& out) -> int {
+            HIP_TRY(launch_lb_resume(S, 1, s));
+            for (int r = 0;; ++r) {  // at most ls_max_evals trials end a search
+                if (r > pr.ls_max_evals) return fail(OCTMC_E_DEVICE, "device line search did not end");
+                OCTMC_TRY(trial_slot(0));
+                OCTMC_TRY(read_now(out));
+                if (out.ls_done) break;
+            }
+            HIP_TRY(launch_lb_resume(S, 0, s));
+            HIP_TRY(launch_lb_accept(S, sv->x, sv->g, sv->xt, sv->gt, n, s));
+            return OCTMC_OK;
+        };
+        LbStatus cur{};
+        OCTMC_TRY(read_now(cur));
+        if (cur.status == 0) {  // the first iteration, with its trials one at a time
+            OCTMC_TRY(head());
+            OCTMC_TRY(read_now(cur));
+            if (cur.status == 0) OCTMC_TRY(finish_search(cur));
+        }
+        struct Batch {
+            int slot, k;
+        };
+        Batch q[2];
+        int nq = 0, next = 0;
+        int it_known = cur.it, inflight = 0;  // inflight: iterations enqueued after the status last read
+        while (cur.status == 0) {
+            while (nq < 2 && it_known + inflight < pr.iters_per_level) {
+                const int k = std::min(kLbBatch, pr.iters_per_level - it_known - inflight);
+                for (int i = 0; i < k; ++i) {
+                    OCTMC_TRY(head());
+                    OCTMC_TRY(trial_slot(1));
+                    HIP_TRY(launch_lb_accept(S, sv->x, sv->g, sv->xt, sv->gt, n, s));
+                }
+                HIP_TRY(hipMemcpyAsync(&hs[next], S, sizeof(LbStatus), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipEventRecord(evs.e[next], s));
+                q[nq++] = Batch{next, k};
+                next ^= 1;
+                inflight += k;
+            }
+            if (nq == 0) break;  // every step the level allows is made (the status says so)
+            const Batch b = q[0];
+            q[0] = q[1];
+            --nq;
+            HIP_TRY(hipEventSynchronize(evs.e[b.slot]));
+            cur = hs[b.slot];
+            inflight -= b.k;
+            it_known = cur.it;
+            if (cur.status != 0) break;
+            if (cur.stall) {  // the iterations enqueued after the stall do nothing
+                HIP_TRY(hipStreamSynchronize(s));
+                nq = 0;
+                inflight = 0;
+                OCTMC_TRY(finish_search(cur));
+                it_known = cur.it;
+            }
+        }
+        OCTMC_TRY(read_now(cur));
+        st.iters = cur.it;
+        st.evals = cur.evals;
+        st.f_start = cur.f_start;
+        st.f_end = cur.f;
+        st.ls_fail = cur.status == 2;
+        evals = cur.evals;
+        return OCTMC_OK;
     }
 
     int run(const octmc_params& pr, LevelStats& st)
@@ -378,6 +510,7 @@ struct LevelRun {
 
 struct DirectEvaluator final : Evaluator {
     int eval(const EvalArgs& ea, hipStream_t s) override { return eval_group(&ea, 1, s); }
+    bool enqueue_only() const override { return true; }
 };
 
 }  // namespace octmc

@@ -111,6 +111,7 @@ struct Worker {
 
 struct DirectEval final : Evaluator {
     int eval(const EvalArgs& ea, hipStream_t s) override { return eval_group(&ea, 1, s); }
+    bool enqueue_only() const override { return true; }
 };
 
 }  // namespace
