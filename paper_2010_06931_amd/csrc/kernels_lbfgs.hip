@@ -157,15 +157,13 @@ struct RowMap {
 };
 constexpr int kFinalThreads = 1024;
 
-__global__ __launch_bounds__(kFinalThreads) void k_multidot_final(int nrow, int gmax_row, int nblk, const RowMap map,
-                                                                  const double* __restrict__ blk,
-                                                                  double* __restrict__ out,
-                                                                  const int* __restrict__ skip)
+// rows q of the final sums, dealt to the block's waves (nthreads / 64)
+__device__ __forceinline__ void final_rows(int nrow, int gmax_row, int nblk, const RowMap& map,
+                                           const double* __restrict__ blk, double* out, int nthreads)
 {
-    if (skip && *skip) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int per = (nblk + 63) / 64;
-    for (int q = wv; q < nrow; q += kFinalThreads / 64) {
+    for (int q = wv; q < nrow; q += nthreads / 64) {
         const bool mx = q == gmax_row;
         const int r = map.row[q];
         double s = 0.0;
@@ -179,6 +177,13 @@ __global__ __launch_bounds__(kFinalThreads) void k_multidot_final(int nrow, int 
         s = wave_reduce(s, mx);
         if (lane == 0) out[q] = s;
     }
+}
+
+__global__ __launch_bounds__(kFinalThreads) void k_multidot_final(int nrow, int gmax_row, int nblk, const RowMap map,
+                                                                  const double* __restrict__ blk,
+                                                                  double* __restrict__ out)
+{
+    final_rows(nrow, gmax_row, nblk, map, blk, out, kFinalThreads);
 }
 
 __global__ void k_lincomb(const CombSpec spec, size_t n, double* __restrict__ out)
@@ -291,8 +296,7 @@ hipError_t launch_multidot(const DotSpec& spec, size_t n, double* blk, double* o
         for (int q = 0; q <= nd; ++q) map.row[q] = (unsigned char)q;
         hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(kB), 0, s, spec, n, blk);
     }
-    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(kFinalThreads), 0, s, nd + 1, nd, nb, map, blk, out,
-                       nullptr);
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(kFinalThreads), 0, s, nd + 1, nd, nb, map, blk, out);
     return hipGetLastError();
 }
 hipError_t launch_lincomb(const CombSpec& spec, size_t n, double* out, hipStream_t s)
@@ -330,16 +334,35 @@ hipError_t launch_fill_u32(unsigned* p, unsigned v, size_t n, hipStream_t s)
 
 
 // ===========================================================================
-// The iteration with its decisions on the device.  The controllers run on one
-// lane; they follow LevelRun::run step for step (the same tests, the same
-// float64 expressions in the same order, FMA contraction off), so that the
-// two forms give the same iterates bit for bit.
+// The iteration with its decisions on the device.  The controllers follow
+// LevelRun::run step for step (the same tests, the same float64 expressions
+// in the same order, FMA contraction off), so that the two forms give the
+// same iterates bit for bit.  Each controller launch reads the whole state
+// (and its inputs) into LDS with all its lanes in one round of loads, takes
+// the decisions on one lane, and writes the state back with all lanes: its
+// cost is then about two memory round trips rather than one per dependent
+// field.
 
 namespace {
 
 constexpr int M = kLbMaxM;
+static_assert(sizeof(LbState) % 8 == 0 && alignof(LbState) == 8, "the state moves as 64-bit words");
+constexpr int kLbWords = (int)(sizeof(LbState) / 8);
 
-__device__ void lb_stop(LbState* st, int status)
+__device__ __forceinline__ void state_in(LbState& S, const LbState* st, int nthreads)
+{
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(st);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(&S);
+    for (int w = threadIdx.x; w < kLbWords; w += nthreads) dst[w] = src[w];
+}
+__device__ __forceinline__ void state_out(LbState* st, const LbState& S, int nthreads)
+{
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(&S);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(st);
+    for (int w = threadIdx.x; w < kLbWords; w += nthreads) dst[w] = src[w];
+}
+
+__device__ __forceinline__ void lb_stop(LbState* st, int status)
 {
     st->h.status = status;
     st->skip_iter = 1;
@@ -384,11 +407,10 @@ __global__ __launch_bounds__(64) void k_lb_init(LbState* __restrict__ st, const 
 // direction from the compact form and the start of the line search.  The dot
 // products are by position: 0 g.g; 1+k S_k.g; 1+m+k Y_k.g; 1+2m+k S_k.y_c;
 // 1+3m+k y_c.Y_k; 1+4m s_c.g; 2+4m y_c.g; 3+4m s_c.y_c; 4+4m y_c.y_c; 5+4m
-// max |g|.  Every register array is indexed by unrolled constants only.
-__global__ __launch_bounds__(64) void k_lb_c1(LbState* __restrict__ st, const double* __restrict__ dots)
+// max |g|.  Every array is indexed by unrolled constants only.
+__device__ __forceinline__ void c1_decide(LbState* st, const double* dots)
 {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0) return;
     st->do_accept = 0;  // the previous iteration's accept has run
     if (st->skip_iter) return;
     if (st->h.it >= st->iters_max) {
@@ -398,14 +420,12 @@ __global__ __launch_bounds__(64) void k_lb_c1(LbState* __restrict__ st, const do
     const int m = st->m;
     int c = st->count;
     const double gg = dots[0], gmax = dots[5 + 4 * m];
-    double SY[M][M], YY[M][M], a_s[M], b_y[M];
+    // the history's products are updated in place (st is the launch's LDS copy)
+    double(&SY)[M][M] = st->SY;
+    double(&YY)[M][M] = st->YY;
+    double a_s[M], b_y[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-#pragma unroll
-        for (int l = 0; l < M; ++l) {
-            SY[k][l] = st->SY[k][l];
-            YY[k][l] = st->YY[k][l];
-        }
         a_s[k] = k < c ? dots[1 + k] : 0.0;
         b_y[k] = k < c ? dots[1 + m + k] : 0.0;
     }
@@ -471,13 +491,6 @@ __global__ __launch_bounds__(64) void k_lb_c1(LbState* __restrict__ st, const do
         }
         st->has_cand = 0;
     }
-#pragma unroll
-    for (int k = 0; k < M; ++k)
-#pragma unroll
-        for (int l = 0; l < M; ++l) {
-            st->SY[k][l] = SY[k][l];
-            st->YY[k][l] = YY[k][l];
-        }
     const double f = st->h.f;
     const double af = fabs(f);
     if (gmax <= 1e-10 * (1.0 < af ? af : 1.0)) {
@@ -562,12 +575,30 @@ __global__ __launch_bounds__(64) void k_lb_c1(LbState* __restrict__ st, const do
     st->skip_trial = 0;
 }
 
-__global__ void k_lb_lincomb(const LbState* __restrict__ st, size_t n, double* __restrict__ out)
+// The final sums of the iteration's dot products (as k_multidot_final forms
+// them), then c1_decide.
+__global__ __launch_bounds__(kFinalThreads) void k_lb_c1(LbState* __restrict__ st, int nd, int nblk,
+                                                         const RowMap map, const double* __restrict__ blk)
+{
+    __shared__ LbState S;
+    __shared__ double dots[kMaxDots + 1];
+    state_in(S, st, kFinalThreads);
+    final_rows(nd + 1, nd, nblk, map, blk, dots, kFinalThreads);
+    __syncthreads();
+    if (threadIdx.x == 0) c1_decide(&S, dots);
+    __syncthreads();
+    state_out(st, S, kFinalThreads);
+}
+
+// The search direction and the first trial point x + p (a_try = 1 after
+// c1_decide), each term in the order of k_lincomb and k_trial.
+__global__ void k_lb_lincomb(const LbState* __restrict__ st, const double* __restrict__ x, size_t n,
+                             double* __restrict__ out, double* __restrict__ xt, float* __restrict__ xt32)
 {
     if (st->skip_iter) return;
     const int nc = st->ncomb, m = st->m;
     const double* g = st->vec[0];
-    const double cg = st->c_g;
+    const double cg = st->c_g, alpha = st->a_try;
     const double* sp[M];
     const double* yp[M];
     double cs[M], cy[M];
@@ -578,7 +609,6 @@ __global__ void k_lb_lincomb(const LbState* __restrict__ st, size_t n, double* _
         cs[k] = st->c_s[k];
         cy[k] = st->c_y[k];
     }
-    // the terms in the order of k_lincomb's: g, then S_k, Y_k oldest first
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
         double s = fma(cg, g[t], 0.0);
 #pragma unroll
@@ -589,6 +619,9 @@ __global__ void k_lb_lincomb(const LbState* __restrict__ st, size_t n, double* _
             }
         }
         out[t] = s;
+        const double v = fma(alpha, s, x[t]);
+        xt[t] = v;
+        xt32[t] = (float)v;
     }
 }
 
@@ -606,12 +639,10 @@ __global__ void k_lb_trial(const LbState* __restrict__ st, const double* __restr
 
 // After a trial evaluation: one step of the strong Wolfe line search
 // (bracketing, then zoom with the safeguarded cubic step).
-__global__ __launch_bounds__(64) void k_lb_c2(LbState* __restrict__ st, const double* __restrict__ terms, int last)
+__device__ __forceinline__ void c2_decide(LbState* st, double fa, double ga, int last)
 {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0) return;
     if (st->skip_trial) return;
-    const double fa = terms[OCTMC_TERM_F], ga = terms[OCTMC_TERM_GP];
     const double a = st->a_try, f0 = st->f0, g0 = st->g0, c1 = st->c1, c2 = st->c2;
     st->h.evals += 1;
     bool ok = false;
@@ -683,6 +714,20 @@ __global__ __launch_bounds__(64) void k_lb_c2(LbState* __restrict__ st, const do
     }
 }
 
+__global__ __launch_bounds__(64) void k_lb_c2(LbState* __restrict__ st, const double* __restrict__ terms, int last)
+{
+    __shared__ LbState S;
+    __shared__ double fg[2];
+    state_in(S, st, 64);
+    if (threadIdx.x == 0) fg[0] = terms[OCTMC_TERM_F];
+    if (threadIdx.x == 1) fg[1] = terms[OCTMC_TERM_GP];
+    __syncthreads();
+    const bool run = !S.skip_trial;  // uniform
+    if (threadIdx.x == 0) c2_decide(&S, fg[0], fg[1], last);
+    __syncthreads();
+    if (run) state_out(st, S, 64);
+}
+
 __global__ void k_lb_accept(const LbState* __restrict__ st, double* __restrict__ x, double* __restrict__ g,
                             const double* __restrict__ xt, const double* __restrict__ gt, size_t n)
 {
@@ -721,11 +766,12 @@ hipError_t launch_lb_init(LbState* st, const LbInit& in, const double* terms, hi
     hipLaunchKernelGGL(k_lb_init, dim3(1), dim3(64), 0, s, st, in, terms);
     return hipGetLastError();
 }
-hipError_t launch_lb_dots(LbState* st, int m, size_t n, double* blk, double* out, hipStream_t s)
+hipError_t launch_lb_head(LbState* st, int m, size_t n, double* blk, const double* x, double* p, double* xt,
+                          float* xt32, hipStream_t s)
 {
     if (m < 1 || m > kLbMaxM) return hipErrorInvalidValue;
     // vectors 0 g, 1 s_c, 2 y_c, 3 + k S_k, 3 + m + k Y_k; the products in the
-    // order k_lb_c1 reads them
+    // order c1_decide reads them
     DotSpec ds{};
     int nd = 0;
     auto dot = [&](int a, int b) {
@@ -749,19 +795,9 @@ hipError_t launch_lb_dots(LbState* st, int m, size_t n, double* blk, double* out
     RowMap map;
     if (nd > kMaxDots || !keyed_plan(ds, kd, map) || kd.nv != 3 + 2 * m || kd.key1 != 2) return hipErrorInvalidValue;
     const int nb = grid_for(n, kMaxBlocks);
-    const int* skip = &st->skip_iter;
-    hipLaunchKernelGGL(k_multidot_keyed<true>, dim3(nb), dim3(kB), 0, s, kd, st->vec, skip, n, blk);
-    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(kFinalThreads), 0, s, nd + 1, nd, nb, map, blk, out, skip);
-    return hipGetLastError();
-}
-hipError_t launch_lb_c1(LbState* st, const double* dots, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_lb_c1, dim3(1), dim3(64), 0, s, st, dots);
-    return hipGetLastError();
-}
-hipError_t launch_lb_lincomb(const LbState* st, size_t n, double* p, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_lb_lincomb, dim3(grid_for(n)), dim3(256), 0, s, st, n, p);
+    hipLaunchKernelGGL(k_multidot_keyed<true>, dim3(nb), dim3(kB), 0, s, kd, st->vec, &st->skip_iter, n, blk);
+    hipLaunchKernelGGL(k_lb_c1, dim3(1), dim3(kFinalThreads), 0, s, st, nd, nb, map, blk);
+    hipLaunchKernelGGL(k_lb_lincomb, dim3(grid_for(n)), dim3(256), 0, s, st, x, n, p, xt, xt32);
     return hipGetLastError();
 }
 hipError_t launch_lb_trial(const LbState* st, const double* x, const double* p, size_t n, double* xt, float* xt32,

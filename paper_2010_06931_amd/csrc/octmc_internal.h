@@ -332,10 +332,13 @@ struct LbInit {
     double c1, c2;
 };
 hipError_t launch_lb_init(LbState* st, const LbInit& in, const double* terms, hipStream_t s);
-// the iteration's dot products (and max |g|) over st->vec, skipped with skip_iter
-hipError_t launch_lb_dots(LbState* st, int m, size_t n, double* blk, double* out, hipStream_t s);
-hipError_t launch_lb_c1(LbState* st, const double* dots, hipStream_t s);
-hipError_t launch_lb_lincomb(const LbState* st, size_t n, double* p, hipStream_t s);
+// The head of an iteration, each kernel skipped with skip_iter: the dot
+// products (and max |g|) over st->vec into the block partials blk, the
+// history update and search direction, then p and the first trial point
+// x + p (xt, and xt32 in float32).
+hipError_t launch_lb_head(LbState* st, int m, size_t n, double* blk, const double* x, double* p, double* xt,
+                          float* xt32, hipStream_t s);
+// a further trial point x + a_try p (skipped with skip_trial)
 hipError_t launch_lb_trial(const LbState* st, const double* x, const double* p, size_t n, double* xt, float* xt32,
                            hipStream_t s);
 // last = 1: the iteration's only trial slot (an unfinished search stalls)

@@ -199,9 +199,10 @@ struct LevelRun {
     // batches in flight and reads a 40-byte status per batch.  Each iteration
     // holds one trial of its line search; a search that needs more stalls the
     // later iterations, which then do nothing, and the host drives its
-    // remaining trials one round trip at a time, as run() does (so too for the
-    // first iteration of a level, whose unit step along the scaled steepest
-    // descent direction is the one least often accepted at once).
+    // remaining trials one round trip at a time, as run() does.  The first
+    // iteration of a level, whose unit step along the scaled steepest descent
+    // direction is the one least often accepted at once, is enqueued alone
+    // and continued in the same way without stalling.
     static constexpr int kLbBatch = 4;
     int run_device(const octmc_params& pr, LevelStats& st)
     {
@@ -237,18 +238,20 @@ struct LevelRun {
             }
         } evs;
         for (hipEvent_t& e : evs.e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        auto trial_slot = [&](int last) -> int {
-            HIP_TRY(launch_lb_trial(S, sv->x, sv->p, n, sv->xt, sv->xt32, s));
+        // the evaluation at the trial point and the line-search step after it
+        auto eval_step = [&](int last) -> int {
             EvalArgs ea{P, sv->xt32, P->terms, nullptr, sv->p, sv->gt, level, 1};
             ea.skip = &S->skip_trial;
             OCTMC_TRY(ev->eval(ea, s));
             HIP_TRY(launch_lb_c2(S, P->terms, last, s));
             return OCTMC_OK;
         };
-        auto head = [&]() -> int {  // dot products, history update, direction
-            HIP_TRY(launch_lb_dots(S, m, n, P->dot_blk, P->dot_out, s));
-            HIP_TRY(launch_lb_c1(S, P->dot_out, s));
-            HIP_TRY(launch_lb_lincomb(S, n, sv->p, s));
+        // one iteration: dot products, history update, direction and its
+        // first trial point, the evaluation there, then the accept
+        auto iteration = [&](int last) -> int {
+            HIP_TRY(launch_lb_head(S, m, n, P->dot_blk, sv->x, sv->p, sv->xt, sv->xt32, s));
+            OCTMC_TRY(eval_step(last));
+            HIP_TRY(launch_lb_accept(S, sv->x, sv->g, sv->xt, sv->gt, n, s));
             return OCTMC_OK;
         };
         auto read_now = [&](LbStatus& out) -> int {
@@ -262,7 +265,8 @@ struct LevelRun {
             HIP_TRY(launch_lb_resume(S, 1, s));
             for (int r = 0;; ++r) {  // at most ls_max_evals trials end a search
                 if (r > pr.ls_max_evals) return fail(OCTMC_E_DEVICE, "device line search did not end");
-                OCTMC_TRY(trial_slot(0));
+                HIP_TRY(launch_lb_trial(S, sv->x, sv->p, n, sv->xt, sv->xt32, s));
+                OCTMC_TRY(eval_step(0));
                 OCTMC_TRY(read_now(out));
                 if (out.ls_done) break;
             }
@@ -272,10 +276,10 @@ struct LevelRun {
         };
         LbStatus cur{};
         OCTMC_TRY(read_now(cur));
-        if (cur.status == 0) {  // the first iteration, with its trials one at a time
-            OCTMC_TRY(head());
+        if (cur.status == 0) {  // the first iteration, then its further trials one at a time
+            OCTMC_TRY(iteration(0));
             OCTMC_TRY(read_now(cur));
-            if (cur.status == 0) OCTMC_TRY(finish_search(cur));
+            if (cur.status == 0 && !cur.ls_done) OCTMC_TRY(finish_search(cur));
         }
         struct Batch {
             int slot, k;
@@ -286,11 +290,7 @@ struct LevelRun {
         while (cur.status == 0) {
             while (nq < 2 && it_known + inflight < pr.iters_per_level) {
                 const int k = std::min(kLbBatch, pr.iters_per_level - it_known - inflight);
-                for (int i = 0; i < k; ++i) {
-                    OCTMC_TRY(head());
-                    OCTMC_TRY(trial_slot(1));
-                    HIP_TRY(launch_lb_accept(S, sv->x, sv->g, sv->xt, sv->gt, n, s));
-                }
+                for (int i = 0; i < k; ++i) OCTMC_TRY(iteration(1));
                 HIP_TRY(hipMemcpyAsync(&hs[next], S, sizeof(LbStatus), hipMemcpyDeviceToHost, s));
                 HIP_TRY(hipEventRecord(evs.e[next], s));
                 q[nq++] = Batch{next, k};
