@@ -88,7 +88,9 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
                                        single-thread kernels in the same float64 operations, with
                                        the same result bit for bit, and the host enqueues several
                                        iterations ahead (lbfgs_m <= 6; the host form otherwise, and
-                                       always for octmc_multi_register and grouped serving) */
+                                       always for octmc_multi_register and grouped serving).  Applies
+                                       to octmc_register and to the stage-1 solve (octmc_prealign,
+                                       OCTMC_PREALIGN) */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the
  * solver.  [P] = value fixed by the paper; [R] = a reading of a point the
@@ -283,7 +285,8 @@ OCTMC_API int octmc_enface_workspace_size(int32_t w, int32_t h, int32_t d, uint6
  * field (the pair's parameters and stored eta; the paper's stage 1 has
  * delta0 = 0, as the pair OCTMC_PREALIGN creates), T (host, may be NULL) and
  * d(F + T)/d(theta) (host float64[2 (h + w)], may be NULL).  Synchronises
- * `stream`.  Errors: OCTMC_E_INVALID, OCTMC_E_OOM, OCTMC_E_NAN, OCTMC_E_DEVICE. */
+ * `stream`.  Errors: OCTMC_E_INVALID, OCTMC_E_BUSY (a solve holds the pair),
+ * OCTMC_E_OOM, OCTMC_E_NAN, OCTMC_E_DEVICE. */
 OCTMC_API int octmc_prealign_eval(octmc_pair* pair, int32_t level, const double* theta, double gamma_tilt,
                                   double* terms, double* tilt_term, double* grad_theta, void* stream);
 
@@ -292,8 +295,11 @@ OCTMC_API int octmc_prealign_eval(octmc_pair* pair, int32_t level, const double*
  * line search constants), between levels the fine field is twice the coarse
  * field at the fine A-scan's coarse position, linear along the fast axis and
  * interpolated linearly between B-scans.  theta_out: host float64[2 (h + w)]
- * at the finest level; rep (may be NULL) as octmc_register (eta = 1).
- * Synchronises `stream`.  Errors: as octmc_prealign_eval. */
+ * at the finest level; rep (may be NULL) as octmc_register (eta = 1).  The
+ * L-BFGS iteration is octmc_register's, with its decisions on the device
+ * unless the pair's flags hold OCTMC_HOST_LINE_SEARCH (the same result bit for
+ * bit).  Synchronises `stream`.  Errors: as octmc_prealign_eval (OCTMC_E_NAN:
+ * the objective is not finite at the end of a level). */
 OCTMC_API int octmc_prealign(octmc_pair* pair, double gamma_tilt, int32_t iters_per_level, double* theta_out,
                              octmc_report* rep, void* stream);
 

@@ -16,8 +16,9 @@ namespace {
 // [2][h][w][3] float32 field (dx = dy = 0) and, if dz != nullptr, the axial
 // component alone as [2][h][w].
 __global__ void k_tilt_expand(const double* __restrict__ th, int w, int h, float* __restrict__ disp,
-                              float* __restrict__ dz)
+                              float* __restrict__ dz, const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     const size_t na = (size_t)w * h;
     const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= 2 * na) return;
@@ -39,8 +40,9 @@ __global__ void k_tilt_expand(const double* __restrict__ th, int w, int h, float
 // Adjoint of the expansion: one wave per B-scan sums the axial gradient and
 // its first moment about the B-scan centre in float64, in a fixed order.
 __global__ __launch_bounds__(256) void k_tilt_reduce(const float* __restrict__ grad, int w, int h,
-                                                     double* __restrict__ gth)
+                                                     double* __restrict__ gth, const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     const int lane = threadIdx.x & 63;
     const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wid >= h + w) return;  // uniform per wave
@@ -66,6 +68,57 @@ __global__ __launch_bounds__(256) void k_tilt_reduce(const float* __restrict__ g
         o[0] = s0;
         o[1] = s1;
     }
+}
+
+// Sum over a 256-thread workgroup in a fixed tree order (every thread gets it).
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// The tilt term of one evaluation: T = sum_V kappa_V (sum_b t_b)^2 with
+// kappa_V = gamma_t d n_f (n_f^2 - 1) / (24 n_b), its gradient 2 kappa_V
+// sum_b t_b on every tilt of scan V, then F + T and g . p.
+__global__ __launch_bounds__(256) void k_tilt_finish(const double* __restrict__ th, double* __restrict__ g, int w,
+                                                     int h, int d, double gamma, const double* __restrict__ tin,
+                                                     const double* __restrict__ p, double* __restrict__ tout,
+                                                     double* __restrict__ T_out, const int* __restrict__ skip)
+{
+    if (skip && *skip) return;
+    __shared__ double sh[256];
+    double sum[2], kap[2];
+    for (int V = 0; V < 2; ++V) {
+        const int nb = V == 0 ? h : w, nf = V == 0 ? w : h;
+        const double* t = th + (V == 0 ? 0 : 2 * (size_t)h);
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) v += t[2 * b + 1];
+        sum[V] = block_sum(v, sh);
+        kap[V] = gamma * d * (double)nf * ((double)nf * nf - 1.0) / (24.0 * nb);
+    }
+    const double T = kap[0] * sum[0] * sum[0] + kap[1] * sum[1] * sum[1];
+    const int n = 2 * (w + h);
+    double gp = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        double gk = g[k];
+        if (k & 1) gk += 2.0 * (k < 2 * h ? kap[0] * sum[0] : kap[1] * sum[1]);
+        g[k] = gk;
+        if (p) gp += gk * p[k];
+    }
+    gp = block_sum(gp, sh);
+    if (threadIdx.x < OCTMC_NTERMS) {
+        const int q = threadIdx.x;
+        tout[q] = q == OCTMC_TERM_F ? tin[q] + T : (q == OCTMC_TERM_GP ? gp : tin[q]);
+    }
+    if (threadIdx.x == 0 && T_out) *T_out = T;
 }
 
 // out(i, j, k) = I(vol, i, j, k + dz(i, j)): the cubic Hermite interpolator
@@ -102,16 +155,28 @@ __global__ void k_resample_z(const float* __restrict__ vol, const float* __restr
 
 }  // namespace
 
-hipError_t launch_tilt_expand(const double* theta, int w, int h, float* disp, float* dz, hipStream_t s)
+hipError_t launch_tilt_expand(const double* theta, int w, int h, float* disp, float* dz, hipStream_t s,
+                              const int* skip)
 {
     const size_t n = 2 * (size_t)w * h;
-    hipLaunchKernelGGL(k_tilt_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, w, h, disp, dz);
+    hipLaunchKernelGGL(k_tilt_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, w, h, disp, dz,
+                       skip);
     return hipGetLastError();
 }
 
-hipError_t launch_tilt_reduce(const float* grad, int w, int h, double* gtheta, hipStream_t s)
+hipError_t launch_tilt_reduce(const float* grad, int w, int h, double* gtheta, hipStream_t s, const int* skip)
 {
-    hipLaunchKernelGGL(k_tilt_reduce, dim3((unsigned)((w + h + 3) / 4)), dim3(256), 0, s, grad, w, h, gtheta);
+    hipLaunchKernelGGL(k_tilt_reduce, dim3((unsigned)((w + h + 3) / 4)), dim3(256), 0, s, grad, w, h, gtheta,
+                       skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_tilt_finish(const double* theta, double* gtheta, int w, int h, int d, double gamma_t,
+                              const double* terms_in, const double* p, double* terms_out, double* T_out,
+                              hipStream_t s, const int* skip)
+{
+    hipLaunchKernelGGL(k_tilt_finish, dim3(1), dim3(256), 0, s, theta, gtheta, w, h, d, gamma_t, terms_in, p,
+                       terms_out, T_out, skip);
     return hipGetLastError();
 }
 

@@ -62,6 +62,8 @@ struct EvalArgs {
     bool axial = false;              // dx = dy = 0 everywhere (stage 1): the x, y partials are left at 0
     const EvalView* view = nullptr;  // the level's data, parameters and scratch; null: those of pair at level
     const int* skip = nullptr;       // device flag: when nonzero every kernel of the evaluation does nothing
+    const double* x64 = nullptr;     // the solver's float64 point (x or the trial point), for evaluators
+                                     // whose parameters are not the field itself (stage 1)
 };
 
 // The hot path over up to kMaxJobs jobs (distinct pairs, one storage type,
@@ -208,8 +210,18 @@ hipError_t launch_upsample(const double* coarse, int wc, int hc, double* fine, i
 // its axial component [2][h][w] (dz); launch_tilt_reduce the gradient with
 // respect to theta from a field gradient; launch_resample_z the volume
 // resampled along depth by a per-A-scan field.
-hipError_t launch_tilt_expand(const double* theta, int w, int h, float* disp, float* dz, hipStream_t s);
-hipError_t launch_tilt_reduce(const float* grad, int w, int h, double* gtheta, hipStream_t s);
+// skip (device flag, may be null): when nonzero the launch does nothing.
+hipError_t launch_tilt_expand(const double* theta, int w, int h, float* disp, float* dz, hipStream_t s,
+                              const int* skip = nullptr);
+hipError_t launch_tilt_reduce(const float* grad, int w, int h, double* gtheta, hipStream_t s,
+                              const int* skip = nullptr);
+// The tilt term T at theta (gamma_t: its weight, d: the level's depth) added
+// to the stage-1 objective: terms_out = terms_in with F + T, T's gradient
+// added to gtheta, terms_out[GP] = gtheta . p (0 without p), T into T_out
+// (may be null).  One workgroup, fixed order of summation.
+hipError_t launch_tilt_finish(const double* theta, double* gtheta, int w, int h, int d, double gamma_t,
+                              const double* terms_in, const double* p, double* terms_out, double* T_out,
+                              hipStream_t s, const int* skip = nullptr);
 hipError_t launch_resample_z(const float* vol, const float* dz, size_t na, int d, float* out, hipStream_t s);
 // stage-1 solve over the pair's pyramid (theta at the finest level)
 int prealign_solve(octmc_pair* pair, double gamma, int iters, std::vector<double>& theta, octmc_report* rep,

@@ -5,10 +5,11 @@
 // the prealigned volumes.
 //
 // The stage evaluates the pair's objective with the library's kernels at the
-// field expanded from theta (kernels_prealign.hip) and reduces the field
-// gradient back onto theta.  theta has 2 (h + w) values at a level of w x h
-// A-scans, so its L-BFGS state lives on the host in float64; each
-// evaluation moves 16 (h + w) bytes each way.
+// field expanded from theta (kernels_prealign.hip), reduces the field
+// gradient back onto theta and adds T on the device.  theta has 2 (h + w)
+// values at a level of w x h A-scans; it is solved by the same L-BFGS
+// iteration as the 3-D registration (LevelRun), with its decisions on the
+// device unless OCTMC_HOST_LINE_SEARCH asks for the host form.
 //
 // T is defined only in earlier work that is not available.  Reading: a
 // quadratic penalty on the sum of each scan's tilts,
@@ -17,10 +18,9 @@
 // plane a x + b y added to both scans' fields) as M fixes the translations;
 // a uniform tilt tau then costs gamma_t d N_A var_f tau^2 / 2.
 #include <cmath>
-#include <deque>
 #include <vector>
 
-#include "octmc_internal.h"
+#include "runtime_types.h"
 
 namespace octmc {
 namespace {
@@ -40,22 +40,6 @@ struct DevMem {
         return static_cast<T*>(q);
     }
 };
-
-double tilt_term(const std::vector<double>& th, int w, int h, int d, double gamma, std::vector<double>* g)
-{
-    double T = 0.0;
-    for (int V = 0; V < 2; ++V) {
-        const int nb = V == 0 ? h : w, nf = V == 0 ? w : h;
-        const size_t off = V == 0 ? 0 : 2 * (size_t)h;
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += th[off + 2 * b + 1];
-        const double kap = gamma * d * (double)nf * ((double)nf * nf - 1.0) / (24.0 * nb);
-        T += kap * s * s;
-        if (g)
-            for (int b = 0; b < nb; ++b) (*g)[off + 2 * b + 1] += 2.0 * kap * s;
-    }
-    return T;
-}
 
 // Level transition: the fine field is twice the coarse field at the coarse
 // position ((f - 0.5)/2, (b - 0.5)/2), linear along the fast axis as the
@@ -81,184 +65,84 @@ std::vector<double> upsample_theta(const std::vector<double>& c, int wc, int hc,
     return f;
 }
 
-// One stage-1 evaluation at one level: device buffers sized for the finest
-// level, host copies of theta and of its gradient.
-struct StageEval {
+// One stage-1 evaluation at one level, as an evaluator of the L-BFGS
+// iteration: theta is ea.x64 (float64, device), its gradient goes to
+// ea.grad64 and the terms, with F + T and g . p, to ea.terms.  The field and
+// its gradient live in device buffers sized for the finest level.  Every
+// launch honours ea.skip, so the device form of the iteration can enqueue it
+// ahead of its decisions.
+struct StageEvaluator final : Evaluator {
     octmc_pair* P;
-    int level, w, h, d;
+    int w, h, d;
     double gamma;
-    hipStream_t s;
-    double* th_d;
-    double* gth_d;
-    double* terms_d;
+    double* terms_d;  // the field objective's terms (without T)
+    double* T_d;      // T of the last evaluation
     float* disp;
     float* grad;
-    std::vector<double> terms = std::vector<double>(OCTMC_NTERMS);
-    double T = 0.0;
-    int evals = 0;
-
-    int operator()(const std::vector<double>& th, double& f, std::vector<double>& g)
+    StageEvaluator(octmc_pair* p, int w_, int h_, int d_, double g, double* terms, double* T, float* di, float* gr)
+        : P(p), w(w_), h(h_), d(d_), gamma(g), terms_d(terms), T_d(T), disp(di), grad(gr)
     {
-        const size_t n = th.size();
-        HIP_TRY(hipMemcpyAsync(th_d, th.data(), n * 8, hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_tilt_expand(th_d, w, h, disp, nullptr, s));
-        EvalArgs ea{P, disp, terms_d, grad, nullptr, nullptr, level, 1};
-        ea.axial = true;  // the field has dx = dy = 0; only its z gradient is used
-        OCTMC_TRY(eval_group(&ea, 1, s));
-        HIP_TRY(launch_tilt_reduce(grad, w, h, gth_d, s));
-        g.resize(n);
-        HIP_TRY(hipMemcpyAsync(g.data(), gth_d, n * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(terms.data(), terms_d, OCTMC_NTERMS * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        T = tilt_term(th, w, h, d, gamma, &g);
-        f = terms[OCTMC_TERM_F] + T;
-        ++evals;
-        return std::isfinite(f) ? OCTMC_OK : fail(OCTMC_E_NAN, "non-finite stage-1 objective");
+    }
+    int eval(const EvalArgs& ea, hipStream_t s) override
+    {
+        HIP_TRY(launch_tilt_expand(ea.x64, w, h, disp, nullptr, s, ea.skip));
+        EvalArgs e{P, disp, terms_d, grad, nullptr, nullptr, ea.level, 1};
+        e.axial = true;  // the field has dx = dy = 0; only its z gradient is used
+        e.skip = ea.skip;
+        OCTMC_TRY(eval_group(&e, 1, s));
+        HIP_TRY(launch_tilt_reduce(grad, w, h, ea.grad64, s, ea.skip));
+        HIP_TRY(launch_tilt_finish(ea.x64, ea.grad64, w, h, d, gamma, terms_d, ea.p, ea.terms, T_d, s, ea.skip));
+        return OCTMC_OK;
+    }
+    bool enqueue_only() const override { return true; }
+};
+
+// Device memory of a stage-1 solve: the field, its gradient and the solver's
+// vectors, sized for the finest level.
+struct StageMem {
+    DevMem mem;
+    Solver sv;
+    double* terms_d = nullptr;
+    double* T_d = nullptr;
+    float* disp = nullptr;
+    float* grad = nullptr;
+    int alloc(size_t na, size_t nth, int m)
+    {
+        terms_d = mem.get<double>(OCTMC_NTERMS);
+        T_d = mem.get<double>(1);
+        disp = mem.get<float>(2 * na * 3);
+        grad = mem.get<float>(2 * na * 3);
+        sv.m = m;
+        double** vecs[] = {&sv.x, &sv.g, &sv.p, &sv.xt, &sv.xprev, &sv.sc, &sv.yc, &sv.gt};
+        for (double** v : vecs) *v = mem.get<double>(nth);
+        bool ok = terms_d && T_d && disp && grad;
+        for (double** v : vecs) ok = ok && *v;
+        for (int k = 0; k < m; ++k) {
+            sv.S[k] = mem.get<double>(nth);
+            sv.Y[k] = mem.get<double>(nth);
+            ok = ok && sv.S[k] && sv.Y[k];
+        }
+        sv.xt32 = mem.get<float>(nth);
+        ok = ok && sv.xt32;
+        return ok ? OCTMC_OK : fail(OCTMC_E_OOM, "out of device memory (stage 1)");
     }
 };
 
-double dotv(const std::vector<double>& a, const std::vector<double>& b)
-{
-    double s = 0.0;
-    for (size_t k = 0; k < a.size(); ++k) s += a[k] * b[k];
-    return s;
-}
-
-// L-BFGS with the two-loop recursion and a strong Wolfe line search (initial
-// step 1, doubling bracket, safeguarded cubic zoom), float64 on the host; the
-// same rules as the device solver of the 3-D registration.
-int host_lbfgs(std::vector<double>& x, StageEval& fg, int m, int max_iter, int ls_max, double c1, double c2,
-               LevelStats& st)
-{
-    const size_t n = x.size();
-    std::vector<double> g, gt, xt(n), p(n), q(n);
-    double f;
-    OCTMC_TRY(fg(x, f, g));
-    st.f_start = f;
-    std::deque<std::vector<double>> S, Y;
-    std::deque<double> rho;
-    int it = 0;
-    while (it < max_iter) {
-        double gmax = 0.0;
-        for (double v : g) gmax = std::max(gmax, std::fabs(v));
-        if (gmax <= 1e-10 * std::max(1.0, std::fabs(f))) break;
-        auto steepest = [&]() {
-            for (size_t k = 0; k < n; ++k) p[k] = -g[k] / gmax;
-        };
-        if (S.empty()) {
-            steepest();
-        } else {
-            q = g;
-            std::vector<double> al(S.size());
-            for (int c = (int)S.size() - 1; c >= 0; --c) {
-                al[c] = rho[c] * dotv(S[c], q);
-                for (size_t k = 0; k < n; ++k) q[k] -= al[c] * Y[c][k];
-            }
-            const double gamma = dotv(S.back(), Y.back()) / dotv(Y.back(), Y.back());
-            for (size_t k = 0; k < n; ++k) q[k] *= gamma;
-            for (size_t c = 0; c < S.size(); ++c) {
-                const double bta = rho[c] * dotv(Y[c], q);
-                for (size_t k = 0; k < n; ++k) q[k] += (al[c] - bta) * S[c][k];
-            }
-            for (size_t k = 0; k < n; ++k) p[k] = -q[k];
-        }
-        double g0 = dotv(g, p);
-        if (!(g0 < 0)) {  // not a descent direction: drop the memory
-            S.clear();
-            Y.clear();
-            rho.clear();
-            steepest();
-            g0 = dotv(g, p);
-        }
-        // strong Wolfe line search along p
-        const int start = fg.evals;
-        auto trial = [&](double a, double& fa, double& ga) -> int {
-            for (size_t k = 0; k < n; ++k) xt[k] = x[k] + a * p[k];
-            OCTMC_TRY(fg(xt, fa, gt));
-            ga = dotv(gt, p);
-            return OCTMC_OK;
-        };
-        bool ok = false;
-        double fn = f;
-        {
-            double a_prev = 0, f_prev = f, g_prev = g0, a = 1.0;
-            double lo = 0, flo = f, glo = g0, hi = 0, fhi = f, ghi = g0;
-            bool bracket = false;
-            for (int i = 1;; ++i) {
-                if (fg.evals - start >= ls_max) break;
-                double fa, ga;
-                OCTMC_TRY(trial(a, fa, ga));
-                if (fa > f + c1 * a * g0 || (i > 1 && fa >= f_prev)) {
-                    lo = a_prev; flo = f_prev; glo = g_prev;
-                    hi = a; fhi = fa; ghi = ga;
-                    bracket = true;
-                    break;
-                }
-                if (std::fabs(ga) <= -c2 * g0) {
-                    ok = true;
-                    fn = fa;
-                    break;
-                }
-                if (ga >= 0) {
-                    lo = a; flo = fa; glo = ga;
-                    hi = a_prev; fhi = f_prev; ghi = g_prev;
-                    bracket = true;
-                    break;
-                }
-                a_prev = a; f_prev = fa; g_prev = ga;
-                a = 2.0 * a;
-            }
-            while (bracket && !ok) {
-                if (fg.evals - start >= ls_max) break;
-                const double aj = cubic_min(lo, flo, glo, hi, fhi, ghi);
-                double fj, gj;
-                OCTMC_TRY(trial(aj, fj, gj));
-                if (fj > f + c1 * aj * g0 || fj >= flo) {
-                    hi = aj; fhi = fj; ghi = gj;
-                } else {
-                    if (std::fabs(gj) <= -c2 * g0) {
-                        ok = true;
-                        fn = fj;
-                        break;
-                    }
-                    if (gj * (hi - lo) >= 0) {
-                        hi = lo; fhi = flo; ghi = glo;
-                    }
-                    lo = aj; flo = fj; glo = gj;
-                }
-            }
-        }
-        if (!ok) {
-            st.ls_fail = 1;
-            break;
-        }
-        // the new pair enters the memory only if it passes the curvature test
-        std::vector<double> sv(n), yv(n);
-        for (size_t k = 0; k < n; ++k) {
-            sv[k] = xt[k] - x[k];
-            yv[k] = gt[k] - g[k];
-        }
-        const double sy = dotv(sv, yv), yy = dotv(yv, yv);
-        if (sy > 1e-12 * yy && yy > 0) {
-            if ((int)S.size() == m) {
-                S.pop_front();
-                Y.pop_front();
-                rho.pop_front();
-            }
-            S.push_back(std::move(sv));
-            Y.push_back(std::move(yv));
-            rho.push_back(1.0 / sy);
-        }
-        x = xt;
-        g = gt;
-        f = fn;
-        ++it;
+struct PinnedScratch {
+    double* terms = nullptr;
+    double* dots = nullptr;
+    int alloc()
+    {
+        HIP_TRY(hipHostMalloc(&terms, OCTMC_NTERMS * 8, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(&dots, (kMaxDots + 1) * 8, hipHostMallocDefault));
+        return OCTMC_OK;
     }
-    st.iters = it;
-    st.evals = fg.evals;
-    st.f_end = f;
-    return OCTMC_OK;
-}
+    ~PinnedScratch()
+    {
+        if (terms) (void)hipHostFree(terms);
+        if (dots) (void)hipHostFree(dots);
+    }
+};
 
 int check_theta_level(const octmc_pair* pair, int level)
 {
@@ -275,15 +159,14 @@ int prealign_solve(octmc_pair* pair, double gamma, int iters, std::vector<double
     const int L = pair_nlev(pair);
     int w0, h0, d0;
     OCTMC_TRY(octmc_pair_level_shape(pair, 0, &w0, &h0, &d0));
-    DevMem mem;
     const size_t na0 = (size_t)w0 * h0, nth0 = 2 * (size_t)(w0 + h0);
-    double* th_d = mem.get<double>(nth0);
-    double* gth_d = mem.get<double>(nth0);
-    double* terms_d = mem.get<double>(OCTMC_NTERMS);
-    float* disp = mem.get<float>(2 * na0 * 3);
-    float* grad = mem.get<float>(2 * na0 * 3);
-    if (!th_d || !gth_d || !terms_d || !disp || !grad) return fail(OCTMC_E_OOM, "out of device memory (stage 1)");
-    const octmc_params& pr = pair_params(pair);
+    octmc_params pr = pair_params(pair);
+    pr.iters_per_level = iters;
+    StageMem sm;
+    OCTMC_TRY(sm.alloc(na0, nth0, pr.lbfgs_m));
+    PinnedScratch hs;
+    OCTMC_TRY(hs.alloc());
+    const bool device_ls = !(pr.flags & OCTMC_HOST_LINE_SEARCH) && pr.lbfgs_m <= kLbMaxM;
     std::vector<double> th;
     int wc = 0, hc = 0;
     if (rep) *rep = octmc_report{};
@@ -291,9 +174,19 @@ int prealign_solve(octmc_pair* pair, double gamma, int iters, std::vector<double
         int w, h, d;
         OCTMC_TRY(octmc_pair_level_shape(pair, l, &w, &h, &d));
         th = th.empty() ? std::vector<double>(2 * (size_t)(w + h), 0.0) : upsample_theta(th, wc, hc, w, h);
-        StageEval fg{pair, l, w, h, d, gamma, s, th_d, gth_d, terms_d, disp, grad};
+        const size_t n = th.size();
+        HIP_TRY(hipMemcpyAsync(sm.sv.x, th.data(), n * 8, hipMemcpyHostToDevice, s));
+        sm.sv.n = n;
+        StageEvaluator ev(pair, w, h, d, gamma, sm.terms_d, sm.T_d, sm.disp, sm.grad);
+        LevelRun run{pair, l, &sm.sv, s, n, hs.terms, hs.dots, &ev};
         LevelStats st{};
-        OCTMC_TRY(host_lbfgs(th, fg, pr.lbfgs_m, iters, pr.ls_max_evals, pr.c1, pr.c2, st));
+        if (device_ls)
+            OCTMC_TRY(run.run_device(pr, st));
+        else
+            OCTMC_TRY(run.run(pr, st));
+        HIP_TRY(hipMemcpyAsync(th.data(), sm.sv.x, n * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (!std::isfinite(st.f_end)) return fail(OCTMC_E_NAN, "non-finite stage-1 objective");
         if (rep) {
             const int r = L - 1 - l;
             rep->iters[r] = st.iters;
@@ -322,6 +215,7 @@ int octmc_prealign_eval(octmc_pair* pair, int32_t level, const double* theta, do
 {
     OCTMC_TRY(check_theta_level(pair, level));
     if (!theta || !terms) return fail(OCTMC_E_INVALID, "theta and terms are required");
+    if (pair->busy.load()) return fail(OCTMC_E_BUSY, "pair is in use");
     if (!std::isfinite(gamma_tilt) || gamma_tilt < 0) return fail(OCTMC_E_INVALID, "gamma_tilt must be >= 0");
     HIP_TRY(hipSetDevice(pair_device(pair)));
     int w, h, d;
@@ -330,19 +224,23 @@ int octmc_prealign_eval(octmc_pair* pair, int32_t level, const double* theta, do
     DevMem mem;
     double* th_d = mem.get<double>(nth);
     double* gth_d = mem.get<double>(nth);
-    double* terms_d = mem.get<double>(OCTMC_NTERMS);
+    double* terms_d = mem.get<double>(2 * OCTMC_NTERMS + 1);
     float* disp = mem.get<float>(2 * na * 3);
     float* grad = mem.get<float>(2 * na * 3);
     if (!th_d || !gth_d || !terms_d || !disp || !grad) return fail(OCTMC_E_OOM, "out of device memory (stage 1)");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    StageEval fg{pair, level, w, h, d, gamma_tilt, s, th_d, gth_d, terms_d, disp, grad};
-    std::vector<double> th(theta, theta + nth), g;
-    double f;
-    OCTMC_TRY(fg(th, f, g));
-    for (int q = 0; q < OCTMC_NTERMS; ++q) terms[q] = fg.terms[q];
-    if (tilt_term_out) *tilt_term_out = fg.T;
-    if (grad_theta)
-        for (size_t q = 0; q < nth; ++q) grad_theta[q] = g[q];
+    StageEvaluator ev(pair, w, h, d, gamma_tilt, terms_d, terms_d + 2 * OCTMC_NTERMS, disp, grad);
+    HIP_TRY(hipMemcpyAsync(th_d, theta, nth * 8, hipMemcpyHostToDevice, s));
+    EvalArgs ea{pair, nullptr, terms_d + OCTMC_NTERMS, nullptr, nullptr, gth_d, level, 1};
+    ea.x64 = th_d;
+    OCTMC_TRY(ev.eval(ea, s));
+    std::vector<double> out(2 * OCTMC_NTERMS + 1);
+    HIP_TRY(hipMemcpyAsync(out.data(), terms_d, out.size() * 8, hipMemcpyDeviceToHost, s));
+    if (grad_theta) HIP_TRY(hipMemcpyAsync(grad_theta, gth_d, nth * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!std::isfinite(out[OCTMC_NTERMS + OCTMC_TERM_F])) return fail(OCTMC_E_NAN, "non-finite stage-1 objective");
+    for (int q = 0; q < OCTMC_NTERMS; ++q) terms[q] = out[q];  // the field objective's terms, without T
+    if (tilt_term_out) *tilt_term_out = out[2 * OCTMC_NTERMS];
     return OCTMC_OK;
 }
 
@@ -352,6 +250,12 @@ int octmc_prealign(octmc_pair* pair, double gamma_tilt, int32_t iters_per_level,
     if (!pair || !theta_out) return fail(OCTMC_E_INVALID, "pair and theta_out are required");
     if (!std::isfinite(gamma_tilt) || gamma_tilt < 0) return fail(OCTMC_E_INVALID, "gamma_tilt must be >= 0");
     if (iters_per_level < 0) return fail(OCTMC_E_INVALID, "iters_per_level must be >= 0");
+    int idle = 0;
+    if (!pair->busy.compare_exchange_strong(idle, 1)) return fail(OCTMC_E_BUSY, "pair is in use");
+    struct Unbusy {
+        octmc_pair* p;
+        ~Unbusy() { p->busy.store(0); }
+    } ub{pair};
     HIP_TRY(hipSetDevice(pair_device(pair)));
     std::vector<double> th;
     OCTMC_TRY(prealign_solve(pair, gamma_tilt, iters_per_level, th, rep, static_cast<hipStream_t>(stream)));

@@ -445,7 +445,7 @@ int octmc::prealign_create(octmc_ctx* ctx, const octmc_params* params, const oct
     if (!zero || !dz || !th_d) return fail(OCTMC_E_OOM, "out of device memory (prealignment)");
     HIP_TRY(launch_fill_u32(reinterpret_cast<unsigned*>(zero), 0u, na, s));
     octmc_params p1 = *params;
-    p1.flags &= OCTMC_CHECK_NAN;
+    p1.flags &= OCTMC_CHECK_NAN | OCTMC_HOST_LINE_SEARCH;
     p1.delta0 = 0.0;  // the en face OCTA data is not used in this stage (Sec. 2.4)
     octmc_shape sh1 = *shape;
     sh1.mem = OCTMC_MEM_DEVICE;

@@ -134,6 +134,7 @@ struct LevelRun {
     {
         HIP_TRY(launch_trial(sv->x, sv->p, alpha, n, sv->xt, sv->xt32, s));
         EvalArgs ea{P, sv->xt32, P->terms, nullptr, sv->p, sv->gt, level, 1};
+        ea.x64 = sv->xt;
         OCTMC_TRY(ev->eval(ea, s));
         HIP_TRY(hipMemcpyAsync(h_terms, P->terms, sizeof(double) * OCTMC_NTERMS, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -211,6 +212,7 @@ struct LevelRun {
         HIP_TRY(launch_to_f32(sv->x, sv->xt32, n, s));
         {
             EvalArgs ea{P, sv->xt32, P->terms, nullptr, nullptr, sv->g, level, 0};
+            ea.x64 = sv->x;
             OCTMC_TRY(ev->eval(ea, s));
         }
         LbInit in{};
@@ -242,6 +244,7 @@ struct LevelRun {
         auto eval_step = [&](int last) -> int {
             EvalArgs ea{P, sv->xt32, P->terms, nullptr, sv->p, sv->gt, level, 1};
             ea.skip = &S->skip_trial;
+            ea.x64 = sv->xt;
             OCTMC_TRY(ev->eval(ea, s));
             HIP_TRY(launch_lb_c2(S, P->terms, last, s));
             return OCTMC_OK;
@@ -331,6 +334,7 @@ struct LevelRun {
         HIP_TRY(launch_to_f32(sv->x, sv->xt32, n, s));
         {
             EvalArgs ea{P, sv->xt32, P->terms, nullptr, nullptr, sv->g, level, 0};
+            ea.x64 = sv->x;
             OCTMC_TRY(ev->eval(ea, s));
         }
         HIP_TRY(hipMemcpyAsync(h_terms, P->terms, sizeof(double) * OCTMC_NTERMS, hipMemcpyDeviceToHost, s));

@@ -12,6 +12,7 @@ need more than one trial (the host then drives the rest), line searches that
 fail (ls_max_evals = 1), a step limit that is not a multiple of the batch of
 enqueued iterations, no step at all, and a gradient that is zero at the start.
 """
+import numpy as np
 import pytest
 import torch
 
@@ -83,3 +84,27 @@ def test_zero_gradient_stops_at_once(octmc):
     assert torch.equal(Dd, Dh)
     assert all(r["iters"] == 0 for r in rd)
     assert float(Dd.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("dtype,levels,iters", [("f32", 2, 60), ("bf16", 3, 40)])
+def test_stage1_device_decisions_equal_host_decisions(octmc, dtype, levels, iters):
+    """The stage-1 solve (per-B-scan offsets and tilts) runs the same
+    iteration with the stage-1 evaluator: both forms give the same theta and
+    report bit for bit."""
+    h = w = 40
+    d = 64
+    mX, mY = synth.planted_axial_motion(h, w, seed=3)
+    X, Y = synth.layered_axial_pair(h, w, d, mX, mY)
+    z = torch.zeros((h, w))
+    out = []
+    for host in (False, True):
+        P = octmc.Pair(torch.from_numpy(X).float(), torch.from_numpy(Y).float(), ax=z, ay=z, delta0=0.0,
+                       levels=levels, dtype=dtype, host_line_search=host)
+        log(f"stage 1 {dtype} levels {levels} ({'host' if host else 'device'} decisions)")
+        out.append(P.prealign(1.0, iters))
+        P.close()
+    (thd, rd), (thh, rh) = out
+    print("device", rd)
+    print("host  ", rh)
+    assert rd == rh
+    assert np.array_equal(thd, thh)
