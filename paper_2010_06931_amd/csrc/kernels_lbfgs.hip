@@ -84,20 +84,35 @@ struct KeyedDots {
 constexpr int kKeyedRows = 2 * kMaxDotVecs + 1;
 static_assert(kKeyedRows <= kMaxDots + 1, "keyed rows must fit the partial buffer");
 
-// TAB: the vectors' addresses come from the device table `tab` (the device
-// solver's vec[]) instead of spec.v; skip (device flag, may be null): when
-// nonzero the launch does nothing.
-template <bool TAB>
-__global__ __launch_bounds__(kB) void k_multidot_keyed(const KeyedDots spec, double* const* __restrict__ tab,
-                                                       const int* __restrict__ skip, size_t n,
-                                                       double* __restrict__ blk)
+// The pending accept of the device solver (LB): when st->do_accept is set,
+// the step found by the previous iteration's line search is committed here,
+// element by element, before the products use the new values: s_c = x_t - x,
+// y_c = g_t - g into vec[1], vec[2], then x = x_t, g = g_t (the arithmetic of
+// k_accept).
+struct LbAccept {
+    double* x;
+    const double* xt;
+    const double* gt;
+};
+
+// LB: the device solver's form: the vectors' addresses come from its table
+// st->vec (vector 0 the gradient, 1 and 2 the candidate pair), the launch does
+// nothing when st->skip_iter is set, and the pending accept is done first.
+template <bool LB>
+__global__ __launch_bounds__(kB) void k_multidot_keyed(const KeyedDots spec, const LbState* __restrict__ st,
+                                                       const LbAccept acc, size_t n, double* __restrict__ blk)
 {
-    if (skip && *skip) return;
+    bool accept = false;
+    if constexpr (LB) {
+        if (st->skip_iter) return;
+        accept = st->do_accept != 0;  // uniform
+    }
     const int nv = spec.nv;
     const bool two = spec.key1 >= 0;
-    const double* vp[kMaxDotVecs];
+    double* vp[kMaxDotVecs];
 #pragma unroll
-    for (int v = 0; v < kMaxDotVecs; ++v) vp[v] = TAB ? (v < nv ? tab[v] : nullptr) : spec.v[v];
+    for (int v = 0; v < kMaxDotVecs; ++v)
+        vp[v] = LB ? (v < nv ? st->vec[v] : nullptr) : const_cast<double*>(spec.v[v]);
     double acc0[kMaxDotVecs], acc1[kMaxDotVecs];
 #pragma unroll
     for (int v = 0; v < kMaxDotVecs; ++v) acc0[v] = acc1[v] = 0.0;
@@ -105,7 +120,18 @@ __global__ __launch_bounds__(kB) void k_multidot_keyed(const KeyedDots spec, dou
     for (size_t t = (size_t)blockIdx.x * kB + threadIdx.x; t < n; t += (size_t)gridDim.x * kB) {
         double x[kMaxDotVecs];
 #pragma unroll
-        for (int v = 0; v < kMaxDotVecs; ++v) x[v] = v < nv ? vp[v][t] : 0.0;
+        for (int v = 0; v < kMaxDotVecs; ++v) x[v] = v < nv && !(accept && (v == 1 || v == 2)) ? vp[v][t] : 0.0;
+        if (LB && accept) {
+            const double xn = acc.xt[t], gn = acc.gt[t];
+            const double sv = xn - acc.x[t], yv = gn - x[0];
+            vp[1][t] = sv;
+            vp[2][t] = yv;
+            acc.x[t] = xn;
+            vp[0][t] = gn;
+            x[0] = gn;
+            x[1] = sv;
+            x[2] = yv;
+        }
         double k0 = 0.0, k1 = 0.0;
 #pragma unroll
         for (int v = 0; v < kMaxDotVecs; ++v) {
@@ -290,7 +316,7 @@ hipError_t launch_multidot(const DotSpec& spec, size_t n, double* blk, double* o
     KeyedDots kd;
     RowMap map;
     if (keyed_plan(spec, kd, map)) {
-        hipLaunchKernelGGL(k_multidot_keyed<false>, dim3(nb), dim3(kB), 0, s, kd, nullptr, nullptr, n, blk);
+        hipLaunchKernelGGL(k_multidot_keyed<false>, dim3(nb), dim3(kB), 0, s, kd, nullptr, LbAccept{}, n, blk);
     } else {
         map = RowMap{};
         for (int q = 0; q <= nd; ++q) map.row[q] = (unsigned char)q;
@@ -411,8 +437,8 @@ __global__ __launch_bounds__(64) void k_lb_init(LbState* __restrict__ st, const 
 __device__ __forceinline__ void c1_decide(LbState* st, const double* dots)
 {
 #pragma clang fp contract(off)
-    st->do_accept = 0;  // the previous iteration's accept has run
-    if (st->skip_iter) return;
+    if (st->skip_iter) return;  // a pending accept is left to the level's last accept
+    st->do_accept = 0;          // the dot-product pass has committed the pending accept
     if (st->h.it >= st->iters_max) {
         lb_stop(st, 3);
         return;
@@ -766,8 +792,8 @@ hipError_t launch_lb_init(LbState* st, const LbInit& in, const double* terms, hi
     hipLaunchKernelGGL(k_lb_init, dim3(1), dim3(64), 0, s, st, in, terms);
     return hipGetLastError();
 }
-hipError_t launch_lb_head(LbState* st, int m, size_t n, double* blk, const double* x, double* p, double* xt,
-                          float* xt32, hipStream_t s)
+hipError_t launch_lb_head(LbState* st, int m, size_t n, double* blk, double* x, const double* gt, double* p,
+                          double* xt, float* xt32, hipStream_t s)
 {
     if (m < 1 || m > kLbMaxM) return hipErrorInvalidValue;
     // vectors 0 g, 1 s_c, 2 y_c, 3 + k S_k, 3 + m + k Y_k; the products in the
@@ -795,7 +821,7 @@ hipError_t launch_lb_head(LbState* st, int m, size_t n, double* blk, const doubl
     RowMap map;
     if (nd > kMaxDots || !keyed_plan(ds, kd, map) || kd.nv != 3 + 2 * m || kd.key1 != 2) return hipErrorInvalidValue;
     const int nb = grid_for(n, kMaxBlocks);
-    hipLaunchKernelGGL(k_multidot_keyed<true>, dim3(nb), dim3(kB), 0, s, kd, st->vec, &st->skip_iter, n, blk);
+    hipLaunchKernelGGL(k_multidot_keyed<true>, dim3(nb), dim3(kB), 0, s, kd, st, LbAccept{x, xt, gt}, n, blk);
     hipLaunchKernelGGL(k_lb_c1, dim3(1), dim3(kFinalThreads), 0, s, st, nd, nb, map, blk);
     hipLaunchKernelGGL(k_lb_lincomb, dim3(grid_for(n)), dim3(256), 0, s, st, x, n, p, xt, xt32);
     return hipGetLastError();

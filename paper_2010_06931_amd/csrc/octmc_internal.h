@@ -344,17 +344,19 @@ struct LbInit {
     double c1, c2;
 };
 hipError_t launch_lb_init(LbState* st, const LbInit& in, const double* terms, hipStream_t s);
-// The head of an iteration, each kernel skipped with skip_iter: the dot
-// products (and max |g|) over st->vec into the block partials blk, the
-// history update and search direction, then p and the first trial point
-// x + p (xt, and xt32 in float32).
-hipError_t launch_lb_head(LbState* st, int m, size_t n, double* blk, const double* x, double* p, double* xt,
-                          float* xt32, hipStream_t s);
+// The head of an iteration, each kernel skipped with skip_iter: the pending
+// accept of the previous step (x = xt, g = gt, the candidate pair formed)
+// and the dot products (and max |g|) over st->vec into the block partials
+// blk, the history update and search direction, then p and the first trial
+// point x + p (xt, and xt32 in float32).
+hipError_t launch_lb_head(LbState* st, int m, size_t n, double* blk, double* x, const double* gt, double* p,
+                          double* xt, float* xt32, hipStream_t s);
 // a further trial point x + a_try p (skipped with skip_trial)
 hipError_t launch_lb_trial(const LbState* st, const double* x, const double* p, size_t n, double* xt, float* xt32,
                            hipStream_t s);
 // last = 1: the iteration's only trial slot (an unfinished search stalls)
 hipError_t launch_lb_c2(LbState* st, const double* terms, int last, hipStream_t s);
+// the pending accept alone (the level's last step)
 hipError_t launch_lb_accept(const LbState* st, double* x, double* g, const double* xt, const double* gt, size_t n,
                             hipStream_t s);
 // resume = 1: a stalled line search continues, one trial per host round trip; resume = 0: it ended

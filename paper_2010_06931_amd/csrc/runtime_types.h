@@ -249,12 +249,13 @@ struct LevelRun {
             HIP_TRY(launch_lb_c2(S, P->terms, last, s));
             return OCTMC_OK;
         };
-        // one iteration: dot products, history update, direction and its
-        // first trial point, the evaluation there, then the accept
+        // one iteration: the previous step's accept with the dot products,
+        // history update, direction and its first trial point, then the
+        // evaluation there (its accept waits for the next iteration's head,
+        // or for the accept after the level's last step)
         auto iteration = [&](int last) -> int {
-            HIP_TRY(launch_lb_head(S, m, n, P->dot_blk, sv->x, sv->p, sv->xt, sv->xt32, s));
+            HIP_TRY(launch_lb_head(S, m, n, P->dot_blk, sv->x, sv->gt, sv->p, sv->xt, sv->xt32, s));
             OCTMC_TRY(eval_step(last));
-            HIP_TRY(launch_lb_accept(S, sv->x, sv->g, sv->xt, sv->gt, n, s));
             return OCTMC_OK;
         };
         auto read_now = [&](LbStatus& out) -> int {
@@ -263,7 +264,7 @@ struct LevelRun {
             out = hs[2];
             return OCTMC_OK;
         };
-        // the trials of a stalled line search, then its accept
+        // the trials of a stalled line search (its accept is left pending)
         auto finish_search = [&](LbStatus& out) -> int {
             HIP_TRY(launch_lb_resume(S, 1, s));
             for (int r = 0;; ++r) {  // at most ls_max_evals trials end a search
@@ -274,7 +275,6 @@ struct LevelRun {
                 if (out.ls_done) break;
             }
             HIP_TRY(launch_lb_resume(S, 0, s));
-            HIP_TRY(launch_lb_accept(S, sv->x, sv->g, sv->xt, sv->gt, n, s));
             return OCTMC_OK;
         };
         LbStatus cur{};
@@ -317,6 +317,7 @@ struct LevelRun {
                 it_known = cur.it;
             }
         }
+        HIP_TRY(launch_lb_accept(S, sv->x, sv->g, sv->xt, sv->gt, n, s));  // the last step's, if pending
         OCTMC_TRY(read_now(cur));
         st.iters = cur.it;
         st.evals = cur.evals;
