@@ -666,6 +666,10 @@ def main():
                     help="only the timed evaluations and the calibration copies (for rocprofv3)")
     ap.add_argument("--profile-workload", default="dense", choices=["dense", "clinical"],
                     help="with --profile-only: the dense pair (--dtype storage) or the clinical pair (float32)")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="only two full registrations of the dense pair (--dtype storage, automatic pyramid depth; "
+                         "with --host-line-search the host-decision form), for rocprofv3")
+    ap.add_argument("--host-line-search", action="store_true", help="with --profile-solve: OCTMC_HOST_LINE_SEARCH")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic of the structural kernel from two rocprofv3 counter passes")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "k_struct_dense_counters.json"))
@@ -704,6 +708,22 @@ def main():
         extra["pipeline"] = pipeline_bench(octmc, torch, log)
         extra["enface_projection"] = enface_bench(octmc, torch, log)
         print(json.dumps(extra), flush=True)
+        return
+    if args.profile_solve:
+        log(f"generating the dense pair {args.n}x{args.n}x{args.d} on cuda")
+        pair = synth.make_pair("dense", n=args.n, d=args.d, device="cuda", octa_volumes=False)
+        P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, dtype=args.dtype, levels=0,
+                       host_line_search=args.host_line_search)
+        secs = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, _, rep = P.register()
+            torch.cuda.synchronize()
+            secs.append(round(time.perf_counter() - t0, 4))
+        print(json.dumps({"workload": f"dense {args.n}x{args.n}x{args.d} {args.dtype}, automatic depth",
+                          "decisions": "host" if args.host_line_search else "device", "seconds": secs,
+                          "levels": len(rep), "evals": sum(r["evals"] for r in rep)}))
         return
     if args.profile_only and args.profile_workload == "clinical":
         # the clinical workload's finest-level evaluations alone (float32 storage), for rocprofv3
