@@ -88,8 +88,8 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
                                        single-thread kernels in the same float64 operations, with
                                        the same result bit for bit, and the host enqueues several
                                        iterations ahead (lbfgs_m <= 6; the host form otherwise, and
-                                       always for octmc_multi_register and grouped serving).  Applies
-                                       to octmc_register and to the stage-1 solve (octmc_prealign,
+                                       always for grouped serving).  Applies to octmc_register,
+                                       octmc_multi_register and the stage-1 solve (octmc_prealign,
                                        OCTMC_PREALIGN) */
 
 /* Parameters of the objective (Eq. 1 without the stage-1 tilt term) and of the

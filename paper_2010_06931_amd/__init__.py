@@ -409,7 +409,8 @@ class Multi:
 
     def __init__(self, vols, orients, *, octa=None, enface=None, valid=None, params: Params | None = None,
                  dtype: str = "f32", ctx: Context | None = None, stream=None, detect_invalid: bool = False,
-                 project_enface: bool = False, pairwise: bool = False, **param_overrides):
+                 project_enface: bool = False, pairwise: bool = False, host_line_search: bool = False,
+                 **param_overrides):
         self.ctx = ctx or context(0)
         dev = torch.device("cuda", self.ctx.device)
         self.params = params if params is not None else default_params()
@@ -421,6 +422,8 @@ class Multi:
             self.params.flags |= ENFACE_PROJECT
         if pairwise:
             self.params.flags |= MULTI_PAIRWISE
+        if host_line_search:  # L-BFGS decisions on the host (the device form gives the same bits)
+            self.params.flags |= HOST_LINE_SEARCH
         n = len(vols)
         self._has_octa = octa is not None
         S = [_f32(v, dev) for v in vols]

@@ -1043,11 +1043,13 @@ struct StructMultiJob {
     int w, h, d, na;
     uint32_t vol_bytes;
     float eps_h;
+    const int* skip;  // device flag: when nonzero the launch does nothing (may be null)
 };
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_struct_multi(const StructMultiJob<N> J)
 {
+    if (J.skip && *J.skip) return;
     constexpr int NP = N * (N - 1) / 2;
     const int wv = uni((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -1139,6 +1141,7 @@ __global__ __launch_bounds__(256) void k_struct_multi(const StructMultiJob<N> J)
 template <int N>
 __global__ __launch_bounds__(256, 3) void k_struct_multi1(const StructMultiJob<N> J)
 {
+    if (J.skip && *J.skip) return;
     constexpr int NP = N * (N - 1) / 2;
     const int wv = uni((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -1302,9 +1305,11 @@ hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t
 
 template <int N>
 static hipError_t launch_struct_multi_n(const void* const* vol, const float* disp, float* const* part, int w, int h,
-                                        int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s)
+                                        int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s,
+                                        const int* skip)
 {
     StructMultiJob<N> J{};
+    J.skip = skip;
     for (int V = 0; V < N; ++V) J.vol[V] = vol[V];
     for (int q = 0; q < N * (N - 1) / 2; ++q) J.part[q] = part[q];
     J.disp = disp;
@@ -1331,11 +1336,11 @@ bool struct_multi_supported(int n, int d, octmc_dtype dt)
 }
 
 hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp, float* const* part, int w, int h,
-                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s)
+                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s, const int* skip)
 {
     if (!struct_multi_supported(n, d, dt)) return hipErrorInvalidValue;
-    if (n == 3) return launch_struct_multi_n<3>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s);
-    return launch_struct_multi_n<4>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s);
+    if (n == 3) return launch_struct_multi_n<3>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s, skip);
+    return launch_struct_multi_n<4>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s, skip);
 }
 
 }  // namespace octmc

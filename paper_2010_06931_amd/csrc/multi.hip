@@ -55,8 +55,12 @@ struct VolumePyr {
 };
 
 // sum of all fields per component, block partials then a fixed-order final
-__global__ __launch_bounds__(kMB) void k_field_sum(const float* __restrict__ disp, size_t nq, double* __restrict__ blk)
+// skip (device flag, may be null) on every kernel here: when nonzero the
+// launch does nothing (the solver's device form enqueues evaluations ahead)
+__global__ __launch_bounds__(kMB) void k_field_sum(const float* __restrict__ disp, size_t nq, double* __restrict__ blk,
+                                                   const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     __shared__ double red[3][kMB];
     double s[3] = {0.0, 0.0, 0.0};
     for (size_t q = (size_t)blockIdx.x * kMB + threadIdx.x; q < nq; q += (size_t)gridDim.x * kMB)
@@ -89,8 +93,9 @@ __device__ __forceinline__ double wave_sum_rows(const double* __restrict__ blk, 
 
 // the three field sums from the block partials of k_field_sum (one wave each)
 __global__ __launch_bounds__(kMB) void k_field_sum_final(const double* __restrict__ blk, int nblk,
-                                                         double* __restrict__ S)
+                                                         double* __restrict__ S, const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     const int wv = threadIdx.x >> 6;
     if (wv >= 3) return;  // uniform per wave
     const double s = wave_sum_rows(blk, 3, wv, nblk);
@@ -108,8 +113,9 @@ struct GatherSpec {
 __global__ __launch_bounds__(kMB) void k_gather(const GatherSpec spec, size_t na, const double* __restrict__ Sdev,
                                                 double mscale, const double* __restrict__ p,
                                                 double* __restrict__ g64, float* __restrict__ g32,
-                                                double* __restrict__ blk)
+                                                double* __restrict__ blk, const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     __shared__ double red[kMB];
     const double S[3] = {Sdev[0], Sdev[1], Sdev[2]};
     double gp = 0.0;
@@ -145,8 +151,9 @@ struct FinalSpec {
 // multi-volume terms from the pairs' terms (pair order), M and g . p; one wave
 __global__ __launch_bounds__(64) void k_multi_final(const FinalSpec spec, const double* __restrict__ Sdev,
                                                     const double* __restrict__ gp_blk, int ngp,
-                                                    double* __restrict__ terms)
+                                                    double* __restrict__ terms, const int* __restrict__ skip)
 {
+    if (skip && *skip) return;
     const double gp = wave_sum_rows(gp_blk, 1, 0, ngp);
     if (threadIdx.x != 0) return;
     const double S[3] = {Sdev[0], Sdev[1], Sdev[2]};
@@ -246,6 +253,7 @@ struct MultiEvaluator final : Evaluator {
             const float* fQ = ea.disp + (size_t)M->pairs[q].second * na * 3;
             args[q] = EvalArgs{M->views[q].get(), fP, M->pterms + (size_t)q * OCTMC_NTERMS, nullptr, nullptr,
                                M->pgrad + (size_t)q * 2 * na0 * 3, level, ea.eta_mode};
+            args[q].skip = ea.skip;
             if (fused) {
                 args[q].disp_y = fQ;  // the remaining pair kernels read the two fields where they are
                 continue;
@@ -263,14 +271,14 @@ struct MultiEvaluator final : Evaluator {
             for (int q = 0; q < np; ++q) parts[q] = M->views[q]->part;
             const Level& L = M->views[0]->lev[level];
             HIP_TRY(launch_struct_multi(vols, M->n, ea.disp, parts, L.w, L.h, L.d, L.vol_bytes,
-                                        (float)M->params.eps_huber, M->dtype, s));
+                                        (float)M->params.eps_huber, M->dtype, s, ea.skip));
         }
         for (int q0 = 0; q0 < np; q0 += kMaxJobs)
             OCTMC_TRY(eval_group(args.data() + q0, std::min(kMaxJobs, np - q0), s, nullptr, !fused));
         const size_t nq = (size_t)M->n * na;
         const int nsum = grid_n(nq);
-        hipLaunchKernelGGL(k_field_sum, dim3(nsum), dim3(kMB), 0, s, ea.disp, nq, M->sum_blk);
-        hipLaunchKernelGGL(k_field_sum_final, dim3(1), dim3(kMB), 0, s, M->sum_blk, nsum, M->fsum);
+        hipLaunchKernelGGL(k_field_sum, dim3(nsum), dim3(kMB), 0, s, ea.disp, nq, M->sum_blk, ea.skip);
+        hipLaunchKernelGGL(k_field_sum_final, dim3(1), dim3(kMB), 0, s, M->sum_blk, nsum, M->fsum, ea.skip);
         GatherSpec gs{};
         gs.n = M->n;
         int cnt[kMaxVol] = {};
@@ -286,7 +294,7 @@ struct MultiEvaluator final : Evaluator {
         const double mscale = 2.0 * pr.mean_weight * M->d[level] / ((double)M->n * (double)na);
         const int ng = grid_n(na * 3);
         hipLaunchKernelGGL(k_gather, dim3(ng), dim3(kMB), 0, s, gs, na, M->fsum, mscale, ea.p, ea.grad64, ea.grad,
-                           M->gp_blk);
+                           M->gp_blk, ea.skip);
         FinalSpec fs{};
         for (int q = 0; q < np; ++q) fs.pt[q] = M->pterms + (size_t)q * OCTMC_NTERMS;
         fs.npairs = np;
@@ -295,10 +303,13 @@ struct MultiEvaluator final : Evaluator {
         fs.gamma = pr.mean_weight;
         fs.alpha = pr.alpha;
         fs.na = (double)na;
-        hipLaunchKernelGGL(k_multi_final, dim3(1), dim3(64), 0, s, fs, M->fsum, M->gp_blk, ng, ea.terms);
+        hipLaunchKernelGGL(k_multi_final, dim3(1), dim3(64), 0, s, fs, M->fsum, M->gp_blk, ng, ea.terms, ea.skip);
         HIP_TRY(hipGetLastError());
         return OCTMC_OK;
     }
+    // every launch honours ea.skip; the pair-by-pair form's field copies run
+    // regardless, which is harmless: only the skipped kernels read them
+    bool enqueue_only() const override { return true; }
 };
 
 // ingest one volume: staging, validity, en face image, OCTA substitution,
@@ -621,7 +632,10 @@ int octmc_multi_register(octmc_multi* m, float* disp_out, float* merged_oct, flo
         sv.n = n;
         LevelRun run{carrier, l, &sv, s, n, h_terms, h_dots, &ev};
         LevelStats st;
-        OCTMC_TRY(run.run(pr, st));
+        if (!(pr.flags & OCTMC_HOST_LINE_SEARCH) && sv.m <= kLbMaxM)
+            OCTMC_TRY(run.run_device(pr, st));
+        else
+            OCTMC_TRY(run.run(pr, st));
         if (rep) {
             const int r = m->nlev - 1 - l;
             rep->iters[r] = st.iters;

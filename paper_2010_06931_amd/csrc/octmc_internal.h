@@ -189,10 +189,12 @@ hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t
 // the structural partials of every volume pair of n volumes at one level,
 // each volume resampled once (n = 3 or 4; float32 storage, or 16-bit storage
 // at an even depth: see struct_multi_supported); part[q] is pair q's [na][8]
-// partial buffer, the pairs (P, Q), P < Q, in lexicographic order
+// partial buffer, the pairs (P, Q), P < Q, in lexicographic order; skip
+// (device flag, may be null): when nonzero the launch does nothing
 bool struct_multi_supported(int n, int d, octmc_dtype dt);
 hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp, float* const* part, int w, int h,
-                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s);
+                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s,
+                               const int* skip = nullptr);
 
 // preparation (kernels_prep.hip)
 hipError_t launch_to_storage(const float* in, void* out, size_t n, octmc_dtype dt, hipStream_t s);

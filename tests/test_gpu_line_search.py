@@ -108,3 +108,24 @@ def test_stage1_device_decisions_equal_host_decisions(octmc, dtype, levels, iter
     print("host  ", rh)
     assert rd == rh
     assert np.array_equal(thd, thh)
+
+
+@pytest.mark.parametrize("dtype,pairwise", [("f32", False), ("bf16", False), ("f32", True)])
+def test_multi_device_decisions_equal_host_decisions(octmc, dtype, pairwise):
+    """The joint solve of four volumes (two orthogonal pairs), fused or pair
+    by pair: both forms of the iteration give the same fields and report."""
+    sc = synth.make_scans("tiny", 2, (0, 1, 0, 1), n=40, d=64, white_lines=True)
+    out = []
+    for host in (False, True):
+        M = octmc.Multi(sc.S, sc.orient, enface=sc.A, valid=sc.V, levels=2, iters_per_level=40, dtype=dtype,
+                        pairwise=pairwise, host_line_search=host)
+        log(f"four volumes {dtype} pairwise={pairwise} ({'host' if host else 'device'} decisions)")
+        D, _, _, rep = M.register()
+        torch.cuda.synchronize()
+        out.append((D, rep))
+        M.close()
+    (Dd, rd), (Dh, rh) = out
+    print("device", rd)
+    print("host  ", rh)
+    assert rd == rh
+    assert torch.equal(Dd, Dh)
