@@ -43,6 +43,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def warm_clock(torch, step, seconds=None):
+    """Untimed evaluations until `seconds` of device work have run: the
+    device's clocks ramp up over the first tens of milliseconds of load after
+    idle (20 evaluations of the dense pair right after idle ran at 1.18 ms
+    each, later ones at 1.105 ms).  Returns the number of evaluations run."""
+    seconds = WARM_SECONDS if seconds is None else seconds
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            step()
+        torch.cuda.synchronize()
+        n += 10
+    return n
+
+
 def source_sha():
     """Hash of the structural kernels' source (the part of kernels_eval.hip
     before the reduction helpers: stencils, k_struct, k_struct2), so that
@@ -365,7 +381,7 @@ def _rms_px(a, b):
     return [round(float(x), 4) for x in np.sqrt(((a - b) ** 2).reshape(-1, 3).mean(axis=0))]
 
 
-def clinical_bench(octmc, torch, log, steps=200, warmup=20):
+def clinical_bench(octmc, torch, log, steps=200, warmup=20, cpu=True):
     """The clinical workload (300 x 300 A-scans x 640 samples, float32
     storage): evaluations per second of the full objective and gradient at
     the finest level, the structural kernel (k_struct<float>) against its
@@ -385,7 +401,7 @@ def clinical_bench(octmc, torch, log, steps=200, warmup=20):
     P.eval(0, D, grad=grad, terms=terms, eta_mode=0)
     for _ in range(warmup):
         P.eval(0, D, grad=grad, terms=terms)
-    torch.cuda.synchronize()
+    warm_clock(torch, lambda: P.eval(0, D, grad=grad, terms=terms))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
@@ -438,6 +454,9 @@ def clinical_bench(octmc, torch, log, steps=200, warmup=20):
             sol[f"{dt}_levels{levels}"] = r
             log(f"clinical solve {dt} levels {L}: {el:.3f} s, {r}")
     out["solve"] = sol
+    if cpu:
+        log("clinical: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(pair, D, target_s=6.0)
     del pair
     torch.cuda.empty_cache()
     return out
@@ -752,18 +771,10 @@ def main():
     for _ in range(args.warmup):
         P.eval(0, D, grad=grad, terms=terms)
     torch.cuda.synchronize()
-    # The device's clocks ramp up over the first tens of milliseconds of load
-    # after idle (the first 20 evaluations ran at 1.18 ms each, the next ones
-    # at 1.105 ms): after the W warmup steps, evaluations continue untimed
-    # until WARM_SECONDS of device work have run, so the K timed steps see the
-    # steady clock whatever W is.
-    extra_warm = 0
-    tw = time.perf_counter()
-    while time.perf_counter() - tw < WARM_SECONDS:
-        for _ in range(10):
-            P.eval(0, D, grad=grad, terms=terms)
-        torch.cuda.synchronize()
-        extra_warm += 10
+    # after the W warmup steps, evaluations continue untimed until
+    # WARM_SECONDS of device work have run, so that the K timed steps see the
+    # steady clock whatever W is (warm_clock)
+    extra_warm = warm_clock(torch, lambda: P.eval(0, D, grad=grad, terms=terms))
     log(f"timing {args.steps} evaluations (after {args.warmup} + {extra_warm} warmup evaluations)")
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -843,7 +854,7 @@ def main():
             Q.eval(0, D, grad=grad, terms=terms, eta_mode=0)
             for _ in range(args.warmup):
                 Q.eval(0, D, grad=grad, terms=terms)
-            torch.cuda.synchronize()
+            warm_clock(torch, lambda: Q.eval(0, D, grad=grad, terms=terms))
             e0.record()
             for _ in range(args.steps):
                 Q.eval(0, D, grad=grad, terms=terms)
@@ -933,7 +944,7 @@ def main():
     for v in out.get("storage_variants", {}).values():
         v.pop("solution", None)
     if not args.no_clinical:
-        out["clinical"] = clinical_bench(octmc, torch, log)
+        out["clinical"] = clinical_bench(octmc, torch, log, cpu=not args.no_cpu_baseline)
     if not args.no_prealign:
         out["prealign"] = prealign_bench(octmc, torch, pair, args.dtype, log)
     if not args.no_serve:
