@@ -82,8 +82,9 @@ constexpr uint32_t kRsrcWord3 = 0x00020000u;
 
 // Per-scan stencil of one output A-scan: 16 lateral columns with their
 // (wave-uniform) byte offsets and blend weights, and the depth taps.  The
-// lateral derivative taps are recomputed from the fractions after the depth
-// loop, so they do not occupy registers during it.
+// lateral derivative taps are recomputed after the depth loop (from tx, ty,
+// or from make_stencils' per-lane taps), so they do not occupy registers
+// during it.
 struct Stencil {
     float w[16];
     uint32_t off[16];
@@ -92,6 +93,9 @@ struct Stencil {
     int base;  // source sample of the first depth tap of output sample 0
 };
 
+// One scan's stencil, every tap and product computed on wave-uniform values
+// (the two-samples-per-lane kernel's form: with the per-lane form below its
+// register allocation changed and the BF16 kernel ran 21 % slower).
 template <typename T>
 __device__ __forceinline__ void make_stencil(Stencil& s, int i, int j, float dx, float dy, float dz, int w,
                                              int h, int d)
@@ -126,6 +130,87 @@ __device__ __forceinline__ void make_stencil(Stencil& s, int i, int j, float dx,
     s.tx = uni(tx);
     s.ty = uni(ty);
     s.base = uni(nz - 1);
+}
+
+// Both scans' stencils of one output A-scan.  The taps are computed one per
+// lane, lane 12 V + 4 p + c holding tap c of scan V's coordinate p (0: x,
+// 1: y, 2: z), and the lateral weights w_ab = wx_a wy_b one per lane (lane
+// 32 + 16 V + 4 b + a); each is then read out as a wave-uniform value.  That
+// takes a few dozen instructions per wave instead of computing every tap and
+// product on uniform operands one after another.  tw and tdw keep each
+// lane's tap and tap derivative for the lateral gradient after the depth
+// loop (tap_x/tap_y read them).
+template <typename T>
+__device__ __forceinline__ void make_stencils(Stencil& SX, Stencil& SY, float& tw, float& tdw, int i, int j,
+                                              const float* dX, const float* dY, int w, int h, int d, int lane)
+{
+    float t[6];
+    int n[6];
+    split(i, uni(dX[0]), n[0], t[0]);
+    split(j, uni(dX[1]), n[1], t[1]);
+    split(0, uni(dX[2]), n[2], t[2]);
+    split(i, uni(dY[0]), n[3], t[3]);
+    split(j, uni(dY[1]), n[4], t[4]);
+    split(0, uni(dY[2]), n[5], t[5]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) n[k] = uni(n[k]);
+    const int p = lane >> 2, c = lane & 3;
+    float tl = t[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) tl = p == k ? t[k] : tl;
+    float wv[4], dv[4];
+    cr_taps(tl, wv, dv);
+    float wl = wv[0], dl = dv[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        wl = c == k ? wv[k] : wl;
+        dl = c == k ? dv[k] : dl;
+    }
+    tw = wl;
+    tdw = dl;
+    // lanes 32 + 16 V + 4 b + a: wx_a wy_b of scan V
+    const int V = (lane >> 4) & 1, b = (lane >> 2) & 3, a = lane & 3;
+    const float prod = __shfl(wl, 12 * V + a) * __shfl(wl, 12 * V + 4 + b);
+    const int pb = __builtin_bit_cast(int, prod), wb = __builtin_bit_cast(int, wl), db = __builtin_bit_cast(int, dl);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        SX.w[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(pb, 32 + q));
+        SY.w[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(pb, 48 + q));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        SX.wz[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(wb, 8 + k));
+        SX.dwz[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(db, 8 + k));
+        SY.wz[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(wb, 20 + k));
+        SY.dwz[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(db, 20 + k));
+    }
+    Stencil* S[2] = {&SX, &SY};
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        const int nx = n[3 * v], ny = n[3 * v + 1];
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            const int row = clampi(ny - 1 + bb, 0, h - 1);
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+                const int col = clampi(nx - 1 + aa, 0, w - 1);
+                S[v]->off[bb * 4 + aa] = (uint32_t)uni((int)((uint32_t)(row * w + col) * (uint32_t)d * esize<T>::v));
+            }
+        }
+        S[v]->base = n[3 * v + 2] - 1;
+    }
+}
+
+// The lateral taps and their derivatives of scan V (x: p = 0, y: p = 1),
+// read back from make_stencils' per-lane values.
+__device__ __forceinline__ void lateral_taps(float tw, float tdw, int V, int p, float w[4], float dw[4])
+{
+    const int wb = __builtin_bit_cast(int, tw), db = __builtin_bit_cast(int, tdw);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(wb, 12 * V + 4 * p + k));
+        dw[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(db, 12 * V + 4 * p + k));
+    }
 }
 
 // Depth is processed in steps of 61 output samples on 64 lanes: lane l holds
@@ -171,27 +256,31 @@ __device__ __forceinline__ float shr1(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138, 0xF, 0xF, true));
 }
 
-// Sum over the wave: float32 within each row of 16 lanes (DPP row shifts; the
-// last lane of a row ends with the row's sum), float64 over the four rows.
-// Returns the sum in every lane.
+// Sum over the wave in float32, left in lane 63: within each row of 16 lanes
+// (DPP row shifts; the last lane of a row ends with the row's sum), then two
+// row broadcasts (rows 1 and 3 add the last lane of the row before them, then
+// rows 2 and 3 add lane 31): (r3 + r2) + (r1 + r0).  Six DPP additions, no
+// lane reads.
 template <int S>
 __device__ __forceinline__ float row_shr_add(float v)
 {
     return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 | S, 0xF,
                                                                      0xF, true));
 }
-__device__ __forceinline__ float wave_sum(float x)
+__device__ __forceinline__ float wave_sum_last(float x)
 {
     float v = row_shr_add<1>(x);
     v = row_shr_add<2>(v);
     v = row_shr_add<4>(v);
     v = row_shr_add<8>(v);
-    const int b = __builtin_bit_cast(int, v);
-    const double s = (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 15)) +
-                     (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 31)) +
-                     (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 47)) +
-                     (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(b, 63));
-    return (float)s;
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+    return v;
+}
+// the same sum, wave-uniform (lane 63's)
+__device__ __forceinline__ float wave_sum(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wave_sum_last(x)), 63));
 }
 
 // Logical block of a physical one: workgroups are dispatched to the 8 XCDs
@@ -237,8 +326,8 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     const float* dX = J.disp + (size_t)a * 3;
     const float* dY = J.disp + ((size_t)J.na + a) * 3;
     Stencil SX, SY;
-    make_stencil<T>(SX, i, j, dX[0], dX[1], dX[2], w, h, d);
-    make_stencil<T>(SY, i, j, dY[0], dY[1], dY[2], w, h, d);
+    float tw, tdw;
+    make_stencils<T>(SX, SY, tw, tdw, i, j, dX, dY, w, h, d, lane);
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
     const __amdgpu_buffer_rsrc_t ry =
@@ -318,8 +407,8 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     float wx[4], dwx[4], wy[4], dwy[4];
     float gxx = 0.f, gyx = 0.f, gxy = 0.f, gyy = 0.f;
     if constexpr (!AXIAL) {
-        cr_taps(SX.tx, wx, dwx);
-        cr_taps(SX.ty, wy, dwy);
+        lateral_taps(tw, tdw, 0, 0, wx, dwx);
+        lateral_taps(tw, tdw, 0, 1, wy, dwy);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             float rv = 0.f, rd = 0.f;
@@ -331,8 +420,8 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
             gxx = fmaf(wy[b], rd, gxx);
             gyx = fmaf(dwy[b], rv, gyx);
         }
-        cr_taps(SY.tx, wx, dwx);
-        cr_taps(SY.ty, wy, dwy);
+        lateral_taps(tw, tdw, 1, 0, wx, dwx);
+        lateral_taps(tw, tdw, 1, 1, wy, dwy);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             float rv = 0.f, rd = 0.f;
@@ -891,21 +980,6 @@ __global__ __launch_bounds__(kRedBlock) void k_finalize(const CombineJobs jobs)
         t[OCTMC_TERM_GP] = s[7];
         t[OCTMC_TERM_F] = s[0] + J.alpha * s[3] + m;
     }
-}
-
-// Sum over the wave in float32, left in lane 63: the row sums as in
-// wave_sum, then two row broadcasts (rows 1 and 3 add the last lane of the
-// row before them, then rows 2 and 3 add lane 31).  Six DPP additions,
-// no lane reads: for kernels that reduce many values per wave.
-__device__ __forceinline__ float wave_sum_last(float x)
-{
-    float v = row_shr_add<1>(x);
-    v = row_shr_add<2>(v);
-    v = row_shr_add<4>(v);
-    v = row_shr_add<8>(v);
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
-    return v;
 }
 
 // ---------------------------------------------------------------------------
