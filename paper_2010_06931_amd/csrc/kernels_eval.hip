@@ -80,6 +80,12 @@ template <> struct esize<float> { static constexpr uint32_t v = 4; };
 
 constexpr uint32_t kRsrcWord3 = 0x00020000u;
 
+// Stage 1 (rough axial prealignment) evaluates at dx = dy = 0, where the
+// lateral weights are (0, 1, 0, 0) in x and y: the blend of the 16 columns
+// is exactly the centre column (index 5; every other product is an exact 0),
+// so the axial kernels load that column alone and skip the lateral adjoint.
+constexpr int kCentre = 5;
+
 // Per-scan stencil of one output A-scan: 16 lateral columns with their
 // (wave-uniform) byte offsets and blend weights, and the depth taps.  The
 // lateral derivative taps are recomputed after the depth loop (from tx, ty,
@@ -130,6 +136,28 @@ __device__ __forceinline__ void make_stencil(Stencil& s, int i, int j, float dx,
     s.tx = uni(tx);
     s.ty = uni(ty);
     s.base = uni(nz - 1);
+}
+
+// The stencil of the axial kernels (every displacement has dx = dy = 0, so
+// the lateral weights are (0, 1, 0, 0) along x and y and the blend is the
+// centre column): the depth taps, the centre column's offset and the base;
+// the other offsets and weights are left unset (the axial kernels read
+// neither).
+template <typename T>
+__device__ __forceinline__ void make_stencil_axial(Stencil& s, int i, int j, float dz, int w, int d)
+{
+    int nz;
+    float tz;
+    split(0, uni(dz), nz, tz);
+    cr_taps(uni(tz), s.wz, s.dwz);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        s.wz[c] = uni(s.wz[c]);
+        s.dwz[c] = uni(s.dwz[c]);
+    }
+    s.off[kCentre] = (uint32_t)((uint32_t)(j * w + i) * (uint32_t)d * esize<T>::v);
+    s.tx = s.ty = 0.f;
+    s.base = uni(nz) - 1;
 }
 
 // Both scans' stencils of one output A-scan.  The taps are computed one per
@@ -230,11 +258,6 @@ __device__ __forceinline__ void load_cols(float (&v)[16], __amdgpu_buffer_rsrc_t
     for (int q = 0; q < 16; ++q) v[q] = ldv<T>(r, voff, s.off[q]);
 }
 
-// Stage 1 (rough axial prealignment) evaluates at dx = dy = 0, where the
-// lateral weights are (0, 1, 0, 0) in x and y: the blend of the 16 columns
-// is exactly the centre column (index 5; every other product is an exact 0),
-// so the axial kernels load that column alone and skip the lateral adjoint.
-constexpr int kCentre = 5;
 
 __device__ __forceinline__ float blend(const float (&v)[16], const Stencil& s)
 {
@@ -326,8 +349,13 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     const float* dX = J.disp + (size_t)a * 3;
     const float* dY = J.disp + ((size_t)J.na + a) * 3;
     Stencil SX, SY;
-    float tw, tdw;
-    make_stencils<T>(SX, SY, tw, tdw, i, j, dX, dY, w, h, d, lane);
+    float tw = 0.f, tdw = 0.f;
+    if constexpr (AXIAL) {
+        make_stencil_axial<T>(SX, i, j, dX[2], w, d);
+        make_stencil_axial<T>(SY, i, j, dY[2], w, d);
+    } else {
+        make_stencils<T>(SX, SY, tw, tdw, i, j, dX, dY, w, h, d, lane);
+    }
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
     const __amdgpu_buffer_rsrc_t ry =
@@ -520,8 +548,13 @@ __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
     const float* dX = J.disp + (size_t)a * 3;
     const float* dY = J.disp + ((size_t)J.na + a) * 3;
     Stencil SX, SY;
-    make_stencil<T>(SX, i, j, dX[0], dX[1], dX[2], w, h, d);
-    make_stencil<T>(SY, i, j, dY[0], dY[1], dY[2], w, h, d);
+    if constexpr (AXIAL) {
+        make_stencil_axial<T>(SX, i, j, dX[2], w, d);
+        make_stencil_axial<T>(SY, i, j, dY[2], w, d);
+    } else {
+        make_stencil<T>(SX, i, j, dX[0], dX[1], dX[2], w, h, d);
+        make_stencil<T>(SY, i, j, dY[0], dY[1], dY[2], w, h, d);
+    }
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
     const __amdgpu_buffer_rsrc_t ry =
