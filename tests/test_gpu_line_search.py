@@ -47,6 +47,7 @@ CASES = [
     ("tiny", 0, "f32", dict(levels=2, iters_per_level=7)),
     ("tiny", 0, "bf16", dict(levels=2, ls_max_evals=1)),
     ("tiny", 0, "f32", dict(levels=2, iters_per_level=0)),
+    ("tiny", 2, "bf16", dict(levels=2, c2=0.1)),
     ("clinical", 0, "bf16", dict(levels=0)),
 ]
 
@@ -69,6 +70,11 @@ def test_device_decisions_equal_host_decisions(octmc, workload, idx, dtype, kw):
     if kw.get("iters_per_level", 100) >= 60:
         # line searches of more than one trial: the host-driven continuation ran
         assert any(r["evals"] > r["iters"] + 1 for r in rd)
+    if kw.get("c2") == 0.1:
+        # a strict curvature condition: many searches need further trials, far
+        # more than the first iteration of each level accounts for, so the
+        # pipelined iterations stalled and were resumed
+        assert all(r["evals"] > r["iters"] + 10 for r in rd if r["iters"] > 0)
 
 
 def test_zero_gradient_stops_at_once(octmc):
