@@ -97,6 +97,25 @@ def test_eval_parity_odd_depth(octmc, dtype):
             _compare(octmc, P, pyr[level], level, D, f"odd/{dtype}/{level}/{case}")
 
 
+@pytest.mark.parametrize("n,d,dtype", [(4, 4, "f32"), (4, 4, "bf16"), (5, 5, "bf16"), (5, 6, "f16"), (6, 4, "f16"),
+                                       (7, 9, "f32")])
+def test_eval_parity_minimal_shapes(octmc, n, d, dtype):
+    """The smallest scans the library takes (4 x 4 x 4) and a few other tiny
+    shapes: every A-scan's 4 x 4 x 4 neighbourhood reaches past the volume on
+    some side (random fields of up to 3 px, smooth ones of 2.5 px), an odd
+    width leaves the 2 x 2 tiles of the last row and column partly outside
+    the scan, and the depth is far below one depth step of the structural
+    kernels (odd depths take the one-sample-per-lane kernel, even 16-bit
+    depths the two-samples-per-lane one)."""
+    pair = synth.make_pair("tiny", n=n, d=d)
+    P = _gpu_pair(octmc, pair, dtype=dtype, levels=1)
+    lv = oracle.level_from(round_storage(pair.sx, dtype), round_storage(pair.sy, dtype), pair.ax, pair.ay,
+                           pair.vx, pair.vy)
+    for case, seed in (("uniform", 1), ("smooth", 2)):
+        D = synth.random_field(n, n, 3.0, seed) if case == "uniform" else synth.smooth_random_field(n, n, 2.5, seed)
+        _compare(octmc, P, lv, 0, D, f"minimal/{n}x{n}x{d}/{dtype}/{case}")
+
+
 def test_eval_parity_validity_and_white_lines(octmc):
     pair = synth.make_pair("tiny", n=48, d=64, white_lines=True)
     assert (pair.vx == 0).any() and (pair.vy == 0).any()
