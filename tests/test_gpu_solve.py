@@ -47,6 +47,26 @@ def test_register_matches_oracle_tiny(octmc, iters):
     assert diff <= 0.05, diff
 
 
+@pytest.mark.parametrize("n,d,dtype,levels", [(4, 4, "f32", 1), (6, 8, "bf16", 1), (9, 11, "f32", 2)])
+def test_register_minimal_shapes_vs_oracle(octmc, n, d, dtype, levels):
+    """Whole solves of the smallest scans (every neighbourhood reaches past
+    the volume; a 9 x 9 x 11 pair has a second level of 5 x 5 x 6): the
+    final field within 0.05 px RMS of the oracle's solve on the volumes as
+    stored."""
+    pair = synth.make_pair("tiny", n=n, d=d)
+    P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, levels=levels, dtype=dtype)
+    log(f"register minimal {n}x{n}x{d} {dtype} levels={levels}")
+    D, _, _, rep = P.register()
+    torch.cuda.synchronize()
+    prm = _orc_params(P.params)
+    prm.store = {"f32": 0, "bf16": 1, "f16": 2}[dtype]
+    Do, orep = oracle.register(oracle.level_from_pair(pair), prm)
+    diff = np.sqrt(((D.double().cpu().numpy() - Do) ** 2).mean())
+    print("levels gpu", rep, "oracle", orep, "rms diff", diff)
+    assert len(rep) == levels
+    assert diff <= 0.05, diff
+
+
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 def test_register_storage_types_vs_oracle(octmc, dtype):
     """BF16 / FP16 storage: the displacement error against the FP64 oracle,
