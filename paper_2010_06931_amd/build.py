@@ -19,7 +19,7 @@ ARCH = os.environ.get("OCTMC_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", f"--offload-arch={ARCH}", "-fvisibility=hidden", "-DOCTMC_BUILD",
          # no packed FP32 instructions in generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+         "-Wall"]
 
 
 def _compile(src: str) -> str:

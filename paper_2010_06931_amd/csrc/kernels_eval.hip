@@ -743,14 +743,6 @@ __device__ __forceinline__ void sum_rows(const double* blk, int nblk, double (&o
     for (int q = 0; q < N; ++q) out[q] = sh[q][0];
 }
 
-__device__ __forceinline__ int find_job(const int* begins, int n)
-{
-    int jid = 0;
-    for (int q = 1; q < n; ++q)
-        if ((int)blockIdx.x >= begins[q]) jid = q;
-    return jid;
-}
-
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kRedBlock) void k_sum(const SumJobs jobs)

@@ -15,8 +15,6 @@
 namespace octmc {
 namespace {
 
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
 __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f)
 {
     uint32_t u = __builtin_bit_cast(uint32_t, f);
