@@ -95,6 +95,31 @@ def test_register_storage_types_vs_oracle(octmc, dtype):
     assert storage <= 0.25, storage
 
 
+def test_module_register_equals_pair_register(octmc):
+    """The one-call form (octmc.register: create, solve, merge, destroy) gives
+    the field, merged volumes and report of the explicit pair, bit for bit,
+    with en face images and with OCTA volumes (projected en face images)."""
+    pair = synth.make_pair("tiny", n=48, d=64)
+    log("module-level register against the explicit pair")
+    D1, mo1, ma1, rep1 = octmc.register(pair.sx, pair.sy, enface_x=pair.ax, enface_y=pair.ay, valid_x=pair.vx,
+                                        valid_y=pair.vy, levels=2)
+    P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, levels=2)
+    D2, mo2, ma2, rep2 = P.register(merged=True)
+    torch.cuda.synchronize()
+    P.close()
+    assert rep1 == rep2
+    assert torch.equal(D1, D2) and torch.equal(mo1, mo2)
+    assert ma1 is None and ma2 is None
+    D3, mo3, ma3, rep3 = octmc.register(pair.sx, pair.sy, pair.ox, pair.oy, levels=2, dtype="bf16",
+                                        project_enface=True)
+    Q = octmc.Pair(pair.sx, pair.sy, ox=pair.ox, oy=pair.oy, levels=2, dtype="bf16", project_enface=True)
+    D4, mo4, ma4, rep4 = Q.register(merged=True)
+    torch.cuda.synchronize()
+    Q.close()
+    assert rep3 == rep4
+    assert torch.equal(D3, D4) and torch.equal(mo3, mo4) and torch.equal(ma3, ma4)
+
+
 def test_register_recovers_motion(octmc):
     # pair 1 needs more than 100 steps per level to converge (so does the oracle)
     pair = synth.make_pair("tiny", pair=1)
