@@ -327,6 +327,7 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     if (jid < 0) return;  // whole block
     const StructJob& J = jobs.j[jid];
     const int w = J.w, h = J.h, d = J.d;
+    const int dp = J.dp;  // storage pitch: d, or d + 1 (a padding sample) for an odd depth in 16-bit storage
     // 2 x 2 tile of output A-scans per workgroup, one per wave.  The tile
     // rows form 8 bands (one per XCD when the job fills the grid); a band is
     // swept column by column, so the rows a tile reads are still in that
@@ -351,10 +352,10 @@ __global__ __launch_bounds__(256) void k_struct(const StructJobs jobs)
     Stencil SX, SY;
     float tw = 0.f, tdw = 0.f;
     if constexpr (AXIAL) {
-        make_stencil_axial<T>(SX, i, j, dX[2], w, d);
-        make_stencil_axial<T>(SY, i, j, dY[2], w, d);
+        make_stencil_axial<T>(SX, i, j, dX[2], w, dp);
+        make_stencil_axial<T>(SY, i, j, dY[2], w, dp);
     } else {
-        make_stencils<T>(SX, SY, tw, tdw, i, j, dX, dY, w, h, d, lane);
+        make_stencils<T>(SX, SY, tw, tdw, i, j, dX, dY, w, h, dp, lane);
     }
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
@@ -512,9 +513,9 @@ __device__ __forceinline__ void ld2<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t vo
 
 template <typename T>
 __device__ __forceinline__ void load_pairs(float (&q0)[16], float (&q1)[16], __amdgpu_buffer_rsrc_t rs,
-                                           const Stencil& S, int m, int d)
+                                           const Stencil& S, int m, int dp)
 {
-    const int mc = clampi(m, 0, d - 2);
+    const int mc = clampi(m, 0, dp - 2);
     const uint32_t voff = (uint32_t)mc * esize<T>::v;
 #pragma unroll
     for (int q = 0; q < 16; ++q) ld2<T>(rs, voff, S.off[q], q0[q], q1[q]);
@@ -533,6 +534,7 @@ __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
     if (jid < 0) return;  // whole block
     const StructJob& J = jobs.j[jid];
     const int w = J.w, h = J.h, d = J.d;
+    const int dp = J.dp;  // storage pitch: d, or d + 1 (a padding sample) for an odd depth in 16-bit storage
     // 2 x 2 tiles in 8 bands of tile rows, swept column by column (as k_struct)
     const int tpr = (w + 1) >> 1;
     const int trows = (h + 1) >> 1;
@@ -549,11 +551,11 @@ __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
     const float* dY = J.disp + ((size_t)J.na + a) * 3;
     Stencil SX, SY;
     if constexpr (AXIAL) {
-        make_stencil_axial<T>(SX, i, j, dX[2], w, d);
-        make_stencil_axial<T>(SY, i, j, dY[2], w, d);
+        make_stencil_axial<T>(SX, i, j, dX[2], w, dp);
+        make_stencil_axial<T>(SY, i, j, dY[2], w, dp);
     } else {
-        make_stencil<T>(SX, i, j, dX[0], dX[1], dX[2], w, h, d);
-        make_stencil<T>(SY, i, j, dY[0], dY[1], dY[2], w, h, d);
+        make_stencil<T>(SX, i, j, dX[0], dX[1], dX[2], w, h, dp);
+        make_stencil<T>(SY, i, j, dY[0], dY[1], dY[2], w, h, dp);
     }
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.sx), (short)0, (int)J.vol_bytes, kRsrcWord3);
@@ -578,18 +580,19 @@ __global__ __launch_bounds__(256) void k_struct2(const StructJobs jobs)
             const int mY = EY + kOutPerStep2 * n + 2 * lane;
             float bx0, bx1, by0, by1;
             if constexpr (AXIAL) {
-                ld2<T>(rx, (uint32_t)clampi(mX, 0, d - 2) * esize<T>::v, SX.off[kCentre], bx0, bx1);
-                ld2<T>(ry, (uint32_t)clampi(mY, 0, d - 2) * esize<T>::v, SY.off[kCentre], by0, by1);
+                ld2<T>(rx, (uint32_t)clampi(mX, 0, dp - 2) * esize<T>::v, SX.off[kCentre], bx0, bx1);
+                ld2<T>(ry, (uint32_t)clampi(mY, 0, dp - 2) * esize<T>::v, SY.off[kCentre], by0, by1);
             } else {
-                load_pairs<T>(x0, x1, rx, SX, mX, d);
-                load_pairs<T>(y0, y1, ry, SY, mY, d);
+                load_pairs<T>(x0, x1, rx, SX, mX, dp);
+                load_pairs<T>(y0, y1, ry, SY, mY, dp);
                 bx0 = blend(x0, SX);
                 bx1 = blend(x1, SX);
                 by0 = blend(y0, SY);
                 by1 = blend(y1, SY);
             }
             // clamp: a pair below the A-scan holds sample 0 twice, one above it sample d - 1 twice
-            const bool loX = mX < 0, hiX = mX > d - 2, loY = mY < 0, hiY = mY > d - 2;
+            // (with an odd depth the last stored pair is sample d - 1 and its padding copy)
+            const bool loX = mX < 0, hiX = mX > dp - 2, loY = mY < 0, hiY = mY > dp - 2;
             const float cx0 = hiX ? bx1 : bx0, cx1 = loX ? bx0 : bx1;
             const float ty0 = hiY ? by1 : by0, ty1 = loY ? by0 : by1;
             // Y positions start one sample after the pair boundary when rY = 1
@@ -1348,18 +1351,20 @@ hipError_t launch_sum(const SumJobs& jobs, int total_blocks, hipStream_t s)
 template <typename T, bool AXIAL>
 static hipError_t launch_struct_subsets(const StructJobs& jobs, hipStream_t s)
 {
-    // 16-bit storage: two samples per lane for the jobs whose depth is even;
-    // an odd depth keeps one sample per lane (the last pair of an A-scan
-    // would start at an odd sample, not 32-bit aligned).  The kernel is chosen
-    // per job, so a job's result does not depend on the other jobs of its
-    // launch; each subset has its own grid (a multiple of the 8 XCDs).
+    // 16-bit storage: two samples per lane for the jobs whose storage pitch
+    // is even (every level of a pair: an odd depth is stored with one padding
+    // sample); an odd pitch (volumes in the caller's layout with an odd depth)
+    // keeps one sample per lane, since its sample pairs would not all be
+    // 32-bit aligned.  The kernel is chosen per job, so a job's result does not
+    // depend on the other jobs of its launch; each subset has its own grid (a
+    // multiple of the 8 XCDs).
     StructJobs even{}, odd{};
     even.skip = odd.skip = jobs.skip;
     int be = 0, bo = 0;
     for (int q = 0; q < jobs.n; ++q) {
         StructJob J = jobs.j[q];
         const int nb = struct_blocks(J.w, J.h);
-        if (J.d % 2 == 0) {
+        if (J.dp % 2 == 0) {
             J.blk_begin = be;
             be += nb;
             even.j[even.n++] = J;

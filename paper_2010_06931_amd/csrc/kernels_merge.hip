@@ -142,8 +142,10 @@ __device__ __forceinline__ float ld<f16_t>(const void* p, size_t q)
 template <typename T>
 __global__ __launch_bounds__(256) void k_merge_volume(const void* __restrict__ sx, const void* __restrict__ sy,
                                                       const float* __restrict__ disp, const float4* __restrict__ wts,
-                                                      int which, int w, int h, int d, float* __restrict__ out)
+                                                      int which, int w, int h, int d, int dp,
+                                                      float* __restrict__ out)
 {
+    // sx, sy: [h][w] columns of dp samples (the first d are the A-scan); out: [h][w][d]
     __shared__ float ring_all[4][2][128];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int na = w * h;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void k_merge_volume(const void* __restrict__ s
         cr_w(dv[2] - fzf, wz[V]);
         for (int b = 0; b < 4; ++b)
             for (int c = 0; c < 4; ++c) {
-                off[V][b * 4 + c] = ((size_t)clampi(ny - 1 + b, 0, h - 1) * w + clampi(nx - 1 + c, 0, w - 1)) * d;
+                off[V][b * 4 + c] = ((size_t)clampi(ny - 1 + b, 0, h - 1) * w + clampi(nx - 1 + c, 0, w - 1)) * dp;
                 wl[V][b * 4 + c] = wx[c] * wy[b];
             }
         base[V] = nz - 1;
@@ -331,21 +333,21 @@ hipError_t launch_merge_weights(const float* disp, int w, int h, const unsigned 
     return hipGetLastError();
 }
 hipError_t launch_merge_volume(const void* vx_, const void* vy_, octmc_dtype dt, const float* disp,
-                               const float4* wts, int which, int w, int h, int d, float* out, hipStream_t s)
+                               const float4* wts, int which, int w, int h, int d, int dp, float* out, hipStream_t s)
 {
     const int blocks = (w * h + 3) / 4;
     switch (dt) {
     case OCTMC_F32:
-        hipLaunchKernelGGL(k_merge_volume<float>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h, d,
+        hipLaunchKernelGGL(k_merge_volume<float>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h, d, dp,
                            out);
         break;
     case OCTMC_BF16:
         hipLaunchKernelGGL(k_merge_volume<bf16_t>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h,
-                           d, out);
+                           d, dp, out);
         break;
     case OCTMC_F16:
         hipLaunchKernelGGL(k_merge_volume<f16_t>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h,
-                           d, out);
+                           d, dp, out);
         break;
     default:
         return hipErrorInvalidValue;

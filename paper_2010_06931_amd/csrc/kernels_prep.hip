@@ -37,6 +37,20 @@ __global__ void k_to_storage(const float* __restrict__ in, void* __restrict__ ou
     }
 }
 
+// The same into A-scan columns of dp >= d samples: samples d .. dp - 1 of a
+// column repeat sample d - 1 (one thread per stored sample).
+__global__ void k_to_storage_pad(const float* __restrict__ in, void* __restrict__ out, int na, int d, int dp, int dt)
+{
+    const size_t n = (size_t)na * dp;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+        const size_t a = q / dp;
+        const int k = (int)(q - a * dp);
+        const float v = in[a * d + (k < d ? k : d - 1)];
+        if (dt == OCTMC_BF16) static_cast<unsigned short*>(out)[q] = f32_to_bf16_rne(v);
+        else static_cast<unsigned short*>(out)[q] = __builtin_bit_cast(unsigned short, (_Float16)v);
+    }
+}
+
 // one thread per coarse sample; depth fastest for coalescing
 __global__ void k_pyr3(const float* __restrict__ in, int w, int h, int d, float* __restrict__ out)
 {
@@ -218,6 +232,15 @@ hipError_t launch_validity(const float* vol, int w, int h, int d, int V, double*
 hipError_t launch_to_storage(const float* in, void* out, size_t n, octmc_dtype dt, hipStream_t s)
 {
     hipLaunchKernelGGL(k_to_storage, dim3(grid_for(n)), dim3(256), 0, s, in, out, n, (int)dt);
+    return hipGetLastError();
+}
+hipError_t launch_to_storage_pitched(const float* in, void* out, int na, int d, int dp, octmc_dtype dt,
+                                     hipStream_t s)
+{
+    if (dp == d) return launch_to_storage(in, out, (size_t)na * d, dt, s);
+    if (dp < d || dt == OCTMC_F32) return hipErrorInvalidValue;  // only 16-bit storage is padded
+    const size_t n = (size_t)na * dp;
+    hipLaunchKernelGGL(k_to_storage_pad, dim3(grid_for(n)), dim3(256), 0, s, in, out, na, d, dp, (int)dt);
     return hipGetLastError();
 }
 hipError_t launch_pyr3(const float* in, int w, int h, int d, float* out, hipStream_t s)

@@ -522,6 +522,7 @@ int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params_in, const octm
                 L.h = M->h[l];
                 L.d = M->d[l];
                 L.na = L.w * L.h;
+                L.dp = L.d;  // the n-volume storage is not padded
                 L.vol_bytes = (uint32_t)((size_t)L.na * L.d * esz(M->dtype));
                 L.sx = M->vol[P].s[l];
                 L.sy = M->vol[Q].s[l];

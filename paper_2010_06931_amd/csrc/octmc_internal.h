@@ -126,6 +126,7 @@ struct StructJob {
     int blk_begin;      // first block of this job in the grid
     uint32_t vol_bytes; // bytes of one volume (buffer range)
     float eps_h;        // pseudo-Huber parameter (Eq. 4)
+    int dp;             // storage pitch: samples between neighbouring A-scans' columns (d or d + 1)
 };
 struct StructJobs {
     StructJob j[kMaxJobs];
@@ -198,6 +199,10 @@ hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp,
 
 // preparation (kernels_prep.hip)
 hipError_t launch_to_storage(const float* in, void* out, size_t n, octmc_dtype dt, hipStream_t s);
+// float32 [na][d] -> storage type [na][dp] (dp >= d; samples d .. dp - 1 of
+// every A-scan repeat sample d - 1)
+hipError_t launch_to_storage_pitched(const float* in, void* out, int na, int d, int dp, octmc_dtype dt,
+                                     hipStream_t s);
 hipError_t launch_pyr3(const float* in, int w, int h, int d, float* out, hipStream_t s);
 hipError_t launch_pyr2(const float* in, int w, int h, float* out, hipStream_t s);
 hipError_t launch_pyr1(const float* in, int n, float* out, hipStream_t s);
@@ -391,6 +396,6 @@ hipError_t launch_merge_weights(const float* disp, int w, int h, const unsigned 
                                 const float* vx, const float* vy, double kappa, double tau, float4* wts,
                                 hipStream_t s);
 hipError_t launch_merge_volume(const void* vx_, const void* vy_, octmc_dtype dt, const float* disp,
-                               const float4* wts, int which, int w, int h, int d, float* out, hipStream_t s);
+                               const float4* wts, int which, int w, int h, int d, int dp, float* out, hipStream_t s);
 
 }  // namespace octmc

@@ -139,7 +139,7 @@ int octmc::eval_group(const EvalArgs* ea, int n, hipStream_t s, hipEvent_t* ev, 
         sj.j[q] = SumJob{{ea[q].disp, dy}, V.sum_blk, L.na, sb, nsum};
         sb += nsum;
         tj.j[q] = StructJob{L.sx, L.sy, ea[q].disp, V.part, L.w, L.h, L.d, L.na, tb, L.vol_bytes,
-                            (float)pr.eps_huber};
+                            (float)pr.eps_huber, L.dp};
         tb += struct_blocks(L.w, L.h);
         const int nc = nblk_combine(L.na);
         const int blen = L.w;  // square scans: every B-scan has w A-scans
@@ -332,7 +332,7 @@ size_t octmc::pair_footprint(const octmc_params& pr, const octmc_shape& sh, bool
     t += slab_bytes(h * 4) + slab_bytes(w * 4);  // validity
     size_t lw = w, lh = h, ld = d;
     for (int l = 0; l < pr.levels; ++l) {
-        t += 2 * slab_bytes(lw * lh * ld * es);
+        t += 2 * slab_bytes(lw * lh * (es == 2 ? ld + (ld & 1) : ld) * es);  // storage, padded to an even pitch
         if (l + 1 < pr.levels) {
             const size_t w2 = (lw + 1) / 2, h2 = (lh + 1) / 2, d2 = (ld + 1) / 2;
             t += 2 * slab_bytes(w2 * h2 * d2 * 4) + 2 * slab_bytes(w2 * h2 * 4) + slab_bytes(h2 * 4) +
@@ -632,12 +632,15 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
         L.h = lh;
         L.d = ld;
         L.na = lw * lh;
-        const size_t lnv = (size_t)L.na * ld;
+        // 16-bit storage of an odd depth gets one padding sample per A-scan, so
+        // that the two-samples-per-lane structural kernel serves every level
+        L.dp = (P->dtype != OCTMC_F32 && (ld & 1)) ? ld + 1 : ld;
+        const size_t lnv = (size_t)L.na * L.dp;
         L.vol_bytes = (uint32_t)(lnv * esize(P->dtype));
         void* st[2];
         for (int V = 0; V < 2; ++V) {
             HIP_TRY(P->alloc(&st[V], lnv * esize(P->dtype)));
-            HIP_TRY(launch_to_storage(cur[V], st[V], lnv, P->dtype, s));
+            HIP_TRY(launch_to_storage_pitched(cur[V], st[V], L.na, ld, L.dp, P->dtype, s));
         }
         L.sx = st[0];
         L.sy = st[1];
@@ -838,6 +841,7 @@ int octmc_eval_noalloc(octmc_ctx* ctx, const octmc_params* params, const octmc_s
     v.L.h = h;
     v.L.d = d;
     v.L.na = (int)na;
+    v.L.dp = d;  // the caller's volumes: [h][w][d]
     v.L.sx = const_cast<void*>(sx);  // read only
     v.L.sy = const_cast<void*>(sy);
     v.L.ax = const_cast<float*>(ax);
@@ -936,10 +940,10 @@ int octmc::merge_impl(octmc_pair* pair, const float* disp, float* merged_oct, fl
     HIP_TRY(launch_density(disp, L.w, L.h, grid, s));
     HIP_TRY(launch_merge_weights(disp, L.w, L.h, grid, merged_octa ? L.vx : nullptr, merged_octa ? L.vy : nullptr,
                                  pair->params.merge_kappa, pair->params.merge_tau, wts, s));
-    HIP_TRY(launch_merge_volume(L.sx, L.sy, pair->dtype, disp, wts, 0, L.w, L.h, L.d, merged_oct, s));
+    HIP_TRY(launch_merge_volume(L.sx, L.sy, pair->dtype, disp, wts, 0, L.w, L.h, L.d, L.dp, merged_oct, s));
     if (merged_octa)
-        HIP_TRY(launch_merge_volume(pair->octa[0], pair->octa[1], OCTMC_F32, disp, wts, 1, L.w, L.h, L.d, merged_octa,
-                                    s));
+        HIP_TRY(launch_merge_volume(pair->octa[0], pair->octa[1], OCTMC_F32, disp, wts, 1, L.w, L.h, L.d, L.d,
+                                    merged_octa, s));
     HIP_TRY(hipStreamSynchronize(s));
     return OCTMC_OK;
 }

@@ -24,6 +24,10 @@ namespace octmc {
 
 struct Level {
     int w = 0, h = 0, d = 0, na = 0;
+    // storage pitch of sx / sy: samples from one A-scan's column to the next
+    // (d, or d + 1 for an odd depth in 16-bit storage: the extra sample repeats
+    // the last one, so that every sample pair starts 32-bit aligned)
+    int dp = 0;
     void* sx = nullptr;
     void* sy = nullptr;
     float* ax = nullptr;

@@ -47,11 +47,13 @@ def test_register_matches_oracle_tiny(octmc, iters):
     assert diff <= 0.05, diff
 
 
-@pytest.mark.parametrize("n,d,dtype,levels", [(4, 4, "f32", 1), (6, 8, "bf16", 1), (9, 11, "f32", 2)])
+@pytest.mark.parametrize("n,d,dtype,levels", [(4, 4, "f32", 1), (6, 8, "bf16", 1), (9, 11, "f32", 2),
+                                              (9, 11, "bf16", 2), (7, 5, "f16", 1)])
 def test_register_minimal_shapes_vs_oracle(octmc, n, d, dtype, levels):
     """Whole solves of the smallest scans (every neighbourhood reaches past
-    the volume; a 9 x 9 x 11 pair has a second level of 5 x 5 x 6): the
-    final field within 0.05 px RMS of the oracle's solve on the volumes as
+    the volume; a 9 x 9 x 11 pair has a second level of 5 x 5 x 6; odd
+    depths in 16-bit storage are stored with a padding sample): the final
+    field within 0.05 px RMS of the oracle's solve on the volumes as
     stored."""
     pair = synth.make_pair("tiny", n=n, d=d)
     P = octmc.Pair(pair.sx, pair.sy, ax=pair.ax, ay=pair.ay, vx=pair.vx, vy=pair.vy, levels=levels, dtype=dtype)
@@ -146,6 +148,27 @@ def test_merge_matches_oracle(octmc):
                                 P.params.merge_kappa, P.params.merge_tau)
     assert np.abs(mo.double().cpu().numpy() - ro).max() < 1e-4 * max(1.0, np.abs(ro).max())
     assert np.abs(ma.double().cpu().numpy() - ra).max() < 1e-4 * max(1.0, np.abs(ra).max())
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_merge_matches_oracle_odd_depth_16bit(octmc, dtype):
+    """The merge of an odd depth in 16-bit storage, whose volumes the library
+    stores with one padding sample per A-scan: element-wise against the
+    oracle's merge of the volumes rounded to the storage type."""
+    pair = synth.make_pair("tiny", n=36, d=71, white_lines=True)
+    P = octmc.Pair(pair.sx, pair.sy, ox=pair.ox, oy=pair.oy, vx=pair.vx, vy=pair.vy, levels=2, dtype=dtype)
+    D = synth.perturbed_field(pair.d_gt, 0.4, 5).float()
+    log(f"merge 36x36x71 {dtype}")
+    mo, _ = P.merge(D.cuda(), octa=False)
+    torch.cuda.synchronize()
+    tt = torch.bfloat16 if dtype == "bf16" else torch.float16
+    sx, sy = pair.sx.to(tt).to(torch.float32), pair.sy.to(tt).to(torch.float32)
+    ox = oracle.substitute_invalid(pair.ox, pair.vx, 0)
+    oy = oracle.substitute_invalid(pair.oy, pair.vy, 1)
+    ro, _, _, _ = oracle.merge(sx, sy, D.double(), ox, oy, pair.vx, pair.vy, P.params.merge_kappa,
+                               P.params.merge_tau)
+    assert mo.shape == (36, 36, 71)
+    assert np.abs(mo.double().cpu().numpy() - ro).max() < 1e-4 * max(1.0, np.abs(ro).max())
 
 
 def test_register_with_merge_and_enface_from_octa(octmc):
