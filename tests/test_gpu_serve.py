@@ -15,9 +15,9 @@ from gpu_util import log
 pytestmark = pytest.mark.gpu
 
 # (n, d, levels, dtype, iterations per level).  The BF16 request of depth 50
-# reaches an odd depth (25) at its second level, where it takes the
-# one-sample structural kernel while the other BF16 requests of a grouped
-# launch take the two-sample one.  The 130 x 130 request's finest level is
+# reaches an odd depth (25) at its second level, which the library stores
+# with a padding sample per A-scan (an even pitch) in the same grouped
+# launches as the even depths.  The 130 x 130 request's finest level is
 # large enough (at least 128^2 A-scans) to run on its own stream in grouped
 # mode, its coarser one is grouped.  The last request is the tiny workload's
 # pair, solved as its workload is defined.
