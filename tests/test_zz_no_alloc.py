@@ -2,8 +2,9 @@
 two calls in a row, the second on a smaller pair, each bitwise equal to
 octmc_eval on a pair created from the same level-0 data with the same eta
 (eta set by the call itself, eta_mode 0, then read back, eta_mode 1), in
-float32 and BF16 storage; a pair larger than the static scratch allows is
-refused."""
+float32 and BF16 storage; an odd depth in BF16 (the caller's layout, so
+the one-sample structural kernel) against the oracle; a pair larger than
+the static scratch allows is refused."""
 import pytest
 import torch
 
@@ -53,6 +54,43 @@ def test_noalloc_equals_pair_eval(octmc, dtype):
         torch.cuda.synchronize()
         assert torch.equal(terms, t2)
         P.close()
+
+
+def test_noalloc_odd_depth_matches_oracle(octmc):
+    """An odd depth in BF16 in the caller's layout (no padding sample, so the
+    one-sample structural kernel): every term and the whole gradient against
+    the oracle on the rounded volumes, at 1e-4; the pair path, which stores
+    the depth padded and takes the two-sample kernel, agrees with it to
+    float32 rounding."""
+    import oracle
+    from gpu_util import grad_err, grad_rel, rel, round_storage
+    n, d = 24, 37
+    q = synth.make_pair("tiny", n=n, d=d, octa_volumes=False)
+    P = octmc.Pair(q.sx, q.sy, ax=q.ax, ay=q.ay, vx=q.vx, vy=q.vy, dtype="bf16", levels=1)
+    ins = _inputs(octmc, q, "bf16")
+    D = synth.random_field(n, n, 3.0, 4).float().cuda()
+    eta = torch.zeros(1, dtype=torch.float64, device="cuda")
+    terms = torch.empty(octmc.NTERMS, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(D)
+    log(f"eval_noalloc bf16 {n}x{n}x{d} (odd depth), eta_mode 0")
+    octmc.eval_noalloc(*ins, D, eta, terms, grad, dtype="bf16", params=P.params, eta_mode=0)
+    torch.cuda.synchronize()
+    t = octmc.terms_dict(terms)
+    p = P.params
+    prm = oracle.Params(alpha=p.alpha, delta0=p.delta0, eps_h=p.eps_huber, eps_r=p.eps_reg,
+                        flyback_frac=p.flyback_frac, mean_weight=p.mean_weight)
+    lv = oracle.level_from(round_storage(q.sx, "bf16"), round_storage(q.sy, "bf16"), q.ax, q.ay, q.vx, q.vy)
+    D64 = D.double().cpu().numpy()
+    eta_ref = oracle.eta_at(lv, D64, prm)
+    ref, gref = oracle.evaluate(lv, D64, prm, eta_ref)
+    assert rel(t["eta"], eta_ref) < 1e-4, (t["eta"], eta_ref)
+    for k in ("F", "data", "str", "ang", "reg", "str05", "ang05"):
+        assert rel(t[k], ref[k]) < 1e-4 or abs(t[k] - ref[k]) < 1e-9 * max(1.0, abs(ref["F"])), (k, t[k], ref[k])
+    assert grad_err(grad.double().cpu().numpy(), gref) < 1e-4
+    t2, g2 = P.eval(0, D, eta_mode=0)
+    torch.cuda.synchronize()
+    assert rel(octmc.terms_dict(t2)["F"], t["F"]) < 1e-5
+    assert grad_rel(g2.double().cpu().numpy(), grad.double().cpu().numpy()) < 1e-5
 
 
 def test_noalloc_refuses_more_than_its_scratch(octmc):
