@@ -5,7 +5,12 @@
 //   k_struct  per output A-scan: resample both structural volumes with
 //             their displacement (Eq. 2), residual, pseudo-Huber loss (Eq. 4)
 //             and the depth sums of the loss and of its gradient with respect
-//             to the A-scan's displacement
+//             to the A-scan's displacement; one depth sample per lane (float32
+//             storage, and 16-bit volumes of odd depth in the caller's layout)
+//   k_struct2 the same with two 16-bit samples per lane (every level a pair
+//             stores: an odd depth is stored with one padding sample)
+//   k_struct_multi, k_struct_multi1  the structural partials of every volume
+//             pair of n = 3 or 4 volumes, each volume resampled once
 //   k_combine per output A-scan: en face residual (Eq. 7), resampled
 //             validity (Eq. 5), weight delta (Eq. 8), combination with eta
 //             (Eq. 9), scan-order regulariser, mean term, gradient; float64
