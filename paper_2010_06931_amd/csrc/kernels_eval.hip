@@ -1106,16 +1106,16 @@ struct Resampled {
 
 template <typename T>
 __device__ __forceinline__ void resample_step(Resampled& o, __amdgpu_buffer_rsrc_t rs, const StencilS& S, int E, int r,
-                                              int n, int lane, int d)
+                                              int n, int lane, int dp)
 {
     const int m = E + kOutPerStep2 * n + 2 * lane;
-    const uint32_t voff = (uint32_t)clampi(m, 0, d - 2) * esize<T>::v;
+    const uint32_t voff = (uint32_t)clampi(m, 0, dp - 2) * esize<T>::v;
     float q0[16], q1[16];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int a = 0; a < 4; ++a) ld2<T>(rs, voff, S.roff[b] + S.coff[a], q0[b * 4 + a], q1[b * 4 + a]);
-    const bool lo = m < 0, hi = m > d - 2;
+    const bool lo = m < 0, hi = m > dp - 2;
     float v0, vx0, vy0, v1, vx1, vy1;
     blend3(q0, S, v0, vx0, vy0);
     blend3(q1, S, v1, vx1, vy1);
@@ -1144,10 +1144,11 @@ __device__ __forceinline__ void resample_step(Resampled& o, __amdgpu_buffer_rsrc
 
 template <int N>
 struct StructMultiJob {
-    const void* vol[N];            // storage-type volumes of this level, [h][w][d]
+    const void* vol[N];            // storage-type volumes of this level, [h][w][dp]
     const float* disp;             // [N][h][w][3]
     float* part[N * (N - 1) / 2];  // per pair (P, Q), P < Q in lexicographic order: [na][8]
     int w, h, d, na;
+    int dp;                        // storage pitch (d, or d + 1 for an odd depth in 16-bit storage)
     uint32_t vol_bytes;
     float eps_h;
     const int* skip;  // device flag: when nonzero the launch does nothing (may be null)
@@ -1161,7 +1162,7 @@ __global__ __launch_bounds__(256) void k_struct_multi(const StructMultiJob<N> J)
     const int wv = uni((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
-    const int w = J.w, h = J.h, d = J.d;
+    const int w = J.w, h = J.h, d = J.d, dp = J.dp;
     // 2 x 2 tiles in 8 bands of tile rows, swept column by column (as k_struct2)
     const int tpr = (w + 1) >> 1;
     const int trows = (h + 1) >> 1;
@@ -1178,7 +1179,7 @@ __global__ __launch_bounds__(256) void k_struct_multi(const StructMultiJob<N> J)
 #pragma unroll
     for (int V = 0; V < N; ++V) {
         const float* dv = J.disp + ((size_t)V * J.na + a) * 3;
-        make_stencil_s<T>(S[V], i, j, dv[0], dv[1], dv[2], w, h, d);
+        make_stencil_s<T>(S[V], i, j, dv[0], dv[1], dv[2], w, h, dp);
         rs[V] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(J.vol[V]), (short)0, (int)J.vol_bytes, kRsrcWord3);
     }
     // output grid: position 0 of step 0 holds sample base_0 - s0 of volume 0
@@ -1200,7 +1201,7 @@ __global__ __launch_bounds__(256) void k_struct_multi(const StructMultiJob<N> J)
     for (int n = 0; n < nsteps; ++n) {
         Resampled R[N];
 #pragma unroll
-        for (int V = 0; V < N; ++V) resample_step<T>(R[V], rs[V], S[V], E[V], r[V], n, lane, d);
+        for (int V = 0; V < N; ++V) resample_step<T>(R[V], rs[V], S[V], E[V], r[V], n, lane, dp);
         const int p0 = 2 * lane;
         const int o0 = kOutPerStep2 * n + p0 - s0;
         const bool ok[2] = {p0 >= s0 && p0 <= 121 + s0 && o0 < d, p0 + 1 <= 121 + s0 && o0 + 1 < d};
@@ -1414,8 +1415,8 @@ hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t
 
 template <int N>
 static hipError_t launch_struct_multi_n(const void* const* vol, const float* disp, float* const* part, int w, int h,
-                                        int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s,
-                                        const int* skip)
+                                        int d, int dp, uint32_t vol_bytes, float eps_h, octmc_dtype dt,
+                                        hipStream_t s, const int* skip)
 {
     StructMultiJob<N> J{};
     J.skip = skip;
@@ -1425,6 +1426,7 @@ static hipError_t launch_struct_multi_n(const void* const* vol, const float* dis
     J.w = w;
     J.h = h;
     J.d = d;
+    J.dp = dp;
     J.na = w * h;
     J.vol_bytes = vol_bytes;
     J.eps_h = eps_h;
@@ -1438,18 +1440,20 @@ static hipError_t launch_struct_multi_n(const void* const* vol, const float* dis
     return hipGetLastError();
 }
 
-bool struct_multi_supported(int n, int d, octmc_dtype dt)
+bool struct_multi_supported(int n, int dp, octmc_dtype dt)
 {
-    // 16-bit storage holds two samples per lane, which needs an even depth
-    return (n == 3 || n == 4) && (dt == OCTMC_F32 || ((dt == OCTMC_BF16 || dt == OCTMC_F16) && d % 2 == 0));
+    // 16-bit storage holds two samples per lane, which needs an even pitch
+    // (every level the n-volume path stores: odd depths are padded)
+    return (n == 3 || n == 4) && (dt == OCTMC_F32 || ((dt == OCTMC_BF16 || dt == OCTMC_F16) && dp % 2 == 0));
 }
 
 hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp, float* const* part, int w, int h,
-                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s, const int* skip)
+                               int d, int dp, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s,
+                               const int* skip)
 {
-    if (!struct_multi_supported(n, d, dt)) return hipErrorInvalidValue;
-    if (n == 3) return launch_struct_multi_n<3>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s, skip);
-    return launch_struct_multi_n<4>(vol, disp, part, w, h, d, vol_bytes, eps_h, dt, s, skip);
+    if (!struct_multi_supported(n, dp, dt) || (dt == OCTMC_F32 && dp != d)) return hipErrorInvalidValue;
+    if (n == 3) return launch_struct_multi_n<3>(vol, disp, part, w, h, d, dp, vol_bytes, eps_h, dt, s, skip);
+    return launch_struct_multi_n<4>(vol, disp, part, w, h, d, dp, vol_bytes, eps_h, dt, s, skip);
 }
 
 }  // namespace octmc

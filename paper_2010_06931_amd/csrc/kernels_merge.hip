@@ -246,7 +246,7 @@ __global__ void k_merge_weights_multi(const float* __restrict__ disp, int w, int
 template <typename T>
 __global__ __launch_bounds__(256) void k_merge_volume_multi(const MultiVols mv, const float* __restrict__ disp,
                                                             const float* __restrict__ wts, int w, int h, int d,
-                                                            float* __restrict__ out)
+                                                            int dp, float* __restrict__ out)
 {
     const int na = w * h;
     const size_t total = (size_t)na * d;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_merge_volume_multi(const MultiVols mv, 
             for (int b = 0; b < 4; ++b) {
                 const size_t row = (size_t)clampi(ny - 1 + b, 0, h - 1) * w;
                 for (int c = 0; c < 4; ++c) {
-                    const size_t col = (row + clampi(nx - 1 + c, 0, w - 1)) * d;
+                    const size_t col = (row + clampi(nx - 1 + c, 0, w - 1)) * dp;  // volumes [h][w][dp]
                     float z = 0.f;
                     for (int e = 0; e < 4; ++e) z = fmaf(wz[e], ld<T>(mv.vol[V], col + clampi(nz - 1 + e, 0, d - 1)), z);
                     v = fmaf(wx[c] * wy[b], z, v);
@@ -304,21 +304,21 @@ hipError_t launch_merge_weights_multi(const float* disp, int w, int h, const uns
     return hipGetLastError();
 }
 hipError_t launch_merge_volume_multi(const MultiVols& mv, octmc_dtype dt, const float* disp, const float* wts, int w,
-                                     int h, int d, float* out, hipStream_t s)
+                                     int h, int d, int dp, float* out, hipStream_t s)
 {
     const size_t n = (size_t)w * h * d;
     switch (dt) {
     case OCTMC_F32:
         hipLaunchKernelGGL(k_merge_volume_multi<float>, dim3(grid_for(n)), dim3(256), 0, s, mv, disp, wts, w, h, d,
-                           out);
+                           dp, out);
         break;
     case OCTMC_BF16:
         hipLaunchKernelGGL(k_merge_volume_multi<bf16_t>, dim3(grid_for(n)), dim3(256), 0, s, mv, disp, wts, w, h, d,
-                           out);
+                           dp, out);
         break;
     case OCTMC_F16:
         hipLaunchKernelGGL(k_merge_volume_multi<f16_t>, dim3(grid_for(n)), dim3(256), 0, s, mv, disp, wts, w, h, d,
-                           out);
+                           dp, out);
         break;
     default:
         return hipErrorInvalidValue;

@@ -246,7 +246,7 @@ struct MultiEvaluator final : Evaluator {
         // the structural partials of all pairs in one pass that resamples every
         // volume once, where the fused kernel serves this n, storage and depth
         const bool fused = !(M->params.flags & OCTMC_MULTI_PAIRWISE) &&
-                           struct_multi_supported(M->n, M->d[level], M->dtype);
+                           struct_multi_supported(M->n, storage_pitch(M->d[level], M->dtype), M->dtype);
         std::vector<EvalArgs> args(np);
         for (int q = 0; q < np; ++q) {
             const float* fP = ea.disp + (size_t)M->pairs[q].first * na * 3;
@@ -270,7 +270,7 @@ struct MultiEvaluator final : Evaluator {
             for (int V = 0; V < M->n; ++V) vols[V] = M->vol[V].s[level];
             for (int q = 0; q < np; ++q) parts[q] = M->views[q]->part;
             const Level& L = M->views[0]->lev[level];
-            HIP_TRY(launch_struct_multi(vols, M->n, ea.disp, parts, L.w, L.h, L.d, L.vol_bytes,
+            HIP_TRY(launch_struct_multi(vols, M->n, ea.disp, parts, L.w, L.h, L.d, L.dp, L.vol_bytes,
                                         (float)M->params.eps_huber, M->dtype, s, ea.skip));
         }
         for (int q0 = 0; q0 < np; q0 += kMaxJobs)
@@ -400,9 +400,10 @@ int ingest_volume(octmc_multi* M, int V, const octmc_shape* shape, const float* 
     float* cv = vd;
     for (int l = 0; l < M->nlev; ++l) {
         const int lw = M->w[l], lh = M->h[l], ld = M->d[l];
-        const size_t lnv = (size_t)lw * lh * ld;
-        HIP_TRY(M->alloc(&P.s[l], lnv * esz(M->dtype)));
-        HIP_TRY(launch_to_storage(cur, P.s[l], lnv, M->dtype, s));
+        // stored with an even pitch in 16-bit storage (odd depths padded), as a pair's levels
+        const int lp = storage_pitch(ld, M->dtype);
+        HIP_TRY(M->alloc(&P.s[l], (size_t)lw * lh * lp * esz(M->dtype)));
+        HIP_TRY(launch_to_storage_pitched(cur, P.s[l], lw * lh, ld, lp, M->dtype, s));
         P.a[l] = cen;
         P.v[l] = cv;
         if (l + 1 < M->nlev) {
@@ -442,10 +443,10 @@ int merge_multi_impl(octmc_multi* M, const float* disp, float* merged_oct, float
         mv.orient[V] = M->vol[V].orient;
     }
     HIP_TRY(launch_merge_weights_multi(disp, w, h, grid, mv, M->params.merge_kappa, M->params.merge_tau, wo, wa, s));
-    HIP_TRY(launch_merge_volume_multi(mv, M->dtype, disp, wo, w, h, d, merged_oct, s));
+    HIP_TRY(launch_merge_volume_multi(mv, M->dtype, disp, wo, w, h, d, storage_pitch(d, M->dtype), merged_oct, s));
     if (merged_octa) {
         for (int V = 0; V < M->n; ++V) mv.vol[V] = M->vol[V].octa;
-        HIP_TRY(launch_merge_volume_multi(mv, OCTMC_F32, disp, wa, w, h, d, merged_octa, s));
+        HIP_TRY(launch_merge_volume_multi(mv, OCTMC_F32, disp, wa, w, h, d, d, merged_octa, s));
     }
     HIP_TRY(hipStreamSynchronize(s));  // the temporaries are freed on return
     return OCTMC_OK;
@@ -522,8 +523,8 @@ int octmc_multi_create(octmc_ctx* ctx, const octmc_params* params_in, const octm
                 L.h = M->h[l];
                 L.d = M->d[l];
                 L.na = L.w * L.h;
-                L.dp = L.d;  // the n-volume storage is not padded
-                L.vol_bytes = (uint32_t)((size_t)L.na * L.d * esz(M->dtype));
+                L.dp = storage_pitch(L.d, M->dtype);
+                L.vol_bytes = (uint32_t)((size_t)L.na * L.dp * esz(M->dtype));
                 L.sx = M->vol[P].s[l];
                 L.sy = M->vol[Q].s[l];
                 L.ax = M->vol[P].a[l];

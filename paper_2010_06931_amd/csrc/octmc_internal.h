@@ -111,6 +111,11 @@ int merge_impl(octmc_pair* pair, const float* disp, float* merged_oct, float* me
 int ctx_device(const octmc_ctx* ctx);
 
 constexpr int kMaxJobs = 8;     // jobs (pairs) per grouped launch
+
+// Storage pitch of a volume level (samples from one A-scan's column to the
+// next): the depth, plus one padding sample (a copy of the last) for an odd
+// depth in 16-bit storage, so that every sample pair starts 32-bit aligned.
+inline int storage_pitch(int d, octmc_dtype dt) { return (dt != OCTMC_F32 && (d & 1)) ? d + 1 : d; }
 constexpr int kWavesPerBlock = 4;
 constexpr int kRedBlock = 256;  // threads per block of the reduction kernels
 
@@ -189,12 +194,12 @@ hipError_t launch_struct(const StructJobs& jobs, int total_blocks, octmc_dtype d
 hipError_t launch_combine(const CombineJobs& jobs, int total_blocks, hipStream_t s);
 // the structural partials of every volume pair of n volumes at one level,
 // each volume resampled once (n = 3 or 4; float32 storage, or 16-bit storage
-// at an even depth: see struct_multi_supported); part[q] is pair q's [na][8]
-// partial buffer, the pairs (P, Q), P < Q, in lexicographic order; skip
-// (device flag, may be null): when nonzero the launch does nothing
-bool struct_multi_supported(int n, int d, octmc_dtype dt);
+// at an even storage pitch dp: see struct_multi_supported); part[q] is pair
+// q's [na][8] partial buffer, the pairs (P, Q), P < Q, in lexicographic
+// order; skip (device flag, may be null): when nonzero the launch does nothing
+bool struct_multi_supported(int n, int dp, octmc_dtype dt);
 hipError_t launch_struct_multi(const void* const* vol, int n, const float* disp, float* const* part, int w, int h,
-                               int d, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s,
+                               int d, int dp, uint32_t vol_bytes, float eps_h, octmc_dtype dt, hipStream_t s,
                                const int* skip = nullptr);
 
 // preparation (kernels_prep.hip)
@@ -391,7 +396,7 @@ hipError_t launch_merge_weights_multi(const float* disp, int w, int h, const uns
                                       const MultiVols& mv, double kappa, double tau, float* wo, float* wa,
                                       hipStream_t s);
 hipError_t launch_merge_volume_multi(const MultiVols& mv, octmc_dtype dt, const float* disp, const float* wts, int w,
-                                     int h, int d, float* out, hipStream_t s);
+                                     int h, int d, int dp, float* out, hipStream_t s);
 hipError_t launch_merge_weights(const float* disp, int w, int h, const unsigned long long* grid,
                                 const float* vx, const float* vy, double kappa, double tau, float4* wts,
                                 hipStream_t s);

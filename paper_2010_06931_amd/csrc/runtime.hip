@@ -332,7 +332,7 @@ size_t octmc::pair_footprint(const octmc_params& pr, const octmc_shape& sh, bool
     t += slab_bytes(h * 4) + slab_bytes(w * 4);  // validity
     size_t lw = w, lh = h, ld = d;
     for (int l = 0; l < pr.levels; ++l) {
-        t += 2 * slab_bytes(lw * lh * (es == 2 ? ld + (ld & 1) : ld) * es);  // storage, padded to an even pitch
+        t += 2 * slab_bytes(lw * lh * (size_t)storage_pitch((int)ld, sh.dtype) * es);  // storage at its pitch
         if (l + 1 < pr.levels) {
             const size_t w2 = (lw + 1) / 2, h2 = (lh + 1) / 2, d2 = (ld + 1) / 2;
             t += 2 * slab_bytes(w2 * h2 * d2 * 4) + 2 * slab_bytes(w2 * h2 * 4) + slab_bytes(h2 * 4) +
@@ -634,7 +634,7 @@ int octmc::pair_create_impl(octmc_ctx* ctx, const octmc_params* params, const oc
         L.na = lw * lh;
         // 16-bit storage of an odd depth gets one padding sample per A-scan, so
         // that the two-samples-per-lane structural kernel serves every level
-        L.dp = (P->dtype != OCTMC_F32 && (ld & 1)) ? ld + 1 : ld;
+        L.dp = storage_pitch(ld, P->dtype);
         const size_t lnv = (size_t)L.na * L.dp;
         L.vol_bytes = (uint32_t)(lnv * esize(P->dtype));
         void* st[2];

@@ -126,6 +126,26 @@ def test_multi_merge_parity_and_gap_filling(octmc):
     assert np.all(ma2.cpu().numpy()[np.ix_(bx, by)] == 0.0)
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_multi_merge_odd_depth_16bit(octmc, dtype):
+    """The merge of four volumes of odd depth in 16-bit storage (stored with a
+    padding sample per A-scan) at identity fields: element-wise the oracle's
+    merge of the volumes rounded to the storage type."""
+    sc = synth.make_scans("tiny", 5, (0, 1, 0, 1), n=30, d=37, white_lines=True)
+    log(f"n = 4 merge at identity fields, 30x30x37 {dtype}")
+    M = octmc.Multi(sc.S, sc.orient, octa=sc.O, valid=sc.V, levels=1, iters_per_level=0, dtype=dtype)
+    D, mo, _, _ = M.register(merged=True)
+    torch.cuda.synchronize()
+    assert not D.any()
+    tt = torch.bfloat16 if dtype == "bf16" else torch.float16
+    Sr = [t.to(tt).to(torch.float32) for t in sc.S]
+    Osub = [oracle.substitute_invalid(sc.O[q], sc.V[q], sc.orient[q]) for q in range(4)]
+    om = oracle.Multi(Sr, sc.orient, [oracle.enface_mean(o) for o in Osub], sc.V)
+    rmo, _ = oracle.merge_multi(om, np.zeros((4, 30, 30, 3)), Osub)
+    assert mo.shape == (30, 30, 37)
+    assert np.abs(mo.double().cpu().numpy() - rmo).max() <= 1e-4 * np.abs(rmo).max()
+
+
 def test_multi_rejects_bad_input(octmc, scans):
     sc = scans
     with pytest.raises(octmc.OctmcError):
@@ -193,20 +213,21 @@ def test_multi_fused_objective_parity(octmc, scans, dtype, level, nvol, sigma):
     assert grad_rel(g.double().cpu().numpy(), gp.double().cpu().numpy()) < 1e-5
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "f32"])
-def test_multi_odd_depth_level(octmc, dtype):
-    """A level of odd depth (66 -> 33): pair by pair in BF16 storage (two
-    samples per lane need an even depth), fused in float32 storage; both meet
-    the oracle's bar."""
+@pytest.mark.parametrize("dtype,pairwise", [("bf16", False), ("bf16", True), ("f16", False), ("f32", False)])
+def test_multi_odd_depth_level(octmc, dtype, pairwise):
+    """A level of odd depth (66 -> 33): the 16-bit volumes are stored with a
+    padding sample per A-scan (an even pitch), so the fused pass and the pair
+    kernels both take two samples per lane; float32 storage takes the fused
+    one-sample pass.  Every form meets the oracle's bar."""
     sc = synth.make_scans("tiny", 4, (0, 1, 0, 1), n=36, d=66)
-    M = _gpu_multi(octmc, sc, levels=2, dtype=dtype)
+    M = _gpu_multi(octmc, sc, levels=2, dtype=dtype, pairwise=pairwise)
     w, h, d = M.level_shape(1)
     assert d % 2 == 1
     D = np.random.default_rng(2).normal(0, 0.5, (4, h, w, 3))
     S, A, V = _oracle_level_inputs(sc, 1, range(4), _STORE[dtype])
     om = oracle.Multi(S, sc.orient, A, V)
     ref, _, gref = oracle.evaluate_multi(om, D, oracle.Params(), np.ones(6))
-    log(f"n = 4 {dtype}, odd depth at level 1")
+    log(f"n = 4 {dtype} pairwise={pairwise}, odd depth at level 1")
     t, g = M.eval(1, torch.from_numpy(D).float().cuda(), eta_mode=1)  # stored eta = 1
     torch.cuda.synchronize()
     td = octmc.terms_dict(t)
