@@ -79,8 +79,7 @@ typedef enum { OCTMC_MEM_HOST = 0, OCTMC_MEM_DEVICE = 1 } octmc_mem;
 #define OCTMC_MULTI_PAIRWISE 0x10u /* octmc_multi_*: evaluate the structural term pair by pair (each
                                      volume resampled once per pair it belongs to) instead of the
                                      fused form (each volume resampled once), which serves n = 3 or 4
-                                     volumes in float32 storage, or in 16-bit storage at a level of
-                                     even depth */
+                                     volumes */
 #define OCTMC_HOST_LINE_SEARCH 0x20u /* octmc_register: take the L-BFGS decisions (history update,
                                        search direction, line-search steps) on the host, with a
                                        round trip after every dot-product pass and every trial
@@ -341,9 +340,10 @@ OCTMC_API int octmc_resample_axial(octmc_ctx* ctx, const octmc_shape* shape, con
  * valid (NULL or n vectors of h values for X-fast, w for Y-fast volumes), as
  * octmc_pair_create (OCTMC_DETECT_INVALID and OCTMC_ENFACE_PROJECT apply per
  * volume; OCTMC_PREALIGN is not available here).  Pointers live in
- * shape->mem memory and are copied.  With n = 3 or 4 volumes (float32
- * storage, or BF16/FP16 at a level of even depth) the structural term of
- * all pairs is evaluated in one fused pass that resamples each volume once
+ * shape->mem memory and are copied.  With n = 3 or 4 volumes (any storage
+ * type; BF16/FP16 levels of odd depth are stored with one padding sample per
+ * A-scan) the structural term of all pairs is evaluated in one fused pass
+ * that resamples each volume once
  * (OCTMC_MULTI_PAIRWISE selects the pair-by-pair form; the two agree to
  * float32 rounding).
  * Errors: as octmc_pair_create. */
