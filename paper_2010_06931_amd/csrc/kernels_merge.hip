@@ -137,16 +137,49 @@ __device__ __forceinline__ float ld<f16_t>(const void* p, size_t q)
     return (float)__builtin_bit_cast(_Float16, static_cast<const unsigned short*>(p)[q]);
 }
 
+// 32-bit buffer loads of one sample (wave-uniform column offset in soff)
+template <typename T>
+__device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float ldb<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float ldb<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0) << 16);
+}
+template <>
+__device__ __forceinline__ float ldb<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return (float)__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+template <typename T> struct bytes_of { static constexpr uint32_t v = 2; };
+template <> struct bytes_of<float> { static constexpr uint32_t v = 4; };
+
+// value of the next lane (DPP whole-wave shift; lane 63 reads 0 by bound control)
+__device__ __forceinline__ float next_lane(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+
+// Depth steps of 61 output samples on 64 lanes: lane l holds source sample
+// base + 61 n + l (clamped to the A-scan), and output lane l < 61 reads the
+// blended values of lanes l .. l + 3.
+constexpr int kMergeStep = 61;
+
 // one wavefront per output A-scan, lanes along depth; which = 0 uses the OCT
-// weights (wts.x, wts.y), which = 1 the OCTA weights (wts.z, wts.w)
+// weights (wts.x, wts.y), which = 1 the OCTA weights (wts.z, wts.w).  The 16
+// lateral columns of each scan are read with 32-bit buffer offsets (their
+// offsets and weights wave-uniform), each source sample once per step.
 template <typename T>
 __global__ __launch_bounds__(256) void k_merge_volume(const void* __restrict__ sx, const void* __restrict__ sy,
                                                       const float* __restrict__ disp, const float4* __restrict__ wts,
-                                                      int which, int w, int h, int d, int dp,
+                                                      int which, int w, int h, int d, int dp, uint32_t vol_bytes,
                                                       float* __restrict__ out)
 {
     // sx, sy: [h][w] columns of dp samples (the first d are the A-scan); out: [h][w][d]
-    __shared__ float ring_all[4][2][128];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int na = w * h;
     const int a = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
@@ -155,10 +188,13 @@ __global__ __launch_bounds__(256) void k_merge_volume(const void* __restrict__ s
     const float4 wt = wts[a];
     const float wgt[2] = {which ? wt.z : wt.x, which ? wt.w : wt.y};
     const void* vol[2] = {sx, sy};
-    size_t off[2][16];
+    __amdgpu_buffer_rsrc_t rs[2];
+    uint32_t off[2][16];
     float wl[2][16], wz[2][4];
     int base[2];
+#pragma unroll
     for (int V = 0; V < 2; ++V) {
+        rs[V] = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(vol[V]), (short)0, (int)vol_bytes, 0x00020000);
         const float* dv = disp + ((size_t)V * na + a) * 3;
         const float fxf = floorf(dv[0]), fyf = floorf(dv[1]), fzf = floorf(dv[2]);
         const int nx = i + (int)fxf, ny = j + (int)fyf, nz = (int)fzf;
@@ -166,36 +202,36 @@ __global__ __launch_bounds__(256) void k_merge_volume(const void* __restrict__ s
         cr_w(dv[0] - fxf, wx);
         cr_w(dv[1] - fyf, wy);
         cr_w(dv[2] - fzf, wz[V]);
+#pragma unroll
         for (int b = 0; b < 4; ++b)
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
-                off[V][b * 4 + c] = ((size_t)clampi(ny - 1 + b, 0, h - 1) * w + clampi(nx - 1 + c, 0, w - 1)) * dp;
+                off[V][b * 4 + c] = (uint32_t)__builtin_amdgcn_readfirstlane(
+                    (int)((uint32_t)(clampi(ny - 1 + b, 0, h - 1) * w + clampi(nx - 1 + c, 0, w - 1)) * (uint32_t)dp *
+                          bytes_of<T>::v));
                 wl[V][b * 4 + c] = wx[c] * wy[b];
             }
         base[V] = nz - 1;
     }
-    const int nch = (d + 63) / 64;
-    for (int n = 0; n < nch; ++n) {
+    const int nsteps = (d + kMergeStep - 1) / kMergeStep;
+    for (int n = 0; n < nsteps; ++n) {
         float res = 0.f;
+#pragma unroll
         for (int V = 0; V < 2; ++V) {
-            float* ring = ring_all[wv][V];
-            for (int half = 0; half < 2; ++half) {
-                const int m = clampi(base[V] + (n + half) * 64 + lane, 0, d - 1);
-                float c = 0.f;
-                for (int q = 0; q < 16; ++q) c = fmaf(wl[V][q], ld<T>(vol[V], off[V][q] + m), c);
-                ring[half * 64 + lane] = c;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint32_t voff = (uint32_t)clampi(base[V] + kMergeStep * n + lane, 0, d - 1) * bytes_of<T>::v;
+            float c = 0.f;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) c = fmaf(wl[V][q], ldb<T>(rs[V], voff, off[V][q]), c);
+            const float c1 = next_lane(c), c2 = next_lane(c1), c3 = next_lane(c2);
             float iv = 0.f;
-            for (int c = 0; c < 4; ++c) iv = fmaf(wz[V][c], ring[lane + c], iv);
+            iv = fmaf(wz[V][0], c, iv);
+            iv = fmaf(wz[V][1], c1, iv);
+            iv = fmaf(wz[V][2], c2, iv);
+            iv = fmaf(wz[V][3], c3, iv);
             res = fmaf(wgt[V], iv, res);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        const int k = n * 64 + lane;
-        if (k < d) out[(size_t)a * d + k] = res;
+        const int k = kMergeStep * n + lane;
+        if (lane < kMergeStep && k < d) out[(size_t)a * d + k] = res;
     }
 }
 
@@ -336,18 +372,21 @@ hipError_t launch_merge_volume(const void* vx_, const void* vy_, octmc_dtype dt,
                                const float4* wts, int which, int w, int h, int d, int dp, float* out, hipStream_t s)
 {
     const int blocks = (w * h + 3) / 4;
+    const size_t bytes = (size_t)w * h * dp * (dt == OCTMC_F32 ? 4 : 2);
+    if (bytes >= (1ull << 31)) return hipErrorInvalidValue;  // 32-bit buffer offsets
+    const uint32_t vb = (uint32_t)bytes;
     switch (dt) {
     case OCTMC_F32:
         hipLaunchKernelGGL(k_merge_volume<float>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h, d, dp,
-                           out);
+                           vb, out);
         break;
     case OCTMC_BF16:
         hipLaunchKernelGGL(k_merge_volume<bf16_t>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h,
-                           d, dp, out);
+                           d, dp, vb, out);
         break;
     case OCTMC_F16:
         hipLaunchKernelGGL(k_merge_volume<f16_t>, dim3(blocks), dim3(256), 0, s, vx_, vy_, disp, wts, which, w, h,
-                           d, dp, out);
+                           d, dp, vb, out);
         break;
     default:
         return hipErrorInvalidValue;
