@@ -123,34 +123,35 @@ __global__ __launch_bounds__(256) void k_tilt_finish(const double* __restrict__ 
 
 // out(i, j, k) = I(vol, i, j, k + dz(i, j)): the cubic Hermite interpolator
 // with central-difference tangents (Catmull-Rom) along depth, tap indices
-// clamped to the A-scan.  One thread per output sample.
-__global__ void k_resample_z(const float* __restrict__ vol, const float* __restrict__ dz, size_t na, int d,
-                             float* __restrict__ out)
+// clamped to the A-scan.  One block per A-scan (its shift and taps are
+// uniform), threads along depth.
+__global__ __launch_bounds__(256) void k_resample_z(const float* __restrict__ vol, const float* __restrict__ dz, int d,
+                                                   float* __restrict__ out)
 {
-    const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= na * d) return;
-    const size_t a = q / d;
-    const int k = (int)(q - a * d);
+    const size_t a = blockIdx.x;
     // integer and fractional parts of the shift taken apart so that the
     // fraction is exact (k + dz rounded in float32 would not be); beyond
     // +-(d + 2) every tap is clamped anyway
     const float z = fminf(fmaxf(dz[a], -(float)(d + 2)), (float)(d + 2));
     const float fz = floorf(z);
     const float t = z - fz;
-    const int n = k + (int)fz;
     const float t2 = t * t, t3 = t2 * t;
     const float h00 = 2.0f * t3 - 3.0f * t2 + 1.0f, h10 = t3 - 2.0f * t2 + t;
     const float h01 = -2.0f * t3 + 3.0f * t2, h11 = t3 - t2;
     const float wt[4] = {-0.5f * h10, h00 - 0.5f * h11, h01 + 0.5f * h10, 0.5f * h11};
     const float* __restrict__ col = vol + a * d;
-    float v = 0.0f;
+    float* __restrict__ o = out + a * d;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        const int n = k + (int)fz;
+        float v = 0.0f;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        int idx = n - 1 + e;
-        idx = idx < 0 ? 0 : (idx >= d ? d - 1 : idx);
-        v += wt[e] * col[idx];
+        for (int e = 0; e < 4; ++e) {
+            int idx = n - 1 + e;
+            idx = idx < 0 ? 0 : (idx >= d ? d - 1 : idx);
+            v += wt[e] * col[idx];
+        }
+        o[k] = v;
     }
-    out[q] = v;
 }
 
 }  // namespace
@@ -182,8 +183,9 @@ hipError_t launch_tilt_finish(const double* theta, double* gtheta, int w, int h,
 
 hipError_t launch_resample_z(const float* vol, const float* dz, size_t na, int d, float* out, hipStream_t s)
 {
-    const size_t n = na * d;
-    hipLaunchKernelGGL(k_resample_z, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vol, dz, na, d, out);
+    if (na == 0 || d <= 0) return hipSuccess;
+    if (na > 0x7fffffffu) return hipErrorInvalidValue;  // one block per A-scan
+    hipLaunchKernelGGL(k_resample_z, dim3((unsigned)na), dim3(256), 0, s, vol, dz, d, out);
     return hipGetLastError();
 }
 
