@@ -80,10 +80,10 @@ def test_eval_parity_ragged_all_levels(octmc):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_eval_parity_odd_depth(octmc, dtype):
-    """Odd depth at every level (151, 76, 38): the last sample pair of an
-    A-scan starts at an odd sample (float32) or takes the one-sample-per-lane
-    kernel (16-bit storage); random fields give both parities of the first
-    depth tap in both scans."""
+    """Odd depth at the finest level (151, then 76): with float32 storage the
+    last sample of an A-scan falls in a ragged depth step; 16-bit storage keeps
+    one padding sample per A-scan and the two-samples-per-lane kernel.  Random
+    fields give both parities of the first depth tap in both scans."""
     pair = synth.make_pair("tiny", n=36, d=151)
     # the library builds every level in float32 from the unrounded level above
     # and stores it rounded; the oracle's rounded pyramid takes the same
@@ -105,8 +105,8 @@ def test_eval_parity_minimal_shapes(octmc, n, d, dtype):
     some side (random fields of up to 3 px, smooth ones of 2.5 px), an odd
     width leaves the 2 x 2 tiles of the last row and column partly outside
     the scan, and the depth is far below one depth step of the structural
-    kernels (odd depths take the one-sample-per-lane kernel, even 16-bit
-    depths the two-samples-per-lane one)."""
+    kernels (16-bit storage takes the two-samples-per-lane kernel at every
+    depth, odd ones with a padding sample; float32 the one-sample kernel)."""
     pair = synth.make_pair("tiny", n=n, d=d)
     P = _gpu_pair(octmc, pair, dtype=dtype, levels=1)
     lv = oracle.level_from(round_storage(pair.sx, dtype), round_storage(pair.sy, dtype), pair.ax, pair.ay,
@@ -175,17 +175,18 @@ def test_eval_batched_matches_single(octmc):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("workload,dtype", [("clinical", "f32"), ("dense", "bf16"), ("dense", "f16"),
-                                            ("dense", "f32")])
-def test_eval_parity_full_size_whole_objective(octmc, workload, dtype):
+@pytest.mark.parametrize("workload,dtype,d", [("clinical", "f32", None), ("dense", "bf16", None), ("dense", "f16", None),
+                                              ("dense", "f32", None), ("dense", "bf16", 465)])
+def test_eval_parity_full_size_whole_objective(octmc, workload, dtype, d):
     """The clinical (300 x 300 x 640, float32) and the dense (500 x 500 x 800,
-    BF16, FP16 and float32 storage) pairs, generated on the GPU, in the launch
-    configuration the benchmark times, with the default alpha and mean term and
-    eta computed at the field (Eq. 10): F, every term (both data terms, the
-    regulariser, the mean term, eta) and every gradient entry of all A-scans
-    against the oracle (Eqs. 1-10)."""
-    log(f"generate {workload} on cuda, storage {dtype}")
-    pair = synth.make_pair(workload, device="cuda", octa_volumes=False)
+    BF16, FP16 and float32 storage) pairs, and the dense pair at the paper's
+    depth of 465 samples (odd: BF16 stored with a padding sample), generated
+    on the GPU, in the launch configuration the benchmark times, with the
+    default alpha and mean term and eta computed at the field (Eq. 10): F,
+    every term (both data terms, the regulariser, the mean term, eta) and every
+    gradient entry of all A-scans against the oracle (Eqs. 1-10)."""
+    log(f"generate {workload} (depth {d or 'as defined'}) on cuda, storage {dtype}")
+    pair = synth.make_pair(workload, device="cuda", octa_volumes=False, d=d)
     P = _gpu_pair(octmc, pair, dtype=dtype, levels=4)
     sx, sy = round_storage(pair.sx, dtype), round_storage(pair.sy, dtype)
     lv = oracle.Level(*(oracle._f64(t) for t in (sx, sy, pair.ax, pair.ay, pair.vx, pair.vy)))
